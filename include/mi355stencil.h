@@ -1,0 +1,261 @@
+/*
+ * mi355stencil.h -- C ABI of the MI355X (gfx950) library for iterated 2D
+ * Jacobi stencils with fixed halos, its batched form, 16-bit storage, FP64
+ * norms, and the CNN surrogate that advances a variable-coefficient heat
+ * field K steps at once.
+ *
+ * Conventions for every entry point
+ *   - Returns an int status: ST_OK (0) or a negative ST_E* code.  Never throws.
+ *     stencil_last_error() gives a thread-local message for the last failure.
+ *   - Device pointers are plain HIP device addresses owned by the caller
+ *     (for example torch tensors' data_ptr()).  The library never allocates
+ *     device memory behind the caller's back: scratch space is a caller-owned
+ *     "workspace" whose minimum size is queried first.  Plans, batches and
+ *     models own host memory only (the batched entry point also owns one
+ *     pinned host staging table and one hipGraph).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued on it, asynchronously.  Only the entry
+ *     points marked "synchronises" wait for the device.
+ *   - Fields are row-major with pitch = cols elements: element (i, j) lives at
+ *     base[i * cols + j], i = row in [0, rows), j = column in [0, cols).
+ *   - Launch errors are checked right after each launch (ST_EHIP); faults
+ *     inside a kernel surface at the caller's next synchronisation.
+ */
+#ifndef MI355STENCIL_H
+#define MI355STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ST_OK            0
+#define ST_EINVAL       (-1)  /* bad shape, radius, weights, pointer or count */
+#define ST_EALIAS       (-2)  /* input and output buffers overlap              */
+#define ST_EUNSUPPORTED (-3)  /* no kernel for this combination                */
+#define ST_EHIP         (-4)  /* a HIP runtime call or kernel launch failed     */
+#define ST_ENOWS        (-5)  /* workspace missing or smaller than required    */
+#define ST_ENOMEM       (-6)  /* host allocation failed                        */
+#define ST_ESTATE       (-7)  /* object used in a state that does not allow it */
+
+/* ---- storage types ----------------------------------------------------- */
+#define ST_F32   0   /* IEEE binary32                                     */
+#define ST_BF16  1   /* bfloat16 (upper half of binary32), raw uint16 bits */
+#define ST_F16   2   /* IEEE binary16, raw uint16 bits                     */
+
+/* ---- plan flags -------------------------------------------------------- */
+#define ST_FLAG_NAIVE  0x1u  /* one step per launch, no LDS tiling: the plain GPU reference path */
+#define ST_FLAG_GRAPH  0x2u  /* stencil_run replays its passes from a cached hipGraph            */
+
+#define ST_MAX_RADIUS 4
+
+typedef struct st_plan st_plan;
+typedef struct st_batch st_batch;
+typedef struct sg_model sg_model;
+
+/* stencil_plan -- describe one iterated 2D Jacobi stencil.
+ *
+ * Operation (paper Sec. II-C, Jacobi update equation; Sec. IV-A, zero padding
+ * and halo of depth r; Sec. IV-E, centre-first accumulation):
+ *   for every cell (i, j) of a rows x cols grid,
+ *     u'(i,j) = sum_{dy,dx in [-r, r]} W[dy+r][dx+r] * ~u(i+dy, j+dx),
+ *   where ~u equals u on the grid and the fixed halo value `boundary` outside
+ *   it; the halo is never updated, and every step reads only the previous one.
+ *
+ *   weights   host pointer to (2r+1)^2 floats, row-major; W[dy+r][dx+r]
+ *             multiplies the value dy rows below and dx columns right (a
+ *             correlation).  Copied into the plan.  Must be finite.
+ *   radius    1 <= r <= ST_MAX_RADIUS.
+ *   boundary  fixed halo value b; rounded to the storage type.  Finite.
+ *   storage   ST_F32, ST_BF16 or ST_F16.  Arithmetic is FP32 in every case;
+ *             16-bit fields are rounded (nearest-even) after every step.
+ *   flags     ST_FLAG_* bits.
+ * Per-cell FP32 order: acc = W_c * u_c, then acc = fma(W_k, u_k, acc) over the
+ * footprint taps in row-major (dy, dx) order (star footprint when every weight
+ * off the two axes is zero, else the full box).
+ * Errors: ST_EINVAL (rows or cols < 1, bad radius, non-finite weight or b,
+ * NULL out/weights, unknown storage or flag bits), ST_ENOMEM. */
+int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const float* weights,
+                 double boundary, int storage, uint32_t flags);
+
+/* stencil_plan_varcoef -- variable-coefficient (conservative) heat step, a
+ * Jacobi update (Sec. II-C) whose five weights vary with position:
+ *   u'(c) = u(c) + sum_{nb in N, W, E, S} kf * (u(nb) - u(c)),
+ *   kf = (kappa(c) + kappa(nb)) / 2; at the grid edge kappa(nb) := kappa(c)
+ *   and u(nb) := b.  FP32 order: acc = u(c); for nb in N, W, E, S:
+ *   acc = fma(0.5f * (kappa(c) + kappa(nb)), u(nb) - u(c), acc).
+ * FP32 storage only.  Errors as stencil_plan. */
+int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double boundary, uint32_t flags);
+
+/* stencil_destroy -- free a plan (host memory and any cached graph).  NULL is a no-op. */
+int stencil_destroy(st_plan* plan);
+
+/* stencil_set_blocking -- choose the temporal-blocking depth tb (steps per HBM
+ * round trip, 1..16) and the output tile (tile_x, tile_y) of the tiled
+ * kernel; 0 keeps the current value.  The result is bitwise independent of
+ * these choices.  Errors: ST_EINVAL (value out of range), ST_EUNSUPPORTED
+ * (tile not instantiated; the supported set is listed by stencil_tiles()). */
+int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
+
+/* stencil_get_blocking -- read back the current (tb, tile_x, tile_y). */
+int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y);
+
+/* stencil_tiles -- write up to `cap` supported (tile_x, tile_y) pairs into
+ * `xy` (2 ints each) and their count into *n.  Host-only. */
+int stencil_tiles(int* xy, int cap, int* n);
+
+/* stencil_workspace_bytes -- minimum workspace for stencil_run(plan, ..., steps):
+ * one extra field (rows*cols elements of the storage type) when the run takes
+ * two or more passes, else 0.  Host-only. */
+int stencil_workspace_bytes(const st_plan* plan, int64_t steps, size_t* bytes);
+
+/* stencil_run -- advance `steps` Jacobi steps: out = S^steps(in).
+ *   in, out     device fields of the plan's storage type; `in` is only read.
+ *               They must not overlap (ST_EALIAS).  steps == 0 copies in->out.
+ *   workspace   device scratch of at least stencil_workspace_bytes(steps)
+ *               bytes (ST_ENOWS otherwise); its contents are clobbered.
+ * The passes ping-pong between workspace and out so that the last pass writes
+ * out.  Asynchronous on `stream`.  Varcoef plans use stencil_run_varcoef. */
+int stencil_run(st_plan* plan, const void* in, void* out, int64_t steps, void* workspace,
+                size_t ws_bytes, void* stream);
+
+/* stencil_run_varcoef -- the same for a varcoef plan; kappa is a device FP32
+ * rows x cols diffusivity field (only read). */
+int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, int64_t steps,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* stencil_norms_ws_bytes -- workspace bytes stencil_norms needs (partial sums). */
+int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes);
+
+/* stencil_norms -- FP64 reductions of a field (the host's periodic
+ * convergence check of Sec. IV), written as 4 doubles to the DEVICE pointer
+ * out4:
+ *   out4[0] = sum (u - u_prev)^2     (0 when u_prev is NULL)  -- residual^2
+ *   out4[1] = sum u^2                                        -- energy
+ *   out4[2] = sum u                                          -- mass
+ *   out4[3] = sum_j (u_j - b) S_j + b * rows*cols * sum(W)   -- mass of the next step,
+ *             S_j = sum of the weights W_d whose source cell j - d lies in the grid.
+ * Values are read in the plan's storage type and widened exactly.  The order
+ * of summation is fixed (two-stage tree), so results are run-to-run bitwise
+ * reproducible.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
+                  size_t ws_bytes, void* stream);
+
+/* stencil_autotune -- time every supported (tb, tile) candidate on the
+ * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
+ * Clobbers out and workspace (which must be sized for sample_steps).  Writes
+ * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
+ * Synchronises the stream.  Errors: as stencil_run. */
+int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
+                     int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream);
+
+/* ---- batched: many independent grids, one persistent launch ------------ */
+
+/* stencil_batch_create -- group n plans (FP32, not varcoef; each may differ
+ * in shape, radius, footprint and weights) with their own step counts into one
+ * batch, run by a single persistent kernel whose work items (grid, tile, pass)
+ * wait on per-tile completion counters of the neighbouring tiles' previous
+ * pass (the counter idea of the paper's halo-swap synchronisation, Sec. IV-C).
+ * Each plan's current (tb, tile) is used; run stencil_autotune first to tune.
+ * The plans must outlive the batch.  flags: ST_FLAG_GRAPH captures the
+ * counter reset and the persistent launch in a hipGraph replayed on every run.
+ * Errors: ST_EINVAL, ST_EUNSUPPORTED, ST_ENOMEM. */
+int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int64_t* steps, uint32_t flags);
+
+/* stencil_batch_workspace_bytes -- workspace for the batch: descriptor table,
+ * counters and one extra field per grid. */
+int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
+
+/* stencil_run_batched -- outs[g] = S_g^{steps[g]}(ins[g]) for every grid g.
+ * ins/outs are HOST arrays of n device pointers; no in/out pair may overlap.
+ * Asynchronous on `stream`. */
+int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+/* stencil_batch_status -- read the batch's watchdog flag from the workspace after a run:
+ * *timed_out = 1 if some dependency wait hit its spin limit (results then invalid).  The
+ * persistent kernel bounds every wait so that it always terminates.  Synchronises `stream`. */
+int stencil_batch_status(const st_batch* batch, const void* workspace, int* timed_out, void* stream);
+
+/* stencil_batch_destroy -- free the batch (graph, pinned table).  NULL is a no-op. */
+int stencil_batch_destroy(st_batch* batch);
+
+/* ---- CNN surrogate ------------------------------------------------------ */
+/* Network: 6 conv3x3 layers with zero "same" padding, channels
+ * 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias on every layer, exact-erf GELU
+ * after layers 1-5, residual output  u_hat = u0 + f(u0, (kappa-0.125)/0.075).
+ * Layers 2-5 run as BF16 MFMA implicit GEMMs with FP32 accumulation; layers 1
+ * and 6 run on the vector ALUs in FP32 (BF16 activations are widened exactly).
+ *
+ * Parameter buffer (device, FP32, SG_PARAM_COUNT floats), per layer l = 1..6:
+ *   W_l as [ky][kx][ci][co] (3 x 3 x C_in x C_out), then b_l[C_out].
+ * Optimiser state: Adam m and v, SG_PARAM_COUNT floats each, m then v. */
+#define SG_PARAM_COUNT 37889
+
+/* surrogate_create -- host-side model object (layer table, step counter). */
+int surrogate_create(sg_model** out, uint32_t flags);
+int surrogate_destroy(sg_model* m);
+
+/* surrogate_workspace_bytes -- device workspace for a batch of `batch` fields
+ * of rows x cols: activations, pre-activations, gradients and partial sums. */
+int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_t cols, size_t* bytes);
+
+/* surrogate_forward -- u_hat[b] = surrogate(u0[b], kappa[b]) for `batch`
+ * fields of rows x cols (device FP32, contiguous one after another).
+ * Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+int surrogate_forward(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat,
+                      int batch, int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream);
+
+/* surrogate_loss_grad -- forward, masked MSE loss against `target`, and the
+ * full backward pass:  loss = (1/n) sum_{b, i, j in mask} (u_hat - target)^2
+ * where the mask keeps rows [y_lo, y_hi) x cols [x_lo, x_hi) of every field
+ * (lo_hi = 4 ints) and n counts the kept cells.  Writes d loss / d params to
+ * `grad` (SG_PARAM_COUNT floats) and the loss to the device double *loss.
+ * Deterministic (fixed-order reductions).  Asynchronous. */
+int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa,
+                        const float* target, const int* lo_hi, int batch, int64_t rows, int64_t cols,
+                        float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream);
+
+/* surrogate_adam -- one Adam step (Kingma & Ba, Algorithm 1, bias-corrected)
+ * on params with `grad`; `t` is the 1-based step index.  optim = m then v. */
+int surrogate_adam(sg_model* m, float* params, const float* grad, float* optim, int t, float lr,
+                   float beta1, float beta2, float eps, void* stream);
+
+/* surrogate_synth_fields -- training-data synthesis on the GPU: for each of
+ * `n` coefficient rows (host-drawn random numbers, FP32, 4*(16+8) per row:
+ * 16 sine modes (p, q, a, -) then 8 cosine modes (kx, ky, b, phase)), write
+ *   u0(i,j)    = sum a sin(p pi (i+1)/(rows+1)) sin(q pi (j+1)/(cols+1))
+ *   kappa(i,j) = 0.125 + 0.075 * sum b cos(2 pi (kx j/cols + ky i/rows) + phase) / sum |b|
+ * to u0_out / kappa_out (n fields each, device FP32).  Asynchronous. */
+int surrogate_synth_fields(const float* coef, int n, int64_t rows, int64_t cols, float* u0_out,
+                           float* kappa_out, void* stream);
+
+/* surrogate_crop -- copy n crops of h x w at per-field offsets yx (device
+ * int32 pairs) from fields of rows x cols: src -> dst.  Asynchronous. */
+int surrogate_crop(const float* src, float* dst, const int* yx, int n, int64_t rows, int64_t cols,
+                   int64_t h, int64_t w, void* stream);
+
+/* surrogate_infer_checked -- the surrogate with the plain stencil as judge and
+ * fallback: computes u_hat = surrogate(u0, kappa), then the judge plan
+ * (a varcoef plan) advances u0 by K steps into `out`'s workspace copy and
+ * measures rel = ||u_hat - u_K|| / ||u_K|| in FP64.  If rel <= tol, out =
+ * u_hat; else out = u_K (the plain result) and *used_fallback = 1.  The
+ * surrogate result is therefore never accepted unjudged in this entry point.
+ * Synchronises (to read the error).  Workspace: surrogate workspace for one
+ * field + 2 fields + norms scratch (surrogate_checked_ws_bytes). */
+int surrogate_checked_ws_bytes(const sg_model* m, int64_t rows, int64_t cols, size_t* bytes);
+int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, const float* kappa, float* out,
+                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol,
+                            int* used_fallback, double* rel_err, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- errors ------------------------------------------------------------- */
+const char* stencil_strerror(int code);
+const char* stencil_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355STENCIL_H */

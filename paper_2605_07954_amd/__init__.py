@@ -1,0 +1,330 @@
+"""MI355X (gfx950) library for iterated 2D Jacobi stencils -- Python binding.
+
+A thin ctypes layer over ``include/mi355stencil.h``: every function here has
+the name of the C entry point it calls and only marshals arguments (tensor
+data pointers, the current HIP stream, host arrays).  All arithmetic runs in
+the HIP kernels of ``libmi355stencil.so``; there is no CPU fallback, and every
+call raises if the library is not built or a GPU is not available.
+
+PyTorch supplies device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmi355stencil.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mi355stencil.h")
+
+ST_OK = 0
+ST_F32, ST_BF16, ST_F16 = 0, 1, 2
+ST_FLAG_NAIVE, ST_FLAG_GRAPH = 0x1, 0x2
+SG_PARAM_COUNT = 37889
+STORAGE = {"f32": ST_F32, "bf16": ST_BF16, "f16": ST_F16}
+
+_lib = None
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+
+
+class StencilError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {code} ({_strerror(code)}): {_last_error()}")
+        self.code = code
+
+
+_SIGS = {
+    "stencil_plan": [ctypes.POINTER(_p), _i64, _i64, _int, _p, ctypes.c_double, _int, _u32],
+    "stencil_plan_varcoef": [ctypes.POINTER(_p), _i64, _i64, ctypes.c_double, _u32],
+    "stencil_destroy": [_p],
+    "stencil_set_blocking": [_p, _int, _int, _int],
+    "stencil_get_blocking": [_p, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
+    "stencil_tiles": [ctypes.POINTER(_int), _int, ctypes.POINTER(_int)],
+    "stencil_workspace_bytes": [_p, _i64, ctypes.POINTER(_sz)],
+    "stencil_run": [_p, _p, _p, _i64, _p, _sz, _p],
+    "stencil_run_varcoef": [_p, _p, _p, _p, _i64, _p, _sz, _p],
+    "stencil_norms_ws_bytes": [_p, ctypes.POINTER(_sz)],
+    "stencil_norms": [_p, _p, _p, _p, _p, _sz, _p],
+    "stencil_autotune": [_p, _p, _p, _p, _sz, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                         ctypes.POINTER(_int), _p],
+    "stencil_batch_create": [ctypes.POINTER(_p), _int, ctypes.POINTER(_p), ctypes.POINTER(_i64), _u32],
+    "stencil_batch_workspace_bytes": [_p, ctypes.POINTER(_sz)],
+    "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
+    "stencil_batch_destroy": [_p],
+    "stencil_batch_status": [_p, _p, ctypes.POINTER(_int), _p],
+    "surrogate_create": [ctypes.POINTER(_p), _u32],
+    "surrogate_destroy": [_p],
+    "surrogate_workspace_bytes": [_p, _int, _i64, _i64, ctypes.POINTER(_sz)],
+    "surrogate_forward": [_p, _p, _p, _p, _p, _int, _i64, _i64, _p, _sz, _p],
+    "surrogate_loss_grad": [_p, _p, _p, _p, _p, _p, _int, _i64, _i64, _p, _p, _p, _sz, _p],
+    "surrogate_adam": [_p, _p, _p, _p, _int, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _p],
+    "surrogate_synth_fields": [_p, _int, _i64, _i64, _p, _p, _p],
+    "surrogate_crop": [_p, _p, _p, _int, _i64, _i64, _i64, _i64, _p],
+    "surrogate_checked_ws_bytes": [_p, _i64, _i64, ctypes.POINTER(_sz)],
+    "surrogate_infer_checked": [_p, _p, _p, _p, _p, _i64, _i64, _p, _i64, ctypes.c_double,
+                                ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _p, _sz, _p],
+    "stencil_strerror": [_int],
+    "stencil_last_error": [],
+}
+
+
+def lib():
+    """Load the HIP library.  Raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        try:
+            # load torch's HIP runtime first so that the library binds to the same runtime
+            # instance as the device memory and streams it is handed
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIBPATH)
+        for name, args in _SIGS.items():
+            if not hasattr(L, name):  # reported by the ABI test; calling it raises AttributeError
+                continue
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _int
+        L.stencil_strerror.restype = ctypes.c_char_p
+        L.stencil_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().stencil_strerror(code).decode()
+    except Exception:  # noqa: BLE001 - only used while formatting an error
+        return "?"
+
+
+def _last_error() -> str:
+    try:
+        return lib().stencil_last_error().decode()
+    except Exception:  # noqa: BLE001
+        return ""
+
+
+def _ck(rc: int, what: str):
+    if rc != ST_OK:
+        raise StencilError(rc, what)
+
+
+def _stream(stream):
+    """The HIP stream to enqueue on: an explicit torch stream or torch's current stream."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _p(s.cuda_stream)
+
+
+def _dptr(t, what: str):
+    """Device address of a contiguous GPU tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return _p(t.data_ptr())
+
+
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def storage_code(storage) -> int:
+    return STORAGE[storage] if isinstance(storage, str) else int(storage)
+
+
+# ---------------------------------------------------------------------------
+# plans
+# ---------------------------------------------------------------------------
+
+def stencil_plan(rows: int, cols: int, radius: int, weights, boundary: float = 0.0, storage="f32",
+                 flags: int = 0):
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    h = _p()
+    _ck(lib().stencil_plan(ctypes.byref(h), rows, cols, radius, w.ctypes.data_as(_p), float(boundary),
+                           storage_code(storage), flags), "stencil_plan")
+    return h
+
+
+def stencil_plan_varcoef(rows: int, cols: int, boundary: float = 0.0, flags: int = 0):
+    h = _p()
+    _ck(lib().stencil_plan_varcoef(ctypes.byref(h), rows, cols, float(boundary), flags), "stencil_plan_varcoef")
+    return h
+
+
+def stencil_destroy(plan) -> None:
+    _ck(lib().stencil_destroy(plan), "stencil_destroy")
+
+
+def stencil_set_blocking(plan, tb: int = 0, tile_x: int = 0, tile_y: int = 0) -> None:
+    _ck(lib().stencil_set_blocking(plan, tb, tile_x, tile_y), "stencil_set_blocking")
+
+
+def stencil_get_blocking(plan):
+    tb, tx, ty = _int(), _int(), _int()
+    _ck(lib().stencil_get_blocking(plan, ctypes.byref(tb), ctypes.byref(tx), ctypes.byref(ty)),
+        "stencil_get_blocking")
+    return tb.value, tx.value, ty.value
+
+
+def stencil_tiles():
+    buf = (_int * 64)()
+    n = _int()
+    _ck(lib().stencil_tiles(buf, 32, ctypes.byref(n)), "stencil_tiles")
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(min(n.value, 32))]
+
+
+def stencil_workspace_bytes(plan, steps: int) -> int:
+    n = _sz()
+    _ck(lib().stencil_workspace_bytes(plan, steps, ctypes.byref(n)), "stencil_workspace_bytes")
+    return n.value
+
+
+def stencil_run(plan, inp, out, steps: int, workspace=None, stream=None) -> None:
+    _ck(lib().stencil_run(plan, _dptr(inp, "in"), _dptr(out, "out"), steps, _dptr(workspace, "workspace"),
+                          _nbytes(workspace), _stream(stream)), "stencil_run")
+
+
+def stencil_run_varcoef(plan, inp, kappa, out, steps: int, workspace=None, stream=None) -> None:
+    _ck(lib().stencil_run_varcoef(plan, _dptr(inp, "in"), _dptr(kappa, "kappa"), _dptr(out, "out"), steps,
+                                  _dptr(workspace, "workspace"), _nbytes(workspace), _stream(stream)),
+        "stencil_run_varcoef")
+
+
+def stencil_norms_ws_bytes(plan) -> int:
+    n = _sz()
+    _ck(lib().stencil_norms_ws_bytes(plan, ctypes.byref(n)), "stencil_norms_ws_bytes")
+    return n.value
+
+
+def stencil_norms(plan, u_prev, u, out4, workspace, stream=None) -> None:
+    _ck(lib().stencil_norms(plan, _dptr(u_prev, "u_prev"), _dptr(u, "u"), _dptr(out4, "out4"),
+                            _dptr(workspace, "workspace"), _nbytes(workspace), _stream(stream)), "stencil_norms")
+
+
+def stencil_autotune(plan, inp, out, workspace, sample_steps: int, stream=None):
+    tb, tx, ty = _int(), _int(), _int()
+    _ck(lib().stencil_autotune(plan, _dptr(inp, "in"), _dptr(out, "out"), _dptr(workspace, "workspace"),
+                               _nbytes(workspace), sample_steps, ctypes.byref(tb), ctypes.byref(tx),
+                               ctypes.byref(ty), _stream(stream)), "stencil_autotune")
+    return tb.value, tx.value, ty.value
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+
+def stencil_batch_create(plans, steps, flags: int = 0):
+    n = len(plans)
+    arr = (_p * n)(*[p.value if isinstance(p, _p) else p for p in plans])
+    st = (_i64 * n)(*[int(s) for s in steps])
+    h = _p()
+    _ck(lib().stencil_batch_create(ctypes.byref(h), n, arr, st, flags), "stencil_batch_create")
+    return h
+
+
+def stencil_batch_workspace_bytes(batch) -> int:
+    n = _sz()
+    _ck(lib().stencil_batch_workspace_bytes(batch, ctypes.byref(n)), "stencil_batch_workspace_bytes")
+    return n.value
+
+
+def stencil_run_batched(batch, ins, outs, workspace, stream=None) -> None:
+    n = len(ins)
+    pi = (_p * n)(*[_dptr(t, "in").value for t in ins])
+    po = (_p * n)(*[_dptr(t, "out").value for t in outs])
+    _ck(lib().stencil_run_batched(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace),
+                                  _stream(stream)), "stencil_run_batched")
+
+
+def stencil_batch_status(batch, workspace, stream=None) -> bool:
+    """True if a dependency wait of the last batched run hit its spin limit."""
+    flag = _int()
+    _ck(lib().stencil_batch_status(batch, _dptr(workspace, "workspace"), ctypes.byref(flag), _stream(stream)),
+        "stencil_batch_status")
+    return bool(flag.value)
+
+
+def stencil_batch_destroy(batch) -> None:
+    _ck(lib().stencil_batch_destroy(batch), "stencil_batch_destroy")
+
+
+# ---------------------------------------------------------------------------
+# surrogate
+# ---------------------------------------------------------------------------
+
+def surrogate_create(flags: int = 0):
+    h = _p()
+    _ck(lib().surrogate_create(ctypes.byref(h), flags), "surrogate_create")
+    return h
+
+
+def surrogate_destroy(model) -> None:
+    _ck(lib().surrogate_destroy(model), "surrogate_destroy")
+
+
+def surrogate_workspace_bytes(model, batch: int, rows: int, cols: int) -> int:
+    n = _sz()
+    _ck(lib().surrogate_workspace_bytes(model, batch, rows, cols, ctypes.byref(n)), "surrogate_workspace_bytes")
+    return n.value
+
+
+def surrogate_forward(model, params, u0, kappa, u_hat, batch: int, rows: int, cols: int, workspace,
+                      stream=None) -> None:
+    _ck(lib().surrogate_forward(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
+                                _dptr(u_hat, "u_hat"), batch, rows, cols, _dptr(workspace, "workspace"),
+                                _nbytes(workspace), _stream(stream)), "surrogate_forward")
+
+
+def surrogate_loss_grad(model, params, u0, kappa, target, lo_hi, batch: int, rows: int, cols: int, grad, loss,
+                        workspace, stream=None) -> None:
+    lh = (_int * 4)(*[int(v) for v in lo_hi])
+    _ck(lib().surrogate_loss_grad(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
+                                  _dptr(target, "target"), ctypes.cast(lh, _p), batch, rows, cols,
+                                  _dptr(grad, "grad"), _dptr(loss, "loss"), _dptr(workspace, "workspace"),
+                                  _nbytes(workspace), _stream(stream)), "surrogate_loss_grad")
+
+
+def surrogate_adam(model, params, grad, optim, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8, stream=None) -> None:
+    _ck(lib().surrogate_adam(model, _dptr(params, "params"), _dptr(grad, "grad"), _dptr(optim, "optim"), t,
+                             lr, beta1, beta2, eps, _stream(stream)), "surrogate_adam")
+
+
+def surrogate_synth_fields(coef, n: int, rows: int, cols: int, u0_out, kappa_out, stream=None) -> None:
+    _ck(lib().surrogate_synth_fields(_dptr(coef, "coef"), n, rows, cols, _dptr(u0_out, "u0_out"),
+                                     _dptr(kappa_out, "kappa_out"), _stream(stream)), "surrogate_synth_fields")
+
+
+def surrogate_crop(src, dst, yx, n: int, rows: int, cols: int, h: int, w: int, stream=None) -> None:
+    _ck(lib().surrogate_crop(_dptr(src, "src"), _dptr(dst, "dst"), _dptr(yx, "yx"), n, rows, cols, h, w,
+                             _stream(stream)), "surrogate_crop")
+
+
+def surrogate_checked_ws_bytes(model, rows: int, cols: int) -> int:
+    n = _sz()
+    _ck(lib().surrogate_checked_ws_bytes(model, rows, cols, ctypes.byref(n)), "surrogate_checked_ws_bytes")
+    return n.value
+
+
+def surrogate_infer_checked(model, params, u0, kappa, out, rows: int, cols: int, judge, K: int, tol: float,
+                            workspace, stream=None):
+    used = _int()
+    err = ctypes.c_double()
+    _ck(lib().surrogate_infer_checked(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
+                                      _dptr(out, "out"), rows, cols, judge, K, float(tol), ctypes.byref(used),
+                                      ctypes.byref(err), _dptr(workspace, "workspace"), _nbytes(workspace),
+                                      _stream(stream)), "surrogate_infer_checked")
+    return bool(used.value), err.value

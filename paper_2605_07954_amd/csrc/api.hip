@@ -1,0 +1,394 @@
+// Host side of the C ABI: plans, validation, pass scheduling, graphs, autotuning, errors.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.h"
+
+namespace st {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+size_t elem_size(int storage) { return storage == ST_F32 ? 4 : 2; }
+
+size_t lds_limit() {
+    static std::mutex mu;
+    static size_t cached = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cached) {
+        int dev = 0, optin = 0, plain = 0, count = 0;
+        if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess) {
+            if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+            if (hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) plain = 0;
+        }
+        (void)hipGetLastError();
+        cached = size_t(std::max({optin, plain, 65536}));
+    }
+    return cached;
+}
+
+int prepare_lds(const void* fn, size_t bytes) {
+    if (bytes > lds_limit()) return fail(ST_EUNSUPPORTED, "kernel needs more LDS than a workgroup may have");
+    if (bytes > 65536) ST_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+    return ST_OK;
+}
+
+// Round b to the storage type on the host (nearest even), widened back to float.  The host
+// copy of the conversion is only used for this one plan constant.
+static float round_to_storage(double b, int storage) {
+    float f = float(b);
+    if (storage == ST_F32) return f;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if (storage == ST_BF16) {
+        uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+        float o;
+        std::memcpy(&o, &r, 4);
+        return o;
+    }
+    _Float16 h = (_Float16)f;  // host compiler's IEEE conversion, round to nearest even
+    return (float)h;
+}
+
+static int classify_shape(int r, const float* w) {
+    const int k = 2 * r + 1;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx)
+            if (dy != 0 && dx != 0 && w[(dy + r) * k + dx + r] != 0.0f) return SHAPE_BOX;
+    return SHAPE_STAR;
+}
+
+// default blocking: deeper temporal blocks for cheap stencils, where HBM dominates
+static void default_blocking(st_plan* p) {
+    p->tile_x = 128;
+    p->tile_y = 64;
+    const int taps = p->shape == SHAPE_BOX ? (2 * p->radius + 1) * (2 * p->radius + 1) : 4 * p->radius + 1;
+    int tb = taps >= 40 ? 2 : (taps >= 13 ? 4 : 6);
+    tb = std::min(tb, max_tb(p, p->tile_x, p->tile_y));
+    p->tb = std::max(tb, 1);
+}
+
+static void init_plan(st_plan* p) {
+    std::memset(p, 0, sizeof(*p));
+}
+
+static int check_flags(uint32_t flags) {
+    if (flags & ~(ST_FLAG_NAIVE | ST_FLAG_GRAPH)) return fail(ST_EINVAL, "unknown flag bits");
+    return ST_OK;
+}
+
+// --------------------------------------------------------------------------
+// graphs
+// --------------------------------------------------------------------------
+static void drop_graph(st_plan* p) {
+    if (p->graph_exec) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(p->graph_exec));
+        p->graph_exec = nullptr;
+    }
+}
+
+}  // namespace st
+
+using namespace st;
+
+extern "C" {
+
+const char* stencil_strerror(int code) {
+    switch (code) {
+        case ST_OK: return "success";
+        case ST_EINVAL: return "invalid argument";
+        case ST_EALIAS: return "input and output overlap";
+        case ST_EUNSUPPORTED: return "unsupported configuration";
+        case ST_EHIP: return "HIP runtime error";
+        case ST_ENOWS: return "workspace missing or too small";
+        case ST_ENOMEM: return "host allocation failed";
+        case ST_ESTATE: return "invalid object state";
+    }
+    return "unknown status code";
+}
+
+const char* stencil_last_error(void) { return g_last_error.c_str(); }
+
+int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const float* weights, double boundary,
+                 int storage, uint32_t flags) {
+    if (!out) return fail(ST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (rows < 1 || cols < 1) return fail(ST_EINVAL, "rows and cols must be >= 1");
+    if (rows > (int64_t(1) << 31) || cols > (int64_t(1) << 31)) return fail(ST_EINVAL, "grid side too large");
+    if (radius < 1 || radius > ST_MAX_RADIUS) return fail(ST_EINVAL, "radius must be in [1, 4]");
+    if (!weights) return fail(ST_EINVAL, "weights is NULL");
+    if (storage != ST_F32 && storage != ST_BF16 && storage != ST_F16) return fail(ST_EINVAL, "unknown storage type");
+    if (!std::isfinite(boundary)) return fail(ST_EINVAL, "boundary value must be finite");
+    if (int rc = check_flags(flags)) return rc;
+    const int k = 2 * radius + 1;
+    for (int i = 0; i < k * k; ++i)
+        if (!std::isfinite(weights[i])) return fail(ST_EINVAL, "weights must be finite");
+    st_plan* p = new (std::nothrow) st_plan;
+    if (!p) return fail(ST_ENOMEM, "plan allocation failed");
+    init_plan(p);
+    p->kind = KIND_CONST;
+    p->rows = rows;
+    p->cols = cols;
+    p->radius = radius;
+    p->storage = storage;
+    p->flags = flags;
+    for (int i = 0; i < k * k; ++i) p->w[i] = weights[i];
+    p->shape = classify_shape(radius, weights);
+    p->b = boundary;
+    p->bq = round_to_storage(boundary, storage);
+    double s = 0.0;
+    for (int i = 0; i < k * k; ++i) s += double(weights[i]);
+    p->wsum = s;
+    default_blocking(p);
+    *out = p;
+    return ST_OK;
+}
+
+int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double boundary, uint32_t flags) {
+    if (!out) return fail(ST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (rows < 1 || cols < 1) return fail(ST_EINVAL, "rows and cols must be >= 1");
+    if (rows > (int64_t(1) << 31) || cols > (int64_t(1) << 31)) return fail(ST_EINVAL, "grid side too large");
+    if (!std::isfinite(boundary)) return fail(ST_EINVAL, "boundary value must be finite");
+    if (int rc = check_flags(flags)) return rc;
+    st_plan* p = new (std::nothrow) st_plan;
+    if (!p) return fail(ST_ENOMEM, "plan allocation failed");
+    init_plan(p);
+    p->kind = KIND_VARCOEF;
+    p->rows = rows;
+    p->cols = cols;
+    p->radius = 1;
+    p->shape = SHAPE_STAR;
+    p->storage = ST_F32;
+    p->flags = flags;
+    p->b = boundary;
+    p->bq = float(boundary);
+    p->tb = 4;
+    while (p->tb > 1 && varcoef_lds_bytes(p->tb) > lds_limit()) --p->tb;
+    p->tile_x = 128;
+    p->tile_y = 64;
+    *out = p;
+    return ST_OK;
+}
+
+int stencil_destroy(st_plan* plan) {
+    if (!plan) return ST_OK;
+    drop_graph(plan);
+    delete plan;
+    return ST_OK;
+}
+
+int stencil_tiles(int* xy, int cap, int* n) {
+    if (!n || (cap > 0 && !xy) || cap < 0) return fail(ST_EINVAL, "bad arguments");
+    *n = supported_tiles(xy, cap);
+    return ST_OK;
+}
+
+int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (tb < 0 || tb > 16 || tile_x < 0 || tile_y < 0) return fail(ST_EINVAL, "blocking out of range");
+    const int tx = tile_x ? tile_x : plan->tile_x;
+    const int ty = tile_y ? tile_y : plan->tile_y;
+    if (!tile_supported(plan->shape, plan->radius, tx, ty)) return fail(ST_EUNSUPPORTED, "tile not instantiated");
+    const int t = tb ? tb : plan->tb;
+    if (plan->kind == KIND_CONST && t > max_tb(plan, tx, ty))
+        return fail(ST_EUNSUPPORTED, "temporal block too deep for this tile's LDS budget");
+    if (plan->kind == KIND_VARCOEF && varcoef_lds_bytes(t) > lds_limit())
+        return fail(ST_EUNSUPPORTED, "temporal block too deep for the LDS budget");
+    plan->tb = t;
+    plan->tile_x = tx;
+    plan->tile_y = ty;
+    drop_graph(plan);
+    return ST_OK;
+}
+
+int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (tb) *tb = plan->tb;
+    if (tile_x) *tile_x = plan->tile_x;
+    if (tile_y) *tile_y = plan->tile_y;
+    return ST_OK;
+}
+
+static int64_t n_passes(const st_plan* p, int64_t steps) {
+    if (steps <= 0) return 0;
+    const int64_t tb = (p->flags & ST_FLAG_NAIVE) ? 1 : p->tb;
+    return (steps + tb - 1) / tb;
+}
+
+int stencil_workspace_bytes(const st_plan* plan, int64_t steps, size_t* bytes) {
+    if (!plan || !bytes) return fail(ST_EINVAL, "NULL argument");
+    if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
+    *bytes = n_passes(plan, steps) >= 2 ? size_t(plan->rows * plan->cols) * elem_size(plan->storage) : 0;
+    return ST_OK;
+}
+
+static bool overlap(const void* a, const void* b, size_t n) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + n && y < x + n;
+}
+
+// Enqueue all passes of a run on `s`.
+static int enqueue_run(st_plan* p, const void* in, void* out, const float* kappa, int64_t steps, void* ws,
+                       hipStream_t s) {
+    const size_t bytes = size_t(p->rows * p->cols) * elem_size(p->storage);
+    if (steps == 0) {
+        ST_HIP_CHECK(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
+        return ST_OK;
+    }
+    const bool naive = p->flags & ST_FLAG_NAIVE;
+    const int64_t tb = naive ? 1 : p->tb;
+    const int64_t P = n_passes(p, steps);
+    const void* src = in;
+    for (int64_t k = 0; k < P; ++k) {
+        void* dst = ((P - 1 - k) % 2 == 0) ? out : ws;
+        const int levels = int(std::min<int64_t>(tb, steps - k * tb));
+        int rc;
+        if (p->kind == KIND_VARCOEF)
+            rc = varcoef_launch(p, static_cast<const float*>(src), static_cast<float*>(dst), kappa, naive ? 0 : levels, s);
+        else if (naive)
+            rc = launch_naive(p, src, dst, kappa, s);
+        else
+            rc = launch_pass(p, src, dst, kappa, levels, s);
+        if (rc) return rc;
+        src = dst;
+    }
+    return ST_OK;
+}
+
+static int run_common(st_plan* plan, const void* in, void* out, const float* kappa, int64_t steps, void* workspace,
+                      size_t ws_bytes, void* stream) {
+    if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
+    if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
+    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
+    size_t need = 0;
+    stencil_workspace_bytes(plan, steps, &need);
+    if (need) {
+        if (!workspace || ws_bytes < need) return fail(ST_ENOWS, "workspace too small");
+        if (overlap(workspace, in, bytes) || overlap(workspace, out, bytes))
+            return fail(ST_EALIAS, "workspace overlaps in/out");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!(plan->flags & ST_FLAG_GRAPH) || steps == 0) return enqueue_run(plan, in, out, kappa, steps, workspace, s);
+
+    // graph path: capture the passes once per (in, out, workspace, steps, stream)
+    if (!(plan->graph_exec && plan->g_in == in && plan->g_out == out && plan->g_ws == workspace &&
+          plan->g_steps == steps && plan->g_stream == stream)) {
+        drop_graph(plan);
+        hipStream_t cap;
+        ST_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return fail(ST_EHIP, "hipStreamBeginCapture failed");
+        }
+        int rc = enqueue_run(plan, in, out, kappa, steps, workspace, cap);
+        hipError_t e = hipStreamEndCapture(cap, &graph);
+        (void)hipStreamDestroy(cap);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(ST_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(ST_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        plan->graph_exec = exec;
+        plan->g_in = in;
+        plan->g_out = out;
+        plan->g_ws = workspace;
+        plan->g_steps = steps;
+        plan->g_stream = stream;
+    }
+    ST_HIP_CHECK(hipGraphLaunch(static_cast<hipGraphExec_t>(plan->graph_exec), s));
+    return ST_OK;
+}
+
+int stencil_run(st_plan* plan, const void* in, void* out, int64_t steps, void* workspace, size_t ws_bytes,
+                void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "varcoef plans run through stencil_run_varcoef");
+    return run_common(plan, in, out, nullptr, steps, workspace, ws_bytes, stream);
+}
+
+int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, int64_t steps,
+                        void* workspace, size_t ws_bytes, void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind != KIND_VARCOEF) return fail(ST_EINVAL, "not a varcoef plan");
+    if (!kappa) return fail(ST_EINVAL, "kappa is NULL");
+    const size_t bytes = size_t(plan->rows * plan->cols) * 4;
+    if (overlap(kappa, out, bytes)) return fail(ST_EALIAS, "kappa and out overlap");
+    return run_common(plan, in, out, kappa, steps, workspace, ws_bytes, stream);
+}
+
+int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
+                     int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->flags & ST_FLAG_NAIVE) return fail(ST_ESTATE, "naive plans have nothing to tune");
+    if (sample_steps < 1) return fail(ST_EINVAL, "sample_steps must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t saved_flags = plan->flags;
+    plan->flags &= ~ST_FLAG_GRAPH;
+    int best_tb = plan->tb, best_tx = plan->tile_x, best_ty = plan->tile_y;
+    float best_ms = 1e30f;
+    int tiles[32];
+    const int nt = supported_tiles(tiles, 16);
+    static const int kTb[] = {1, 2, 3, 4, 6, 8};
+    hipEvent_t e0, e1;
+    ST_HIP_CHECK(hipEventCreate(&e0));
+    ST_HIP_CHECK(hipEventCreate(&e1));
+    int rc = ST_OK;
+    for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
+        const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
+        for (int tb : kTb) {
+            if (plan->kind == KIND_CONST && tb > max_tb(plan, tx, ty)) continue;
+            if (tb > sample_steps) continue;
+            plan->tb = tb;
+            plan->tile_x = tx;
+            plan->tile_y = ty;
+            size_t need = 0;
+            stencil_workspace_bytes(plan, sample_steps, &need);
+            if (need > ws_bytes) continue;
+            if ((rc = run_common(plan, in, out, nullptr, sample_steps, workspace, ws_bytes, stream))) break;  // warm-up
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
+            if ((rc = run_common(plan, in, out, nullptr, sample_steps, workspace, ws_bytes, stream))) break;
+            if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ST_EHIP, "hipEventSynchronize"); break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_tb = tb;
+                best_tx = tx;
+                best_ty = ty;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->flags = saved_flags;
+    plan->tb = best_tb;
+    plan->tile_x = best_tx;
+    plan->tile_y = best_ty;
+    drop_graph(plan);
+    if (rc) return rc;
+    if (tb_out) *tb_out = best_tb;
+    if (tile_x_out) *tile_x_out = best_tx;
+    if (tile_y_out) *tile_y_out = best_ty;
+    return ST_OK;
+}
+
+}  // extern "C"

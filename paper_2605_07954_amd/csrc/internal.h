@@ -1,0 +1,99 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/mi355stencil.h"
+
+namespace st {
+
+// thread-local error detail, set by fail()
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+// On failure the runtime's sticky last-error is consumed as well, so that it cannot be
+// mistaken later for the status of an unrelated launch (ours or the caller's).
+#define ST_HIP_CHECK(expr)                                                             \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (void)hipGetLastError();                                                   \
+            return ::st::fail(ST_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                              \
+    } while (0)
+
+#define ST_LAUNCH_CHECK(what)                                                          \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return ::st::fail(ST_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+enum Shape { SHAPE_STAR = 0, SHAPE_BOX = 1 };
+enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1 };
+
+constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
+
+// Kernel argument block of one sweep pass (passed by value; weights live in kernargs).
+struct SweepArgs {
+    const void* src;
+    void* dst;
+    const float* kappa;  // varcoef only
+    int64_t rows, cols;
+    int64_t tiles_x, tiles_y;  // tile grid of this launch
+    float b;                   // halo value, already rounded to the storage type
+    int tb;                    // levels (steps) in this pass
+    float w[MAXK];             // dense (2r+1)^2 row-major weights
+};
+
+}  // namespace st
+
+struct st_plan {
+    int kind;         // st::Kind
+    int64_t rows, cols;
+    int radius;
+    int shape;        // st::Shape
+    int storage;      // ST_F32 / ST_BF16 / ST_F16
+    uint32_t flags;
+    float w[st::MAXK];
+    double b;         // as given
+    float bq;         // b rounded to storage, widened to float
+    double wsum;      // sum of the FP32 weights in FP64
+    int tb, tile_x, tile_y;
+    // cached hipGraph of a full run (ST_FLAG_GRAPH)
+    void* graph_exec;
+    const void* g_in;
+    void* g_out;
+    void* g_ws;
+    int64_t g_steps;
+    void* g_stream;
+};
+
+namespace st {
+
+size_t elem_size(int storage);
+
+// launchers (sweep.hip / varcoef.hip); return ST_OK or an error code
+int launch_pass(const st_plan* p, const void* src, void* dst, const float* kappa, int levels, hipStream_t s);
+int launch_naive(const st_plan* p, const void* src, void* dst, const float* kappa, hipStream_t s);
+bool tile_supported(int shape, int radius, int tx, int ty);
+int supported_tiles(int* xy, int cap);
+int max_tb(const st_plan* p, int tx, int ty);
+int varcoef_launch(const st_plan* p, const float* src, float* dst, const float* kappa, int levels, hipStream_t s);
+size_t tiled_lds_bytes(int r, int tb, int tx, int ty);
+size_t varcoef_lds_bytes(int tb);
+
+// Largest dynamic LDS allocation one workgroup may request on the current device (bytes);
+// 64 KiB when no device is visible.
+size_t lds_limit();
+// Allow `fn` to launch with `bytes` of dynamic LDS (ST_EUNSUPPORTED above lds_limit()).
+int prepare_lds(const void* fn, size_t bytes);
+// Drop a stale runtime error left by earlier API calls so that the check after our next
+// launch reports that launch only.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+}  // namespace st

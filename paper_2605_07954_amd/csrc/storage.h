@@ -1,0 +1,97 @@
+// Storage formats of a field and their exact widening to / rounding from FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/mi355stencil.h"
+
+namespace st {
+
+template <int S>
+struct Fmt;
+
+template <>
+struct Fmt<ST_F32> {
+    using T = float;
+    static constexpr int VEC = 4;  // elements per 16-byte chunk
+    __device__ __forceinline__ static float ld(T v) { return v; }
+    __device__ __forceinline__ static T st(float x) { return x; }
+    __device__ __forceinline__ static float rnd(float x) { return x; }
+};
+
+// bfloat16: the upper 16 bits of a binary32; widening is a shift, rounding is
+// gfx950's hardware convert (round to nearest even).
+template <>
+struct Fmt<ST_BF16> {
+    using T = uint16_t;
+    static constexpr int VEC = 8;
+    __device__ __forceinline__ static float ld(T v) { return __uint_as_float(uint32_t(v) << 16); }
+    __device__ __forceinline__ static T st(float x) {
+        __bf16 h = (__bf16)x;
+        return __builtin_bit_cast(uint16_t, h);
+    }
+    __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
+};
+
+// IEEE binary16 with subnormals; hardware convert, round to nearest even.
+template <>
+struct Fmt<ST_F16> {
+    using T = uint16_t;
+    static constexpr int VEC = 8;
+    __device__ __forceinline__ static float ld(T v) { return (float)__builtin_bit_cast(_Float16, v); }
+    __device__ __forceinline__ static T st(float x) {
+        _Float16 h = (_Float16)x;
+        return __builtin_bit_cast(uint16_t, h);
+    }
+    __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
+};
+
+// Load one 16-byte chunk (VEC elements) and widen to FP32.
+template <int S>
+__device__ __forceinline__ void load_chunk(const typename Fmt<S>::T* p, float* v);
+
+template <>
+__device__ __forceinline__ void load_chunk<ST_F32>(const float* p, float* v) {
+    float4 q = *reinterpret_cast<const float4*>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+
+template <int S>
+__device__ __forceinline__ void load_chunk16(const uint16_t* p, float* v) {
+    uint4 q = *reinterpret_cast<const uint4*>(p);
+    uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = Fmt<S>::ld(uint16_t(w[k] & 0xffffu));
+        v[2 * k + 1] = Fmt<S>::ld(uint16_t(w[k] >> 16));
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_chunk<ST_BF16>(const uint16_t* p, float* v) { load_chunk16<ST_BF16>(p, v); }
+template <>
+__device__ __forceinline__ void load_chunk<ST_F16>(const uint16_t* p, float* v) { load_chunk16<ST_F16>(p, v); }
+
+// Store 4 consecutive FP32 values (rounded to the storage type) with one vector store.
+template <int S>
+__device__ __forceinline__ void store4(typename Fmt<S>::T* p, const float* v);
+
+template <>
+__device__ __forceinline__ void store4<ST_F32>(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+template <int S>
+__device__ __forceinline__ void store4_16(uint16_t* p, const float* v) {
+    uint32_t a = uint32_t(Fmt<S>::st(v[0])) | (uint32_t(Fmt<S>::st(v[1])) << 16);
+    uint32_t b = uint32_t(Fmt<S>::st(v[2])) | (uint32_t(Fmt<S>::st(v[3])) << 16);
+    *reinterpret_cast<uint2*>(p) = make_uint2(a, b);
+}
+template <>
+__device__ __forceinline__ void store4<ST_BF16>(uint16_t* p, const float* v) { store4_16<ST_BF16>(p, v); }
+template <>
+__device__ __forceinline__ void store4<ST_F16>(uint16_t* p, const float* v) { store4_16<ST_F16>(p, v); }
+
+}  // namespace st

@@ -1,0 +1,865 @@
+// CNN surrogate of the variable-coefficient heat step: six 3x3 convolutions (zero "same"
+// padding), channels 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias everywhere, exact-erf GELU after
+// layers 1-5, residual output u_hat = u0 + f(u0, (kappa - 0.125) / 0.075).
+//
+//   layer 1 (2 -> 32)   vector ALU, FP32
+//   layers 2-5 (32->32) BF16 MFMA implicit GEMM (v_mfma_f32_16x16x32_bf16), FP32 accumulate:
+//                       M = 16 consecutive pixels of a row, N = 16 output channels, K = the 32
+//                       input channels of one tap; 9 taps x 2 N-halves per 16 pixels
+//   layer 6 (32 -> 1)   vector ALU, FP32 over BF16 activations
+// Backward: dA = the same MFMA convolution with the taps flipped and the channel roles swapped,
+// times GELU'(Z) in the epilogue; dW of layers 2-5 is an MFMA GEMM whose reduction runs over
+// pixels (activation and gradient tiles are staged channel-major in LDS so that 8 consecutive
+// pixels form one 16-byte operand); every weight/bias gradient is reduced from per-block partial
+// sums in a fixed order, so training is deterministic.
+//
+// Activations are NHWC BF16 (32 channels = 64 bytes per pixel); pre-activations Z are FP32.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+namespace st {
+
+namespace {
+
+constexpr int C = 32;
+constexpr int NL = 6;
+// parameter offsets (floats): W_l [ky][kx][ci][co] then b_l[co]
+constexpr int CI[NL] = {2, 32, 32, 32, 32, 32};
+constexpr int CO[NL] = {32, 32, 32, 32, 32, 1};
+constexpr int woff(int l) {
+    int o = 0;
+    for (int k = 0; k < l; ++k) o += 9 * CI[k] * CO[k] + CO[k];
+    return o;
+}
+constexpr int boff(int l) { return woff(l) + 9 * CI[l] * CO[l]; }
+static_assert(woff(NL) == SG_PARAM_COUNT, "parameter count");
+
+constexpr float KMID = 0.125f, KHALF = 0.075f;
+
+// bf16 <-> f32
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// ---------------------------------------------------------------------------
+// weight preparation: FP32 master -> BF16 MFMA B-operand fragments
+// frag[tap][nt][lane][8]: lane holds W'[tap][k = 8*(lane/16) + i][n = 16*nt + lane%16]
+// forward:   W'[tap][ci][co]  = W[tap][ci][co]
+// backward:  W'[tap][co][ci]  = W[8 - tap][ci][co]   (flipped taps, swapped channel roles)
+// ---------------------------------------------------------------------------
+constexpr int FRAG = 9 * 2 * 64 * 8;  // bf16 per layer and direction
+
+__global__ void prep_frags(const float* params, uint16_t* frags) {
+    // frags: [4 layers][2 directions][FRAG]
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 4 * 2 * FRAG) return;
+    const int l = idx / (2 * FRAG), dir = (idx / FRAG) % 2, r = idx % FRAG;
+    const int tap = r / (2 * 64 * 8), nt = (r / (64 * 8)) % 2, lane = (r / 8) % 64, i = r % 8;
+    const int k = 8 * (lane / 16) + i, n = 16 * nt + lane % 16;
+    const float* W = params + woff(l + 1);
+    float v;
+    if (dir == 0) v = W[(tap * C + k) * C + n];
+    else v = W[((8 - tap) * C + n) * C + k];
+    frags[idx] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// layer 1: 2 -> 32, vector ALU
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* u0, const float* kappa, int nb,
+                                              int H, int W, float* Z, uint16_t* A) {
+    __shared__ float w[9 * 2 * C + C];
+    for (int k = threadIdx.x; k < 9 * 2 * C + C; k += 256) w[k] = params[k];
+    __syncthreads();
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= int64_t(nb) * H * W) return;
+    const int64_t b = p / (int64_t(H) * W);
+    const int y = int((p / W) % H), x = int(p % W);
+    float in[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            const int64_t q = (b * H + yy) * W + xx;
+            in[t][0] = u0[q];
+            in[t][1] = (kappa[q] - KMID) / KHALF;
+        } else {
+            in[t][0] = in[t][1] = 0.0f;
+        }
+    }
+    uint32_t packed[C / 2];
+#pragma unroll
+    for (int co = 0; co < C; ++co) {
+        float acc = w[9 * 2 * C + co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            acc = __builtin_fmaf(w[(t * 2 + 0) * C + co], in[t][0], acc);
+            acc = __builtin_fmaf(w[(t * 2 + 1) * C + co], in[t][1], acc);
+        }
+        if (Z) Z[p * C + co] = acc;
+        const uint32_t h = f2bf(gelu(acc));
+        if (co & 1) packed[co / 2] |= h << 16; else packed[co / 2] = h;
+    }
+    uint4* dst = reinterpret_cast<uint4*>(A + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// 32 -> 32 MFMA convolution (forward, or backward-data with flipped fragments)
+// Tile: TH x TW pixels per 256-thread workgroup; each wave owns TH/4 rows x TW pixels.
+// ---------------------------------------------------------------------------
+constexpr int TH = 8, TW = 32;
+
+enum Epi { EPI_FWD = 0, EPI_BWD_BF16 = 1, EPI_BWD_F32 = 2 };
+
+struct ConvArgs {
+    const uint16_t* X;      // input activations (fwd) or dZ (bwd), NHWC bf16
+    const uint16_t* frags;  // 9 x 2 x 64 x 8 bf16
+    const float* bias;      // fwd only
+    const float* Zprev;     // bwd: pre-activations whose GELU' scales the result
+    float* Zout;            // fwd: pre-activation out (nullable)
+    uint16_t* Aout;         // fwd: GELU(Z) bf16; bwd: dZ bf16
+    float* Fout;            // bwd: dZ fp32 (layer-1 target)
+    int nb, H, W;
+    int epi;
+};
+
+__global__ __launch_bounds__(256) void conv_mfma(ConvArgs a) {
+    __shared__ uint4 tile[(TH + 2) * (TW + 2) * 4];  // pixels x 4 chunks of 8 channels
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+    const int64_t bt = blockIdx.x;
+    const int b = int(bt / (int64_t(tiles_x) * tiles_y));
+    const int tr = int(bt % (int64_t(tiles_x) * tiles_y));
+    const int y0 = (tr / tiles_x) * TH, x0 = (tr % tiles_x) * TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // stage the haloed input tile (zero outside the field)
+    for (int k = threadIdx.x; k < (TH + 2) * (TW + 2) * 4; k += 256) {
+        const int pix = k >> 2, ch = k & 3;
+        const int yy = y0 - 1 + pix / (TW + 2), xx = x0 - 1 + pix % (TW + 2);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+            v = reinterpret_cast<const uint4*>(a.X + ((int64_t(b) * a.H + yy) * a.W + xx) * C)[ch];
+        tile[k] = v;
+    }
+    // B fragments of all taps into registers
+    bf16x8_t bfr[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+            bfr[t][nt] = *reinterpret_cast<const bf16x8_t*>(a.frags + ((t * 2 + nt) * 64 + lane) * 8);
+    __syncthreads();
+
+    constexpr int ROWS = TH / 4;   // rows per wave
+    constexpr int MT = TW / 16;    // M-tiles per row
+    f32x4_t acc[ROWS][MT][2];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[r][m][nt] = f32x4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int ty = wave * ROWS + r;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int py = ty + t / 3, px = m * 16 + (lane & 15) + t % 3;
+                const uint4 q = tile[(py * (TW + 2) + px) * 4 + (lane >> 4)];
+                const bf16x8_t av = __builtin_bit_cast(bf16x8_t, q);
+                acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bfr[t][0], acc[r][m][0], 0, 0, 0);
+                acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bfr[t][1], acc[r][m][1], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds D[pixel m = 4*(lane/16) + i][channel 16*nt + lane%16]
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + wave * ROWS + r;
+        if (y >= a.H) continue;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int x = x0 + m * 16 + 4 * (lane >> 4) + i;
+                    if (x >= a.W) continue;
+                    const int co = 16 * nt + (lane & 15);
+                    const int64_t o = ((int64_t(b) * a.H + y) * a.W + x) * C + co;
+                    float v = acc[r][m][nt][i];
+                    if (a.epi == EPI_FWD) {
+                        v += a.bias[co];
+                        if (a.Zout) a.Zout[o] = v;
+                        a.Aout[o] = f2bf(gelu(v));
+                    } else {
+                        v *= gelu_grad(a.Zprev[o]);
+                        if (a.epi == EPI_BWD_BF16) a.Aout[o] = f2bf(v);
+                        else a.Fout[o] = v;
+                    }
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layer 6: 32 -> 1 (forward with residual; backward data)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void l6_fwd(const float* params, const uint16_t* A5, const float* u0, int nb, int H,
+                                              int W, float* uhat) {
+    __shared__ float w[9 * C + 1];
+    for (int k = threadIdx.x; k < 9 * C + 1; k += 256) w[k] = params[woff(5) + k];
+    __syncthreads();
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= int64_t(nb) * H * W) return;
+    const int64_t b = p / (int64_t(H) * W);
+    const int y = int((p / W) % H), x = int(p % W);
+    float acc = w[9 * C];
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+        const uint4* src = reinterpret_cast<const uint4*>(A5 + ((b * H + yy) * W + xx) * C);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = src[q];
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ci = q * 8 + 2 * e;
+                acc = __builtin_fmaf(w[t * C + ci], bf2f(uint16_t(wd[e] & 0xffffu)), acc);
+                acc = __builtin_fmaf(w[t * C + ci + 1], bf2f(uint16_t(wd[e] >> 16)), acc);
+            }
+        }
+    }
+    uhat[p] = u0[p] + acc;
+}
+
+// dF = (2/n) (u_hat - target) on the mask; per-block FP64 partial sums of the squared error
+__global__ __launch_bounds__(256) void loss_grad(const float* uhat, const float* target, int nb, int H, int W,
+                                                 int ylo, int yhi, int xlo, int xhi, double inv_n, float* dF,
+                                                 double* partial) {
+    __shared__ double red[256];
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double e2 = 0.0;
+    if (p < int64_t(nb) * H * W) {
+        const int y = int((p / W) % H), x = int(p % W);
+        const bool in = y >= ylo && y < yhi && x >= xlo && x < xhi;
+        const float d = in ? uhat[p] - target[p] : 0.0f;
+        dF[p] = float(2.0 * inv_n) * d;
+        e2 = double(d) * double(d);
+    }
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void loss_finish(const double* partial, int n, double inv_n, double* loss) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) s += partial[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * inv_n;
+}
+
+// dZ5[p][ci] = GELU'(Z5[p][ci]) * sum_t W6[t][ci] dF[p - t + (1,1)]   (bf16)
+__global__ __launch_bounds__(256) void l6_bwd_data(const float* params, const float* dF, const float* Z5, int nb,
+                                                   int H, int W, uint16_t* dZ5) {
+    __shared__ float w[9 * C];
+    for (int k = threadIdx.x; k < 9 * C; k += 256) w[k] = params[woff(5) + k];
+    __syncthreads();
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= int64_t(nb) * H * W) return;
+    const int64_t b = p / (int64_t(H) * W);
+    const int y = int((p / W) % H), x = int(p % W);
+    float g[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+        g[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? dF[(b * H + yy) * W + xx] : 0.0f;
+    }
+    uint32_t packed[C / 2];
+#pragma unroll
+    for (int ci = 0; ci < C; ++ci) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = __builtin_fmaf(w[t * C + ci], g[t], acc);
+        const uint32_t h = f2bf(acc * gelu_grad(Z5[p * C + ci]));
+        if (ci & 1) packed[ci / 2] |= h << 16; else packed[ci / 2] = h;
+    }
+    uint4* dst = reinterpret_cast<uint4*>(dZ5 + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: per-block partials over a 32 x 32 pixel region, reduced later in fixed order
+// ---------------------------------------------------------------------------
+constexpr int RH = 32, RW = 32;  // pixels per partial block
+
+// layer 1: dW1[t][ci][co] = sum_p X0[p + t][ci] dZ1[p][co], db1[co] = sum_p dZ1[p][co]  (all FP32)
+// one thread per (t, ci, co) output (576) plus 32 bias threads; loops over the region's pixels.
+__global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const float* kappa, const float* dZ1, int nb,
+                                                     int H, int W, float* partial) {
+    const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
+    const int blk = blockIdx.x;
+    const int b = blk / (rx * ry), r = blk % (rx * ry);
+    const int y0 = (r / rx) * RH, x0 = (r % rx) * RW;
+    const int j = threadIdx.x;
+    if (j >= 9 * 2 * C + C) return;
+    float acc = 0.0f;
+    if (j < 9 * 2 * C) {
+        const int t = j / (2 * C), ci = (j / C) % 2, co = j % C;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        for (int y = y0; y < min(y0 + RH, H); ++y)
+            for (int x = x0; x < min(x0 + RW, W); ++x) {
+                const int yy = y + dy, xx = x + dx;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const int64_t q = (int64_t(b) * H + yy) * W + xx;
+                const float xin = ci == 0 ? u0[q] : (kappa[q] - KMID) / KHALF;
+                acc = __builtin_fmaf(xin, dZ1[((int64_t(b) * H + y) * W + x) * C + co], acc);
+            }
+    } else {
+        const int co = j - 9 * 2 * C;
+        for (int y = y0; y < min(y0 + RH, H); ++y)
+            for (int x = x0; x < min(x0 + RW, W); ++x) acc += dZ1[((int64_t(b) * H + y) * W + x) * C + co];
+    }
+    partial[int64_t(blk) * (9 * 2 * C + C) + j] = acc;
+}
+
+// layer 6: dW6[t][ci] = sum_p A5[p + t][ci] dF[p], db6 = sum_p dF[p]
+__global__ __launch_bounds__(320) void l6_bwd_weight(const uint16_t* A5, const float* dF, int nb, int H, int W,
+                                                     float* partial) {
+    const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
+    const int blk = blockIdx.x;
+    const int b = blk / (rx * ry), r = blk % (rx * ry);
+    const int y0 = (r / rx) * RH, x0 = (r % rx) * RW;
+    const int j = threadIdx.x;
+    if (j >= 9 * C + 1) return;
+    float acc = 0.0f;
+    if (j < 9 * C) {
+        const int t = j / C, ci = j % C;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        for (int y = y0; y < min(y0 + RH, H); ++y)
+            for (int x = x0; x < min(x0 + RW, W); ++x) {
+                const int yy = y + dy, xx = x + dx;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                acc = __builtin_fmaf(bf2f(A5[((int64_t(b) * H + yy) * W + xx) * C + ci]),
+                                     dF[(int64_t(b) * H + y) * W + x], acc);
+            }
+    } else {
+        for (int y = y0; y < min(y0 + RH, H); ++y)
+            for (int x = x0; x < min(x0 + RW, W); ++x) acc += dF[(int64_t(b) * H + y) * W + x];
+    }
+    partial[int64_t(blk) * (9 * C + 1) + j] = acc;
+}
+
+// layers 2-5: dW[t][ci][co] = sum_p A[p + t][ci] dZ[p][co] on MFMA.  The region is processed in
+// 8-row chunks; per chunk the activation tile (with halo) is staged channel-major three times,
+// shifted by 0, 1, 2 pixels in x, and the gradient tile channel-major, so that each MFMA
+// operand (8 consecutive pixels of one channel) is one aligned 16-byte LDS read.
+// Wave w owns the output quarter (ci half w/2, co half w%2) for all 9 taps.
+// db[co] = sum_p dZ[p][co] is accumulated from the staged gradient tile.
+constexpr int CH = 8;  // rows per chunk
+__global__ __launch_bounds__(256) void mfma_bwd_weight(const uint16_t* A, const uint16_t* dZ, int nb, int H, int W,
+                                                       float* partial) {
+    __shared__ uint16_t at[3][C][CH + 2][RW];  // [shift][ci][row][x]: A at (row-1, x+shift-1) of the chunk
+    __shared__ uint16_t gt[C][CH][RW];         // [co][row][x]
+    __shared__ float bsum[4][C];
+    const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
+    const int blk = blockIdx.x;
+    const int b = blk / (rx * ry), r = blk % (rx * ry);
+    const int y0 = (r / rx) * RH, x0 = (r % rx) * RW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mh = wave >> 1, nh = wave & 1;
+    f32x4_t acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4_t{0, 0, 0, 0};
+    float bacc = 0.0f;  // thread c < 32: running bias sum of channel c... computed below
+    if (threadIdx.x < 4 * C) bsum[threadIdx.x / C][threadIdx.x % C] = 0.0f;
+    for (int c0 = 0; c0 < RH; c0 += CH) {
+        const int cy0 = y0 + c0;
+        __syncthreads();
+        // stage A: rows cy0-1 .. cy0+CH, cols x0-1 .. x0+RW (34 pixels), 4 chunks of 8 channels each
+        for (int k = threadIdx.x; k < (CH + 2) * (RW + 2) * 4; k += 256) {
+            const int pix = k >> 2, cq = k & 3;
+            const int row = pix / (RW + 2), col = pix % (RW + 2);
+            const int yy = cy0 - 1 + row, xx = x0 - 1 + col;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = reinterpret_cast<const uint4*>(A + ((int64_t(b) * H + yy) * W + xx) * C)[cq];
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint16_t h = uint16_t(e & 1 ? wd[e >> 1] >> 16 : wd[e >> 1] & 0xffffu);
+                const int ci = cq * 8 + e;
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const int x = col - s;  // tile column col holds A(x0-1+col); copy s at x holds A(x0-1+x+s)
+                    if (x >= 0 && x < RW) at[s][ci][row][x] = h;
+                }
+            }
+        }
+        // stage dZ: rows cy0 .. cy0+CH-1, cols x0 .. x0+RW-1 (zero outside the field)
+        for (int k = threadIdx.x; k < CH * RW * 4; k += 256) {
+            const int pix = k >> 2, cq = k & 3;
+            const int row = pix / RW, col = pix % RW;
+            const int yy = cy0 + row, xx = x0 + col;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy < H && xx < W) v = reinterpret_cast<const uint4*>(dZ + ((int64_t(b) * H + yy) * W + xx) * C)[cq];
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                gt[cq * 8 + e][row][col] = uint16_t(e & 1 ? wd[e >> 1] >> 16 : wd[e >> 1] & 0xffffu);
+        }
+        __syncthreads();
+        // bias partial: thread j < 128 sums channel j%32 over a quarter of the chunk's pixels
+        if (threadIdx.x < 4 * C) {
+            const int co = threadIdx.x % C, q = threadIdx.x / C;
+            float s = 0.0f;
+            for (int rr = q * (CH / 4); rr < (q + 1) * (CH / 4); ++rr)
+                for (int x = 0; x < RW; ++x) s += bf2f(gt[co][rr][x]);
+            bsum[q][co] += s;
+        }
+        // MFMA over the chunk: K = 32 pixels of one row per instruction
+#pragma unroll
+        for (int rr = 0; rr < CH; ++rr) {
+            const bf16x8_t bv = *reinterpret_cast<const bf16x8_t*>(&gt[nh * 16 + (lane & 15)][rr][8 * (lane >> 4)]);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int ky = t / 3, kx = t % 3;
+                const bf16x8_t av =
+                    *reinterpret_cast<const bf16x8_t*>(&at[kx][mh * 16 + (lane & 15)][rr + ky][8 * (lane >> 4)]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+    // D layout: lane holds D[ci = 16*mh + 4*(lane/16) + i][co = 16*nh + lane%16]
+    float* out = partial + int64_t(blk) * (9 * C * C + C);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ci = 16 * mh + 4 * (lane >> 4) + i, co = 16 * nh + (lane & 15);
+            out[(t * C + ci) * C + co] = acc[t][i];
+        }
+    if (threadIdx.x < C) out[9 * C * C + threadIdx.x] = ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) +
+                                                          bsum[2][threadIdx.x]) + bsum[3][threadIdx.x];
+    (void)bacc;
+}
+
+// grad[off + j] = sum_{blk} partial[blk][j] in block order (FP64 accumulation)
+__global__ void reduce_partials(const float* partial, int nblk, int len, float* grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= len) return;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += double(partial[int64_t(k) * len + j]);
+    grad[j] = float(s);
+}
+
+// ---------------------------------------------------------------------------
+// Adam (Kingma & Ba, Algorithm 1) with bias correction
+// ---------------------------------------------------------------------------
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mhat = mi / c1, vhat = vi / c2;
+    p[i] -= lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// training-data synthesis and crops
+// ---------------------------------------------------------------------------
+constexpr int NU = 16, NK = 8;
+__global__ void synth_kernel(const float* coef, int n, int rows, int cols, float* u0, float* kappa) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(n) * rows * cols) return;
+    const int t = int(idx / (int64_t(rows) * cols));
+    const int i = int((idx / cols) % rows), j = int(idx % cols);
+    const float* c = coef + int64_t(t) * 4 * (NU + NK);
+    const double pi = 3.14159265358979323846;
+    double u = 0.0;
+    for (int m = 0; m < NU; ++m) {
+        const double p = c[4 * m], q = c[4 * m + 1], a = c[4 * m + 2];
+        u += a * sin(p * pi * (i + 1) / (rows + 1)) * sin(q * pi * (j + 1) / (cols + 1));
+    }
+    double g = 0.0, nrm = 0.0;
+    for (int m = NU; m < NU + NK; ++m) {
+        const double kx = c[4 * m], ky = c[4 * m + 1], bb = c[4 * m + 2], ph = c[4 * m + 3];
+        g += bb * cos(2.0 * pi * (kx * j / cols + ky * double(i) / rows) + ph);
+        nrm += fabs(bb);
+    }
+    u0[idx] = float(u);
+    kappa[idx] = float(0.125 + 0.075 * g / fmax(nrm, 1e-30));
+}
+
+__global__ void crop_kernel(const float* src, float* dst, const int* yx, int n, int rows, int cols, int h, int w) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(n) * h * w) return;
+    const int t = int(idx / (int64_t(h) * w));
+    const int i = int((idx / w) % h), j = int(idx % w);
+    const int y = yx[2 * t] + i, x = yx[2 * t + 1] + j;
+    dst[idx] = (y >= 0 && y < rows && x >= 0 && x < cols) ? src[(int64_t(t) * rows + y) * cols + x] : 0.0f;
+}
+
+// FP64 sums of (a - b)^2 and b^2 (judge error), two-stage fixed order
+__global__ void diff_norms(const float* a, const float* b, int64_t n, double* partial) {
+    __shared__ double r0[256], r1[256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
+        const double d = double(a[k]) - double(b[k]);
+        s0 += d * d;
+        s1 += double(b[k]) * double(b[k]);
+    }
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            r0[threadIdx.x] += r0[threadIdx.x + h];
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = r0[0];
+        partial[2 * blockIdx.x + 1] = r1[0];
+    }
+}
+
+__global__ void diff_norms_finish(const double* partial, int nblk, double* out2) {
+    if (threadIdx.x != 0) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        s0 += partial[2 * k];
+        s1 += partial[2 * k + 1];
+    }
+    out2[0] = s0;
+    out2[1] = s1;
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// workspace layout for a batch of nb fields of H x W
+struct WsLayout {
+    size_t frags, act[5], z[5], dzb[2], dz1, dF, partial, lossp, total;
+    int64_t npix;
+    int nblk_px, nblk_rg;
+};
+
+WsLayout layout(int nb, int64_t H, int64_t W, bool train) {
+    WsLayout L;
+    L.npix = int64_t(nb) * H * W;
+    L.nblk_px = int((L.npix + 255) / 256);
+    L.nblk_rg = int(nb * ((H + RH - 1) / RH) * ((W + RW - 1) / RW));
+    size_t off = 0;
+    L.frags = off;
+    off = a256(off + size_t(4) * 2 * FRAG * 2);
+    const size_t actb = size_t(L.npix) * C * 2, zb = size_t(L.npix) * C * 4;
+    for (int l = 0; l < 5; ++l) {
+        if (train || l < 2) {
+            L.act[l] = off;
+            off = a256(off + actb);
+        } else {
+            L.act[l] = L.act[l % 2];  // inference ping-pongs two activation buffers
+        }
+    }
+    for (int l = 0; l < 5; ++l) {
+        if (train) {
+            L.z[l] = off;
+            off = a256(off + zb);
+        } else {
+            L.z[l] = 0;
+        }
+    }
+    if (train) {
+        L.dzb[0] = off;
+        off = a256(off + actb);
+        L.dzb[1] = off;
+        off = a256(off + actb);
+        L.dz1 = off;
+        off = a256(off + zb);
+        L.dF = off;
+        off = a256(off + size_t(L.npix) * 4);
+        L.partial = off;
+        off = a256(off + size_t(L.nblk_rg) * (9 * C * C + C) * 4);
+        L.lossp = off;
+        off = a256(off + size_t(L.nblk_px) * 8);
+    } else {
+        L.dzb[0] = L.dzb[1] = L.dz1 = L.dF = L.partial = L.lossp = 0;
+    }
+    L.total = off;
+    return L;
+}
+
+int check_dims(int nb, int64_t H, int64_t W) {
+    if (nb < 1 || H < 1 || W < 1 || H > 32768 || W > 32768 || int64_t(nb) * H * W > (int64_t(1) << 31))
+        return fail(ST_EINVAL, "bad surrogate batch/shape");
+    return ST_OK;
+}
+
+int forward_impl(const float* params, const float* u0, const float* kappa, float* uhat, int nb, int H, int W,
+                 char* ws, const WsLayout& L, bool train, hipStream_t s) {
+    uint16_t* frags = reinterpret_cast<uint16_t*>(ws + L.frags);
+    clear_stale_error();
+    hipLaunchKernelGGL(prep_frags, dim3((4 * 2 * FRAG + 255) / 256), dim3(256), 0, s, params, frags);
+    ST_LAUNCH_CHECK("prep_frags");
+    const unsigned gpx = unsigned(L.nblk_px);
+    auto act = [&](int l) { return reinterpret_cast<uint16_t*>(ws + L.act[l]); };
+    auto zz = [&](int l) { return train ? reinterpret_cast<float*>(ws + L.z[l]) : nullptr; };
+    hipLaunchKernelGGL(l1_fwd, dim3(gpx), dim3(256), 0, s, params, u0, kappa, nb, H, W, zz(0), act(0));
+    ST_LAUNCH_CHECK("l1_fwd");
+    const unsigned gt = unsigned(int64_t(nb) * ((H + TH - 1) / TH) * ((W + TW - 1) / TW));
+    for (int l = 1; l <= 4; ++l) {
+        ConvArgs a;
+        a.X = act(l - 1);
+        a.frags = frags + size_t(l - 1) * 2 * FRAG;
+        a.bias = params + boff(l);
+        a.Zprev = nullptr;
+        a.Zout = zz(l);
+        a.Aout = act(l);
+        a.Fout = nullptr;
+        a.nb = nb;
+        a.H = H;
+        a.W = W;
+        a.epi = EPI_FWD;
+        hipLaunchKernelGGL(conv_mfma, dim3(gt), dim3(256), 0, s, a);
+        ST_LAUNCH_CHECK("conv_mfma fwd");
+    }
+    hipLaunchKernelGGL(l6_fwd, dim3(gpx), dim3(256), 0, s, params, act(4), u0, nb, H, W, uhat);
+    ST_LAUNCH_CHECK("l6_fwd");
+    return ST_OK;
+}
+
+}  // namespace
+
+}  // namespace st
+
+using namespace st;
+
+struct sg_model {
+    uint32_t flags;
+};
+
+extern "C" {
+
+int surrogate_create(sg_model** out, uint32_t flags) {
+    if (!out) return fail(ST_EINVAL, "out is NULL");
+    if (flags) return fail(ST_EINVAL, "no surrogate flags are defined");
+    sg_model* m = new (std::nothrow) sg_model;
+    if (!m) return fail(ST_ENOMEM, "model allocation failed");
+    m->flags = flags;
+    *out = m;
+    return ST_OK;
+}
+
+int surrogate_destroy(sg_model* m) {
+    delete m;
+    return ST_OK;
+}
+
+int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_t cols, size_t* bytes) {
+    if (!m || !bytes) return fail(ST_EINVAL, "NULL argument");
+    if (int rc = check_dims(batch, rows, cols)) return rc;
+    *bytes = layout(batch, rows, cols, true).total;
+    return ST_OK;
+}
+
+int surrogate_forward(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat, int batch,
+                      int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream) {
+    if (!m || !params || !u0 || !kappa || !u_hat) return fail(ST_EINVAL, "NULL argument");
+    if (int rc = check_dims(batch, rows, cols)) return rc;
+    const WsLayout L = layout(batch, rows, cols, false);
+    if (!workspace || ws_bytes < L.total) return fail(ST_ENOWS, "workspace too small");
+    return forward_impl(params, u0, kappa, u_hat, batch, int(rows), int(cols), static_cast<char*>(workspace), L, false,
+                        static_cast<hipStream_t>(stream));
+}
+
+int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa, const float* target,
+                        const int* lo_hi, int batch, int64_t rows, int64_t cols, float* grad, double* loss,
+                        void* workspace, size_t ws_bytes, void* stream) {
+    if (!m || !params || !u0 || !kappa || !target || !lo_hi || !grad || !loss) return fail(ST_EINVAL, "NULL argument");
+    if (int rc = check_dims(batch, rows, cols)) return rc;
+    const int ylo = std::max(0, lo_hi[0]), yhi = std::min<int>(int(rows), lo_hi[1]);
+    const int xlo = std::max(0, lo_hi[2]), xhi = std::min<int>(int(cols), lo_hi[3]);
+    if (yhi <= ylo || xhi <= xlo) return fail(ST_EINVAL, "empty loss mask");
+    const WsLayout L = layout(batch, rows, cols, true);
+    if (!workspace || ws_bytes < L.total) return fail(ST_ENOWS, "workspace too small");
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int H = int(rows), W = int(cols), nb = batch;
+    float* uhat = reinterpret_cast<float*>(ws + L.dz1);  // scratch: dz1 is not needed until layer-2 backward
+    if (int rc = forward_impl(params, u0, kappa, uhat, nb, H, W, ws, L, true, s)) return rc;
+    const double n = double(nb) * (yhi - ylo) * (xhi - xlo);
+    float* dF = reinterpret_cast<float*>(ws + L.dF);
+    double* lossp = reinterpret_cast<double*>(ws + L.lossp);
+    const unsigned gpx = unsigned(L.nblk_px);
+    hipLaunchKernelGGL(loss_grad, dim3(gpx), dim3(256), 0, s, uhat, target, nb, H, W, ylo, yhi, xlo, xhi, 1.0 / n,
+                       dF, lossp);
+    ST_LAUNCH_CHECK("loss_grad");
+    hipLaunchKernelGGL(loss_finish, dim3(1), dim3(256), 0, s, lossp, L.nblk_px, 1.0 / n, loss);
+    ST_LAUNCH_CHECK("loss_finish");
+    auto act = [&](int l) { return reinterpret_cast<uint16_t*>(ws + L.act[l]); };
+    auto zz = [&](int l) { return reinterpret_cast<float*>(ws + L.z[l]); };
+    float* partial = reinterpret_cast<float*>(ws + L.partial);
+    const unsigned grg = unsigned(L.nblk_rg);
+    // layer 6
+    hipLaunchKernelGGL(l6_bwd_weight, dim3(grg), dim3(320), 0, s, act(4), dF, nb, H, W, partial);
+    ST_LAUNCH_CHECK("l6_bwd_weight");
+    hipLaunchKernelGGL(reduce_partials, dim3((9 * C + 1 + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg, 9 * C + 1,
+                       grad + woff(5));
+    ST_LAUNCH_CHECK("reduce l6");
+    uint16_t* dzb[2] = {reinterpret_cast<uint16_t*>(ws + L.dzb[0]), reinterpret_cast<uint16_t*>(ws + L.dzb[1])};
+    hipLaunchKernelGGL(l6_bwd_data, dim3(gpx), dim3(256), 0, s, params, dF, zz(4), nb, H, W, dzb[0]);
+    ST_LAUNCH_CHECK("l6_bwd_data");
+    // layers 5 .. 2 (index l = 4 .. 1): dZ_l in dzb[cur]
+    const uint16_t* frags = reinterpret_cast<const uint16_t*>(ws + L.frags);
+    const unsigned gt = unsigned(int64_t(nb) * ((H + TH - 1) / TH) * ((W + TW - 1) / TW));
+    int cur = 0;
+    float* dz1 = reinterpret_cast<float*>(ws + L.dz1);
+    for (int l = 4; l >= 1; --l) {
+        hipLaunchKernelGGL(mfma_bwd_weight, dim3(grg), dim3(256), 0, s, act(l - 1), dzb[cur], nb, H, W, partial);
+        ST_LAUNCH_CHECK("mfma_bwd_weight");
+        hipLaunchKernelGGL(reduce_partials, dim3((9 * C * C + C + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg,
+                           9 * C * C + C, grad + woff(l));
+        ST_LAUNCH_CHECK("reduce mfma layer");
+        ConvArgs a;
+        a.X = dzb[cur];
+        a.frags = frags + size_t(l - 1) * 2 * FRAG + FRAG;
+        a.bias = nullptr;
+        a.Zprev = zz(l - 1);
+        a.Zout = nullptr;
+        a.Aout = l > 1 ? dzb[cur ^ 1] : nullptr;
+        a.Fout = l > 1 ? nullptr : dz1;
+        a.nb = nb;
+        a.H = H;
+        a.W = W;
+        a.epi = l > 1 ? EPI_BWD_BF16 : EPI_BWD_F32;
+        hipLaunchKernelGGL(conv_mfma, dim3(gt), dim3(256), 0, s, a);
+        ST_LAUNCH_CHECK("conv_mfma bwd");
+        cur ^= 1;
+    }
+    // layer 1
+    hipLaunchKernelGGL(l1_bwd_weight, dim3(grg), dim3(640), 0, s, u0, kappa, dz1, nb, H, W, partial);
+    ST_LAUNCH_CHECK("l1_bwd_weight");
+    hipLaunchKernelGGL(reduce_partials, dim3((9 * 2 * C + C + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg,
+                       9 * 2 * C + C, grad + woff(0));
+    ST_LAUNCH_CHECK("reduce l1");
+    return ST_OK;
+}
+
+int surrogate_adam(sg_model* m, float* params, const float* grad, float* optim, int t, float lr, float beta1,
+                   float beta2, float eps, void* stream) {
+    if (!m || !params || !grad || !optim) return fail(ST_EINVAL, "NULL argument");
+    if (t < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(ST_EINVAL, "bad Adam hyper-parameters");
+    const float c1 = float(1.0 - std::pow(double(beta1), t)), c2 = float(1.0 - std::pow(double(beta2), t));
+    clear_stale_error();
+    hipLaunchKernelGGL(adam_kernel, dim3((SG_PARAM_COUNT + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       params, grad, optim, optim + SG_PARAM_COUNT, SG_PARAM_COUNT, lr, beta1, beta2, eps, c1, c2);
+    ST_LAUNCH_CHECK("adam");
+    return ST_OK;
+}
+
+int surrogate_synth_fields(const float* coef, int n, int64_t rows, int64_t cols, float* u0_out, float* kappa_out,
+                           void* stream) {
+    if (!coef || !u0_out || !kappa_out) return fail(ST_EINVAL, "NULL argument");
+    if (n < 1 || rows < 1 || cols < 1 || int64_t(n) * rows * cols > (int64_t(1) << 33)) return fail(ST_EINVAL, "bad sizes");
+    const int64_t total = int64_t(n) * rows * cols;
+    clear_stale_error();
+    hipLaunchKernelGGL(synth_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       coef, n, int(rows), int(cols), u0_out, kappa_out);
+    ST_LAUNCH_CHECK("synth");
+    return ST_OK;
+}
+
+int surrogate_crop(const float* src, float* dst, const int* yx, int n, int64_t rows, int64_t cols, int64_t h, int64_t w,
+                   void* stream) {
+    if (!src || !dst || !yx) return fail(ST_EINVAL, "NULL argument");
+    if (n < 1 || h < 1 || w < 1 || rows < 1 || cols < 1) return fail(ST_EINVAL, "bad sizes");
+    const int64_t total = int64_t(n) * h * w;
+    clear_stale_error();
+    hipLaunchKernelGGL(crop_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       src, dst, yx, n, int(rows), int(cols), int(h), int(w));
+    ST_LAUNCH_CHECK("crop");
+    return ST_OK;
+}
+
+int surrogate_checked_ws_bytes(const sg_model* m, int64_t rows, int64_t cols, size_t* bytes) {
+    if (!m || !bytes) return fail(ST_EINVAL, "NULL argument");
+    if (int rc = check_dims(1, rows, cols)) return rc;
+    const size_t field = a256(size_t(rows * cols) * 4);
+    *bytes = layout(1, rows, cols, false).total + 3 * field + a256(1024 * 16) + 256;
+    return ST_OK;
+}
+
+int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, const float* kappa, float* out,
+                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol, int* used_fallback,
+                            double* rel_err, void* workspace, size_t ws_bytes, void* stream) {
+    if (!m || !params || !u0 || !kappa || !out || !judge || !used_fallback || !rel_err)
+        return fail(ST_EINVAL, "NULL argument");
+    if (judge->kind != KIND_VARCOEF || judge->rows != rows || judge->cols != cols)
+        return fail(ST_EINVAL, "judge must be a varcoef plan of the same shape");
+    if (K < 0 || !(tol >= 0.0)) return fail(ST_EINVAL, "bad K or tol");
+    size_t need = 0;
+    if (int rc = surrogate_checked_ws_bytes(m, rows, cols, &need)) return rc;
+    if (!workspace || ws_bytes < need) return fail(ST_ENOWS, "workspace too small");
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const WsLayout L = layout(1, rows, cols, false);
+    const size_t field = a256(size_t(rows * cols) * 4);
+    float* uhat = reinterpret_cast<float*>(ws + L.total);
+    float* uk = reinterpret_cast<float*>(ws + L.total + field);
+    float* jws = reinterpret_cast<float*>(ws + L.total + 2 * field);
+    double* part = reinterpret_cast<double*>(ws + L.total + 3 * field);
+    double* sums = reinterpret_cast<double*>(ws + L.total + 3 * field + a256(1024 * 16));
+    if (int rc = forward_impl(params, u0, kappa, uhat, 1, int(rows), int(cols), ws, L, false, s)) return rc;
+    // the judge: K plain steps of the stencil
+    if (int rc = stencil_run_varcoef(judge, u0, kappa, uk, K, jws, field, stream)) return rc;
+    const int64_t n = rows * cols;
+    const int nblk = int(std::min<int64_t>(1024, (n + 255) / 256));
+    hipLaunchKernelGGL(diff_norms, dim3(nblk), dim3(256), 0, s, uhat, uk, n, part);
+    ST_LAUNCH_CHECK("diff_norms");
+    hipLaunchKernelGGL(diff_norms_finish, dim3(1), dim3(64), 0, s, part, nblk, sums);
+    ST_LAUNCH_CHECK("diff_norms_finish");
+    double h[2] = {0, 0};
+    ST_HIP_CHECK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
+    ST_HIP_CHECK(hipStreamSynchronize(s));
+    const double rel = h[1] > 1e-60 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0] / double(n));
+    *rel_err = rel;
+    const bool fallback = !(rel <= tol);
+    *used_fallback = fallback ? 1 : 0;
+    ST_HIP_CHECK(hipMemcpyAsync(out, fallback ? uk : uhat, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,210 @@
+"""GPU parity of the CNN surrogate kernels (MFMA forward, backward, Adam, data synthesis, the judged
+entry point) against the FP64 CNN oracle.
+
+The GPU rounds activations, the 32->32 weights and the back-propagated dZ of layers 2-5 to BF16;
+the oracle's emulating mode rounds the same operands (``q``), so the remaining difference is FP32
+accumulation order (rel-L2 ~1e-6).  Tolerances: forward 1e-3, gradients 5e-3 (rel-L2 per layer).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import cnn
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import gpuhelp
+    return gpuhelp
+
+
+def q_bf16(x):
+    t = torch.from_numpy(np.asarray(x, dtype=np.float64)).float().to(torch.bfloat16)
+    return t.to(torch.float64).numpy()
+
+
+def flat_params(params):
+    out = []
+    for (w, b) in params:
+        out.append(np.asarray(w).transpose(2, 3, 1, 0).reshape(-1))
+        out.append(np.asarray(b).reshape(-1))
+    return np.concatenate(out).astype(np.float32)
+
+
+def unflat(vec):
+    params, o = [], 0
+    for l in range(cnn.N_LAYERS):
+        ci, co = cnn.CHANNELS[l], cnn.CHANNELS[l + 1]
+        w = vec[o:o + 9 * ci * co].reshape(3, 3, ci, co).transpose(3, 2, 0, 1)
+        o += 9 * ci * co
+        b = vec[o:o + co]
+        o += co
+        params.append((w.astype(np.float64), b.astype(np.float64)))
+    assert o == vec.size
+    return params
+
+
+def test_param_layout_roundtrip():
+    p = cnn.init_params(1)
+    v = flat_params(p)
+    import paper_2605_07954_amd as lib
+    assert v.size == lib.SG_PARAM_COUNT
+    for (a, b), (c, d) in zip(p, unflat(v)):
+        np.testing.assert_allclose(a.astype(np.float32), c)
+
+
+def _fields(nb, h, w, seed):
+    u0s, ks = [], []
+    for s in range(nb):
+        u0, k = wl.varcoef_problem(h, w, seed=seed + s)
+        u0s.append(u0 * 3.0)
+        ks.append(k)
+    return np.stack(u0s), np.stack(ks)
+
+
+def _params(seed):
+    p = cnn.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    # non-zero biases and a stronger last layer so every term is exercised
+    p = [(w, rng.normal(0, 0.1, size=b.shape)) for (w, b) in p]
+    p[-1] = (p[-1][0] * 10.0, p[-1][1])
+    return p
+
+
+def test_forward_vs_oracle(g):
+    import paper_2605_07954_amd as lib
+    nb, h, w = 2, 40, 70
+    u0, kap = _fields(nb, h, w, 3)
+    params = _params(7)
+    pv = flat_params(params)
+    m = lib.surrogate_create()
+    try:
+        ws = torch.empty(lib.surrogate_workspace_bytes(m, nb, h, w), dtype=torch.uint8, device=g.DEV)
+        out = torch.empty((nb, h, w), dtype=torch.float32, device=g.DEV)
+        lib.surrogate_forward(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, nb, h, w, ws)
+        got = g.to_host(out)
+    finally:
+        lib.surrogate_destroy(m)
+    p32 = unflat(pv)
+    for s in range(nb):
+        ref_q, _ = cnn.forward(p32, u0[s], kap[s], q=q_bf16)
+        ref, _ = cnn.forward(p32, u0[s], kap[s])
+        e_q = oracle.rel_l2(got[s] - u0[s], ref_q - u0[s])
+        e = oracle.rel_l2(got[s] - u0[s], ref - u0[s])
+        say(f"sample {s}: rel-L2 of f = u_hat - u0 vs bf16-emulating oracle {e_q:.2e}, vs exact fp64 {e:.2e}")
+        assert e_q < 1e-3
+
+
+def test_loss_grad_vs_oracle(g):
+    import paper_2605_07954_amd as lib
+    nb, h, w = 2, 24, 40
+    u0, kap = _fields(nb, h, w, 11)
+    tgt = (u0 + 0.05 * np.random.default_rng(2).standard_normal(u0.shape)).astype(np.float32)
+    params = _params(9)
+    pv = flat_params(params)
+    lo_hi = (2, 21, 3, 38)
+    m = lib.surrogate_create()
+    try:
+        ws = torch.empty(lib.surrogate_workspace_bytes(m, nb, h, w), dtype=torch.uint8, device=g.DEV)
+        grad = torch.zeros(lib.SG_PARAM_COUNT, dtype=torch.float32, device=g.DEV)
+        loss = torch.zeros(1, dtype=torch.float64, device=g.DEV)
+        lib.surrogate_loss_grad(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), g.to_dev(tgt), lo_hi, nb, h, w, grad,
+                                loss, ws)
+        gv = g.to_host(grad)
+        lv = float(loss.cpu()[0])
+        grad2 = torch.zeros_like(grad)
+        lib.surrogate_loss_grad(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), g.to_dev(tgt), lo_hi, nb, h, w, grad2,
+                                loss, ws)
+        assert torch.equal(grad, grad2)  # deterministic
+    finally:
+        lib.surrogate_destroy(m)
+    mask = np.zeros((h, w))
+    mask[lo_hi[0]:lo_hi[1], lo_hi[2]:lo_hi[3]] = 1
+    samples = [(u0[s], kap[s], tgt[s], mask) for s in range(nb)]
+    p32 = unflat(pv)
+    ref_loss, ref_grads = cnn.loss_and_grads(p32, samples, q=q_bf16)
+    say(f"loss gpu {lv:.8e} oracle {ref_loss:.8e}")
+    assert abs(lv - ref_loss) <= 1e-3 * ref_loss
+    got = unflat(gv)
+    for l in range(cnn.N_LAYERS):
+        ew = oracle.rel_l2(got[l][0], ref_grads[l][0])
+        eb = oracle.rel_l2(got[l][1], ref_grads[l][1])
+        say(f"layer {l + 1}: dW rel-L2 {ew:.2e}, db rel-L2 {eb:.2e}")
+        assert ew < 5e-3 and eb < 5e-3
+
+
+def test_adam_vs_closed_form(g):
+    import paper_2605_07954_amd as lib
+    rng = np.random.default_rng(3)
+    n = lib.SG_PARAM_COUNT
+    p = rng.standard_normal(n).astype(np.float32)
+    gr = rng.standard_normal(n).astype(np.float32)
+    m = lib.surrogate_create()
+    try:
+        pd, gd = g.to_dev(p), g.to_dev(gr)
+        opt = torch.zeros(2 * n, dtype=torch.float32, device=g.DEV)
+        lib.surrogate_adam(m, pd, gd, opt, 1, 1e-3)
+        lib.surrogate_adam(m, pd, gd, opt, 2, 1e-3)
+        got = g.to_host(pd)
+    finally:
+        lib.surrogate_destroy(m)
+    ref, mm, vv = cnn.adam_step(p.astype(np.float64), gr.astype(np.float64), 0, 0, 1, 1e-3)
+    ref, _, _ = cnn.adam_step(ref, gr.astype(np.float64), mm, vv, 2, 1e-3)
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
+
+
+def test_synth_and_crop(g):
+    import paper_2605_07954_amd as lib
+    coef = wl.field_coefficients(3, 5)
+    rows, cols = 96, 130
+    u = torch.empty((3, rows, cols), device=g.DEV)
+    k = torch.empty_like(u)
+    lib.surrogate_synth_fields(g.to_dev(coef), 3, rows, cols, u, k)
+    for t in range(3):
+        hu, hk = wl.synth_fields(coef[t], rows, cols)
+        np.testing.assert_allclose(g.to_host(u[t]), hu, atol=2e-6)
+        np.testing.assert_allclose(g.to_host(k[t]), hk, atol=2e-6)
+    yx = np.array([[0, 0], [10, 50], [90, 120]], dtype=np.int32)
+    dst = torch.empty((3, 16, 20), device=g.DEV)
+    lib.surrogate_crop(u, dst, g.to_dev(yx), 3, rows, cols, 16, 20)
+    hu = g.to_host(u)
+    d = g.to_host(dst)
+    np.testing.assert_array_equal(d[0], hu[0, :16, :20])
+    np.testing.assert_array_equal(d[1], hu[1, 10:26, 50:70])
+    assert d[2][0, 0] == hu[2, 90, 120] and d[2][15, 19] == 0.0
+
+
+def test_infer_checked_judge_and_fallback(g):
+    import paper_2605_07954_amd as lib
+    rows, cols, K = 64, 96, 16
+    u0, kap = wl.varcoef_problem(rows, cols, seed=21)
+    pv = flat_params(_params(4))
+    plain = oracle.varcoef_f32(u0, kap, 0.0, K)
+    m = lib.surrogate_create()
+    judge = lib.stencil_plan_varcoef(rows, cols, 0.0)
+    try:
+        ws = torch.empty(lib.surrogate_checked_ws_bytes(m, rows, cols), dtype=torch.uint8, device=g.DEV)
+        out = torch.empty((rows, cols), device=g.DEV)
+        fb, err = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, rows, cols, judge, K,
+                                              0.0, ws)
+        assert fb and err > 0
+        np.testing.assert_array_equal(g.to_host(out), plain)
+        fb2, err2 = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, rows, cols, judge,
+                                                K, 1e9, ws)
+        assert not fb2 and err2 == err
+        fwd = torch.empty((1, rows, cols), device=g.DEV)
+        ws2 = torch.empty(lib.surrogate_workspace_bytes(m, 1, rows, cols), dtype=torch.uint8, device=g.DEV)
+        lib.surrogate_forward(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), fwd, 1, rows, cols, ws2)
+        np.testing.assert_array_equal(g.to_host(out), g.to_host(fwd[0]))
+        assert abs(err - oracle.rel_l2(g.to_host(fwd[0]), plain)) < 1e-9
+    finally:
+        lib.stencil_destroy(judge)
+        lib.surrogate_destroy(m)

@@ -1,0 +1,204 @@
+"""GPU parity of the plain sweep against the CPU oracle (through the C ABI).
+
+The kernels follow the oracle's FP32 order (centre product, then one FMA per
+footprint tap in row-major order), so FP32 results are compared BIT FOR BIT
+with the FP32-canonical oracle; the accuracy gate is rel-L2 <= 1e-5 against
+the FP64 oracle, and the FP64 error is printed for every case.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch  # noqa: F401
+    import gpuhelp
+    return gpuhelp
+
+
+def _weights(shape, r, seed):
+    return wl.random_footprint_weights(np.random.default_rng(seed), shape, r)
+
+
+def test_heat2d_512_100(g):
+    p = wl.heat2d()
+    ref32 = oracle.stencil_f32(p.u0, p.weights, 0.0, p.steps)
+    ref64 = oracle.stencil_f64(p.u0, p.weights, 0.0, p.steps)
+    for flags, tb, tile in [(1, 0, None), (0, 1, None), (0, 4, (128, 64)), (0, 7, (64, 64)), (0, 10, (256, 32)),
+                            (2, 5, (128, 32))]:
+        say("heat2d", flags, tb, tile)
+        got = g.run_problem(p.u0, p.weights, 0.0, p.steps, flags=flags, tb=tb, tile=tile)
+        e64 = oracle.rel_l2(got, ref64)
+        say(f"  rel-L2 vs f64 = {e64:.3e}")
+        assert e64 <= TOL
+        np.testing.assert_array_equal(got, ref32)
+
+
+CASES = [
+    # rows, cols, shape, r, b, steps
+    (1, 1, wl.STAR, 1, 0.0, 3),
+    (3, 5, wl.BOX, 2, 1.5, 4),
+    (2, 200, wl.BOX, 4, 0.0, 2),
+    (37, 61, wl.STAR, 3, 0.0, 7),
+    (130, 67, wl.BOX, 1, -0.5, 9),
+    (257, 513, wl.BOX, 3, 0.0, 5),
+    (300, 129, wl.STAR, 4, 0.25, 6),
+    (64, 64, wl.STAR, 2, 0.0, 0),
+    (515, 1030, wl.STAR, 1, 0.0, 13),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in CASES])
+def test_ragged_bitwise(g, case):
+    rows, cols, shape, r, b, steps = case
+    W = _weights(shape, r, rows * 7 + cols)
+    u0 = np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32)
+    ref32 = oracle.stencil_f32(u0, W, b, steps)
+    for flags, tb, tile in [(1, 0, None), (0, 1, (64, 64)), (0, 2, (128, 32)), (0, 3, (128, 64)),
+                            (0, 4, (256, 32))]:
+        say(case, flags, tb, tile)
+        got = g.run_problem(u0, W, b, steps, flags=flags, tb=tb, tile=tile)
+        np.testing.assert_array_equal(got, ref32)
+
+
+def test_box49_crop_1024_1000(g):
+    """Box-2D49P on the 1024x1024 top-left crop of the seed-1 field, 1000 steps."""
+    p = wl.box49(crop=(1024, 1024))
+    say("oracle f32 ...")
+    ref32 = oracle.stencil_f32(p.u0, p.weights, 0.0, p.steps)
+    say("oracle f64 ...")
+    ref64 = oracle.stencil_f64(p.u0, p.weights, 0.0, p.steps)
+    for tb in (1, 2, 4):
+        got = g.run_problem(p.u0, p.weights, 0.0, p.steps, tb=tb, tile=(128, 64))
+        e64 = oracle.rel_l2(got, ref64)
+        say(f"box49 crop tb={tb}: rel-L2 vs f64 = {e64:.3e}, vs f32-canonical = {oracle.rel_l2(got, ref32):.3e}")
+        assert e64 <= TOL
+        np.testing.assert_array_equal(got, ref32)
+
+
+def test_bitwise_across_blocking_and_graph(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols = 1000, 777
+    W = _weights(wl.BOX, 3, 5)
+    u0 = np.random.default_rng(5).random((rows, cols), dtype=np.float32)
+    base = g.run_problem(u0, W, 0.0, 13, flags=lib.ST_FLAG_NAIVE)
+    for tile in lib.stencil_tiles():
+        for tb in (1, 2, 3, 5, 6):
+            got = g.run_problem(u0, W, 0.0, 13, tb=tb, tile=tile)
+            np.testing.assert_array_equal(got, base)
+    # graph replays (with eager work between them) equal the direct run, every time
+    plan = lib.stencil_plan(rows, cols, 3, W, 0.0, "f32", lib.ST_FLAG_GRAPH)
+    try:
+        x = g.to_dev(u0)
+        out = torch.empty_like(x)
+        ws = torch.empty(lib.stencil_workspace_bytes(plan, 13), dtype=torch.uint8, device=g.DEV)
+        for rep in range(3):
+            out.zero_()
+            lib.stencil_run(plan, x, out, 13, ws)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.to_host(out), base)
+            _ = (x * 2).sum().item()
+    finally:
+        lib.stencil_destroy(plan)
+    # run(a) then run(b) == run(a+b)
+    mid = g.run_problem(u0, W, 0.0, 6, tb=4)
+    np.testing.assert_array_equal(g.run_problem(mid, W, 0.0, 7, tb=3), base)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_lowp_storage_bitwise(g, storage):
+    p = wl.star9_precision(rows=300, cols=257, steps=23)
+    bits = oracle.to_bits(p.u0, storage)
+    ref = oracle.stencil_lowp(bits, p.weights, 0.0, p.steps, storage)
+    for flags, tb in [(1, 0), (0, 1), (0, 3), (0, 8)]:
+        got = g.run_problem(bits, p.weights, 0.0, p.steps, storage=storage, flags=flags, tb=tb)
+        np.testing.assert_array_equal(got, ref)
+    x = oracle.from_bits(bits, storage)
+    e = oracle.rel_l2(oracle.from_bits(got, storage), oracle.stencil_f64(x, p.weights, 0.0, p.steps))
+    say(f"{storage} storage: rel-L2 vs f64 after {p.steps} steps = {e:.3e}")
+
+
+def test_norms(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    rng = np.random.default_rng(4)
+    for (rows, cols, shape, r, b) in [(513, 300, wl.BOX, 3, 0.0), (64, 70, wl.STAR, 2, 1.5), (5, 3, wl.BOX, 4, 0.5)]:
+        W = _weights(shape, r, rows)
+        u = rng.standard_normal((rows, cols)).astype(np.float32)
+        up = rng.standard_normal((rows, cols)).astype(np.float32)
+        plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
+        try:
+            ws = torch.empty(lib.stencil_norms_ws_bytes(plan), dtype=torch.uint8, device=g.DEV)
+            o = torch.zeros(4, dtype=torch.float64, device=g.DEV)
+            lib.stencil_norms(plan, g.to_dev(up), g.to_dev(u), o, ws)
+            got = o.cpu().numpy()
+            ref = oracle.norms_f64(u, W, b, up)
+            np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-9)
+            o2 = torch.zeros(4, dtype=torch.float64, device=g.DEV)
+            lib.stencil_norms(plan, g.to_dev(up), g.to_dev(u), o2, ws)
+            assert torch.equal(o, o2)  # deterministic
+            # the predicted next mass is the mass of the next step
+            nxt = g.run_problem(u, W, b, 1)
+            assert abs(got[3] - nxt.astype(np.float64).sum()) < 1e-5 * (1 + abs(got[3]))
+        finally:
+            lib.stencil_destroy(plan)
+
+
+def test_varcoef(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    for (rows, cols, b, steps) in [(1024, 1024, 0.0, 16), (77, 130, 0.3, 9), (1, 5, 0.0, 3)]:
+        u0, kap = wl.varcoef_problem(rows, cols, seed=rows)
+        ref32 = oracle.varcoef_f32(u0, kap, b, steps)
+        ref64 = oracle.varcoef_f64(u0, kap, b, steps)
+        for flags, tb in [(lib.ST_FLAG_NAIVE, 0), (0, 1), (0, 4), (0, 8)]:
+            plan = lib.stencil_plan_varcoef(rows, cols, b, flags)
+            try:
+                if tb:
+                    lib.stencil_set_blocking(plan, tb)
+                x, k = g.to_dev(u0), g.to_dev(kap)
+                out = torch.empty_like(x)
+                nws = lib.stencil_workspace_bytes(plan, steps)
+                ws = torch.empty(nws, dtype=torch.uint8, device=g.DEV) if nws else None
+                lib.stencil_run_varcoef(plan, x, k, out, steps, ws)
+                got = g.to_host(out)
+            finally:
+                lib.stencil_destroy(plan)
+            e = oracle.rel_l2(got, ref64)
+            say(f"varcoef {rows}x{cols} tb={tb}: rel-L2 vs f64 {e:.3e}")
+            assert e <= TOL
+            np.testing.assert_array_equal(got, ref32)
+
+
+def test_error_paths(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    W = wl.heat5_weights()
+    plan = lib.stencil_plan(64, 64, 1, W, 0.0, "f32", 0)
+    try:
+        x = torch.zeros((64, 64), device=g.DEV)
+        with pytest.raises(lib.StencilError) as ei:
+            lib.stencil_run(plan, x, x, 5, None)
+        assert ei.value.code == -2
+        y = torch.zeros_like(x)
+        lib.stencil_set_blocking(plan, 1)
+        with pytest.raises(lib.StencilError) as ei:
+            lib.stencil_run(plan, x, y, 5, None)
+        assert ei.value.code == -5
+    finally:
+        lib.stencil_destroy(plan)
