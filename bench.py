@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark: iterated 2D Jacobi Box-2D49P sweep on one MI355X.
+
+Workload (the headline configuration): a 7x7 box stencil (radius 3) with 49 weights drawn
+uniform[0,1) from seed 1 and normalised to sum 1 (FP32), on a 16384 x 16384 FP32 grid with a zero
+Dirichlet halo, interior uniform[0,1), 1000 Jacobi steps.  One benchmark "step" is one full
+1000-step run through ``stencil_run`` (the C ABI), with input and output resident in HBM.
+
+Metric: GStencil/s = T * Nx * Ny / (t * 1e9)  (paper Sec. VI-A, Eq. 1), t = pure kernel time
+measured with HIP events on the stream the kernels run on.
+
+The JSON line also carries
+  roofline      the sweep kernel's achieved FLOP/s against the vector-ALU roof (it is the binding
+                roof for this stencil: 97 FLOP and 8/tb bytes per update), with the HBM traffic
+                measured by rocprofv3 when the committed counters match the current kernel source;
+  cpu_baseline  the CPU oracle (FP32-canonical mode, all host cores) timed on a bounded sample;
+  extras        the other workloads (heat 512^2, batched 256 grids, 16-bit storage, surrogate) at a
+                glance -- their parity lives in the test suite.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+VALU_FP32_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: FP32 FMA issued one lane-op per cycle (no packed math)
+VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP32 (not used by these kernels)
+HBM_PEAK = 8.0e12
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tb: int, tile) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source with the same blocking; else None."""
+    path = os.path.join(ROOT, "profiles", "box49_16384_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("tb") != tb or list(d.get("tile", [])) != list(tile):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_runs(fn, reps: int, stream) -> float:
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(p) -> dict:
+    import oracle
+    rows = cols = 1024
+    steps = int(os.environ.get("BENCH_CPU_STEPS", "400"))
+    u0 = np.ascontiguousarray(p.u0[:rows, :cols])
+    t0 = time.perf_counter()
+    oracle.stencil_f32(u0, p.weights, 0.0, steps)
+    dt = time.perf_counter() - t0
+    return {"value": steps * rows * cols / dt / 1e9, "unit": "GStencil/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"box2d49p FP32-canonical oracle on the 1024x1024 top-left crop, {steps} steps ({dt:.1f} s)"}
+
+
+def main_line(args, torch, lib, stream):
+    p = wl.box49(rows=args.size, cols=args.size, steps=args.jacobi_steps)
+    rows, cols = p.rows, p.cols
+    x = torch.from_numpy(p.u0).to("cuda")
+    out = torch.empty_like(x)
+    plan = lib.stencil_plan(rows, cols, p.radius, p.weights, 0.0, "f32", 0)
+    t0 = time.perf_counter()
+    tune_steps = 24
+    ws = torch.empty_like(x)
+    if args.tb:
+        lib.stencil_set_blocking(plan, args.tb, *(args.tile or (0, 0)))
+        tb, tx, ty = lib.stencil_get_blocking(plan)
+    else:
+        tb, tx, ty = lib.stencil_autotune(plan, x, out, ws, tune_steps, stream)
+    tune_s = time.perf_counter() - t0
+    T = p.steps
+    run = lambda: lib.stencil_run(plan, x, out, T, ws, stream)  # noqa: E731
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t = time_runs(run, args.steps, stream)
+    ms = t / args.steps * 1e3
+    value = T * rows * cols * args.steps / t / 1e9
+    launches = math.ceil(T / tb) * args.steps
+    flops = 97.0 * T * rows * cols * args.steps  # 1 multiply + 48 FMA per update
+    achieved = flops / t
+    traffic = measured_traffic(tb, (tx, ty))
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / VALU_FP32_PEAK, "traffic": traffic,
+            "kernel": "sweep_tiled<f32, r=3, box>", "launches": launches, "avg_launch_us": t / launches * 1e6,
+            "alg_flop_per_launch": 97.0 * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
+            "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
+            "alu_roof_gstencil": VALU_FP32_PEAK / 97.0 / 1e9,
+            "frac_of_packed_fp32_peak": achieved / VALU_FP32_PEAK_PACKED,
+            "alg_hbm_gbps": 8.0 / tb * T * rows * cols * args.steps / t / 1e9}
+    lib.stencil_destroy(plan)
+    del x, out, ws
+    torch.cuda.empty_cache()
+    return p, value, ms, roof, (tb, tx, ty), tune_s
+
+
+def extras(torch, lib, stream) -> dict:
+    ex = {}
+    # heat 512^2, 100 steps (launch-bound, L2-resident)
+    p = wl.heat2d()
+    x = torch.from_numpy(p.u0).to("cuda")
+    out = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    plan = lib.stencil_plan(p.rows, p.cols, 1, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
+    tb, _, _ = lib.stencil_autotune(plan, x, out, ws, 20, stream)
+    run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
+    run()
+    t = time_runs(run, 20, stream) / 20
+    ex["heat2d_512_100"] = {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "us": t * 1e6, "tb": tb}
+    lib.stencil_destroy(plan)
+    # 16-bit storage: Star-2D9P 8192^2, 500 steps
+    p = wl.star9_precision(rows=8192, cols=8192, steps=500)
+    res = {}
+    for st in ("f32", "bf16", "f16"):
+        if st == "f32":
+            xh = torch.from_numpy(p.u0).to("cuda")
+        else:
+            xh = torch.from_numpy(p.u0).to("cuda").to(torch.bfloat16 if st == "bf16" else torch.float16).view(torch.int16)
+        o = torch.empty_like(xh)
+        w2 = torch.empty_like(xh)
+        plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, st, 0)
+        tb, _, _ = lib.stencil_autotune(plan, xh, o, w2, 20, stream)
+        run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
+        run()
+        t = time_runs(run, 2, stream) / 2
+        res[st] = {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "ms": t * 1e3, "tb": tb}
+        lib.stencil_destroy(plan)
+        del xh, o, w2
+    ex["star9_8192_500"] = res
+    torch.cuda.empty_cache()
+    # batched: 256 grids, one persistent graph launch vs per-grid launches
+    probs = wl.batch_problems()
+    ins = [torch.from_numpy(q.u0).to("cuda") for q in probs]
+    outs = [torch.empty_like(i) for i in ins]
+    wss = [torch.empty_like(i) for i in ins]
+    plans = [lib.stencil_plan(q.rows, q.cols, q.radius, q.weights, 0.0, "f32", 0) for q in probs]
+    tuned = {}
+    for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):  # one autotune per stencil class
+        key = (q.shape, q.radius)
+        if key not in tuned and q.rows * q.cols >= 512 * 512:
+            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream)
+    for q, pl in zip(probs, plans):
+        if (q.shape, q.radius) in tuned:
+            lib.stencil_set_blocking(pl, *tuned[(q.shape, q.radius)])
+    per_grid = lambda: [lib.stencil_run(pl, i, o, q.steps, w, stream)  # noqa: E731
+                        for q, pl, i, o, w in zip(probs, plans, ins, outs, wss)]
+    per_grid()
+    t_per = time_runs(per_grid, 1, stream)
+    batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
+    bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+    runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
+    runb()
+    t_b = time_runs(runb, 3, stream) / 3
+    timed_out = lib.stencil_batch_status(batch, bws, stream)
+    cells = sum(q.rows * q.cols * q.steps for q in probs)
+    ex["batched_256"] = {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "per_grid_ms": t_per * 1e3,
+                         "speedup_vs_per_grid": t_per / t_b, "watchdog": bool(timed_out)}
+    lib.stencil_batch_destroy(batch)
+    for pl in plans:
+        lib.stencil_destroy(pl)
+    del ins, outs, wss, bws
+    torch.cuda.empty_cache()
+    # surrogate inference vs 16 plain varcoef steps on 1024^2 (timing only; accuracy is in the tests)
+    u0, kap = wl.varcoef_problem(1024, 1024, seed=0)
+    u = torch.from_numpy(u0).to("cuda")
+    k = torch.from_numpy(kap).to("cuda")
+    o = torch.empty_like(u)
+    w = torch.empty_like(u)
+    vplan = lib.stencil_plan_varcoef(1024, 1024, 0.0, lib.ST_FLAG_GRAPH)
+    best = None
+    for tb in (2, 4, 8):
+        try:
+            lib.stencil_set_blocking(vplan, tb)
+        except lib.StencilError:
+            continue
+        run = lambda: lib.stencil_run_varcoef(vplan, u, k, o, 16, w, stream)  # noqa: E731
+        run()
+        tt = time_runs(run, 20, stream) / 20
+        best = tt if best is None else min(best, tt)
+    m = lib.surrogate_create()
+    from oracle import cnn  # parameters only: the network's random initialisation
+    params = np.concatenate([np.concatenate([wt.transpose(2, 3, 1, 0).reshape(-1), b])
+                             for (wt, b) in cnn.init_params(0)]).astype(np.float32)
+    pd = torch.from_numpy(params).to("cuda")
+    sws = torch.empty(lib.surrogate_workspace_bytes(m, 1, 1024, 1024), dtype=torch.uint8, device="cuda")
+    uh = torch.empty((1, 1024, 1024), device="cuda")
+    run = lambda: lib.surrogate_forward(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
+    run()
+    ts = time_runs(run, 10, stream) / 10
+    ex["surrogate_1024_K16"] = {"plain_16_steps_us": best * 1e6, "cnn_infer_us": ts * 1e6,
+                                "speedup_vs_plain": best / ts, "cnn_tflops": 75456.0 * 1024 * 1024 / ts / 1e12}
+    lib.surrogate_destroy(m)
+    lib.stencil_destroy(vplan)
+    return ex
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=16384)
+    ap.add_argument("--jacobi-steps", type=int, default=1000)
+    ap.add_argument("--tb", type=int, default=0)
+    ap.add_argument("--tile", type=int, nargs=2, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "row-slab decomposition is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2605_07954_amd as lib
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    p, value, ms, roof, (tb, tx, ty), tune_s = main_line(args, torch, lib, stream)
+    line = {"metric": "GStencil/s", "value": value, "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"box2d49p-{p.rows}x{p.cols}-{p.steps}steps", "stencil": "box", "radius": 3,
+                       "grid": [p.rows, p.cols], "jacobi_steps": p.steps, "boundary": "dirichlet-0",
+                       "tb": tb, "tile": [tx, ty], "autotune_s": round(tune_s, 2)},
+            "roofline": roof}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p)
+    if not args.no_extras:
+        try:
+            line["extras"] = extras(torch, lib, stream)
+        except Exception as e:  # noqa: BLE001 - the headline line is still valid; say what failed
+            line["extras"] = {"error": repr(e)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -210,9 +210,10 @@ int surrogate_forward(sg_model* m, const float* params, const float* u0, const f
                       int batch, int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream);
 
 /* surrogate_loss_grad -- forward, masked MSE loss against `target`, and the
- * full backward pass:  loss = (1/n) sum_{b, i, j in mask} (u_hat - target)^2
- * where the mask keeps rows [y_lo, y_hi) x cols [x_lo, x_hi) of every field
- * (lo_hi = 4 ints) and n counts the kept cells.  Writes d loss / d params to
+ * full backward pass:  loss = (1/n) sum_{b, i, j in mask_b} (u_hat - target)^2
+ * where mask_b keeps rows [lo_hi[4b], lo_hi[4b+1]) x cols [lo_hi[4b+2],
+ * lo_hi[4b+3]) of field b (lo_hi: HOST array of 4*batch ints, batch <= 64)
+ * and n counts the kept cells of all fields.  Writes d loss / d params to
  * `grad` (SG_PARAM_COUNT floats) and the loss to the device double *loss.
  * Deterministic (fixed-order reductions).  Asynchronous. */
 int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa,

@@ -290,7 +290,10 @@ def surrogate_forward(model, params, u0, kappa, u_hat, batch: int, rows: int, co
 
 def surrogate_loss_grad(model, params, u0, kappa, target, lo_hi, batch: int, rows: int, cols: int, grad, loss,
                         workspace, stream=None) -> None:
-    lh = (_int * 4)(*[int(v) for v in lo_hi])
+    flat = [int(v) for v in np.asarray(lo_hi).reshape(-1)]
+    if len(flat) == 4 and batch > 1:  # one mask for every field
+        flat = flat * batch
+    lh = (_int * len(flat))(*flat)
     _ck(lib().surrogate_loss_grad(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
                                   _dptr(target, "target"), ctypes.cast(lh, _p), batch, rows, cols,
                                   _dptr(grad, "grad"), _dptr(loss, "loss"), _dptr(workspace, "workspace"),

@@ -15,6 +15,7 @@
 // XCDs) -> barrier -> counter store.  Consumer: counter load -> __threadfence() (agent-scope
 // acquire) -> barrier -> loads.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -143,9 +144,20 @@ __global__ __launch_bounds__(NT) void batched_persistent(BatchArgs a) {
             for (int64_t yy = max<int64_t>(0, ty - ry); yy <= min<int64_t>(d.tiles_y - 1, ty + ry); ++yy)
                 for (int64_t xx = max<int64_t>(0, tx - rx); xx <= min<int64_t>(d.tiles_x - 1, tx + rx); ++xx) {
                     const int* c = cnt + yy * d.tiles_x + xx;
-                    while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < p) {
+                    int seen;
+                    while ((seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < p) {
                         if (++spins > a.spin_limit) {
-                            __hip_atomic_store(a.timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            // first timeout wins the diagnostic record: item, grid, tile, pass,
+                            // waited-on tile and the counter value it showed
+                            if (atomicCAS(a.timeout_flag, 0, 1) == 0) {
+                                long long* rec = reinterpret_cast<long long*>(a.timeout_flag) + 1;
+                                rec[0] = item;
+                                rec[1] = g;
+                                rec[2] = t;
+                                rec[3] = p;
+                                rec[4] = yy * d.tiles_x + xx;
+                                rec[5] = seen;
+                            }
                             break;
                         }
                         __builtin_amdgcn_s_sleep(2);
@@ -171,6 +183,7 @@ __global__ void batch_reset(unsigned long long* head, int* timeout_flag, int* co
         *head = 0ull;
         *timeout_flag = 0;
     }
+    if (i < 6) reinterpret_cast<long long*>(timeout_flag)[1 + i] = -1;
     for (int64_t k = i; k < n; k += int64_t(gridDim.x) * blockDim.x) counters[k] = 0;
 }
 
@@ -198,6 +211,8 @@ struct st_batch {
     int64_t total_items, total_tiles;
     size_t off_cnt, off_desc, off_pstart, off_tprefix, off_order, off_fields, ws_bytes;
     std::vector<size_t> field_off;  // per grid: workspace offset of its ping-pong field (0 = none)
+    std::vector<int> zero_steps;    // grids with steps == 0 (copied, not queued)
+    int64_t spin_limit;             // polls before a dependency wait gives up
     size_t lds;
     int blocks;
     // staging + graph
@@ -256,8 +271,14 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
         d.b = p->bq;
         d.steps = int(steps[g]);
         std::memcpy(d.w, p->w, sizeof(d.w));
+        if (steps[g] == 0) {  // plain copy in -> out, enqueued by stencil_run_batched
+            d.passes = 0;
+            d.tiles_x = d.tiles_y = 1;
+            B->zero_steps.push_back(g);
+            continue;
+        }
         const size_t rl = resident_lds_bytes(p->radius, p->rows, p->cols);
-        if (rl <= batch_lds_budget() && steps[g] > 0) {
+        if (rl <= batch_lds_budget()) {
             d.resident = 1;
             d.passes = 1;
             d.tb = d.steps;
@@ -291,15 +312,20 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->max_passes = tiled.empty() ? 0 : B->desc[tiled[0]].passes;
     B->pass_start.assign(1, 0);
     for (int p = 0; p < B->max_passes; ++p) {
-        int active = 0;  // grids still running at pass p form a prefix of the tiled order
+        int active = 0;  // grids still running at pass p form a prefix of the tiled order (passes descending)
         while (active < B->n_tiled && B->desc[tiled[active]].passes > p) ++active;
         B->pass_start.push_back(B->pass_start.back() + B->tile_prefix[active]);
     }
+    for (size_t k = 1; k < B->pass_start.size(); ++k)
+        if (B->pass_start[k] <= B->pass_start[k - 1]) {  // every pass below max_passes has at least one tile
+            delete B;
+            return fail(ST_EINVAL, "internal: empty pass in the batch queue");
+        }
     if (B->pass_start.size() < 2) B->pass_start.push_back(0);
     B->total_tiles = cnt_total;
     B->total_items = B->n_res + B->pass_start[B->max_passes];
     // workspace layout
-    size_t off = 256;  // header: queue head (8 B) + timeout flag
+    size_t off = 256;  // header: queue head (8 B), timeout flag (4 B), first-timeout record (6 x 8 B at 16)
     B->off_cnt = off;
     off = align256(off + size_t(std::max<int64_t>(cnt_total, 1)) * sizeof(int));
     B->off_desc = off;
@@ -328,6 +354,10 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->g_ws = nullptr;
     B->g_stream = nullptr;
     B->blocks = 0;
+    // ~1 s of polling by default: far above any legitimate wait, and it ends a wait that a bug
+    // would make endless.  MI355STENCIL_BATCH_SPIN overrides it (tests use a short limit).
+    B->spin_limit = int64_t(1) << 20;
+    if (const char* e = std::getenv("MI355STENCIL_BATCH_SPIN")) B->spin_limit = std::max<int64_t>(1, std::atoll(e));
     *out = B;
     return ST_OK;
 }
@@ -363,7 +393,7 @@ static int enqueue_batch(st_batch* B, char* ws, hipStream_t s) {
     a.n_res = B->n_res;
     a.n_tiled = B->n_tiled;
     a.max_passes = B->max_passes;
-    a.spin_limit = int64_t(1) << 24;  // far above any legitimate wait; ends a wait that a bug would make endless
+    a.spin_limit = B->spin_limit;
     clear_stale_error();
     hipLaunchKernelGGL(batch_reset, dim3(64), dim3(256), 0, s, a.head, a.timeout_flag, a.counters,
                        std::max<int64_t>(B->total_tiles, 1));
@@ -423,6 +453,10 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
         B->last_out.assign(outs, outs + B->n);
         B->last_ws = workspace;
     }
+    for (int g : B->zero_steps)
+        ST_HIP_CHECK(hipMemcpyAsync(outs[g], ins[g], size_t(B->desc[g].rows * B->desc[g].cols) * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s));
+    if (B->total_items == 0) return ST_OK;
     if (!(B->flags & ST_FLAG_GRAPH)) return enqueue_batch(B, ws, s);
     if (!(B->exec && B->g_ws == workspace)) {
         if (B->exec) {

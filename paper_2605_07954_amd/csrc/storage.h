@@ -74,6 +74,29 @@ __device__ __forceinline__ void load_chunk<ST_BF16>(const uint16_t* p, float* v)
 template <>
 __device__ __forceinline__ void load_chunk<ST_F16>(const uint16_t* p, float* v) { load_chunk16<ST_F16>(p, v); }
 
+// Widen one raw 16-byte chunk (VEC elements) to FP32.
+template <int S>
+__device__ __forceinline__ void widen_chunk(uint4 q, float* v);
+
+template <>
+__device__ __forceinline__ void widen_chunk<ST_F32>(uint4 q, float* v) {
+    v[0] = __uint_as_float(q.x); v[1] = __uint_as_float(q.y); v[2] = __uint_as_float(q.z); v[3] = __uint_as_float(q.w);
+}
+
+template <int S>
+__device__ __forceinline__ void widen_chunk16(uint4 q, float* v) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = Fmt<S>::ld(uint16_t(w[k] & 0xffffu));
+        v[2 * k + 1] = Fmt<S>::ld(uint16_t(w[k] >> 16));
+    }
+}
+template <>
+__device__ __forceinline__ void widen_chunk<ST_BF16>(uint4 q, float* v) { widen_chunk16<ST_BF16>(q, v); }
+template <>
+__device__ __forceinline__ void widen_chunk<ST_F16>(uint4 q, float* v) { widen_chunk16<ST_F16>(q, v); }
+
 // Store 4 consecutive FP32 values (rounded to the storage type) with one vector store.
 template <int S>
 __device__ __forceinline__ void store4(typename Fmt<S>::T* p, const float* v);

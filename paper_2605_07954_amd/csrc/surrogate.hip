@@ -248,16 +248,22 @@ __global__ __launch_bounds__(256) void l6_fwd(const float* params, const uint16_
     uhat[p] = u0[p] + acc;
 }
 
+constexpr int MAXB = 64;  // largest training batch (per-sample loss masks travel in the kernel arguments)
+struct MaskArgs {
+    int lohi[4 * MAXB];  // per sample: rows [lohi[0], lohi[1]) x cols [lohi[2], lohi[3])
+};
+
 // dF = (2/n) (u_hat - target) on the mask; per-block FP64 partial sums of the squared error
 __global__ __launch_bounds__(256) void loss_grad(const float* uhat, const float* target, int nb, int H, int W,
-                                                 int ylo, int yhi, int xlo, int xhi, double inv_n, float* dF,
-                                                 double* partial) {
+                                                 MaskArgs mk, double inv_n, float* dF, double* partial) {
     __shared__ double red[256];
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
     double e2 = 0.0;
     if (p < int64_t(nb) * H * W) {
+        const int b = int(p / (int64_t(H) * W));
         const int y = int((p / W) % H), x = int(p % W);
-        const bool in = y >= ylo && y < yhi && x >= xlo && x < xhi;
+        const int* m = mk.lohi + 4 * b;
+        const bool in = y >= m[0] && y < m[1] && x >= m[2] && x < m[3];
         const float d = in ? uhat[p] - target[p] : 0.0f;
         dF[p] = float(2.0 * inv_n) * d;
         e2 = double(d) * double(d);
@@ -500,26 +506,60 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int n,
 // training-data synthesis and crops
 // ---------------------------------------------------------------------------
 constexpr int NU = 16, NK = 8;
-__global__ void synth_kernel(const float* coef, int n, int rows, int cols, float* u0, float* kappa) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= int64_t(n) * rows * cols) return;
-    const int t = int(idx / (int64_t(rows) * cols));
-    const int i = int((idx / cols) % rows), j = int(idx % cols);
+constexpr int SY = 16, SX = 64;  // cells per synthesis block (4 per thread)
+
+// Both fields are separable per mode: sin(a i) sin(b j) for u0, and
+// cos(A_j + B_i) = cos A_j cos B_i - sin A_j sin B_i for kappa.  Each block evaluates the
+// per-row and per-column factors of its 16 x 64 cells once (FP64 trigonometry, rounded to FP32)
+// and combines them with FMAs.
+__global__ __launch_bounds__(256) void synth_kernel(const float* coef, int n, int rows, int cols, float* u0,
+                                                    float* kappa) {
+    __shared__ float su[NU][SY], tu[NU][SX], cb[NK][SY], sb[NK][SY], ca[NK][SX], sa[NK][SX];
+    __shared__ float amp[NU], bamp[NK], binv;
+    const int bx = (cols + SX - 1) / SX, by = (rows + SY - 1) / SY;
+    const int t = blockIdx.x / (bx * by), r = blockIdx.x % (bx * by);
+    const int i0 = (r / bx) * SY, j0 = (r % bx) * SX;
     const float* c = coef + int64_t(t) * 4 * (NU + NK);
     const double pi = 3.14159265358979323846;
-    double u = 0.0;
-    for (int m = 0; m < NU; ++m) {
-        const double p = c[4 * m], q = c[4 * m + 1], a = c[4 * m + 2];
-        u += a * sin(p * pi * (i + 1) / (rows + 1)) * sin(q * pi * (j + 1) / (cols + 1));
+    for (int k = threadIdx.x; k < NU * (SY + SX); k += 256) {
+        const int m = k / (SY + SX), q = k % (SY + SX);
+        if (q < SY) su[m][q] = float(sin(double(c[4 * m]) * pi * (i0 + q + 1) / (rows + 1)));
+        else tu[m][q - SY] = float(sin(double(c[4 * m + 1]) * pi * (j0 + q - SY + 1) / (cols + 1)));
     }
-    double g = 0.0, nrm = 0.0;
-    for (int m = NU; m < NU + NK; ++m) {
-        const double kx = c[4 * m], ky = c[4 * m + 1], bb = c[4 * m + 2], ph = c[4 * m + 3];
-        g += bb * cos(2.0 * pi * (kx * j / cols + ky * double(i) / rows) + ph);
-        nrm += fabs(bb);
+    for (int k = threadIdx.x; k < NK * (SY + SX); k += 256) {
+        const int m = k / (SY + SX), q = k % (SY + SX);
+        const float* cm = c + 4 * (NU + m);
+        if (q < SY) {
+            const double B = 2.0 * pi * double(cm[1]) * double(i0 + q) / rows;
+            cb[m][q] = float(cos(B));
+            sb[m][q] = float(sin(B));
+        } else {
+            const double A = 2.0 * pi * double(cm[0]) * double(j0 + q - SY) / cols + double(cm[3]);
+            ca[m][q - SY] = float(cos(A));
+            sa[m][q - SY] = float(sin(A));
+        }
     }
-    u0[idx] = float(u);
-    kappa[idx] = float(0.125 + 0.075 * g / fmax(nrm, 1e-30));
+    if (threadIdx.x < NU) amp[threadIdx.x] = c[4 * threadIdx.x + 2];
+    if (threadIdx.x < NK) bamp[threadIdx.x] = c[4 * (NU + threadIdx.x) + 2];
+    if (threadIdx.x == 0) {
+        double nrm = 0.0;
+        for (int m = 0; m < NK; ++m) nrm += fabs(double(c[4 * (NU + m) + 2]));
+        binv = float(0.075 / fmax(nrm, 1e-30));
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SY * SX; k += 256) {
+        const int q = k / SX, e = k % SX;
+        const int i = i0 + q, j = j0 + e;
+        if (i >= rows || j >= cols) continue;
+        float u = 0.0f, g = 0.0f;
+#pragma unroll
+        for (int m = 0; m < NU; ++m) u = __builtin_fmaf(amp[m] * su[m][q], tu[m][e], u);
+#pragma unroll
+        for (int m = 0; m < NK; ++m) g = __builtin_fmaf(bamp[m], ca[m][e] * cb[m][q] - sa[m][e] * sb[m][q], g);
+        const int64_t o = (int64_t(t) * rows + i) * cols + j;
+        u0[o] = u;
+        kappa[o] = 0.125f + g * binv;
+    }
 }
 
 __global__ void crop_kernel(const float* src, float* dst, const int* yx, int n, int rows, int cols, int h, int w) {
@@ -709,9 +749,20 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
                         void* workspace, size_t ws_bytes, void* stream) {
     if (!m || !params || !u0 || !kappa || !target || !lo_hi || !grad || !loss) return fail(ST_EINVAL, "NULL argument");
     if (int rc = check_dims(batch, rows, cols)) return rc;
-    const int ylo = std::max(0, lo_hi[0]), yhi = std::min<int>(int(rows), lo_hi[1]);
-    const int xlo = std::max(0, lo_hi[2]), xhi = std::min<int>(int(cols), lo_hi[3]);
-    if (yhi <= ylo || xhi <= xlo) return fail(ST_EINVAL, "empty loss mask");
+    if (batch > MAXB) return fail(ST_EINVAL, "training batch larger than 64");
+    MaskArgs mk;
+    std::memset(&mk, 0, sizeof(mk));
+    double n = 0.0;
+    for (int b = 0; b < batch; ++b) {
+        const int* m = lo_hi + 4 * b;
+        mk.lohi[4 * b] = std::max(0, m[0]);
+        mk.lohi[4 * b + 1] = std::min<int>(int(rows), m[1]);
+        mk.lohi[4 * b + 2] = std::max(0, m[2]);
+        mk.lohi[4 * b + 3] = std::min<int>(int(cols), m[3]);
+        n += double(std::max(0, mk.lohi[4 * b + 1] - mk.lohi[4 * b])) *
+             double(std::max(0, mk.lohi[4 * b + 3] - mk.lohi[4 * b + 2]));
+    }
+    if (n <= 0.0) return fail(ST_EINVAL, "empty loss mask");
     const WsLayout L = layout(batch, rows, cols, true);
     if (!workspace || ws_bytes < L.total) return fail(ST_ENOWS, "workspace too small");
     char* ws = static_cast<char*>(workspace);
@@ -719,12 +770,10 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
     const int H = int(rows), W = int(cols), nb = batch;
     float* uhat = reinterpret_cast<float*>(ws + L.dz1);  // scratch: dz1 is not needed until layer-2 backward
     if (int rc = forward_impl(params, u0, kappa, uhat, nb, H, W, ws, L, true, s)) return rc;
-    const double n = double(nb) * (yhi - ylo) * (xhi - xlo);
     float* dF = reinterpret_cast<float*>(ws + L.dF);
     double* lossp = reinterpret_cast<double*>(ws + L.lossp);
     const unsigned gpx = unsigned(L.nblk_px);
-    hipLaunchKernelGGL(loss_grad, dim3(gpx), dim3(256), 0, s, uhat, target, nb, H, W, ylo, yhi, xlo, xhi, 1.0 / n,
-                       dF, lossp);
+    hipLaunchKernelGGL(loss_grad, dim3(gpx), dim3(256), 0, s, uhat, target, nb, H, W, mk, 1.0 / n, dF, lossp);
     ST_LAUNCH_CHECK("loss_grad");
     hipLaunchKernelGGL(loss_finish, dim3(1), dim3(256), 0, s, lossp, L.nblk_px, 1.0 / n, loss);
     ST_LAUNCH_CHECK("loss_finish");
@@ -794,10 +843,10 @@ int surrogate_synth_fields(const float* coef, int n, int64_t rows, int64_t cols,
                            void* stream) {
     if (!coef || !u0_out || !kappa_out) return fail(ST_EINVAL, "NULL argument");
     if (n < 1 || rows < 1 || cols < 1 || int64_t(n) * rows * cols > (int64_t(1) << 33)) return fail(ST_EINVAL, "bad sizes");
-    const int64_t total = int64_t(n) * rows * cols;
+    const int64_t blocks = int64_t(n) * ((rows + SY - 1) / SY) * ((cols + SX - 1) / SX);
     clear_stale_error();
-    hipLaunchKernelGGL(synth_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       coef, n, int(rows), int(cols), u0_out, kappa_out);
+    hipLaunchKernelGGL(synth_kernel, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(stream), coef, n,
+                       int(rows), int(cols), u0_out, kappa_out);
     ST_LAUNCH_CHECK("synth");
     return ST_OK;
 }

@@ -87,37 +87,59 @@ __device__ __forceinline__ void tile_body(const void* srcv, void* dstv, int64_t 
         const int c_lo = (OFF - H) & ~(VEC - 1);
         const int c_hi = (OFF + TX + H + VEC - 1) & ~(VEC - 1);
         const int nch = (c_hi - c_lo) / VEC;
+        // The BH x nch chunks are dealt round-robin to the NT threads; each thread walks its
+        // chunks with an incremental (row, column) update instead of a division per chunk, and
+        // keeps up to U chunks in flight (raw 16-byte words first, widened into LDS after all of
+        // them were issued), so the load phase costs about one memory latency.
+        constexpr int U = 12;
         const int total = BH * nch;
-        constexpr int U = 4;  // chunks in flight per thread
+        const int dq = NT / nch, dr = NT % nch;
+        int br = int(threadIdx.x) / nch, cc = int(threadIdx.x) % nch;
         for (int k0 = threadIdx.x; k0 < total; k0 += U * NT) {
-            float v[U][VEC];
-            int br[U], bc[U];
+            uint4 raw[U];
+            int dstoff[U];
+            bool got[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int k = k0 + u * NT;
-                br[u] = k / nch;
-                bc[u] = c_lo + (k - br[u] * nch) * VEC;
-                const int64_t gy = y0 - H + br[u], gx = x0 - OFF + bc[u];
-                const bool live = k < total;
-                if (!live || gy < 0 || gy >= rows || gx + VEC <= 0 || gx >= cols) {
+                got[u] = false;
+                dstoff[u] = 0;
+                if (k0 + u * NT < total) {
+                    const int bc = c_lo + cc * VEC;
+                    const int64_t gy = y0 - H + br, gx = x0 - OFF + bc;
+                    dstoff[u] = br * BW + bc;
+                    float4* p = reinterpret_cast<float4*>(buf0 + dstoff[u]);
+                    if (gy < 0 || gy >= rows || gx + VEC <= 0 || gx >= cols) {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) v[u][e] = b;
-                } else if (vec_ok && gx >= 0 && gx + VEC <= cols) {
-                    load_chunk<S>(src + gy * cols + gx, v[u]);
-                } else {
+                        for (int e = 0; e < VEC; e += 4) p[e / 4] = make_float4(b, b, b, b);
+                    } else if (vec_ok && gx >= 0 && gx + VEC <= cols) {
+                        raw[u] = *reinterpret_cast<const uint4*>(src + gy * cols + gx);
+                        got[u] = true;
+                    } else {
+                        float v[VEC];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        const int64_t x = gx + e;
-                        v[u][e] = (x >= 0 && x < cols) ? F::ld(src[gy * cols + x]) : b;
+                        for (int e = 0; e < VEC; ++e) {
+                            const int64_t x = gx + e;
+                            v[e] = (x >= 0 && x < cols) ? F::ld(src[gy * cols + x]) : b;
+                        }
+#pragma unroll
+                        for (int e = 0; e < VEC; e += 4) p[e / 4] = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
                     }
+                }
+                br += dq;
+                cc += dr;
+                if (cc >= nch) {
+                    cc -= nch;
+                    ++br;
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (k0 + u * NT >= total) break;
-                float4* p = reinterpret_cast<float4*>(buf0 + br[u] * BW + bc[u]);
+                if (!got[u]) continue;
+                float v[VEC];
+                widen_chunk<S>(raw[u], v);
+                float4* p = reinterpret_cast<float4*>(buf0 + dstoff[u]);
 #pragma unroll
-                for (int e = 0; e < VEC; e += 4) p[e / 4] = make_float4(v[u][e], v[u][e + 1], v[u][e + 2], v[u][e + 3]);
+                for (int e = 0; e < VEC; e += 4) p[e / 4] = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
             }
         }
     }

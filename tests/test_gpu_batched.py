@@ -1,5 +1,6 @@
 """GPU parity of the batched persistent kernel: every grid of a mixed batch equals the FP32-canonical
 oracle bit for bit (and the per-grid launch path), with and without the captured hipGraph."""
+import os
 import sys
 
 import numpy as np
@@ -9,6 +10,10 @@ import oracle
 import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+# a short dependency-wait limit: a scheduling bug then ends the kernel in milliseconds, and the
+# workspace header says which wait gave up
+os.environ.setdefault("MI355STENCIL_BATCH_SPIN", "20000")
 
 
 def say(*a):
@@ -42,7 +47,10 @@ def _run_batch(g, problems, flags, tbs=None, tiles=None, reps=2):
                     o.fill_(float("nan"))
                 lib.stencil_run_batched(batch, ins, outs, ws)
                 torch.cuda.synchronize()
-                assert not lib.stencil_batch_status(batch, ws)
+                if lib.stencil_batch_status(batch, ws):
+                    rec = ws[16:64].cpu().numpy().view(np.int64)
+                    raise AssertionError(f"dependency wait timed out: item {rec[0]} grid {rec[1]} tile {rec[2]} "
+                                         f"pass {rec[3]} waited on tile {rec[4]} whose counter was {rec[5]}")
                 results.append([g.to_host(o) for o in outs])
                 _ = (ins[0] * 3).sum().item()  # eager work between replays
             return results
@@ -69,6 +77,23 @@ def _mixed(n, seed, lo=40, hi=700, steps=(5, 17)):
     out.append(wl.Problem("bnz", 150, 260, 2, wl.BOX, wl.random_footprint_weights(rng, wl.BOX, 2), 0.75, 9,
                           rng.random((150, 260), dtype=np.float32)))
     return out
+
+
+def test_batched_single_grid(g):
+    """One tiled grid, several passes; then two grids; then one LDS-resident grid."""
+    rng = np.random.default_rng(1)
+    w5 = wl.heat5_weights()
+    a = wl.Problem("a", 300, 260, 1, wl.STAR, w5, 0.0, 6, rng.random((300, 260), dtype=np.float32))
+    b = wl.Problem("b", 130, 517, 3, wl.BOX, wl.random_footprint_weights(rng, wl.BOX, 3), 0.0, 5,
+                   rng.random((130, 517), dtype=np.float32))
+    c = wl.Problem("c", 40, 50, 2, wl.STAR, wl.random_footprint_weights(rng, wl.STAR, 2), 0.5, 9,
+                   rng.random((40, 50), dtype=np.float32))
+    for probs, tbs in (([a], [1]), ([a], [2]), ([a, b], [1, 2]), ([c], [1]), ([a, b, c], [3, 1, 1])):
+        say("batch", [(p.name, p.rows, p.cols, p.steps) for p in probs], "tb", tbs)
+        res = _run_batch(g, probs, 0, tbs=tbs, tiles=[(128, 64)], reps=1)
+        for p, got in zip(probs, res[0]):
+            np.testing.assert_array_equal(got, oracle.stencil_f32(p.u0, p.weights, p.boundary, p.steps),
+                                          err_msg=p.name)
 
 
 @pytest.mark.parametrize("graph", [0, 2])

@@ -97,10 +97,21 @@ def test_bitwise_across_blocking_and_graph(g):
     W = _weights(wl.BOX, 3, 5)
     u0 = np.random.default_rng(5).random((rows, cols), dtype=np.float32)
     base = g.run_problem(u0, W, 0.0, 13, flags=lib.ST_FLAG_NAIVE)
+    checked = 0
     for tile in lib.stencil_tiles():
         for tb in (1, 2, 3, 5, 6):
+            probe = lib.stencil_plan(rows, cols, 3, W, 0.0, "f32", 0)
+            try:
+                lib.stencil_set_blocking(probe, tb, *tile)
+            except lib.StencilError as e:  # deeper than this tile's LDS budget: refused up front
+                assert e.code == -3
+                continue
+            finally:
+                lib.stencil_destroy(probe)
             got = g.run_problem(u0, W, 0.0, 13, tb=tb, tile=tile)
             np.testing.assert_array_equal(got, base)
+            checked += 1
+    assert checked >= 12
     # graph replays (with eager work between them) equal the direct run, every time
     plan = lib.stencil_plan(rows, cols, 3, W, 0.0, "f32", lib.ST_FLAG_GRAPH)
     try:
@@ -148,12 +159,14 @@ def test_norms(g):
             lib.stencil_norms(plan, g.to_dev(up), g.to_dev(u), o, ws)
             got = o.cpu().numpy()
             ref = oracle.norms_f64(u, W, b, up)
+            say(f"norms {rows}x{cols} r={r} b={b}: gpu {got.tolist()} oracle {ref.tolist()}")
             np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-9)
             o2 = torch.zeros(4, dtype=torch.float64, device=g.DEV)
             lib.stencil_norms(plan, g.to_dev(up), g.to_dev(u), o2, ws)
             assert torch.equal(o, o2)  # deterministic
             # the predicted next mass is the mass of the next step
             nxt = g.run_problem(u, W, b, 1)
+            say(f"  next-step mass: predicted {got[3]!r}, summed {nxt.astype(np.float64).sum()!r}")
             assert abs(got[3] - nxt.astype(np.float64).sum()) < 1e-5 * (1 + abs(got[3]))
         finally:
             lib.stencil_destroy(plan)
