@@ -47,7 +47,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tb: int, tile) -> float | None:
+def measured_traffic(tb: int, tile, variant: int) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source with the same blocking; else None."""
     path = os.path.join(ROOT, "profiles", "box49_16384_traffic.json")
@@ -57,7 +57,8 @@ def measured_traffic(tb: int, tile) -> float | None:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_source_hash() or d.get("tb") != tb or list(d.get("tile", [])) != list(tile):
+    if (d.get("kernel_hash") != kernel_source_hash() or d.get("tb") != tb or list(d.get("tile", [])) != list(tile)
+            or d.get("variant") != variant):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -98,10 +99,13 @@ def main_line(args, torch, lib, stream):
     tune_steps = 24
     ws = torch.empty_like(x)
     if args.tb:
-        lib.stencil_set_blocking(plan, args.tb, *(args.tile or (0, 0)))
+        lib.stencil_set_blocking(plan, 1, *(args.tile or (0, 0)))
+        lib.stencil_set_variant(plan, args.variant)
+        lib.stencil_set_blocking(plan, args.tb)
         tb, tx, ty = lib.stencil_get_blocking(plan)
     else:
         tb, tx, ty = lib.stencil_autotune(plan, x, out, ws, tune_steps, stream)
+    variant = lib.stencil_get_variant(plan)
     tune_s = time.perf_counter() - t0
     T = p.steps
     run = lambda: lib.stencil_run(plan, x, out, T, ws, stream)  # noqa: E731
@@ -114,10 +118,10 @@ def main_line(args, torch, lib, stream):
     launches = math.ceil(T / tb) * args.steps
     flops = 97.0 * T * rows * cols * args.steps  # 1 multiply + 48 FMA per update
     achieved = flops / t
-    traffic = measured_traffic(tb, (tx, ty))
+    traffic = measured_traffic(tb, (tx, ty), variant)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / VALU_FP32_PEAK, "traffic": traffic,
-            "kernel": "sweep_tiled<f32, r=3, box>", "launches": launches, "avg_launch_us": t / launches * 1e6,
+            "kernel": ("sweep_stream" if variant == 1 else "sweep_tiled") + "<f32, r=3, box>", "launches": launches, "avg_launch_us": t / launches * 1e6,
             "alg_flop_per_launch": 97.0 * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
             "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
             "alu_roof_gstencil": VALU_FP32_PEAK / 97.0 / 1e9,
@@ -126,7 +130,7 @@ def main_line(args, torch, lib, stream):
     lib.stencil_destroy(plan)
     del x, out, ws
     torch.cuda.empty_cache()
-    return p, value, ms, roof, (tb, tx, ty), tune_s
+    return p, value, ms, roof, (tb, tx, ty, variant), tune_s
 
 
 def extras(torch, lib, stream) -> dict:
@@ -172,11 +176,19 @@ def extras(torch, lib, stream) -> dict:
     tuned = {}
     for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):  # one autotune per stencil class
         key = (q.shape, q.radius)
-        if key not in tuned and q.rows * q.cols >= 512 * 512:
-            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream)
+        if key not in tuned and q.rows * q.cols >= 512 * 512 and q.cols % 4 == 0:
+            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
     for q, pl in zip(probs, plans):
-        if (q.shape, q.radius) in tuned:
-            lib.stencil_set_blocking(pl, *tuned[(q.shape, q.radius)])
+        if (q.shape, q.radius) not in tuned:
+            continue
+        tb, tx, ty, var = tuned[(q.shape, q.radius)]
+        try:
+            lib.stencil_set_blocking(pl, 1, tx, ty)
+            if var == lib.ST_VARIANT_STREAM and q.cols % 4 == 0:
+                lib.stencil_set_variant(pl, var)
+            lib.stencil_set_blocking(pl, tb)
+        except lib.StencilError:
+            pass
     per_grid = lambda: [lib.stencil_run(pl, i, o, q.steps, w, stream)  # noqa: E731
                         for q, pl, i, o, w in zip(probs, plans, ins, outs, wss)]
     per_grid()
@@ -238,6 +250,7 @@ def main():
     ap.add_argument("--jacobi-steps", type=int, default=1000)
     ap.add_argument("--tb", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=None)
+    ap.add_argument("--variant", type=int, default=1, help="with --tb: 0 = tiled, 1 = streaming")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
@@ -249,13 +262,14 @@ def main():
     import paper_2605_07954_amd as lib
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    p, value, ms, roof, (tb, tx, ty), tune_s = main_line(args, torch, lib, stream)
+    p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)
     line = {"metric": "GStencil/s", "value": value, "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"box2d49p-{p.rows}x{p.cols}-{p.steps}steps", "stencil": "box", "radius": 3,
                        "grid": [p.rows, p.cols], "jacobi_steps": p.steps, "boundary": "dirichlet-0",
-                       "tb": tb, "tile": [tx, ty], "autotune_s": round(tune_s, 2)},
+                       "tb": tb, "tile": [tx, ty], "variant": ["tiled", "stream"][variant],
+                       "autotune_s": round(tune_s, 2)},
             "roofline": roof}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)

@@ -100,6 +100,17 @@ int stencil_destroy(st_plan* plan);
  * (tile not instantiated; the supported set is listed by stencil_tiles()). */
 int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
 
+/* kernel variants of the constant-weight sweep */
+#define ST_VARIANT_TILED   0  /* one launch per pass, one tile per workgroup                    */
+#define ST_VARIANT_STREAM  1  /* persistent workgroups; the next tile is copied into LDS by DMA
+                                 while the current one computes (FP32, cols % 4 == 0)          */
+
+/* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
+ * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage, cols % 4 == 0 and
+ * a constant-weight plan; or the current tb does not fit the variant's LDS budget). */
+int stencil_set_variant(st_plan* plan, int variant);
+int stencil_get_variant(const st_plan* plan, int* variant);
+
 /* stencil_get_blocking -- read back the current (tb, tile_x, tile_y). */
 int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y);
 
@@ -144,13 +155,27 @@ int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes);
 int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
                   size_t ws_bytes, void* stream);
 
-/* stencil_autotune -- time every supported (tb, tile) candidate on the
+/* stencil_autotune -- time every supported (variant, tb, tile) candidate on the
  * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
  * Synchronises the stream.  Errors: as stencil_run. */
 int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
                      int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream);
+
+/* stencil_solve_ws_bytes -- workspace stencil_solve needs for this check interval. */
+int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* bytes);
+
+/* stencil_solve -- iterate to convergence with a periodic check (the host-side convergence
+ * check between otherwise host-free iterations, paper Sec. IV): every `check_every` steps the
+ * FP64 relative residual ||u_t - u_{t-1}||_2 / ||u_t||_2 of the last step is computed on the
+ * device and read back; the loop stops once it is <= tol or after max_steps steps.  `out`
+ * receives the last iterate, *steps_done the number of steps taken (a multiple of check_every
+ * unless max_steps cut the last interval), *rel_residual the last residual.  The result is
+ * bitwise the same as stencil_run(plan, in, out, *steps_done).  Synchronises at every check.
+ * Errors: as stencil_run; ST_EINVAL for a varcoef plan or bad counts. */
+int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
+                  int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- batched: many independent grids, one persistent launch ------------ */
 

@@ -185,7 +185,10 @@ def support_sums(rows: int, cols: int, W: np.ndarray) -> np.ndarray:
             w = float(W[dy + r, dx + r])
             if w == 0.0:
                 continue
-            S[max(dy, 0):min(rows + dy, rows), max(dx, 0):min(cols + dx, cols)] += w
+            y0, y1 = max(dy, 0), max(0, min(rows + dy, rows))  # empty when |dy| >= rows
+            x0, x1 = max(dx, 0), max(0, min(cols + dx, cols))
+            if y0 < y1 and x0 < x1:
+                S[y0:y1, x0:x1] += w
     return S
 
 

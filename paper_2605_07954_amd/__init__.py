@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mi355stencil.h")
 ST_OK = 0
 ST_F32, ST_BF16, ST_F16 = 0, 1, 2
 ST_FLAG_NAIVE, ST_FLAG_GRAPH = 0x1, 0x2
+ST_VARIANT_TILED, ST_VARIANT_STREAM = 0, 1
 SG_PARAM_COUNT = 37889
 STORAGE = {"f32": ST_F32, "bf16": ST_BF16, "f16": ST_F16}
 
@@ -45,6 +46,8 @@ _SIGS = {
     "stencil_destroy": [_p],
     "stencil_set_blocking": [_p, _int, _int, _int],
     "stencil_get_blocking": [_p, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
+    "stencil_set_variant": [_p, _int],
+    "stencil_get_variant": [_p, ctypes.POINTER(_int)],
     "stencil_tiles": [ctypes.POINTER(_int), _int, ctypes.POINTER(_int)],
     "stencil_workspace_bytes": [_p, _i64, ctypes.POINTER(_sz)],
     "stencil_run": [_p, _p, _p, _i64, _p, _sz, _p],
@@ -53,6 +56,9 @@ _SIGS = {
     "stencil_norms": [_p, _p, _p, _p, _p, _sz, _p],
     "stencil_autotune": [_p, _p, _p, _p, _sz, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
                          ctypes.POINTER(_int), _p],
+    "stencil_solve_ws_bytes": [_p, _i64, ctypes.POINTER(_sz)],
+    "stencil_solve": [_p, _p, _p, _i64, _i64, ctypes.c_double, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                      _p, _sz, _p],
     "stencil_batch_create": [ctypes.POINTER(_p), _int, ctypes.POINTER(_p), ctypes.POINTER(_i64), _u32],
     "stencil_batch_workspace_bytes": [_p, ctypes.POINTER(_sz)],
     "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
@@ -172,6 +178,16 @@ def stencil_set_blocking(plan, tb: int = 0, tile_x: int = 0, tile_y: int = 0) ->
     _ck(lib().stencil_set_blocking(plan, tb, tile_x, tile_y), "stencil_set_blocking")
 
 
+def stencil_set_variant(plan, variant: int) -> None:
+    _ck(lib().stencil_set_variant(plan, variant), "stencil_set_variant")
+
+
+def stencil_get_variant(plan) -> int:
+    v = _int()
+    _ck(lib().stencil_get_variant(plan, ctypes.byref(v)), "stencil_get_variant")
+    return v.value
+
+
 def stencil_get_blocking(plan):
     tb, tx, ty = _int(), _int(), _int()
     _ck(lib().stencil_get_blocking(plan, ctypes.byref(tb), ctypes.byref(tx), ctypes.byref(ty)),
@@ -220,6 +236,22 @@ def stencil_autotune(plan, inp, out, workspace, sample_steps: int, stream=None):
                                _nbytes(workspace), sample_steps, ctypes.byref(tb), ctypes.byref(tx),
                                ctypes.byref(ty), _stream(stream)), "stencil_autotune")
     return tb.value, tx.value, ty.value
+
+
+def stencil_solve_ws_bytes(plan, check_every: int) -> int:
+    n = _sz()
+    _ck(lib().stencil_solve_ws_bytes(plan, check_every, ctypes.byref(n)), "stencil_solve_ws_bytes")
+    return n.value
+
+
+def stencil_solve(plan, inp, out, max_steps: int, check_every: int, tol: float, workspace, stream=None):
+    """Returns (steps_done, relative residual of the last step)."""
+    done = _i64()
+    res = ctypes.c_double()
+    _ck(lib().stencil_solve(plan, _dptr(inp, "in"), _dptr(out, "out"), max_steps, check_every, float(tol),
+                            ctypes.byref(done), ctypes.byref(res), _dptr(workspace, "workspace"), _nbytes(workspace),
+                            _stream(stream)), "stencil_solve")
+    return done.value, res.value
 
 
 # ---------------------------------------------------------------------------

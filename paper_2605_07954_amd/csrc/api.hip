@@ -1,6 +1,7 @@
 // Host side of the C ABI: plans, validation, pass scheduling, graphs, autotuning, errors.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <new>
 #include <unordered_set>
@@ -35,6 +36,22 @@ size_t lds_limit() {
         cached = size_t(std::max({optin, plain, 65536}));
     }
     return cached;
+}
+
+int resident_blocks(const void* fn, size_t lds, int* blocks) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, size_t>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({fn, lds});
+    if (it == cache.end()) {
+        int dev = 0, cus = 0, occ = 0;
+        ST_HIP_CHECK(hipGetDevice(&dev));
+        ST_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        ST_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, lds));
+        it = cache.emplace(std::make_pair(fn, lds), std::max(1, cus * std::max(occ, 1))).first;
+    }
+    *blocks = it->second;
+    return ST_OK;
 }
 
 int prepare_lds(const void* fn, size_t bytes) {
@@ -212,6 +229,27 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
     return ST_OK;
 }
 
+int stencil_set_variant(st_plan* plan, int variant) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM) return fail(ST_EINVAL, "unknown variant");
+    if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
+        return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
+    const int old = plan->variant;
+    plan->variant = variant;
+    if (plan->tb > max_tb(plan, plan->tile_x, plan->tile_y)) {  // keep the plan launchable
+        plan->variant = old;
+        return fail(ST_EUNSUPPORTED, "current temporal block too deep for this variant; lower it first");
+    }
+    drop_graph(plan);
+    return ST_OK;
+}
+
+int stencil_get_variant(const st_plan* plan, int* variant) {
+    if (!plan || !variant) return fail(ST_EINVAL, "NULL argument");
+    *variant = plan->variant;
+    return ST_OK;
+}
+
 int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
     if (tb) *tb = plan->tb;
@@ -342,7 +380,7 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const uint32_t saved_flags = plan->flags;
     plan->flags &= ~ST_FLAG_GRAPH;
-    int best_tb = plan->tb, best_tx = plan->tile_x, best_ty = plan->tile_y;
+    int best_tb = plan->tb, best_tx = plan->tile_x, best_ty = plan->tile_y, best_var = plan->variant;
     float best_ms = 1e30f;
     int tiles[32];
     const int nt = supported_tiles(tiles, 16);
@@ -351,8 +389,11 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
+    const int nvar = (plan->kind == KIND_CONST && stream_usable(plan)) ? 2 : 1;
+    for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
+        plan->variant = var;
         for (int tb : kTb) {
             if (plan->kind == KIND_CONST && tb > max_tb(plan, tx, ty)) continue;
             if (tb > sample_steps) continue;
@@ -374,12 +415,14 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
                 best_tb = tb;
                 best_tx = tx;
                 best_ty = ty;
+                best_var = var;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     plan->flags = saved_flags;
+    plan->variant = best_var;
     plan->tb = best_tb;
     plan->tile_x = best_tx;
     plan->tile_y = best_ty;
@@ -388,6 +431,64 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     if (tb_out) *tb_out = best_tb;
     if (tile_x_out) *tile_x_out = best_tx;
     if (tile_y_out) *tile_y_out = best_ty;
+    return ST_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* bytes) {
+    if (!plan || !bytes) return fail(ST_EINVAL, "NULL argument");
+    if (check_every < 1) return fail(ST_EINVAL, "check_every must be >= 1");
+    size_t nb = 0, run_ws = 0;
+    if (int rc = stencil_norms_ws_bytes(plan, &nb)) return rc;
+    if (int rc = stencil_workspace_bytes(plan, check_every, &run_ws)) return rc;
+    const size_t field = (size_t(plan->rows * plan->cols) * elem_size(plan->storage) + 255) & ~size_t(255);
+    *bytes = field + std::max(run_ws, field) + ((nb + 255) & ~size_t(255)) + 256;
+    return ST_OK;
+}
+
+int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
+                  int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream) {
+    if (!plan || !in || !out || !steps_done || !rel_residual) return fail(ST_EINVAL, "NULL argument");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "stencil_solve takes a constant-weight plan");
+    if (max_steps < 1 || check_every < 1 || !(tol >= 0.0)) return fail(ST_EINVAL, "bad max_steps/check_every/tol");
+    size_t need = 0;
+    if (int rc = stencil_solve_ws_bytes(plan, check_every, &need)) return rc;
+    if (!workspace || ws_bytes < need) return fail(ST_ENOWS, "workspace too small");
+    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
+    const size_t field = (bytes + 255) & ~size_t(255);
+    size_t run_ws = 0, nb = 0;
+    stencil_workspace_bytes(plan, check_every, &run_ws);
+    stencil_norms_ws_bytes(plan, &nb);
+    char* ws = static_cast<char*>(workspace);
+    void* prev = ws;                                   // the iterate one step before `out`
+    void* scratch = ws + field;                        // stencil_run's own ping-pong field
+    const size_t scratch_bytes = std::max(run_ws, field);
+    void* nscr = ws + field + scratch_bytes;           // norms partial sums
+    double* sums = reinterpret_cast<double*>(static_cast<char*>(nscr) + ((nb + 255) & ~size_t(255)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const void* cur = in;
+    int64_t done = 0;
+    double rel = 0.0;
+    while (done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        // k - 1 steps into `prev`, then the last step into `out`: the residual compares them
+        if (int rc = stencil_run(plan, cur, prev, k - 1, scratch, scratch_bytes, stream)) return rc;
+        if (int rc = stencil_run(plan, prev, out, 1, scratch, scratch_bytes, stream)) return rc;
+        done += k;
+        if (int rc = stencil_norms(plan, prev, out, sums, nscr, nb, stream)) return rc;
+        double h[4];
+        ST_HIP_CHECK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
+        ST_HIP_CHECK(hipStreamSynchronize(s));
+        rel = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+        if (rel <= tol) break;
+        cur = out;
+    }
+    *steps_done = done;
+    *rel_residual = rel;
     return ST_OK;
 }
 

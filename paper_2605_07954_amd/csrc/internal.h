@@ -35,6 +35,7 @@ int fail(int code, const std::string& msg);
 
 enum Shape { SHAPE_STAR = 0, SHAPE_BOX = 1 };
 enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1 };
+enum Variant { VARIANT_TILED = ST_VARIANT_TILED, VARIANT_STREAM = ST_VARIANT_STREAM };
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
 
@@ -64,6 +65,7 @@ struct st_plan {
     float bq;         // b rounded to storage, widened to float
     double wsum;      // sum of the FP32 weights in FP64
     int tb, tile_x, tile_y;
+    int variant;      // st::Variant (FP32 grids with cols % 4 == 0 may stream)
     // cached hipGraph of a full run (ST_FLAG_GRAPH)
     void* graph_exec;
     const void* g_in;
@@ -92,6 +94,9 @@ size_t varcoef_lds_bytes(int tb);
 size_t lds_limit();
 // Allow `fn` to launch with `bytes` of dynamic LDS (ST_EUNSUPPORTED above lds_limit()).
 int prepare_lds(const void* fn, size_t bytes);
+// Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
+int resident_blocks(const void* fn, size_t lds, int* blocks);
+bool stream_usable(const st_plan* p);
 // Drop a stale runtime error left by earlier API calls so that the check after our next
 // launch reports that launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }

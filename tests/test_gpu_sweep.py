@@ -215,3 +215,73 @@ def test_error_paths(g):
         assert ei.value.code == -5
     finally:
         lib.stencil_destroy(plan)
+
+
+@pytest.mark.parametrize("rows,cols,shape,r,b,steps", [(1024, 1024, wl.BOX, 3, 0.0, 7), (260, 516, wl.STAR, 1, 0.5, 9),
+                                                      (131, 64, wl.BOX, 2, -1.0, 5), (700, 1200, wl.STAR, 3, 0.0, 8)])
+def test_stream_variant_bitwise(g, rows, cols, shape, r, b, steps):
+    """The persistent LDS-DMA variant equals the FP32-canonical oracle bit for bit, every tile and depth."""
+    import torch
+    import paper_2605_07954_amd as lib
+    W = _weights(shape, r, rows + cols + r)
+    u0 = np.random.default_rng(rows * cols).random((rows, cols), dtype=np.float32)
+    ref = oracle.stencil_f32(u0, W, b, steps)
+    x = g.to_dev(u0)
+    n = 0
+    for tile in lib.stencil_tiles():
+        for tb in (1, 2, 3):
+            plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
+            try:
+                try:
+                    lib.stencil_set_blocking(plan, 1, *tile)
+                    lib.stencil_set_variant(plan, lib.ST_VARIANT_STREAM)
+                    lib.stencil_set_blocking(plan, tb)
+                except lib.StencilError as e:
+                    assert e.code == -3
+                    continue
+                out = torch.full_like(x, float("nan"))
+                ws = torch.empty_like(x)
+                lib.stencil_run(plan, x, out, steps, ws)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"tile {tile} tb {tb}")
+                n += 1
+            finally:
+                lib.stencil_destroy(plan)
+    assert n >= 6
+    # grids whose width is not a multiple of 4 refuse the streaming variant
+    plan = lib.stencil_plan(rows, cols + 1, r, W, b, "f32", 0)
+    try:
+        with pytest.raises(lib.StencilError):
+            lib.stencil_set_variant(plan, lib.ST_VARIANT_STREAM)
+    finally:
+        lib.stencil_destroy(plan)
+
+
+def test_solve_until_converged(g):
+    """Periodic convergence check: stops at the first check whose relative residual is <= tol, and
+    the field equals a plain run of that many steps."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, b = 32, 40, 1.0
+    W = wl.heat5_weights()
+    u0 = np.random.default_rng(17).random((rows, cols), dtype=np.float32)
+    plan = lib.stencil_plan(rows, cols, 1, W, b, "f32", 0)
+    try:
+        x = g.to_dev(u0)
+        out = torch.empty_like(x)
+        ws = torch.empty(lib.stencil_solve_ws_bytes(plan, 100), dtype=torch.uint8, device=g.DEV)
+        done, res = lib.stencil_solve(plan, x, out, 50000, 100, 1e-6, ws)
+        got = g.to_host(out)
+    finally:
+        lib.stencil_destroy(plan)
+    say(f"solve: {done} steps, relative residual {res:.3e}")
+    assert done % 100 == 0 and 100 < done < 50000
+    ref = oracle.stencil_f32(u0, W, b, done)
+    np.testing.assert_array_equal(got, ref)
+    before = oracle.stencil_f32(u0, W, b, done - 1).astype(np.float64)
+    rr = np.sqrt(np.sum((ref - before) ** 2) / np.sum(ref.astype(np.float64) ** 2))
+    assert abs(rr - res) <= 1e-9 * max(rr, 1e-30) + 1e-15
+    assert res <= 1e-6
+    a = oracle.stencil_f32(u0, W, b, done - 100).astype(np.float64)
+    a1 = oracle.stencil_f32(u0, W, b, done - 101).astype(np.float64)
+    assert np.sqrt(np.sum((a - a1) ** 2) / np.sum(a * a)) > 1e-6   # the previous check had not converged

@@ -154,6 +154,18 @@ def test_mass_budget(shape, r, b):
                - nxt.sum()) > 1e-6
 
 
+@pytest.mark.parametrize("rows,cols,r", [(5, 3, 4), (1, 1, 3), (2, 7, 4), (3, 2, 1), (4, 4, 4)])
+def test_mass_budget_grids_smaller_than_the_stencil(rows, cols, r):
+    """The support sum must ignore taps that reach past the whole grid (|d| >= side)."""
+    rng = np.random.default_rng(rows * 10 + cols + r)
+    W = wl.random_footprint_weights(rng, wl.BOX, r)
+    u = rng.standard_normal((rows, cols)).astype(np.float32)
+    for b in (0.0, 0.5):
+        nxt = oracle.stencil_f64(u, W, b, 1).sum()
+        pred = oracle.norms_f64(u, W, b)[3]
+        assert abs(pred - nxt) < 1e-12 * (1 + abs(nxt))
+
+
 def test_linearity_and_semigroup():
     rng = np.random.default_rng(3)
     W = wl.random_footprint_weights(rng, wl.BOX, 2)
