@@ -177,33 +177,30 @@ int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* byt
 int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
                   int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream);
 
-/* ---- batched: many independent grids, one persistent launch ------------ */
+/* ---- batched: many independent grids, one graph launch ------------------ */
 
-/* stencil_batch_create -- group n plans (FP32, not varcoef; each may differ
- * in shape, radius, footprint and weights) with their own step counts into one
- * batch, run by a single persistent kernel whose work items (grid, tile, pass)
- * wait on per-tile completion counters of the neighbouring tiles' previous
- * pass (the counter idea of the paper's halo-swap synchronisation, Sec. IV-C).
- * Each plan's current (tb, tile) is used; run stencil_autotune first to tune.
- * The plans must outlive the batch.  flags: ST_FLAG_GRAPH captures the
- * counter reset and the persistent launch in a hipGraph replayed on every run.
+/* stencil_batch_create -- group n plans (FP32, constant weights, r <= 3; each may differ in
+ * shape, radius, footprint and weights) with their own step counts into one batch.
+ * Grids that fit a workgroup's LDS together with their halo and a ping-pong copy stay
+ * resident in LDS for all their steps (one workgroup per grid).  The others are tiled
+ * (128 x 64 tiles) with their plan's temporal depth (lowered if the batch tile would not fit
+ * the LDS budget); pass p of all tiled grids is one multi-grid kernel, and the passes follow
+ * each other, so each tile's dependency on its neighbours' previous pass (the tiles' halo
+ * swap, paper Sec. IV-B/C) is carried by the kernel boundary.  Steps == 0 is a copy.  The
+ * plans must outlive the batch.  flags: ST_FLAG_GRAPH captures the whole run (resident
+ * grids on a parallel branch) in one hipGraph replayed by every run.
  * Errors: ST_EINVAL, ST_EUNSUPPORTED, ST_ENOMEM. */
 int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int64_t* steps, uint32_t flags);
 
-/* stencil_batch_workspace_bytes -- workspace for the batch: descriptor table,
- * counters and one extra field per grid. */
+/* stencil_batch_workspace_bytes -- workspace for the batch: descriptor and queue tables and
+ * one ping-pong field per grid that takes two or more passes. */
 int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
 
 /* stencil_run_batched -- outs[g] = S_g^{steps[g]}(ins[g]) for every grid g.
- * ins/outs are HOST arrays of n device pointers; no in/out pair may overlap.
- * Asynchronous on `stream`. */
+ * ins/outs are HOST arrays of n device pointers; no in/out pair may overlap.  Results are
+ * bitwise those of stencil_run on each grid.  Asynchronous on `stream`. */
 int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
                         size_t ws_bytes, void* stream);
-
-/* stencil_batch_status -- read the batch's watchdog flag from the workspace after a run:
- * *timed_out = 1 if some dependency wait hit its spin limit (results then invalid).  The
- * persistent kernel bounds every wait so that it always terminates.  Synchronises `stream`. */
-int stencil_batch_status(const st_batch* batch, const void* workspace, int* timed_out, void* stream);
 
 /* stencil_batch_destroy -- free the batch (graph, pinned table).  NULL is a no-op. */
 int stencil_batch_destroy(st_batch* batch);

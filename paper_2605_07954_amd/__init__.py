@@ -63,7 +63,6 @@ _SIGS = {
     "stencil_batch_workspace_bytes": [_p, ctypes.POINTER(_sz)],
     "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
     "stencil_batch_destroy": [_p],
-    "stencil_batch_status": [_p, _p, ctypes.POINTER(_int), _p],
     "surrogate_create": [ctypes.POINTER(_p), _u32],
     "surrogate_destroy": [_p],
     "surrogate_workspace_bytes": [_p, _int, _i64, _i64, ctypes.POINTER(_sz)],
@@ -279,14 +278,6 @@ def stencil_run_batched(batch, ins, outs, workspace, stream=None) -> None:
     po = (_p * n)(*[_dptr(t, "out").value for t in outs])
     _ck(lib().stencil_run_batched(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace),
                                   _stream(stream)), "stencil_run_batched")
-
-
-def stencil_batch_status(batch, workspace, stream=None) -> bool:
-    """True if a dependency wait of the last batched run hit its spin limit."""
-    flag = _int()
-    _ck(lib().stencil_batch_status(batch, _dptr(workspace, "workspace"), ctypes.byref(flag), _stream(stream)),
-        "stencil_batch_status")
-    return bool(flag.value)
 
 
 def stencil_batch_destroy(batch) -> None:

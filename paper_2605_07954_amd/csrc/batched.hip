@@ -1,19 +1,14 @@
-// Batched persistent kernel: many independent grids of uneven size and mixed stencil shape in
-// one launch.
+// Batched sweep: many independent grids of uneven size and mixed stencil shape, run by one
+// hipGraph launch.
 //
-// Work items are (grid, tile, pass).  Items are handed out by one atomic queue head in an
-// order where every item's dependencies come earlier: first the whole-grid items (small grids
-// that stay resident in LDS for all their steps), then the tiled items pass by pass.  Before a
-// tiled item of pass p starts, the tiles around it must have finished pass p-1; each tile has a
-// completion counter that its owner bumps after storing (the per-tile counterpart of the
-// send/receive counters that gate the paper's halo swap, Sec. IV-C).  Because an item only ever
-// waits on items handed out before it, which are held by running workgroups, the queue cannot
-// deadlock; a spin limit still ends every wait so that a bug cannot hang the device (the
-// timeout flag in the workspace header records it).
-//
-// Producer: stores -> __threadfence() (agent-scope release, makes the tile visible to other
-// XCDs) -> barrier -> counter store.  Consumer: counter load -> __threadfence() (agent-scope
-// acquire) -> barrier -> loads.
+// Small grids that fit a workgroup's LDS (with their halo and a ping-pong copy) are resident:
+// one workgroup keeps the grid in LDS for all of its steps, so it never round-trips through HBM.
+// The other grids are tiled; pass p of every tiled grid (tb steps each, as in the single-grid
+// sweep) is one multi-grid kernel whose workgroups each take one (grid, tile) of that pass, so a
+// pass of all grids costs one launch instead of one per grid.  Passes follow each other inside
+// the graph, so the dependency of a tile on its neighbours' previous pass (the halo exchange of
+// the paper's tiles, Sec. IV-B/C) is carried by the kernel boundary; the resident grids run on a
+// parallel branch of the same graph.
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
@@ -33,37 +28,27 @@ struct BatchDesc {
     float* ws;
     int64_t rows, cols;
     int64_t tiles_x, tiles_y;
-    int64_t cnt_off;
-    int r, shape, tile_id, tb, steps, passes, resident, pad;
+    int r, shape, tb, steps, passes, resident;
     float b;
     float w[MAXK];
 };
 
-struct BatchArgs {
-    unsigned long long* head;
-    int* timeout_flag;
-    int* counters;
+struct PassArgs {
     const BatchDesc* desc;
-    const int64_t* pass_start;   // [max_passes + 1] item offsets of the tiled passes (after the resident items)
-    const int64_t* tile_prefix;  // [n_tiled + 1] tile offsets within one pass, in queue order
-    const int* order;            // [n]: resident grids first, then tiled grids by pass count, descending
-    int64_t total;
-    int n_res, n_tiled, max_passes;
-    int64_t spin_limit;
+    const int* order;            // tiled grids by pass count, descending
+    const int64_t* tile_prefix;  // [n_tiled + 1] tile offsets in that order
+    int n_active;                // grids with more than p passes (a prefix of the order)
+    int p;                       // pass index
 };
 
-constexpr int kBatchTiles[][2] = {{64, 64}, {128, 32}, {128, 64}, {256, 32}};
-constexpr int kRS = 8;
+// One tile shape for every tiled grid of a batch keeps the kernel's register use at the level of a
+// single sweep body (each extra shape multiplies the inlined code).
+constexpr int kTX = 128, kTY = 64, kRS = 8;
 
 template <int R, int SH>
 __device__ __forceinline__ void run_tile(const BatchDesc& d, const float* src, float* dst, int levels, int64_t y0,
                                          int64_t x0, float* lds) {
-    switch (d.tile_id) {
-        case 0: tile_body<ST_F32, R, SH, 64, 64, kRS>(src, dst, d.rows, d.cols, d.b, levels, y0, x0, d.w, lds); break;
-        case 1: tile_body<ST_F32, R, SH, 128, 32, kRS>(src, dst, d.rows, d.cols, d.b, levels, y0, x0, d.w, lds); break;
-        case 2: tile_body<ST_F32, R, SH, 128, 64, kRS>(src, dst, d.rows, d.cols, d.b, levels, y0, x0, d.w, lds); break;
-        default: tile_body<ST_F32, R, SH, 256, 32, kRS>(src, dst, d.rows, d.cols, d.b, levels, y0, x0, d.w, lds); break;
-    }
+    tile_body<ST_F32, R, SH, kTX, kTY, kRS>(src, dst, d.rows, d.cols, d.b, levels, y0, x0, d.w, lds);
 }
 
 __device__ __forceinline__ void dispatch_tile(const BatchDesc& d, const float* src, float* dst, int levels, int64_t y0,
@@ -110,90 +95,31 @@ __device__ __forceinline__ int upper_index(const int64_t* a, int n, int64_t x) {
     return lo;
 }
 
-__global__ __launch_bounds__(NT) void batched_persistent(BatchArgs a) {
+// One pass level of all tiled grids: workgroup o -> (grid, tile) through the tile prefix sums of
+// the grids still active at this pass (a prefix of the queue order).
+__global__ __launch_bounds__(NT) void batched_pass(PassArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
-    __shared__ long long item_sh;
-    for (;;) {
-        if (threadIdx.x == 0) item_sh = (long long)atomicAdd(a.head, 1ull);
-        __syncthreads();
-        const long long item = item_sh;
-        __syncthreads();
-        if (item >= a.total) break;
-        if (item < a.n_res) {
-            const BatchDesc& d = a.desc[a.order[item]];
-            dispatch_resident(d, lds);
-            __syncthreads();
-            continue;
-        }
-        const int64_t i = item - a.n_res;
-        const int p = upper_index(a.pass_start, a.max_passes + 1, i);
-        const int64_t o = i - a.pass_start[p];
-        const int k = upper_index(a.tile_prefix, a.n_tiled + 1, o);
-        const int g = a.order[a.n_res + k];
-        const BatchDesc& d = a.desc[g];
-        const int64_t t = o - a.tile_prefix[k];
-        const int64_t ty = t / d.tiles_x, tx = t - ty * d.tiles_x;
-        const int TX = kBatchTiles[d.tile_id][0], TY = kBatchTiles[d.tile_id][1];
-        int* cnt = a.counters + d.cnt_off;
-        if (p > 0 && threadIdx.x == 0) {
-            // wait until every tile within reach of this tile's halo has finished pass p-1
-            const int H = d.r * d.tb;
-            const int ry = (H + TY - 1) / TY, rx = (H + TX - 1) / TX;
-            int64_t spins = 0;
-            for (int64_t yy = max<int64_t>(0, ty - ry); yy <= min<int64_t>(d.tiles_y - 1, ty + ry); ++yy)
-                for (int64_t xx = max<int64_t>(0, tx - rx); xx <= min<int64_t>(d.tiles_x - 1, tx + rx); ++xx) {
-                    const int* c = cnt + yy * d.tiles_x + xx;
-                    int seen;
-                    while ((seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < p) {
-                        if (++spins > a.spin_limit) {
-                            // first timeout wins the diagnostic record: item, grid, tile, pass,
-                            // waited-on tile and the counter value it showed
-                            if (atomicCAS(a.timeout_flag, 0, 1) == 0) {
-                                long long* rec = reinterpret_cast<long long*>(a.timeout_flag) + 1;
-                                rec[0] = item;
-                                rec[1] = g;
-                                rec[2] = t;
-                                rec[3] = p;
-                                rec[4] = yy * d.tiles_x + xx;
-                                rec[5] = seen;
-                            }
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                }
-            __threadfence();
-        }
-        __syncthreads();
-        const int P = d.passes;
-        const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // buffer written by pass p-1
-        float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
-        const int levels = min(d.tb, d.steps - p * d.tb);
-        dispatch_tile(d, src, dst, levels, ty * TY, tx * TX, lds);
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_store(cnt + t, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const int64_t o = blockIdx.x;
+    const int k = upper_index(a.tile_prefix, a.n_active + 1, o);
+    const BatchDesc& d = a.desc[a.order[k]];
+    const int64_t t = o - a.tile_prefix[k];
+    const int64_t ty = t / d.tiles_x, tx = t - ty * d.tiles_x;
+    const int p = a.p, P = d.passes;
+    const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
+    float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
+    const int levels = min(d.tb, d.steps - p * d.tb);
+    dispatch_tile(d, src, dst, levels, ty * kTY, tx * kTX, lds);
 }
 
-__global__ void batch_reset(unsigned long long* head, int* timeout_flag, int* counters, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        *head = 0ull;
-        *timeout_flag = 0;
-    }
-    if (i < 6) reinterpret_cast<long long*>(timeout_flag)[1 + i] = -1;
-    for (int64_t k = i; k < n; k += int64_t(gridDim.x) * blockDim.x) counters[k] = 0;
+// The LDS-resident grids: one workgroup per grid for all of its steps.
+__global__ __launch_bounds__(NT) void batched_resident(const BatchDesc* desc, const int* res) {
+    extern __shared__ float4 lds4[];
+    dispatch_resident(desc[res[blockIdx.x]], reinterpret_cast<float*>(lds4));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int batch_tile_id(int tx, int ty) {
-    for (int i = 0; i < 4; ++i)
-        if (kBatchTiles[i][0] == tx && kBatchTiles[i][1] == ty) return i;
-    return -1;
-}
 
 }  // namespace
 
@@ -205,16 +131,15 @@ struct st_batch {
     int n;
     uint32_t flags;
     std::vector<BatchDesc> desc;
-    std::vector<int64_t> pass_start, tile_prefix;
-    std::vector<int> order;
-    int n_res, n_tiled, max_passes;
-    int64_t total_items, total_tiles;
-    size_t off_cnt, off_desc, off_pstart, off_tprefix, off_order, off_fields, ws_bytes;
-    std::vector<size_t> field_off;  // per grid: workspace offset of its ping-pong field (0 = none)
-    std::vector<int> zero_steps;    // grids with steps == 0 (copied, not queued)
-    int64_t spin_limit;             // polls before a dependency wait gives up
-    size_t lds;
-    int blocks;
+    std::vector<int64_t> tile_prefix;  // over `order`
+    std::vector<int> order;            // tiled grids by pass count, descending
+    std::vector<int> res;              // LDS-resident grids
+    std::vector<int> zero_steps;       // grids with steps == 0 (copied, not computed)
+    std::vector<int> active;           // active[p]: tiled grids with more than p passes
+    int max_passes;
+    size_t off_desc, off_tprefix, off_order, off_res, off_fields, ws_bytes;
+    std::vector<size_t> field_off;     // per grid: workspace offset of its ping-pong field (0 = none)
+    size_t lds_pass, lds_res;
     // staging + graph
     void* pinned;
     size_t pinned_bytes;
@@ -225,18 +150,13 @@ struct st_batch {
     void* last_ws;
     hipGraphExec_t exec;
     void* g_ws;
-    void* g_stream;
 };
 
 namespace {
 
-// LDS budget per workgroup of the persistent kernel: two workgroups per CU when the device
-// allows 80 KiB per workgroup.
+// LDS budget per workgroup of the batched kernels: two workgroups per CU when the device allows
+// 80 KiB per workgroup.
 size_t batch_lds_budget() { return std::min<size_t>(80 * 1024, lds_limit()); }
-
-size_t tile_lds(int r, int tb, int tid) {
-    return tiled_lds_bytes(r, tb, kBatchTiles[tid][0], kBatchTiles[tid][1]);
-}
 
 }  // namespace
 
@@ -252,9 +172,8 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->flags = flags;
     B->desc.resize(n);
     B->field_off.assign(n, 0);
-    std::vector<int> res, tiled;
-    int64_t cnt_total = 0;
-    size_t lds_max = 0;
+    std::vector<int> tiled;
+    size_t lds_pass = 0, lds_res = 0;
     for (int g = 0; g < n; ++g) {
         const st_plan* p = plans[g];
         if (!p || p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3 || steps[g] < 0 ||
@@ -272,8 +191,6 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
         d.steps = int(steps[g]);
         std::memcpy(d.w, p->w, sizeof(d.w));
         if (steps[g] == 0) {  // plain copy in -> out, enqueued by stencil_run_batched
-            d.passes = 0;
-            d.tiles_x = d.tiles_y = 1;
             B->zero_steps.push_back(g);
             continue;
         }
@@ -282,60 +199,41 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
             d.resident = 1;
             d.passes = 1;
             d.tb = d.steps;
-            d.tiles_x = d.tiles_y = 1;
-            lds_max = std::max(lds_max, rl);
-            res.push_back(g);
+            lds_res = std::max(lds_res, rl);
+            B->res.push_back(g);
             continue;
         }
-        int tid = batch_tile_id(p->tile_x, p->tile_y);
-        if (tid < 0) tid = 2;
+        // the plan's temporal depth, lowered until the batch tile fits the LDS budget
         int tb = std::max(1, p->tb);
-        while (tb > 1 && tile_lds(p->radius, tb, tid) > batch_lds_budget()) --tb;
-        d.tile_id = tid;
+        while (tb > 1 && tiled_lds_bytes(p->radius, tb, kTX, kTY) > batch_lds_budget()) --tb;
         d.tb = tb;
-        d.tiles_x = (p->cols + kBatchTiles[tid][0] - 1) / kBatchTiles[tid][0];
-        d.tiles_y = (p->rows + kBatchTiles[tid][1] - 1) / kBatchTiles[tid][1];
-        d.passes = d.steps == 0 ? 0 : (d.steps + tb - 1) / tb;
-        d.cnt_off = cnt_total;
-        cnt_total += d.tiles_x * d.tiles_y;
-        lds_max = std::max(lds_max, tile_lds(p->radius, tb, tid));
+        d.tiles_x = (p->cols + kTX - 1) / kTX;
+        d.tiles_y = (p->rows + kTY - 1) / kTY;
+        d.passes = (d.steps + tb - 1) / tb;
+        lds_pass = std::max(lds_pass, tiled_lds_bytes(p->radius, tb, kTX, kTY));
         tiled.push_back(g);
     }
     std::stable_sort(tiled.begin(), tiled.end(),
                      [&](int a, int b) { return B->desc[a].passes > B->desc[b].passes; });
-    B->n_res = int(res.size());
-    B->n_tiled = int(tiled.size());
-    B->order = res;
-    B->order.insert(B->order.end(), tiled.begin(), tiled.end());
+    B->order = tiled;
     B->tile_prefix.assign(1, 0);
     for (int g : tiled) B->tile_prefix.push_back(B->tile_prefix.back() + B->desc[g].tiles_x * B->desc[g].tiles_y);
     B->max_passes = tiled.empty() ? 0 : B->desc[tiled[0]].passes;
-    B->pass_start.assign(1, 0);
     for (int p = 0; p < B->max_passes; ++p) {
-        int active = 0;  // grids still running at pass p form a prefix of the tiled order (passes descending)
-        while (active < B->n_tiled && B->desc[tiled[active]].passes > p) ++active;
-        B->pass_start.push_back(B->pass_start.back() + B->tile_prefix[active]);
+        int a = 0;
+        while (a < int(tiled.size()) && B->desc[tiled[a]].passes > p) ++a;
+        B->active.push_back(a);
     }
-    for (size_t k = 1; k < B->pass_start.size(); ++k)
-        if (B->pass_start[k] <= B->pass_start[k - 1]) {  // every pass below max_passes has at least one tile
-            delete B;
-            return fail(ST_EINVAL, "internal: empty pass in the batch queue");
-        }
-    if (B->pass_start.size() < 2) B->pass_start.push_back(0);
-    B->total_tiles = cnt_total;
-    B->total_items = B->n_res + B->pass_start[B->max_passes];
-    // workspace layout
-    size_t off = 256;  // header: queue head (8 B), timeout flag (4 B), first-timeout record (6 x 8 B at 16)
-    B->off_cnt = off;
-    off = align256(off + size_t(std::max<int64_t>(cnt_total, 1)) * sizeof(int));
+    // workspace: descriptor table, queue tables, one ping-pong field per multi-pass grid
+    size_t off = 0;
     B->off_desc = off;
     off = align256(off + size_t(n) * sizeof(BatchDesc));
-    B->off_pstart = off;
-    off = align256(off + B->pass_start.size() * sizeof(int64_t));
     B->off_tprefix = off;
     off = align256(off + B->tile_prefix.size() * sizeof(int64_t));
     B->off_order = off;
-    off = align256(off + size_t(n) * sizeof(int));
+    off = align256(off + std::max<size_t>(B->order.size(), 1) * sizeof(int));
+    B->off_res = off;
+    off = align256(off + std::max<size_t>(B->res.size(), 1) * sizeof(int));
     B->off_fields = off;
     for (int g : tiled) {
         if (B->desc[g].passes >= 2) {
@@ -343,8 +241,9 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
             off = align256(off + size_t(B->desc[g].rows * B->desc[g].cols) * sizeof(float));
         }
     }
-    B->ws_bytes = off;
-    B->lds = std::max<size_t>(lds_max, 16);
+    B->ws_bytes = std::max<size_t>(off, 256);
+    B->lds_pass = lds_pass;
+    B->lds_res = lds_res;
     B->pinned = nullptr;
     B->pinned_bytes = B->off_fields - B->off_desc;
     B->staged = nullptr;
@@ -352,12 +251,6 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->last_ws = nullptr;
     B->exec = nullptr;
     B->g_ws = nullptr;
-    B->g_stream = nullptr;
-    B->blocks = 0;
-    // ~1 s of polling by default: far above any legitimate wait, and it ends a wait that a bug
-    // would make endless.  MI355STENCIL_BATCH_SPIN overrides it (tests use a short limit).
-    B->spin_limit = int64_t(1) << 20;
-    if (const char* e = std::getenv("MI355STENCIL_BATCH_SPIN")) B->spin_limit = std::max<int64_t>(1, std::atoll(e));
     *out = B;
     return ST_OK;
 }
@@ -380,26 +273,41 @@ extern "C" int stencil_batch_destroy(st_batch* batch) {
     return ST_OK;
 }
 
-static int enqueue_batch(st_batch* B, char* ws, hipStream_t s) {
-    BatchArgs a;
-    a.head = reinterpret_cast<unsigned long long*>(ws);
-    a.timeout_flag = reinterpret_cast<int*>(ws + 8);
-    a.counters = reinterpret_cast<int*>(ws + B->off_cnt);
-    a.desc = reinterpret_cast<const BatchDesc*>(ws + B->off_desc);
-    a.pass_start = reinterpret_cast<const int64_t*>(ws + B->off_pstart);
-    a.tile_prefix = reinterpret_cast<const int64_t*>(ws + B->off_tprefix);
-    a.order = reinterpret_cast<const int*>(ws + B->off_order);
-    a.total = B->total_items;
-    a.n_res = B->n_res;
-    a.n_tiled = B->n_tiled;
-    a.max_passes = B->max_passes;
-    a.spin_limit = B->spin_limit;
-    clear_stale_error();
-    hipLaunchKernelGGL(batch_reset, dim3(64), dim3(256), 0, s, a.head, a.timeout_flag, a.counters,
-                       std::max<int64_t>(B->total_tiles, 1));
-    ST_LAUNCH_CHECK("batch_reset");
-    hipLaunchKernelGGL(batched_persistent, dim3(B->blocks), dim3(NT), B->lds, s, a);
-    ST_LAUNCH_CHECK("batched_persistent");
+// Enqueue the batch's kernels: the resident grids on `side` (joined back into `s` at the end when
+// side != s), the pass levels of the tiled grids on `s`.
+static int enqueue_batch(st_batch* B, char* ws, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+    const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + B->off_desc);
+    const bool branch = side != s;
+    if (!B->res.empty()) {
+        if (int rc = prepare_lds(reinterpret_cast<const void*>(batched_resident), B->lds_res)) return rc;
+        if (branch) {
+            ST_HIP_CHECK(hipEventRecord(fork, s));
+            ST_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
+        }
+        clear_stale_error();
+        hipLaunchKernelGGL(batched_resident, dim3(unsigned(B->res.size())), dim3(NT), B->lds_res, side, desc,
+                           reinterpret_cast<const int*>(ws + B->off_res));
+        ST_LAUNCH_CHECK("batched_resident");
+    }
+    if (B->max_passes > 0) {
+        if (int rc = prepare_lds(reinterpret_cast<const void*>(batched_pass), B->lds_pass)) return rc;
+        for (int p = 0; p < B->max_passes; ++p) {
+            PassArgs a;
+            a.desc = desc;
+            a.order = reinterpret_cast<const int*>(ws + B->off_order);
+            a.tile_prefix = reinterpret_cast<const int64_t*>(ws + B->off_tprefix);
+            a.n_active = B->active[p];
+            a.p = p;
+            const int64_t blocks = B->tile_prefix[B->active[p]];
+            clear_stale_error();
+            hipLaunchKernelGGL(batched_pass, dim3(unsigned(blocks)), dim3(NT), B->lds_pass, s, a);
+            ST_LAUNCH_CHECK("batched_pass");
+        }
+    }
+    if (branch && !B->res.empty()) {
+        ST_HIP_CHECK(hipEventRecord(join, side));
+        ST_HIP_CHECK(hipStreamWaitEvent(s, join, 0));
+    }
     return ST_OK;
 }
 
@@ -416,14 +324,6 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* ws = static_cast<char*>(workspace);
-    if (!B->blocks) {
-        if (int rc = prepare_lds(reinterpret_cast<const void*>(batched_persistent), B->lds)) return rc;
-        int dev = 0, cus = 0, occ = 0;
-        ST_HIP_CHECK(hipGetDevice(&dev));
-        ST_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        ST_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_persistent, NT, B->lds));
-        B->blocks = std::max(1, cus * std::max(occ, 1));
-    }
     // stage the descriptor tables when any pointer changed since the last run
     bool changed = !B->staged_valid || B->last_ws != workspace;
     for (int g = 0; g < B->n && !changed; ++g) changed = B->last_in[g] != ins[g] || B->last_out[g] != outs[g];
@@ -442,10 +342,10 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
             d.ws = B->field_off[g] ? reinterpret_cast<float*>(ws + B->field_off[g]) : nullptr;
             std::memcpy(h + g * sizeof(BatchDesc), &d, sizeof(d));
         }
-        std::memcpy(h + (B->off_pstart - B->off_desc), B->pass_start.data(), B->pass_start.size() * sizeof(int64_t));
-        std::memcpy(h + (B->off_tprefix - B->off_desc), B->tile_prefix.data(),
-                    B->tile_prefix.size() * sizeof(int64_t));
-        std::memcpy(h + (B->off_order - B->off_desc), B->order.data(), B->order.size() * sizeof(int));
+        std::memcpy(h + (B->off_tprefix - B->off_desc), B->tile_prefix.data(), B->tile_prefix.size() * sizeof(int64_t));
+        if (!B->order.empty())
+            std::memcpy(h + (B->off_order - B->off_desc), B->order.data(), B->order.size() * sizeof(int));
+        if (!B->res.empty()) std::memcpy(h + (B->off_res - B->off_desc), B->res.data(), B->res.size() * sizeof(int));
         ST_HIP_CHECK(hipMemcpyAsync(ws + B->off_desc, h, B->pinned_bytes, hipMemcpyHostToDevice, s));
         ST_HIP_CHECK(hipEventRecord(B->staged, s));
         B->staged_valid = true;
@@ -456,43 +356,43 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
     for (int g : B->zero_steps)
         ST_HIP_CHECK(hipMemcpyAsync(outs[g], ins[g], size_t(B->desc[g].rows * B->desc[g].cols) * sizeof(float),
                                     hipMemcpyDeviceToDevice, s));
-    if (B->total_items == 0) return ST_OK;
-    if (!(B->flags & ST_FLAG_GRAPH)) return enqueue_batch(B, ws, s);
+    if (B->res.empty() && B->max_passes == 0) return ST_OK;
+    if (!(B->flags & ST_FLAG_GRAPH)) return enqueue_batch(B, ws, s, s, nullptr, nullptr);
     if (!(B->exec && B->g_ws == workspace)) {
         if (B->exec) {
             (void)hipGraphExecDestroy(B->exec);
             B->exec = nullptr;
         }
-        hipStream_t cap;
-        ST_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        // capture: the resident grids on a side branch forked from and joined back into the main one
+        hipStream_t cap = nullptr, side = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        int rc = ST_OK;
         hipGraph_t graph = nullptr;
-        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            (void)hipStreamDestroy(cap);
-            return fail(ST_EHIP, "hipStreamBeginCapture failed");
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            rc = fail(ST_EHIP, "stream/event creation for graph capture failed");
+        } else if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(ST_EHIP, "hipStreamBeginCapture failed");
+        } else {
+            rc = enqueue_batch(B, ws, cap, side, fork, join);
+            const hipError_t e = hipStreamEndCapture(cap, &graph);
+            if (!rc && e != hipSuccess) rc = fail(ST_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
-        const int rc = enqueue_batch(B, ws, cap);
-        const hipError_t e = hipStreamEndCapture(cap, &graph);
-        (void)hipStreamDestroy(cap);
-        if (rc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
+        if (!rc) {
+            const hipError_t e2 = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+            if (e2 != hipSuccess) rc = fail(ST_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
         }
-        if (e != hipSuccess) return fail(ST_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        const hipError_t e2 = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e2 != hipSuccess) return fail(ST_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        if (graph) (void)hipGraphDestroy(graph);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
+        if (cap) (void)hipStreamDestroy(cap);
+        (void)hipGetLastError();
+        if (rc) return rc;
         B->g_ws = workspace;
     }
     ST_HIP_CHECK(hipGraphLaunch(B->exec, s));
-    return ST_OK;
-}
-
-extern "C" int stencil_batch_status(const st_batch* batch, const void* workspace, int* timed_out, void* stream) {
-    if (!batch || !workspace || !timed_out) return fail(ST_EINVAL, "NULL argument");
-    int flag = 0;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    ST_HIP_CHECK(hipMemcpyAsync(&flag, static_cast<const char*>(workspace) + 8, sizeof(int), hipMemcpyDeviceToHost, s));
-    ST_HIP_CHECK(hipStreamSynchronize(s));
-    *timed_out = flag;
     return ST_OK;
 }

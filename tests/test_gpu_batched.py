@@ -11,9 +11,6 @@ import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-# a short dependency-wait limit: a scheduling bug then ends the kernel in milliseconds, and the
-# workspace header says which wait gave up
-os.environ.setdefault("MI355STENCIL_BATCH_SPIN", "20000")
 
 
 def say(*a):
@@ -47,10 +44,6 @@ def _run_batch(g, problems, flags, tbs=None, tiles=None, reps=2):
                     o.fill_(float("nan"))
                 lib.stencil_run_batched(batch, ins, outs, ws)
                 torch.cuda.synchronize()
-                if lib.stencil_batch_status(batch, ws):
-                    rec = ws[16:64].cpu().numpy().view(np.int64)
-                    raise AssertionError(f"dependency wait timed out: item {rec[0]} grid {rec[1]} tile {rec[2]} "
-                                         f"pass {rec[3]} waited on tile {rec[4]} whose counter was {rec[5]}")
                 results.append([g.to_host(o) for o in outs])
                 _ = (ins[0] * 3).sum().item()  # eager work between replays
             return results

@@ -214,14 +214,14 @@ def test_infer_checked_judge_and_fallback(g):
 
 
 def test_training_gains_over_untrained_and_identity(g):
-    """A short GPU training run (100 Adam steps on 128x128 crops of 256x256 trajectories) must beat both
+    """A short GPU training run (500 Adam steps on 128x128 crops of 256x256 trajectories) must beat both
     the untrained network and the identity predictor u_hat = u0 on held-out trajectories, judged
     against 16 plain stencil steps."""
     from paper_2605_07954_amd.surrogate import Trainer
     tr = Trainer(grid=256, crop=128, batch=8, K=16, seed=3)
     try:
         p0 = tr.params.clone()
-        hist = tr.train(800, lr=2e-3, log_every=20)
+        hist = tr.train(4000, lr=2e-3, log_every=100)
         e_tr, e_id = tr.evaluate(tr.params, 16, seed=99)
         e_un, _ = tr.evaluate(p0, 16, seed=99)
         say(f"losses {hist}")
