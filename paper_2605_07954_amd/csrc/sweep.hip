@@ -133,7 +133,8 @@ __global__ __launch_bounds__(NT) void sweep_stream(SweepArgs a) {
     const int tb = a.tb;
     const SGeo g = sgeometry(R, tb, TX, TY);
     const int H = g.H, A = g.A, BW = g.bw, BH = g.bh;
-    float* stage[2] = {lds, lds + BH * BW};
+    // Buffers are picked by offset arithmetic on the LDS base (an array of pointers would make the
+    // compiler lose the LDS address space and fall back to flat loads).
     float* mid = lds + 2 * BH * BW;
     float* wsh = mid + (tb > 1 ? BH * BW : 0);
     const int64_t rows = a.rows, cols = a.cols;
@@ -146,13 +147,13 @@ __global__ __launch_bounds__(NT) void sweep_stream(SweepArgs a) {
     int64_t t = blockIdx.x;
     if (t < ntiles) {
         const int64_t m = xcd_tile(t, ntiles);
-        stream_stage<false>(src, rows, cols, b, g, (m / a.tiles_x) * TY, (m % a.tiles_x) * TX, stage[0]);
+        stream_stage<false>(src, rows, cols, b, g, (m / a.tiles_x) * TY, (m % a.tiles_x) * TX, lds);
     }
     float wreg[K * K];
     for (int it = 0; t < ntiles; ++it, t += gridDim.x) {
         const int64_t m = xcd_tile(t, ntiles);
         const int64_t y0 = (m / a.tiles_x) * TY, x0 = (m % a.tiles_x) * TX;
-        float* cur = stage[it & 1];
+        float* cur = lds + (it & 1) * (BH * BW);
         // Every wave waits for its own DMA of the current tile; the barrier then orders all of
         // them before the out-of-grid repair (same chunks) and the repair before any read.
         __builtin_amdgcn_s_waitcnt(0);
@@ -166,7 +167,8 @@ __global__ __launch_bounds__(NT) void sweep_stream(SweepArgs a) {
         const int64_t tn = t + gridDim.x;
         if (tn < ntiles) {
             const int64_t mn = xcd_tile(tn, ntiles);
-            stream_stage<false>(src, rows, cols, b, g, (mn / a.tiles_x) * TY, (mn % a.tiles_x) * TX, stage[(it + 1) & 1]);
+            stream_stage<false>(src, rows, cols, b, g, (mn / a.tiles_x) * TY, (mn % a.tiles_x) * TX,
+                                lds + ((it + 1) & 1) * (BH * BW));
         }
         const float* sb = cur;
         for (int l = 1; l <= tb; ++l) {

@@ -238,14 +238,14 @@ __device__ __forceinline__ void resident_body(const float* src, float* dst, int 
     constexpr int K = 2 * R + 1;
     constexpr int OFF = 8;
     const int BW = resident_bw(cols), BH = rows + 2 * R;
-    float* bufs[2] = {lds, lds + BH * BW};
+    // buffers by offset arithmetic on the LDS base (keeps the compiler on LDS instructions)
     float* wsh = lds + 2 * BH * BW;
     if (threadIdx.x < K * K) wsh[threadIdx.x] = w[threadIdx.x];
     for (int k = threadIdx.x; k < 2 * BH * BW; k += NT) lds[k] = b;
     __syncthreads();
     for (int k = threadIdx.x; k < rows * cols; k += NT) {
         const int i = k / cols, j = k - i * cols;
-        bufs[0][(i + R) * BW + OFF + j] = src[k];
+        lds[(i + R) * BW + OFF + j] = src[k];
     }
     __syncthreads();
     float wreg[K * K];
@@ -254,8 +254,8 @@ __device__ __forceinline__ void resident_body(const float* src, float* dst, int 
     const int ngx = (cols + 3) >> 2;
     const int nseg = (rows + RS - 1) / RS;
     for (int s = 0; s < steps; ++s) {
-        const float* sb = bufs[s & 1];
-        float* db = bufs[(s + 1) & 1];
+        const float* sb = lds + (s & 1) * (BH * BW);
+        float* db = lds + ((s + 1) & 1) * (BH * BW);
         for (int it = threadIdx.x; it < ngx * nseg; it += NT) {
             const int seg = it / ngx;
             const int gx0 = 4 * (it - seg * ngx);
@@ -293,7 +293,7 @@ __device__ __forceinline__ void resident_body(const float* src, float* dst, int 
         }
         __syncthreads();
     }
-    const float* fin = bufs[steps & 1];
+    const float* fin = lds + (steps & 1) * (BH * BW);
     for (int k = threadIdx.x; k < rows * cols; k += NT) {
         const int i = k / cols, j = k - i * cols;
         dst[k] = fin[(i + R) * BW + OFF + j];

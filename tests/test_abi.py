@@ -72,3 +72,44 @@ def test_host_validation_codes():
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.lib().stencil_strerror(code)
+
+
+def test_batch_create_validation_on_host():
+    """Batch creation is host-only: unsupported plans are refused, sizes are reported."""
+    from workloads import heat5_weights, random_footprint_weights, BOX, STAR
+    rng = np.random.default_rng(0)
+    ok = [lib.stencil_plan(300, 260, 1, heat5_weights(), 0.0, "f32", 0),
+          lib.stencil_plan(40, 50, 3, random_footprint_weights(rng, STAR, 3), 0.0, "f32", 0),
+          lib.stencil_plan(100, 900, 2, random_footprint_weights(rng, BOX, 2), 0.5, "f32", 0)]
+    bad = [lib.stencil_plan(64, 64, 4, np.ones((9, 9), np.float32) / 81, 0.0, "f32", 0),
+           lib.stencil_plan(64, 64, 1, heat5_weights(), 0.0, "f16", 0),
+           lib.stencil_plan_varcoef(64, 64, 0.0, 0)]
+    try:
+        b = lib.stencil_batch_create(ok, [10, 7, 0], lib.ST_FLAG_GRAPH)
+        try:
+            assert lib.stencil_batch_workspace_bytes(b) >= 300 * 260 * 4  # the multi-pass grid's ping-pong field
+        finally:
+            lib.stencil_batch_destroy(b)
+        for p in bad:
+            with pytest.raises(lib.StencilError) as ei:
+                lib.stencil_batch_create(ok + [p], [1, 1, 1, 1], 0)
+            assert ei.value.code == -3
+        with pytest.raises(lib.StencilError):
+            lib.stencil_batch_create(ok, [1, -1, 1], 0)
+        with pytest.raises(lib.StencilError):
+            lib.stencil_batch_create(ok, [1, 1, 1], 0x80)
+    finally:
+        for p in ok + bad:
+            lib.stencil_destroy(p)
+
+
+def test_binding_constants_match_header():
+    """Every status, storage, flag and variant constant of the binding equals the header's #define."""
+    text = open(lib.HEADER).read()
+    defs = {m.group(1): int(m.group(2), 0)
+            for m in re.finditer(r"^#define\s+((?:ST|SG)_[A-Z0-9_]+)\s+\(?(-?(?:0x)?[0-9A-Fa-f]+)\)?", text, re.M)}
+    names = [n for n in dir(lib) if re.fullmatch(r"(ST|SG)_[A-Z0-9_]+", n)]
+    assert len(names) >= 15
+    for n in names:
+        assert n in defs, n
+        assert getattr(lib, n) == defs[n], (n, getattr(lib, n), defs[n])

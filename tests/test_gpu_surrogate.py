@@ -214,7 +214,7 @@ def test_infer_checked_judge_and_fallback(g):
 
 
 def test_training_gains_over_untrained_and_identity(g):
-    """A short GPU training run (500 Adam steps on 128x128 crops of 256x256 trajectories) must beat both
+    """A short GPU training run (4000 Adam steps on 128x128 crops of 256x256 trajectories) must beat both
     the untrained network and the identity predictor u_hat = u0 on held-out trajectories, judged
     against 16 plain stencil steps."""
     from paper_2605_07954_amd.surrogate import Trainer
