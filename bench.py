@@ -79,7 +79,7 @@ def time_runs(fn, reps: int, stream) -> float:
 def cpu_baseline(p) -> dict:
     import oracle
     rows = cols = 1024
-    steps = int(os.environ.get("BENCH_CPU_STEPS", "400"))
+    steps = int(os.environ.get("BENCH_CPU_STEPS", "3000"))
     u0 = np.ascontiguousarray(p.u0[:rows, :cols])
     t0 = time.perf_counter()
     oracle.stencil_f32(u0, p.weights, 0.0, steps)
@@ -133,6 +133,29 @@ def main_line(args, torch, lib, stream):
     return p, value, ms, roof, (tb, tx, ty, variant), tune_s
 
 
+def tune_batch_plans(lib, probs, plans, ins, outs, wss, stream=None) -> dict:
+    """Blocking of a batch's plans: one ``stencil_autotune`` per stencil class (shape, radius), run on
+    that class's first grid of at least 512^2 cells, then applied to every grid of the class where it
+    fits (a grid too small for the depth keeps its default)."""
+    tuned = {}
+    for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):
+        key = (q.shape, q.radius)
+        if key not in tuned and q.rows * q.cols >= 512 * 512 and q.cols % 4 == 0:
+            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
+    for q, pl in zip(probs, plans):
+        if (q.shape, q.radius) not in tuned:
+            continue
+        tb, tx, ty, var = tuned[(q.shape, q.radius)]
+        try:
+            lib.stencil_set_blocking(pl, 1, tx, ty)
+            if var == lib.ST_VARIANT_STREAM and q.cols % 4 == 0:
+                lib.stencil_set_variant(pl, var)
+            lib.stencil_set_blocking(pl, tb)
+        except lib.StencilError:
+            pass
+    return tuned
+
+
 def extras(torch, lib, stream) -> dict:
     ex = {}
     # heat 512^2, 100 steps (launch-bound, L2-resident)
@@ -173,22 +196,7 @@ def extras(torch, lib, stream) -> dict:
     outs = [torch.empty_like(i) for i in ins]
     wss = [torch.empty_like(i) for i in ins]
     plans = [lib.stencil_plan(q.rows, q.cols, q.radius, q.weights, 0.0, "f32", 0) for q in probs]
-    tuned = {}
-    for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):  # one autotune per stencil class
-        key = (q.shape, q.radius)
-        if key not in tuned and q.rows * q.cols >= 512 * 512 and q.cols % 4 == 0:
-            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
-    for q, pl in zip(probs, plans):
-        if (q.shape, q.radius) not in tuned:
-            continue
-        tb, tx, ty, var = tuned[(q.shape, q.radius)]
-        try:
-            lib.stencil_set_blocking(pl, 1, tx, ty)
-            if var == lib.ST_VARIANT_STREAM and q.cols % 4 == 0:
-                lib.stencil_set_variant(pl, var)
-            lib.stencil_set_blocking(pl, tb)
-        except lib.StencilError:
-            pass
+    tune_batch_plans(lib, probs, plans, ins, outs, wss, stream)
     per_grid = lambda: [lib.stencil_run(pl, i, o, q.steps, w, stream)  # noqa: E731
                         for q, pl, i, o, w in zip(probs, plans, ins, outs, wss)]
     per_grid()
@@ -224,10 +232,8 @@ def extras(torch, lib, stream) -> dict:
         tt = time_runs(run, 20, stream) / 20
         best = tt if best is None else min(best, tt)
     m = lib.surrogate_create()
-    from oracle import cnn  # parameters only: the network's random initialisation
-    params = np.concatenate([np.concatenate([wt.transpose(2, 3, 1, 0).reshape(-1), b])
-                             for (wt, b) in cnn.init_params(0)]).astype(np.float32)
-    pd = torch.from_numpy(params).to("cuda")
+    from paper_2605_07954_amd.surrogate import init_params
+    pd = torch.from_numpy(init_params(0)).to("cuda")  # timing only: the weights' values do not matter
     sws = torch.empty(lib.surrogate_workspace_bytes(m, 1, 1024, 1024), dtype=torch.uint8, device="cuda")
     uh = torch.empty((1, 1024, 1024), device="cuda")
     run = lambda: lib.surrogate_forward(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731

@@ -337,20 +337,29 @@ int oracle_stencil_patch_f64(int64_t rows, int64_t cols, int r, const double *W,
             a[ei * ep + ej] = v;
             c[ei * ep + ej] = (gi < 0 || gi >= rows || gj < 0 || gj >= cols) ? b : NAN;
         }
+    /* Step s is computed on the cone region R_s (the patch grown by r*(steps-1-s), clipped to the
+     * grid).  The destination buffer was last written two steps earlier over R_{s-2}, which is R_s
+     * grown by 2r: that band is first poisoned with NaN, so a read that leaves the cone shows up.
+     * Per cell the order is the centre product, then one add per tap in row-major order. */
     for (int64_t s = 0; s < steps; s++) {
-        int64_t m = (int64_t)r * (steps - 1 - s);
+        int64_t m = (int64_t)r * (steps - 1 - s), q = m + 2 * (int64_t)r;
         int64_t ry0 = py0 - m < 0 ? 0 : py0 - m, rx0 = px0 - m < 0 ? 0 : px0 - m;
         int64_t ry1 = py0 + ph + m > rows ? rows : py0 + ph + m;
         int64_t rx1 = px0 + pw + m > cols ? cols : px0 + pw + m;
+        int64_t zy0 = py0 - q < wy0 ? wy0 : py0 - q, zx0 = px0 - q < wx0 ? wx0 : px0 - q;
+        int64_t zy1 = py0 + ph + q > wy1 ? wy1 : py0 + ph + q;
+        int64_t zx1 = px0 + pw + q > wx1 ? wx1 : px0 + pw + q;
 #pragma omp parallel for schedule(static)
-        for (int64_t gi = wy0; gi < wy1; gi++) {
+        for (int64_t gi = zy0; gi < zy1; gi++) {
             double *drow = c + (gi - wy0 + r) * ep + r - wx0;
             const double *srow = a + (gi - wy0 + r) * ep + r - wx0;
-            for (int64_t gj = wx0; gj < wx1; gj++) {
-                if (gi < ry0 || gi >= ry1 || gj < rx0 || gj >= rx1) { drow[gj] = NAN; continue; }
-                double acc = t.c64 * srow[gj];
-                for (int k = 0; k < t.n; k++) acc += t.w64[k] * srow[(int64_t)t.dy[k] * ep + gj + t.dx[k]];
-                drow[gj] = acc;
+            for (int64_t gj = zx0; gj < zx1; gj++) drow[gj] = NAN;
+            if (gi < ry0 || gi >= ry1) continue;
+            for (int64_t gj = rx0; gj < rx1; gj++) drow[gj] = t.c64 * srow[gj];
+            for (int k = 0; k < t.n; k++) {
+                const double w = t.w64[k];
+                const double *tap = srow + (int64_t)t.dy[k] * ep + t.dx[k];
+                for (int64_t gj = rx0; gj < rx1; gj++) drow[gj] += w * tap[gj];
             }
         }
         double *tmp = a; a = c; c = tmp;

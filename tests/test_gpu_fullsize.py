@@ -1,0 +1,247 @@
+"""GPU parity at the full workload sizes, in the launch configuration the benchmark times (blocking
+picked by ``stencil_autotune``), checked on outputs the oracle can compute one by one and on
+properties that hold at any size.
+
+* Box-2D49P, 16384 x 16384, 1000 steps: 8x8 patches at two opposite corners against the FP64
+  light-cone patch oracle (rel-L2 <= 1e-5); a plane wave in the light-cone interior against its
+  closed form: one Jacobi step (Sec. II-C) multiplies the mode exp(i k.x) by
+  lambda(k) = sum_d W_d exp(i k.d), so every cell at least r*T from every edge holds
+  |lambda|^T cos(k.x + phi + T arg lambda) after T steps.
+* Star-2D9P, 8192 x 8192, 500 steps, FP32 / BF16 / FP16 storage: the 8x8 corner patches bit for
+  bit against the FP32-canonical / 16-bit-emulating oracle run on the (8 + r*T)^2 corner crop (a
+  cell at least r*T from the crop's cut edges cannot see them); the sine-mode sum in the
+  light-cone interior against its closed form (each mode scaled by lambda^T).  The FP32 gate is
+  1e-5; the 16-bit error against the exact interior is printed (their gate is the bitwise
+  emulation).
+* The 256-grid batch, 200 steps, with the benchmark's per-class tuning and hipGraph: every 8th
+  grid bit for bit against the FP32-canonical oracle.
+* Surrogate forward on 1024 x 1024: 16x16 patches against the CNN oracle run on each patch's
+  receptive window (6 cells: six 3x3 layers); the judged entry point's error against one
+  computed from the oracle's 16 plain steps.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch  # noqa: F401
+    import gpuhelp
+    return gpuhelp
+
+
+class Tuned:
+    """A plan autotuned on its input the way the benchmark does it, then run for ``steps`` steps."""
+
+    def __init__(self, lib, torch, x, rows, cols, r, W, b, storage):
+        self.lib, self.torch = lib, torch
+        self.plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
+        self.out = torch.empty_like(x)
+        self.ws = torch.empty_like(x)
+        self.cfg = lib.stencil_autotune(self.plan, x, self.out, self.ws, 24) + (lib.stencil_get_variant(self.plan),)
+
+    def run(self, x, steps):
+        self.lib.stencil_run(self.plan, x, self.out, steps, self.ws)
+        self.torch.cuda.synchronize()
+        return self.out
+
+    def close(self):
+        self.lib.stencil_destroy(self.plan)
+
+
+def test_box49_16384_1000(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    p = wl.box49()
+    rows, cols, T, r = p.rows, p.cols, p.steps, p.radius
+    x = g.to_dev(p.u0)
+    tp = Tuned(lib, torch, x, rows, cols, r, p.weights, 0.0, "f32")
+    try:
+        say(f"box49 {rows}x{cols} T={T}: autotuned (tb, tx, ty, variant) = {tp.cfg}")
+        out = tp.run(x, T)
+        corners = [(0, 0), (rows - 8, cols - 8)]
+        got = [g.to_host(out[y:y + 8, xx:xx + 8]) for (y, xx) in corners]
+        # plane wave: u0 = cos(kx j + ky i + phi) in FP32
+        kx, ky, phi = 0.02, 0.013, 0.3
+        ii = np.arange(rows, dtype=np.float64)[:, None]
+        jj = np.arange(cols, dtype=np.float64)[None, :]
+        x.copy_(torch.from_numpy(np.cos(kx * jj + ky * ii + phi).astype(np.float32)))
+        out = tp.run(x, T)
+        m = r * T
+        sample = np.linspace(m, rows - m - 1, 24).astype(np.int64)
+        wave = g.to_host(out[torch.from_numpy(sample).to(g.DEV), m:cols - m])
+    finally:
+        tp.close()
+    del x
+    torch.cuda.empty_cache()
+    for (y, xx), gp in zip(corners, got):
+        say(f"  corner patch ({y}, {xx}): FP64 light-cone oracle ...")
+        ref = oracle.stencil_patch_f64(p.u0, p.weights, 0.0, T, y, xx, 8, 8)
+        e = oracle.rel_l2(gp, ref)
+        say(f"  corner patch ({y}, {xx}): rel-L2 vs FP64 = {e:.3e}")
+        assert e <= TOL
+    W = p.weights.astype(np.float64)
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    lam = np.sum(W * np.exp(1j * (kx * d[None, :] + ky * d[:, None])))
+    ref = np.abs(lam) ** T * np.cos(kx * jj[:, m:cols - m] + ky * sample[:, None].astype(np.float64) + phi
+                                    + T * np.angle(lam))
+    e = oracle.rel_l2(wave, ref)
+    say(f"  plane wave |lambda|^T = {abs(lam) ** T:.4f}, interior rows {sample[0]}..{sample[-1]}: rel-L2 vs closed "
+        f"form = {e:.3e}")
+    assert e <= TOL
+
+
+def _sine_interior(modes, W, rows, cols, T, ii, j0, j1):
+    """Closed form of the sine-mode sum after T steps of a mirror-symmetric stencil, on rows ii and
+    columns [j0, j1): mode (p, q) is scaled by lambda = sum_d W_d cos(theta_p dy) cos(theta_q dx)."""
+    r = (W.shape[0] - 1) // 2
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    jj = np.arange(j0, j1, dtype=np.float64)
+    out = np.zeros((len(ii), j1 - j0))
+    for (pm, qm, a) in modes:
+        tp, tq = pm * math.pi / (rows + 1), qm * math.pi / (cols + 1)
+        lam = float(np.sum(W * np.cos(tp * d)[:, None] * np.cos(tq * d)[None, :]))
+        out += a * lam ** T * np.outer(np.sin(tp * (ii + 1.0)), np.sin(tq * (jj + 1.0)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def star9():
+    return wl.star9_precision()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_star9_8192_500(g, star9, storage):
+    import torch
+    import paper_2605_07954_amd as lib
+    p = star9
+    rows, cols, T, r = p.rows, p.cols, p.steps, p.radius
+    W = p.weights.astype(np.float64)
+    assert np.array_equal(W, W[::-1, :]) and np.array_equal(W, W[:, ::-1])
+    u_in = p.u0 if storage == "f32" else oracle.to_bits(p.u0, storage)
+    x = g.to_dev(u_in)
+    tp = Tuned(lib, torch, x, rows, cols, r, p.weights, 0.0, storage)
+    m = r * T
+    sample = np.linspace(m, rows - m - 1, 24).astype(np.int64)
+    try:
+        say(f"star9 {rows}x{cols} T={T} {storage}: autotuned (tb, tx, ty, variant) = {tp.cfg}")
+        out = tp.run(x, T)
+        got_tl = g.to_host(out[:8, :8])
+        got_br = g.to_host(out[rows - 8:, cols - 8:])
+        inner = g.to_host(out[torch.from_numpy(sample).to(g.DEV), m:cols - m])
+    finally:
+        tp.close()
+    del x
+    torch.cuda.empty_cache()
+    c = 8 + m
+
+    def ref_run(crop):
+        if storage == "f32":
+            return oracle.stencil_f32(crop, p.weights, 0.0, T)
+        return oracle.stencil_lowp(crop, p.weights, 0.0, T, storage)
+
+    say(f"  corner crops {c}x{c}: oracle ...")
+    np.testing.assert_array_equal(got_tl, ref_run(u_in[:c, :c])[:8, :8])
+    np.testing.assert_array_equal(got_br, ref_run(u_in[rows - c:, cols - c:])[c - 8:, c - 8:])
+    modes = wl.fourier_sine_modes(64, 32.0, 4)
+    ref = _sine_interior(modes, W, rows, cols, T, sample.astype(np.float64), m, cols - m)
+    vals = inner if storage == "f32" else oracle.from_bits(inner, storage)
+    e = oracle.rel_l2(vals, ref)
+    say(f"  {storage}: corners bitwise vs the {'FP32-canonical' if storage == 'f32' else 'emulating'} oracle; "
+        f"interior rel-L2 vs the exact sine-mode solution = {e:.3e}")
+    assert np.isfinite(vals).all()
+    if storage == "f32":
+        assert e <= TOL
+
+
+def test_batched_256_200(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    from bench import tune_batch_plans
+    probs = wl.batch_problems()
+    ins = [g.to_dev(q.u0) for q in probs]
+    outs = [torch.empty_like(i) for i in ins]
+    wss = [torch.empty_like(i) for i in ins]
+    plans = [lib.stencil_plan(q.rows, q.cols, q.radius, q.weights, 0.0, "f32", 0) for q in probs]
+    try:
+        tuned = tune_batch_plans(lib, probs, plans, ins, outs, wss)
+        say(f"batch of {len(probs)} grids, per-class blocking {tuned}")
+        del wss
+        batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
+        try:
+            bws = torch.empty(max(lib.stencil_batch_workspace_bytes(batch), 1), dtype=torch.uint8, device=g.DEV)
+            for o in outs:
+                o.fill_(float("nan"))
+            lib.stencil_run_batched(batch, ins, outs, bws)
+            torch.cuda.synchronize()
+            picked = list(range(0, len(probs), 8))
+            got = {k: g.to_host(outs[k]) for k in picked}
+        finally:
+            lib.stencil_batch_destroy(batch)
+    finally:
+        for pl in plans:
+            lib.stencil_destroy(pl)
+    for k in picked:
+        q = probs[k]
+        ref = oracle.stencil_f32(q.u0, q.weights, 0.0, q.steps)
+        np.testing.assert_array_equal(got[k], ref, err_msg=q.name)
+    q = max((probs[k] for k in picked), key=lambda q: q.rows * q.cols)
+    e = oracle.rel_l2(got[probs.index(q)], oracle.stencil_f64(q.u0, q.weights, 0.0, q.steps))
+    say(f"  {len(picked)} grids bitwise; largest checked {q.name} {q.rows}x{q.cols}: rel-L2 vs FP64 {e:.3e}")
+    assert e <= TOL
+
+
+def test_surrogate_1024(g):
+    import torch
+    import paper_2605_07954_amd as lib
+    from oracle import cnn
+    from test_gpu_surrogate import _params, flat_params, q_bf16, unflat
+    n = 1024
+    u0, kap = wl.varcoef_problem(n, n, seed=5)
+    pv = flat_params(_params(13))
+    m = lib.surrogate_create()
+    judge = lib.stencil_plan_varcoef(n, n, 0.0)
+    try:
+        ws = torch.empty(lib.surrogate_workspace_bytes(m, 1, n, n), dtype=torch.uint8, device=g.DEV)
+        out = torch.empty((1, n, n), dtype=torch.float32, device=g.DEV)
+        lib.surrogate_forward(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, 1, n, n, ws)
+        got = g.to_host(out[0])
+        cws = torch.empty(lib.surrogate_checked_ws_bytes(m, n, n), dtype=torch.uint8, device=g.DEV)
+        chk = torch.empty((n, n), dtype=torch.float32, device=g.DEV)
+        fb, err = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), chk, n, n, judge, 16,
+                                              1e9, cws)
+        np.testing.assert_array_equal(g.to_host(chk), got)
+    finally:
+        lib.stencil_destroy(judge)
+        lib.surrogate_destroy(m)
+    p32 = unflat(pv)
+    RF = 6
+    for (y, x) in [(0, 0), (0, 500), (500, 500), (n - 16, n - 16), (777, 3)]:
+        wy0, wx0 = max(0, y - RF), max(0, x - RF)
+        wy1, wx1 = min(n, y + 16 + RF), min(n, x + 16 + RF)
+        ref, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1], q=q_bf16)
+        ref = ref[y - wy0:y - wy0 + 16, x - wx0:x - wx0 + 16]
+        base = u0[y:y + 16, x:x + 16]
+        e = oracle.rel_l2(got[y:y + 16, x:x + 16] - base, ref - base)
+        say(f"surrogate 1024^2 patch ({y}, {x}): rel-L2 of f vs the BF16-emulating oracle {e:.2e}")
+        assert e < 1e-3
+    plain = oracle.varcoef_f32(u0, kap, 0.0, 16)
+    e_ref = oracle.rel_l2(got, plain)
+    say(f"judged error: library {err:.6e}, from the oracle's 16 plain steps {e_ref:.6e} (fallback={fb})")
+    assert not fb
+    assert abs(err - e_ref) <= 1e-9 + 1e-9 * e_ref

@@ -111,26 +111,30 @@ def box49(rows: int = 16384, cols: int = 16384, steps: int = 1000, seed: int = 1
     return Problem("box49", rows, cols, 3, BOX, w, 0.0, steps, u0)
 
 
-def fourier_sine_field(rows: int, cols: int, n_modes: int, kmax: float, seed: int,
-                       dtype=np.float32) -> np.ndarray:
-    """Sum of ``n_modes`` Dirichlet sine modes sin(p pi (i+1)/(N+1)) sin(q pi (j+1)/(M+1)).
-
-    Distinct integer (p, q) in [1, kmax]^2 with sqrt(p^2+q^2) <= kmax, amplitude
-    a ~ N(0, 1/k^2).  Evaluated in FP64 as an outer product per mode.
-    """
+def fourier_sine_modes(n_modes: int, kmax: float, seed: int) -> list[tuple[int, int, float]]:
+    """(p, q, a) of ``n_modes`` distinct integer wave numbers in [1, kmax]^2 with sqrt(p^2+q^2) <= kmax,
+    amplitude a ~ N(0, 1/k^2), all drawn from ``default_rng(seed)``."""
     rng = np.random.default_rng(seed)
     kmax_i = int(math.floor(kmax))
     cand = [(p, q) for p in range(1, kmax_i + 1) for q in range(1, kmax_i + 1)
             if math.hypot(p, q) <= kmax]
     n_modes = min(n_modes, len(cand))
     idx = rng.choice(len(cand), size=n_modes, replace=False)
+    modes = []
+    for m in idx:
+        p, q = cand[m]
+        modes.append((p, q, float(rng.normal(0.0, 1.0 / math.hypot(p, q)))))
+    return modes
+
+
+def fourier_sine_field(rows: int, cols: int, n_modes: int, kmax: float, seed: int,
+                       dtype=np.float32) -> np.ndarray:
+    """Sum of Dirichlet sine modes a sin(p pi (i+1)/(N+1)) sin(q pi (j+1)/(M+1)) over
+    ``fourier_sine_modes``; evaluated in FP64 as an outer product per mode."""
     i = np.arange(1, rows + 1, dtype=np.float64)
     j = np.arange(1, cols + 1, dtype=np.float64)
     out = np.zeros((rows, cols), dtype=np.float64)
-    for m in idx:
-        p, q = cand[m]
-        k = math.hypot(p, q)
-        a = rng.normal(0.0, 1.0 / k)
+    for p, q, a in fourier_sine_modes(n_modes, kmax, seed):
         out += a * np.outer(np.sin(p * math.pi * i / (rows + 1)), np.sin(q * math.pi * j / (cols + 1)))
     return out.astype(dtype)
 
