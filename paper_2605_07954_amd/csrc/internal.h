@@ -35,7 +35,7 @@ int fail(int code, const std::string& msg);
 
 enum Shape { SHAPE_STAR = 0, SHAPE_BOX = 1 };
 enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1 };
-enum Variant { VARIANT_TILED = ST_VARIANT_TILED, VARIANT_STREAM = ST_VARIANT_STREAM };
+enum Variant { VARIANT_TILED = ST_VARIANT_TILED, VARIANT_STREAM = ST_VARIANT_STREAM, VARIANT_MARCH = ST_VARIANT_MARCH };
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
 
@@ -97,6 +97,10 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
+// Row-marching pass (march.hip): FP32 constant-weight plans with cols % 4 == 0, 1 or 2 levels.
+constexpr int MARCH_MAX_TB = 2;
+bool march_usable(const st_plan* p);
+int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s);
 // Drop a stale runtime error left by earlier API calls so that the check after our next
 // launch reports that launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }

@@ -1,0 +1,250 @@
+// Row-marching Jacobi pass for FP32 grids (paper Sec. II-C update with the fixed halo of Sec. IV-A;
+// per cell the FP32 order of Sec. IV-E: the centre product, then one FMA per footprint tap in
+// row-major order, the same order as the tiled kernels, so results agree bit for bit).
+//
+// One wavefront owns a band of columns, four per lane, and walks down a segment of rows.  Each input
+// row is read from HBM once per band with one 16-byte load per lane; the r columns a lane needs on
+// either side come from the neighbouring lanes through DPP wave shifts, so the pass uses neither LDS
+// nor barriers.  The rows a lane needs sit in a register ring whose slots become fixed registers
+// because the row loop is unrolled over the ring length.  With two levels per pass a second ring
+// holds the intermediate level.  Lanes at a band's edges only supply halo columns: with four columns
+// per lane and r <= 4 each level consumes one lane per side, so a band writes 4 (64 - 2 tb) columns.
+//
+// Segments are sized on the host so that the number of (band, segment) tasks is close to the number
+// of wavefronts the device holds at once: every wavefront runs one task of equal length.
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace st {
+namespace {
+
+constexpr int MWAVES = 4;  // wavefronts per workgroup, each with its own task
+
+struct MarchArgs {
+    const float* src;
+    float* dst;
+    int64_t rows, cols;
+    int64_t tasks;  // bands * segments
+    int64_t seg;    // output rows per task
+    int bands;
+    float b;
+    float w[MAXK];
+};
+
+// DPP wave shifts over the whole wavefront: lane l receives lane l-1 (resp. l+1); lane 0 (resp. 63)
+// receives 0, which only feeds outputs that are never stored.
+__device__ __forceinline__ float from_prev_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// One ring row as seen by a lane: v[R + c] is column c of the lane's four, c in [-R, 3 + R].
+template <int R>
+struct Row {
+    float v[4 + 2 * R];
+};
+
+template <int R>
+__device__ __forceinline__ void fill_sides(Row<R>& x) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        x.v[i] = from_prev_lane(x.v[4 + i]);          // column -R+i: the previous lane's column 4-R+i
+        x.v[R + 4 + i] = from_next_lane(x.v[R + i]);  // column 4+i: the next lane's column i
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void set_own(Row<R>& x, float4 q) {
+    x.v[R] = q.x;
+    x.v[R + 1] = q.y;
+    x.v[R + 2] = q.z;
+    x.v[R + 3] = q.w;
+}
+
+__device__ __forceinline__ bool tap_on(int shape, int dy, int dx) { return shape == SHAPE_BOX || dy == 0 || dx == 0; }
+
+// The four outputs of a lane for one row; `ring[(base + R + dy) % N]` holds input row dy.
+template <int R, int SHAPE, int N>
+__device__ __forceinline__ float4 apply(const Row<R>* ring, int base, const float* w) {
+    constexpr int K = 2 * R + 1;
+    float o[4];
+    const Row<R>& mid = ring[(base + R) % N];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[c] = w[R * K + R] * mid.v[R + c];
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        const Row<R>& x = ring[(base + R + dy) % N];
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            if ((dy == 0 && dx == 0) || !tap_on(SHAPE, dy, dx)) continue;
+            const float wt = w[(dy + R) * K + dx + R];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = __builtin_fmaf(wt, x.v[R + c + dx], o[c]);
+        }
+    }
+    return make_float4(o[0], o[1], o[2], o[3]);
+}
+
+// Loads one input row into `x` (own columns).  EDGE tasks may touch rows or columns outside the
+// grid: those cells hold b.  Interior tasks only clamp the row of a prefetch past the grid's end.
+template <int R, bool EDGE>
+__device__ __forceinline__ void load_row(Row<R>& x, const float* src, int64_t gy, int64_t rows, int64_t cols,
+                                         int64_t gx, bool col_in, float b) {
+    float4 q;
+    if (EDGE) {
+        if (gy >= 0 && gy < rows && col_in)
+            q = *reinterpret_cast<const float4*>(src + gy * cols + gx);
+        else
+            q = make_float4(b, b, b, b);
+    } else {
+        const int64_t g = gy < rows ? gy : rows - 1;
+        q = *reinterpret_cast<const float4*>(src + g * cols + gx);
+    }
+    set_own(x, q);
+}
+
+// One level: output rows [y0, y1) of the band whose first loaded column is X0.
+template <int R, int SHAPE, bool EDGE>
+__device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
+    constexpr int N = 2 * R + 2;  // window of 2R+1 rows plus one row in flight
+    const int64_t rows = a.rows, cols = a.cols;
+    const int64_t gx = X0 + 4 * lane;
+    const bool col_in = gx >= 0 && gx + 4 <= cols;
+    const bool writer = lane >= 1 && lane < 63 && (!EDGE || col_in);
+    const float b = a.b;
+    Row<R> ring[N];
+    const int64_t j0 = y0 - R;  // input row held by slot 0 at the start; row j lives in slot (j - j0) % N
+#pragma unroll
+    for (int t = 0; t < N; ++t) load_row<R, EDGE>(ring[t], a.src, j0 + t, rows, cols, gx, col_in, b);
+#pragma unroll
+    for (int t = 0; t < 2 * R; ++t) fill_sides<R>(ring[t]);
+    for (int64_t k0 = y0; k0 < y1; k0 += N) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int64_t k = k0 + u;
+            if (k >= y1) break;
+            fill_sides<R>(ring[(u + 2 * R) % N]);  // row k+R enters the window
+            const float4 o = apply<R, SHAPE, N>(ring, u, a.w);
+            if (writer) *reinterpret_cast<float4*>(a.dst + k * cols + gx) = o;
+            load_row<R, EDGE>(ring[u], a.src, k - R + N, rows, cols, gx, col_in, b);  // row k-R is done
+        }
+    }
+}
+
+// Two levels: the intermediate level of rows [y0 - R, y1 + R) runs one ring ahead of the output.
+template <int R, int SHAPE, bool EDGE>
+__device__ __forceinline__ void march_two(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
+    constexpr int N = 2 * R + 1;
+    const int64_t rows = a.rows, cols = a.cols;
+    const int64_t gx = X0 + 4 * lane;
+    const bool col_in = gx >= 0 && gx + 4 <= cols;
+    const bool writer = lane >= 2 && lane < 62 && (!EDGE || col_in);
+    const float b = a.b;
+    Row<R> in[N], mid[N];
+    const int64_t j0 = y0 - 2 * R;  // input row in slot 0 at the start
+#pragma unroll
+    for (int t = 0; t < N; ++t) load_row<R, EDGE>(in[t], a.src, j0 + t, rows, cols, gx, col_in, b);
+#pragma unroll
+    for (int t = 0; t < 2 * R; ++t) fill_sides<R>(in[t]);
+    // iteration i computes intermediate row m = y0 - R + i (slot i % N of `mid`) from input rows
+    // m-R .. m+R (slots (i + d) % N), then output row m - R once 2R intermediate rows precede it
+    const int64_t iters = (y1 - y0) + 2 * R;
+    for (int64_t i0 = 0; i0 < iters; i0 += N) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const int64_t i = i0 + u;
+            if (i >= iters) break;
+            const int64_t m = y0 - R + i;
+            fill_sides<R>(in[(u + 2 * R) % N]);
+            float4 q = apply<R, SHAPE, N>(in, u, a.w);
+            if (EDGE && !(m >= 0 && m < rows && col_in)) q = make_float4(b, b, b, b);  // the halo stays b
+            set_own<R>(mid[u], q);
+            fill_sides<R>(mid[u]);
+            load_row<R, EDGE>(in[u], a.src, j0 + i + N, rows, cols, gx, col_in, b);  // input row m-R is done
+            if (i >= 2 * R) {
+                const int64_t k = m - R;
+                // intermediate rows k-R .. k+R = m-2R .. m sit in slots (u + 1 + d) % N
+                const float4 o = apply<R, SHAPE, N>(mid, u + 1, a.w);
+                if (writer) *reinterpret_cast<float4*>(a.dst + k * cols + gx) = o;
+            }
+        }
+    }
+}
+
+template <int R, int SHAPE, int TB>
+__global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
+    const int lane = int(threadIdx.x & 63);
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t task = int64_t(blockIdx.x) * MWAVES + wave;
+    if (task >= a.tasks) return;
+    constexpr int OUTW = 4 * (64 - 2 * TB);
+    const int64_t band = task % a.bands;
+    const int64_t y0 = (task / a.bands) * a.seg;
+    const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
+    const int64_t X0 = band * OUTW - 4 * TB;
+    const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 256 > a.cols;
+    if (TB == 1) {
+        if (edge) march_one<R, SHAPE, true>(a, lane, y0, y1, X0);
+        else march_one<R, SHAPE, false>(a, lane, y0, y1, X0);
+    } else {
+        if (edge) march_two<R, SHAPE, true>(a, lane, y0, y1, X0);
+        else march_two<R, SHAPE, false>(a, lane, y0, y1, X0);
+    }
+}
+
+using MarchFn = void (*)(MarchArgs);
+
+template <int SH, int TB>
+MarchFn march_fn_r(int r) {
+    switch (r) {
+        case 1: return sweep_march<1, SH, TB>;
+        case 2: return sweep_march<2, SH, TB>;
+        case 3: return sweep_march<3, SH, TB>;
+        case 4: return sweep_march<4, SH, TB>;
+    }
+    return nullptr;
+}
+
+MarchFn march_lookup(int shape, int r, int levels) {
+    if (levels == 1) return shape == SHAPE_BOX ? march_fn_r<SHAPE_BOX, 1>(r) : march_fn_r<SHAPE_STAR, 1>(r);
+    if (levels == 2) return shape == SHAPE_BOX ? march_fn_r<SHAPE_BOX, 2>(r) : march_fn_r<SHAPE_STAR, 2>(r);
+    return nullptr;
+}
+
+}  // namespace
+
+bool march_usable(const st_plan* p) {
+    return p->kind == KIND_CONST && p->storage == ST_F32 && p->cols % 4 == 0 && p->radius <= 4;
+}
+
+int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s) {
+    MarchFn fn = march_lookup(p->shape, p->radius, levels);
+    if (!fn) return fail(ST_EUNSUPPORTED, "no row-marching kernel for this shape/radius/depth");
+    MarchArgs a;
+    a.src = static_cast<const float*>(src);
+    a.dst = static_cast<float*>(dst);
+    a.rows = p->rows;
+    a.cols = p->cols;
+    a.b = p->bq;
+    std::memcpy(a.w, p->w, sizeof(a.w));
+    const int64_t outw = 4 * (64 - 2 * levels);
+    a.bands = int((p->cols + outw - 1) / outw);
+    int blocks = 0;
+    if (int rc = resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks)) return rc;
+    const int64_t waves = int64_t(blocks) * MWAVES;
+    const int64_t per_band = std::max<int64_t>(1, waves / a.bands);  // segments per band
+    a.seg = (p->rows + per_band - 1) / per_band;
+    const int64_t segs = (p->rows + a.seg - 1) / a.seg;
+    a.tasks = segs * a.bands;
+    const int64_t grid = (a.tasks + MWAVES - 1) / MWAVES;
+    clear_stale_error();
+    hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(64 * MWAVES), 0, s, a);
+    ST_LAUNCH_CHECK("sweep_march");
+    return ST_OK;
+}
+
+}  // namespace st

@@ -257,6 +257,56 @@ def test_stream_variant_bitwise(g, rows, cols, shape, r, b, steps):
         lib.stencil_destroy(plan)
 
 
+MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exactly one band (tb 1: 248
+    # columns, tb 2: 240), one column group past it, many bands; segments with ragged ends; b != 0;
+    # grids shorter than the radius; odd step counts (the last two-level pass has one level)
+    (1, 4, wl.BOX, 3, 0.0, 3), (5, 8, wl.STAR, 4, 0.5, 4), (37, 248, wl.BOX, 3, 0.0, 5), (40, 240, wl.BOX, 2, 0.25, 5),
+    (33, 252, wl.STAR, 1, -1.0, 7), (300, 516, wl.BOX, 1, 0.0, 9), (257, 1000, wl.STAR, 2, 0.0, 6),
+    (1024, 1024, wl.BOX, 3, 0.0, 7), (700, 1200, wl.STAR, 3, 0.5, 5), (129, 996, wl.BOX, 4, 0.0, 3),
+    (2050, 64, wl.STAR, 4, 0.0, 4)]
+
+
+@pytest.mark.parametrize("case", MARCH_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in MARCH_CASES])
+def test_march_variant_bitwise(g, case):
+    """The row-marching variant (one wavefront per column band, lane-shifted side columns) equals the
+    FP32-canonical oracle bit for bit at both depths; unaligned buffers fall back to tiled kernels."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, shape, r, b, steps = case
+    W = _weights(shape, r, rows + 3 * cols + r)
+    u0 = np.random.default_rng(rows * cols + 7).random((rows, cols), dtype=np.float32)
+    ref = oracle.stencil_f32(u0, W, b, steps)
+    x = g.to_dev(u0)
+    for tb in (1, 2):
+        plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
+        try:
+            lib.stencil_set_blocking(plan, 1)
+            lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
+            lib.stencil_set_blocking(plan, tb)
+            with pytest.raises(lib.StencilError):
+                lib.stencil_set_blocking(plan, 3)
+            out = torch.full_like(x, float("nan"))
+            ws = torch.empty_like(x)
+            lib.stencil_run(plan, x, out, steps, ws)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"tb {tb}")
+            # a buffer 4 bytes past a 16-byte boundary takes the tiled kernels instead
+            xb = torch.empty(rows * cols + 1, dtype=torch.float32, device=g.DEV)
+            xb[1:].copy_(x.reshape(-1))
+            ob = torch.full_like(xb, float("nan"))
+            lib.stencil_run(plan, xb[1:], ob[1:], steps, ws)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.to_host(ob[1:]).reshape(rows, cols), ref, err_msg=f"unaligned tb {tb}")
+        finally:
+            lib.stencil_destroy(plan)
+    plan = lib.stencil_plan(rows, cols + 1, r, W, b, "f32", 0)
+    try:
+        with pytest.raises(lib.StencilError):
+            lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
+    finally:
+        lib.stencil_destroy(plan)
+
+
 def test_solve_until_converged(g):
     """Periodic convergence check: stops at the first check whose relative residual is <= tol, and
     the field equals a plain run of that many steps."""
