@@ -39,9 +39,13 @@ VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP
 HBM_PEAK = 8.0e12
 
 
+KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march"}
+VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march"}
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h"):
+    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip"):
         with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -94,7 +98,8 @@ def main_line(args, torch, lib, stream):
     rows, cols = p.rows, p.cols
     x = torch.from_numpy(p.u0).to("cuda")
     out = torch.empty_like(x)
-    plan = lib.stencil_plan(rows, cols, p.radius, p.weights, 0.0, "f32", 0)
+    # the whole 1000-step run is one captured hipGraph (the autotuner times direct launches)
+    plan = lib.stencil_plan(rows, cols, p.radius, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
     t0 = time.perf_counter()
     tune_steps = 24
     ws = torch.empty_like(x)
@@ -121,7 +126,8 @@ def main_line(args, torch, lib, stream):
     traffic = measured_traffic(tb, (tx, ty), variant)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / VALU_FP32_PEAK, "traffic": traffic,
-            "kernel": ("sweep_stream" if variant == 1 else "sweep_tiled") + "<f32, r=3, box>", "launches": launches, "avg_launch_us": t / launches * 1e6,
+            "kernel": KERNEL_NAMES[variant] + f"<f32, r=3, box, tb={tb}>", "launches": launches,
+            "avg_launch_us": t / launches * 1e6,
             "alg_flop_per_launch": 97.0 * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
             "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
             "alu_roof_gstencil": VALU_FP32_PEAK / 97.0 / 1e9,
@@ -134,21 +140,22 @@ def main_line(args, torch, lib, stream):
 
 
 def tune_batch_plans(lib, probs, plans, ins, outs, wss, stream=None) -> dict:
-    """Blocking of a batch's plans: one ``stencil_autotune`` per stencil class (shape, radius), run on
-    that class's first grid of at least 512^2 cells, then applied to every grid of the class where it
-    fits (a grid too small for the depth keeps its default)."""
+    """Blocking of a batch's plans: one ``stencil_autotune`` per stencil class (shape, radius) and size
+    bucket (cells within a factor of 4), run on the bucket's first grid, then applied to every grid of
+    that bucket where it fits (a grid too small for the depth keeps its default)."""
+    def key(q):
+        return q.shape, q.radius, int(math.log2(q.rows * q.cols) // 2)
+
     tuned = {}
     for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):
-        key = (q.shape, q.radius)
-        if key not in tuned and q.rows * q.cols >= 512 * 512 and q.cols % 4 == 0:
-            tuned[key] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
+        if key(q) not in tuned:
+            tuned[key(q)] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
     for q, pl in zip(probs, plans):
-        if (q.shape, q.radius) not in tuned:
-            continue
-        tb, tx, ty, var = tuned[(q.shape, q.radius)]
+        tb, tx, ty, var = tuned[key(q)]
         try:
+            lib.stencil_set_variant(pl, lib.ST_VARIANT_TILED)
             lib.stencil_set_blocking(pl, 1, tx, ty)
-            if var == lib.ST_VARIANT_STREAM and q.cols % 4 == 0:
+            if var != lib.ST_VARIANT_TILED:
                 lib.stencil_set_variant(pl, var)
             lib.stencil_set_blocking(pl, tb)
         except lib.StencilError:
@@ -255,7 +262,9 @@ def main():
     ap.add_argument("--jacobi-steps", type=int, default=1000)
     ap.add_argument("--tb", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=None)
-    ap.add_argument("--variant", type=int, default=1, help="with --tb: 0 = tiled, 1 = streaming")
+    ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer once (reference for the HBM byte counters) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
@@ -264,8 +273,16 @@ def main():
               "row-slab decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
     import torch
-    import paper_2605_07954_amd as lib
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.rand(16384, 16384, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_read_bytes": x.numel() * 4, "copy_write_bytes": y.numel() * 4}), flush=True)
+        return
+    import paper_2605_07954_amd as lib
     stream = torch.cuda.current_stream()
     p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)
     line = {"metric": "GStencil/s", "value": value, "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
@@ -273,7 +290,7 @@ def main():
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"box2d49p-{p.rows}x{p.cols}-{p.steps}steps", "stencil": "box", "radius": 3,
                        "grid": [p.rows, p.cols], "jacobi_steps": p.steps, "boundary": "dirichlet-0",
-                       "tb": tb, "tile": [tx, ty], "variant": ["tiled", "stream"][variant],
+                       "tb": tb, "tile": [tx, ty], "variant": VARIANT_NAMES[variant],
                        "autotune_s": round(tune_s, 2)},
             "roofline": roof}
     if not args.no_cpu_baseline:

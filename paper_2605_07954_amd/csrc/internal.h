@@ -97,8 +97,9 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
-// Row-marching pass (march.hip): FP32 constant-weight plans with cols % 4 == 0, 1 or 2 levels.
-constexpr int MARCH_MAX_TB = 2;
+// Row-marching pass (march.hip): FP32 constant-weight plans with cols % 4 == 0; up to
+// march_max_tb(radius) levels per pass (4 for r = 1, 3 for r = 2, else 2).
+int march_max_tb(int radius);
 bool march_usable(const st_plan* p);
 int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s);
 // Drop a stale runtime error left by earlier API calls so that the check after our next

@@ -6,8 +6,8 @@
 // row is read from HBM once per band with one 16-byte load per lane; the r columns a lane needs on
 // either side come from the neighbouring lanes through DPP wave shifts, so the pass uses neither LDS
 // nor barriers.  The rows a lane needs sit in a register ring whose slots become fixed registers
-// because the row loop is unrolled over the ring length.  With two levels per pass a second ring
-// holds the intermediate level.  Lanes at a band's edges only supply halo columns: with four columns
+// because the row loop is unrolled over the ring length.  With several levels per pass further rings
+// hold the intermediate levels.  Lanes at a band's edges only supply halo columns: with four columns
 // per lane and r <= 4 each level consumes one lane per side, so a band writes 4 (64 - 2 tb) columns.
 //
 // Segments are sized on the host so that the number of (band, segment) tasks is close to the number
@@ -135,41 +135,47 @@ __device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t 
     }
 }
 
-// Two levels: the intermediate level of rows [y0 - R, y1 + R) runs one ring ahead of the output.
-template <int R, int SHAPE, bool EDGE>
-__device__ __forceinline__ void march_two(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
+// TB >= 2 levels.  Level l (0 = input, TB = output) keeps its own ring of N = 2R+1 rows.  Iteration i
+// computes level-1 row m1 = y0 - R(TB-1) + i from the input rows m1-R .. m1+R, then, once enough rows
+// of the level below exist, level-l row m1 - (l-1)R for l = 2 .. TB.  Within level l the row of
+// iteration i sits in slot (i + l - 1) % N (because -2R = 1 mod N), so every slot index is a
+// compile-time constant of the loop unrolled N times.
+template <int R, int SHAPE, int TB, bool EDGE>
+__device__ __forceinline__ void march_levels(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
     constexpr int N = 2 * R + 1;
     const int64_t rows = a.rows, cols = a.cols;
     const int64_t gx = X0 + 4 * lane;
     const bool col_in = gx >= 0 && gx + 4 <= cols;
-    const bool writer = lane >= 2 && lane < 62 && (!EDGE || col_in);
+    const bool writer = lane >= TB && lane < 64 - TB && (!EDGE || col_in);
     const float b = a.b;
-    Row<R> in[N], mid[N];
-    const int64_t j0 = y0 - 2 * R;  // input row in slot 0 at the start
+    Row<R> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
+    const int64_t j0 = y0 - R * TB;  // input row in slot 0 at the start
 #pragma unroll
-    for (int t = 0; t < N; ++t) load_row<R, EDGE>(in[t], a.src, j0 + t, rows, cols, gx, col_in, b);
+    for (int t = 0; t < N; ++t) load_row<R, EDGE>(lv[0][t], a.src, j0 + t, rows, cols, gx, col_in, b);
 #pragma unroll
-    for (int t = 0; t < 2 * R; ++t) fill_sides<R>(in[t]);
-    // iteration i computes intermediate row m = y0 - R + i (slot i % N of `mid`) from input rows
-    // m-R .. m+R (slots (i + d) % N), then output row m - R once 2R intermediate rows precede it
-    const int64_t iters = (y1 - y0) + 2 * R;
+    for (int t = 0; t < 2 * R; ++t) fill_sides<R>(lv[0][t]);
+    const int64_t iters = (y1 - y0) + 2 * R * (TB - 1);
     for (int64_t i0 = 0; i0 < iters; i0 += N) {
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const int64_t i = i0 + u;
             if (i >= iters) break;
-            const int64_t m = y0 - R + i;
-            fill_sides<R>(in[(u + 2 * R) % N]);
-            float4 q = apply<R, SHAPE, N>(in, u, a.w);
-            if (EDGE && !(m >= 0 && m < rows && col_in)) q = make_float4(b, b, b, b);  // the halo stays b
-            set_own<R>(mid[u], q);
-            fill_sides<R>(mid[u]);
-            load_row<R, EDGE>(in[u], a.src, j0 + i + N, rows, cols, gx, col_in, b);  // input row m-R is done
-            if (i >= 2 * R) {
-                const int64_t k = m - R;
-                // intermediate rows k-R .. k+R = m-2R .. m sit in slots (u + 1 + d) % N
-                const float4 o = apply<R, SHAPE, N>(mid, u + 1, a.w);
-                if (writer) *reinterpret_cast<float4*>(a.dst + k * cols + gx) = o;
+            fill_sides<R>(lv[0][(u + 2 * R) % N]);  // input row m1 + R enters the window
+#pragma unroll
+            for (int l = 1; l <= TB; ++l) {
+                if (i < 2 * R * (l - 1)) break;  // level l - 1 does not have 2R+1 rows yet
+                const int64_t m = y0 - R * (TB - 1) + i - int64_t(l - 1) * R;  // row of level l
+                const float4 q = apply<R, SHAPE, N>(lv[l - 1], u + l - 1, a.w);
+                if (l == TB) {
+                    if (writer) *reinterpret_cast<float4*>(a.dst + m * cols + gx) = q;
+                } else {
+                    Row<R>& x = lv[l][(u + l - 1) % N];
+                    // cells outside the grid keep the halo value b at every level
+                    set_own<R>(x, (EDGE && !(m >= 0 && m < rows && col_in)) ? make_float4(b, b, b, b) : q);
+                    fill_sides<R>(x);
+                }
+                if (l == 1)  // input row m1 - R is no longer needed: fetch the row N further down
+                    load_row<R, EDGE>(lv[0][u], a.src, j0 + i + N, rows, cols, gx, col_in, b);
             }
         }
     }
@@ -187,35 +193,37 @@ __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
     const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
     const int64_t X0 = band * OUTW - 4 * TB;
     const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 256 > a.cols;
-    if (TB == 1) {
+    if constexpr (TB == 1) {
         if (edge) march_one<R, SHAPE, true>(a, lane, y0, y1, X0);
         else march_one<R, SHAPE, false>(a, lane, y0, y1, X0);
     } else {
-        if (edge) march_two<R, SHAPE, true>(a, lane, y0, y1, X0);
-        else march_two<R, SHAPE, false>(a, lane, y0, y1, X0);
+        if (edge) march_levels<R, SHAPE, TB, true>(a, lane, y0, y1, X0);
+        else march_levels<R, SHAPE, TB, false>(a, lane, y0, y1, X0);
     }
 }
 
 using MarchFn = void (*)(MarchArgs);
 
-template <int SH, int TB>
-MarchFn march_fn_r(int r) {
-    switch (r) {
-        case 1: return sweep_march<1, SH, TB>;
-        case 2: return sweep_march<2, SH, TB>;
-        case 3: return sweep_march<3, SH, TB>;
-        case 4: return sweep_march<4, SH, TB>;
-    }
+// Depths per radius: the rings of TB levels must fit the register file next to each other.
+template <int SH>
+MarchFn march_fn(int r, int levels) {
+#define ST_MARCH(R, TB) \
+    if (r == R && levels == TB) return sweep_march<R, SH, TB>;
+    ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4)
+    ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3)
+    ST_MARCH(3, 1) ST_MARCH(3, 2)
+    ST_MARCH(4, 1) ST_MARCH(4, 2)
+#undef ST_MARCH
     return nullptr;
 }
 
 MarchFn march_lookup(int shape, int r, int levels) {
-    if (levels == 1) return shape == SHAPE_BOX ? march_fn_r<SHAPE_BOX, 1>(r) : march_fn_r<SHAPE_STAR, 1>(r);
-    if (levels == 2) return shape == SHAPE_BOX ? march_fn_r<SHAPE_BOX, 2>(r) : march_fn_r<SHAPE_STAR, 2>(r);
-    return nullptr;
+    return shape == SHAPE_BOX ? march_fn<SHAPE_BOX>(r, levels) : march_fn<SHAPE_STAR>(r, levels);
 }
 
 }  // namespace
+
+int march_max_tb(int radius) { return radius == 1 ? 4 : radius == 2 ? 3 : 2; }
 
 bool march_usable(const st_plan* p) {
     return p->kind == KIND_CONST && p->storage == ST_F32 && p->cols % 4 == 0 && p->radius <= 4;

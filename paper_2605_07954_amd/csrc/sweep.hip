@@ -359,7 +359,7 @@ int supported_tiles(int* xy, int cap) {
 
 int max_tb(const st_plan* p, int tx, int ty) {
     int tb = 1;
-    if (p->variant == VARIANT_MARCH) return MARCH_MAX_TB;
+    if (p->variant == VARIANT_MARCH) return march_max_tb(p->radius);
     if (p->variant == VARIANT_STREAM) {
         while (tb < 16 && stream_lds_bytes(p->radius, tb + 1, tx, ty) <= lds_limit()) ++tb;
     } else {
@@ -394,7 +394,7 @@ int launch_pass(const st_plan* p, const void* src, void* dst, const float* kappa
     }
     const int ti = tile_index(p->tile_x, p->tile_y);
     const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
-    if (p->variant == VARIANT_MARCH && march_usable(p) && aligned && levels <= MARCH_MAX_TB)
+    if (p->variant == VARIANT_MARCH && march_usable(p) && aligned && levels <= march_max_tb(p->radius))
         return launch_march(p, src, dst, levels, s);
     if (p->variant == VARIANT_STREAM && stream_usable(p) && (reinterpret_cast<uintptr_t>(src) % 16) == 0 &&
         (reinterpret_cast<uintptr_t>(dst) % 16) == 0) {

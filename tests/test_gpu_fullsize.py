@@ -17,10 +17,14 @@ properties that hold at any size.
   grid bit for bit against the FP32-canonical oracle.
 * Surrogate forward on 1024 x 1024: 64x64 patches against the CNN oracle run on each patch's
   receptive window (6 cells: six 3x3 layers); the judged entry point's error against one
-  computed from the oracle's 16 plain steps.  A patch of 64x64 rather than smaller: where the two
-  sides' FP32 sums of a pre-activation straddle a BF16 rounding boundary, that activation differs
-  by one BF16 ulp (2^-8 relative), and over a handful of cells one such case can dominate the
-  rel-L2 of the update f.
+  computed from the oracle's 16 plain steps.  Tolerance: the two sides round the same operands to
+  BF16, but each rounds its own sum (FP32 MFMA accumulation against FP64), so an activation whose
+  sums straddle a rounding boundary differs by one BF16 ulp.  With sums that agree to ~1e-5
+  relative and a BF16 ulp of 2^-8, about 0.1 % of activations differ, which puts the expected gap
+  at roughly a tenth to a fifth of the BF16 rounding effect itself (the emulating oracle against
+  the exact FP64 network).  Where u0 is large and the update f small, that effect is a few percent
+  of f, so the gate is relative to it: the GPU's f must lie within half of it, and u_hat within
+  1e-3 of the emulating oracle.
 """
 import math
 import sys
@@ -238,11 +242,18 @@ def test_surrogate_1024(g):
         wy0, wx0 = max(0, y - RF), max(0, x - RF)
         wy1, wx1 = min(n, y + P + RF), min(n, x + P + RF)
         ref, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1], q=q_bf16)
+        exact, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1])
         ref = ref[y - wy0:y - wy0 + P, x - wx0:x - wx0 + P]
+        exact = exact[y - wy0:y - wy0 + P, x - wx0:x - wx0 + P]
         base = u0[y:y + P, x:x + P]
-        e = oracle.rel_l2(got[y:y + P, x:x + P] - base, ref - base)
-        say(f"surrogate 1024^2 patch ({y}, {x}) {P}x{P}: rel-L2 of f vs the BF16-emulating oracle {e:.2e}")
-        assert e < 1e-3
+        mine = got[y:y + P, x:x + P]
+        e = oracle.rel_l2(mine - base, ref - base)
+        e_bf16 = oracle.rel_l2(ref - base, exact - base)
+        e_hat = oracle.rel_l2(mine, ref)
+        say(f"surrogate 1024^2 patch ({y}, {x}) {P}x{P}: rel-L2 of f vs the BF16-emulating oracle {e:.2e} "
+            f"(BF16 emulation vs exact FP64: {e_bf16:.2e}); of u_hat {e_hat:.2e}")
+        assert e <= 0.5 * e_bf16
+        assert e_hat <= 1e-3
     plain = oracle.varcoef_f32(u0, kap, 0.0, 16)
     e_ref = oracle.rel_l2(got, plain)
     say(f"judged error: library {err:.6e}, from the oracle's 16 plain steps {e_ref:.6e} (fallback={fb})")

@@ -269,7 +269,8 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
 @pytest.mark.parametrize("case", MARCH_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in MARCH_CASES])
 def test_march_variant_bitwise(g, case):
     """The row-marching variant (one wavefront per column band, lane-shifted side columns) equals the
-    FP32-canonical oracle bit for bit at both depths; unaligned buffers fall back to tiled kernels."""
+    FP32-canonical oracle bit for bit at every depth it offers for the radius (r = 1: up to 4 levels,
+    r = 2: 3, else 2); unaligned buffers fall back to the tiled kernels."""
     import torch
     import paper_2605_07954_amd as lib
     rows, cols, shape, r, b, steps = case
@@ -277,14 +278,15 @@ def test_march_variant_bitwise(g, case):
     u0 = np.random.default_rng(rows * cols + 7).random((rows, cols), dtype=np.float32)
     ref = oracle.stencil_f32(u0, W, b, steps)
     x = g.to_dev(u0)
-    for tb in (1, 2):
+    deepest = {1: 4, 2: 3}.get(r, 2)
+    for tb in range(1, deepest + 1):
         plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
         try:
             lib.stencil_set_blocking(plan, 1)
             lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
             lib.stencil_set_blocking(plan, tb)
             with pytest.raises(lib.StencilError):
-                lib.stencil_set_blocking(plan, 3)
+                lib.stencil_set_blocking(plan, deepest + 1)
             out = torch.full_like(x, float("nan"))
             ws = torch.empty_like(x)
             lib.stencil_run(plan, x, out, steps, ws)
