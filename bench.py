@@ -256,8 +256,8 @@ def extras(torch, lib, stream) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=16384)
     ap.add_argument("--jacobi-steps", type=int, default=1000)
     ap.add_argument("--tb", type=int, default=0)

@@ -106,12 +106,12 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
                                  while the current one computes (FP32, cols % 4 == 0)          */
 #define ST_VARIANT_MARCH   2  /* each wavefront walks a column band down the grid, rows in a
                                  register ring, side columns by lane shifts; tb up to 4 (r = 1),
-                                 3 (r = 2) or 2 (r >= 3); the tile is ignored (FP32,
+                                 3 (r = 2) or 2 (r >= 3); the tile is ignored (any storage,
                                  cols % 4 == 0)                                                 */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
- * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming and marching need FP32 storage,
- * cols % 4 == 0 and a constant-weight plan; or the current tb is deeper than the variant
+ * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage; both streaming
+ * and marching need cols % 4 == 0 and a constant-weight plan; or the current tb is deeper than the variant
  * allows: its LDS budget when streaming, 4/3/2 for r = 1/2/>=3 when marching -- lower tb
  * first).  A run whose
  * buffers are not 16-byte aligned falls back to the tiled kernels. */

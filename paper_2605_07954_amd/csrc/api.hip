@@ -236,7 +236,7 @@ int stencil_set_variant(st_plan* plan, int variant) {
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
         return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
     if (variant == ST_VARIANT_MARCH && !march_usable(plan))
-        return fail(ST_EUNSUPPORTED, "marching needs an FP32 constant-weight plan with cols % 4 == 0");
+        return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan with cols % 4 == 0");
     const int old = plan->variant;
     plan->variant = variant;
     if (plan->tb > max_tb(plan, plan->tile_x, plan->tile_y)) {  // keep the plan launchable
@@ -392,9 +392,10 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
-    const int nvar = (plan->kind == KIND_CONST && stream_usable(plan)) ? 3 : 1;
+    const int nvar = plan->kind == KIND_CONST ? 3 : 1;
     for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
+        if (var == VARIANT_STREAM && !stream_usable(plan)) break;
         if (var == VARIANT_MARCH && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
         plan->variant = var;

@@ -1,9 +1,10 @@
-// Row-marching Jacobi pass for FP32 grids (paper Sec. II-C update with the fixed halo of Sec. IV-A;
-// per cell the FP32 order of Sec. IV-E: the centre product, then one FMA per footprint tap in
-// row-major order, the same order as the tiled kernels, so results agree bit for bit).
+// Row-marching Jacobi pass (paper Sec. II-C update with the fixed halo of Sec. IV-A; per cell the
+// FP32 order of Sec. IV-E: the centre product, then one FMA per footprint tap in row-major order, the
+// same order as the tiled kernels, so results agree bit for bit).  Fields may be stored as FP32,
+// BF16 or FP16; arithmetic is FP32 and every level is rounded to the storage type.
 //
 // One wavefront owns a band of columns, four per lane, and walks down a segment of rows.  Each input
-// row is read from HBM once per band with one 16-byte load per lane; the r columns a lane needs on
+// row is read from HBM once per band with one 16-byte (FP32) or 8-byte (16-bit) load per lane; the r columns a lane needs on
 // either side come from the neighbouring lanes through DPP wave shifts, so the pass uses neither LDS
 // nor barriers.  The rows a lane needs sit in a register ring whose slots become fixed registers
 // because the row loop is unrolled over the ring length.  With several levels per pass further rings
@@ -16,6 +17,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "storage.h"
 
 namespace st {
 namespace {
@@ -23,8 +25,8 @@ namespace {
 constexpr int MWAVES = 4;  // wavefronts per workgroup, each with its own task
 
 struct MarchArgs {
-    const float* src;
-    float* dst;
+    const void* src;
+    void* dst;
     int64_t rows, cols;
     int64_t tasks;  // bands * segments
     int64_t seg;    // output rows per task
@@ -89,26 +91,49 @@ __device__ __forceinline__ float4 apply(const Row<R>* ring, int base, const floa
     return make_float4(o[0], o[1], o[2], o[3]);
 }
 
+// Four consecutive cells of the storage type, widened to FP32 (exact).
+template <int S>
+__device__ __forceinline__ float4 load4(const void* src, int64_t off) {
+    if constexpr (S == ST_F32) {
+        return *reinterpret_cast<const float4*>(static_cast<const float*>(src) + off);
+    } else {
+        const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(src) + off);
+        return make_float4(Fmt<S>::ld(uint16_t(q.x & 0xffffu)), Fmt<S>::ld(uint16_t(q.x >> 16)),
+                           Fmt<S>::ld(uint16_t(q.y & 0xffffu)), Fmt<S>::ld(uint16_t(q.y >> 16)));
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void put4(void* dst, int64_t off, float4 q) {
+    const float v[4] = {q.x, q.y, q.z, q.w};
+    store4<S>(static_cast<typename Fmt<S>::T*>(dst) + off, v);
+}
+
+template <int S>
+__device__ __forceinline__ float4 round4(float4 q) {
+    return make_float4(Fmt<S>::rnd(q.x), Fmt<S>::rnd(q.y), Fmt<S>::rnd(q.z), Fmt<S>::rnd(q.w));
+}
+
 // Loads one input row into `x` (own columns).  EDGE tasks may touch rows or columns outside the
 // grid: those cells hold b.  Interior tasks only clamp the row of a prefetch past the grid's end.
-template <int R, bool EDGE>
-__device__ __forceinline__ void load_row(Row<R>& x, const float* src, int64_t gy, int64_t rows, int64_t cols,
+template <int S, int R, bool EDGE>
+__device__ __forceinline__ void load_row(Row<R>& x, const void* src, int64_t gy, int64_t rows, int64_t cols,
                                          int64_t gx, bool col_in, float b) {
     float4 q;
     if (EDGE) {
         if (gy >= 0 && gy < rows && col_in)
-            q = *reinterpret_cast<const float4*>(src + gy * cols + gx);
+            q = load4<S>(src, gy * cols + gx);
         else
             q = make_float4(b, b, b, b);
     } else {
         const int64_t g = gy < rows ? gy : rows - 1;
-        q = *reinterpret_cast<const float4*>(src + g * cols + gx);
+        q = load4<S>(src, g * cols + gx);
     }
     set_own(x, q);
 }
 
 // One level: output rows [y0, y1) of the band whose first loaded column is X0.
-template <int R, int SHAPE, bool EDGE>
+template <int S, int R, int SHAPE, bool EDGE>
 __device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
     constexpr int N = 2 * R + 2;  // window of 2R+1 rows plus one row in flight
     const int64_t rows = a.rows, cols = a.cols;
@@ -119,7 +144,7 @@ __device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t 
     Row<R> ring[N];
     const int64_t j0 = y0 - R;  // input row held by slot 0 at the start; row j lives in slot (j - j0) % N
 #pragma unroll
-    for (int t = 0; t < N; ++t) load_row<R, EDGE>(ring[t], a.src, j0 + t, rows, cols, gx, col_in, b);
+    for (int t = 0; t < N; ++t) load_row<S, R, EDGE>(ring[t], a.src, j0 + t, rows, cols, gx, col_in, b);
 #pragma unroll
     for (int t = 0; t < 2 * R; ++t) fill_sides<R>(ring[t]);
     for (int64_t k0 = y0; k0 < y1; k0 += N) {
@@ -129,8 +154,8 @@ __device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t 
             if (k >= y1) break;
             fill_sides<R>(ring[(u + 2 * R) % N]);  // row k+R enters the window
             const float4 o = apply<R, SHAPE, N>(ring, u, a.w);
-            if (writer) *reinterpret_cast<float4*>(a.dst + k * cols + gx) = o;
-            load_row<R, EDGE>(ring[u], a.src, k - R + N, rows, cols, gx, col_in, b);  // row k-R is done
+            if (writer) put4<S>(a.dst, k * cols + gx, o);
+            load_row<S, R, EDGE>(ring[u], a.src, k - R + N, rows, cols, gx, col_in, b);  // row k-R is done
         }
     }
 }
@@ -140,7 +165,7 @@ __device__ __forceinline__ void march_one(const MarchArgs& a, int lane, int64_t 
 // of the level below exist, level-l row m1 - (l-1)R for l = 2 .. TB.  Within level l the row of
 // iteration i sits in slot (i + l - 1) % N (because -2R = 1 mod N), so every slot index is a
 // compile-time constant of the loop unrolled N times.
-template <int R, int SHAPE, int TB, bool EDGE>
+template <int S, int R, int SHAPE, int TB, bool EDGE>
 __device__ __forceinline__ void march_levels(const MarchArgs& a, int lane, int64_t y0, int64_t y1, int64_t X0) {
     constexpr int N = 2 * R + 1;
     const int64_t rows = a.rows, cols = a.cols;
@@ -151,7 +176,7 @@ __device__ __forceinline__ void march_levels(const MarchArgs& a, int lane, int64
     Row<R> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
     const int64_t j0 = y0 - R * TB;  // input row in slot 0 at the start
 #pragma unroll
-    for (int t = 0; t < N; ++t) load_row<R, EDGE>(lv[0][t], a.src, j0 + t, rows, cols, gx, col_in, b);
+    for (int t = 0; t < N; ++t) load_row<S, R, EDGE>(lv[0][t], a.src, j0 + t, rows, cols, gx, col_in, b);
 #pragma unroll
     for (int t = 0; t < 2 * R; ++t) fill_sides<R>(lv[0][t]);
     const int64_t iters = (y1 - y0) + 2 * R * (TB - 1);
@@ -167,21 +192,21 @@ __device__ __forceinline__ void march_levels(const MarchArgs& a, int lane, int64
                 const int64_t m = y0 - R * (TB - 1) + i - int64_t(l - 1) * R;  // row of level l
                 const float4 q = apply<R, SHAPE, N>(lv[l - 1], u + l - 1, a.w);
                 if (l == TB) {
-                    if (writer) *reinterpret_cast<float4*>(a.dst + m * cols + gx) = q;
+                    if (writer) put4<S>(a.dst, m * cols + gx, q);
                 } else {
                     Row<R>& x = lv[l][(u + l - 1) % N];
-                    // cells outside the grid keep the halo value b at every level
-                    set_own<R>(x, (EDGE && !(m >= 0 && m < rows && col_in)) ? make_float4(b, b, b, b) : q);
+                    // every level is rounded to the storage type; cells outside the grid keep b
+                    set_own<R>(x, (EDGE && !(m >= 0 && m < rows && col_in)) ? make_float4(b, b, b, b) : round4<S>(q));
                     fill_sides<R>(x);
                 }
                 if (l == 1)  // input row m1 - R is no longer needed: fetch the row N further down
-                    load_row<R, EDGE>(lv[0][u], a.src, j0 + i + N, rows, cols, gx, col_in, b);
+                    load_row<S, R, EDGE>(lv[0][u], a.src, j0 + i + N, rows, cols, gx, col_in, b);
             }
         }
     }
 }
 
-template <int R, int SHAPE, int TB>
+template <int S, int R, int SHAPE, int TB>
 __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -194,21 +219,21 @@ __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
     const int64_t X0 = band * OUTW - 4 * TB;
     const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 256 > a.cols;
     if constexpr (TB == 1) {
-        if (edge) march_one<R, SHAPE, true>(a, lane, y0, y1, X0);
-        else march_one<R, SHAPE, false>(a, lane, y0, y1, X0);
+        if (edge) march_one<S, R, SHAPE, true>(a, lane, y0, y1, X0);
+        else march_one<S, R, SHAPE, false>(a, lane, y0, y1, X0);
     } else {
-        if (edge) march_levels<R, SHAPE, TB, true>(a, lane, y0, y1, X0);
-        else march_levels<R, SHAPE, TB, false>(a, lane, y0, y1, X0);
+        if (edge) march_levels<S, R, SHAPE, TB, true>(a, lane, y0, y1, X0);
+        else march_levels<S, R, SHAPE, TB, false>(a, lane, y0, y1, X0);
     }
 }
 
 using MarchFn = void (*)(MarchArgs);
 
 // Depths per radius: the rings of TB levels must fit the register file next to each other.
-template <int SH>
+template <int S, int SH>
 MarchFn march_fn(int r, int levels) {
 #define ST_MARCH(R, TB) \
-    if (r == R && levels == TB) return sweep_march<R, SH, TB>;
+    if (r == R && levels == TB) return sweep_march<S, R, SH, TB>;
     ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4)
     ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3)
     ST_MARCH(3, 1) ST_MARCH(3, 2)
@@ -217,8 +242,16 @@ MarchFn march_fn(int r, int levels) {
     return nullptr;
 }
 
-MarchFn march_lookup(int shape, int r, int levels) {
-    return shape == SHAPE_BOX ? march_fn<SHAPE_BOX>(r, levels) : march_fn<SHAPE_STAR>(r, levels);
+template <int S>
+MarchFn march_lookup_s(int shape, int r, int levels) {
+    return shape == SHAPE_BOX ? march_fn<S, SHAPE_BOX>(r, levels) : march_fn<S, SHAPE_STAR>(r, levels);
+}
+
+MarchFn march_lookup(int storage, int shape, int r, int levels) {
+    if (storage == ST_F32) return march_lookup_s<ST_F32>(shape, r, levels);
+    if (storage == ST_BF16) return march_lookup_s<ST_BF16>(shape, r, levels);
+    if (storage == ST_F16) return march_lookup_s<ST_F16>(shape, r, levels);
+    return nullptr;
 }
 
 }  // namespace
@@ -226,15 +259,15 @@ MarchFn march_lookup(int shape, int r, int levels) {
 int march_max_tb(int radius) { return radius == 1 ? 4 : radius == 2 ? 3 : 2; }
 
 bool march_usable(const st_plan* p) {
-    return p->kind == KIND_CONST && p->storage == ST_F32 && p->cols % 4 == 0 && p->radius <= 4;
+    return p->kind == KIND_CONST && p->cols % 4 == 0 && p->radius <= 4;
 }
 
 int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s) {
-    MarchFn fn = march_lookup(p->shape, p->radius, levels);
+    MarchFn fn = march_lookup(p->storage, p->shape, p->radius, levels);
     if (!fn) return fail(ST_EUNSUPPORTED, "no row-marching kernel for this shape/radius/depth");
     MarchArgs a;
-    a.src = static_cast<const float*>(src);
-    a.dst = static_cast<float*>(dst);
+    a.src = src;
+    a.dst = dst;
     a.rows = p->rows;
     a.cols = p->cols;
     a.b = p->bq;

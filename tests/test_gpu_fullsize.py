@@ -10,9 +10,9 @@ properties that hold at any size.
 * Star-2D9P, 8192 x 8192, 500 steps, FP32 / BF16 / FP16 storage: the 8x8 corner patches bit for
   bit against the FP32-canonical / 16-bit-emulating oracle run on the (8 + r*T)^2 corner crop (a
   cell at least r*T from the crop's cut edges cannot see them); the sine-mode sum in the
-  light-cone interior against its closed form (each mode scaled by lambda^T).  The FP32 gate is
-  1e-5; the 16-bit error against the exact interior is printed (their gate is the bitwise
-  emulation).
+  light-cone interior against its closed form (each mode scaled by lambda^T); the whole field
+  against the FP64 oracle.  The FP32 gate is 1e-5; the 16-bit errors are printed (their gate is
+  the bitwise emulation).
 * The 256-grid batch, 200 steps, with the benchmark's per-class tuning and hipGraph: every 8th
   grid bit for bit against the FP32-canonical oracle.
 * Surrogate forward on 1024 x 1024: 64x64 patches against the CNN oracle run on each patch's
@@ -132,8 +132,15 @@ def star9():
     return wl.star9_precision()
 
 
+@pytest.fixture(scope="module")
+def star9_f64(star9):
+    """The whole 8192^2 x 500-step field in FP64 (the truth every storage type is measured against)."""
+    say("star9 FP64 oracle on the full grid ...")
+    return oracle.stencil_f64(star9.u0, star9.weights, 0.0, star9.steps)
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
-def test_star9_8192_500(g, star9, storage):
+def test_star9_8192_500(g, star9, star9_f64, storage):
     import torch
     import paper_2605_07954_amd as lib
     p = star9
@@ -151,6 +158,7 @@ def test_star9_8192_500(g, star9, storage):
         got_tl = g.to_host(out[:8, :8])
         got_br = g.to_host(out[rows - 8:, cols - 8:])
         inner = g.to_host(out[torch.from_numpy(sample).to(g.DEV), m:cols - m])
+        whole = g.to_host(out)
     finally:
         tp.close()
     del x
@@ -172,8 +180,11 @@ def test_star9_8192_500(g, star9, storage):
     say(f"  {storage}: corners bitwise vs the {'FP32-canonical' if storage == 'f32' else 'emulating'} oracle; "
         f"interior rel-L2 vs the exact sine-mode solution = {e:.3e}")
     assert np.isfinite(vals).all()
+    e_all = oracle.rel_l2(whole if storage == "f32" else oracle.from_bits(whole, storage), star9_f64)
+    say(f"  {storage}: whole-field rel-L2 vs the FP64 oracle = {e_all:.3e}")
     if storage == "f32":
         assert e <= TOL
+        assert e_all <= TOL
 
 
 def test_batched_256_200(g):

@@ -309,6 +309,28 @@ def test_march_variant_bitwise(g, case):
         lib.stencil_destroy(plan)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("rows,cols,shape,r,b,steps", [(300, 260, wl.STAR, 2, 0.0, 23), (129, 500, wl.BOX, 1, 0.5, 11),
+                                                      (40, 996, wl.BOX, 3, 0.0, 5), (7, 8, wl.STAR, 4, -0.25, 4)])
+def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
+    """Marching with BF16/FP16 storage (8-byte loads, FP32 arithmetic, every level rounded to the
+    storage type) equals the emulating oracle bit for bit at every depth."""
+    import paper_2605_07954_amd as lib
+    W = _weights(shape, r, rows + 5 * cols + r)
+    bits = oracle.to_bits(np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32), storage)
+    ref = oracle.stencil_lowp(bits, W, b, steps, storage)
+    for tb in range(1, {1: 4, 2: 3}.get(r, 2) + 1):
+        plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
+        try:
+            lib.stencil_set_blocking(plan, 1)
+            lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
+            lib.stencil_set_blocking(plan, tb)
+            got = g.run(plan, g.to_dev(bits), steps, rows, cols, storage)
+            np.testing.assert_array_equal(g.to_host(got), ref, err_msg=f"tb {tb}")
+        finally:
+            lib.stencil_destroy(plan)
+
+
 def test_solve_until_converged(g):
     """Periodic convergence check: stops at the first check whose relative residual is <= tol, and
     the field equals a plain run of that many steps."""
