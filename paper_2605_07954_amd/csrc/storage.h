@@ -21,6 +21,15 @@ struct Fmt<ST_F32> {
     __device__ __forceinline__ static float rnd(float x) { return x; }
 };
 
+// Storing a 16-bit cell rounds the finished FP32 value (round to nearest even), i.e. two roundings
+// when the value is the result of an FMA.  Left alone, the compiler may fuse that last FMA with the
+// FP16 conversion into one mixed-precision FMA that rounds once, straight to FP16, which differs in
+// about one cell per thousand; the empty register constraint below keeps the FP32 value as written.
+__device__ __forceinline__ float as_fp32(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // bfloat16: the upper 16 bits of a binary32; widening is a shift, rounding is
 // gfx950's hardware convert (round to nearest even).
 template <>
@@ -29,7 +38,7 @@ struct Fmt<ST_BF16> {
     static constexpr int VEC = 8;
     __device__ __forceinline__ static float ld(T v) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ __forceinline__ static T st(float x) {
-        __bf16 h = (__bf16)x;
+        __bf16 h = (__bf16)as_fp32(x);
         return __builtin_bit_cast(uint16_t, h);
     }
     __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
@@ -42,7 +51,7 @@ struct Fmt<ST_F16> {
     static constexpr int VEC = 8;
     __device__ __forceinline__ static float ld(T v) { return (float)__builtin_bit_cast(_Float16, v); }
     __device__ __forceinline__ static T st(float x) {
-        _Float16 h = (_Float16)x;
+        _Float16 h = (_Float16)as_fp32(x);
         return __builtin_bit_cast(uint16_t, h);
     }
     __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
