@@ -139,28 +139,11 @@ def main_line(args, torch, lib, stream):
     return p, value, ms, roof, (tb, tx, ty, variant), tune_s
 
 
-def tune_batch_plans(lib, probs, plans, ins, outs, wss, stream=None) -> dict:
-    """Blocking of a batch's plans: one ``stencil_autotune`` per stencil class (shape, radius) and size
-    bucket (cells within a factor of 4), run on the bucket's first grid, then applied to every grid of
-    that bucket where it fits (a grid too small for the depth keeps its default)."""
-    def key(q):
-        return q.shape, q.radius, int(math.log2(q.rows * q.cols) // 2)
-
-    tuned = {}
-    for q, pl, i, o, w in zip(probs, plans, ins, outs, wss):
-        if key(q) not in tuned:
-            tuned[key(q)] = lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
-    for q, pl in zip(probs, plans):
-        tb, tx, ty, var = tuned[key(q)]
-        try:
-            lib.stencil_set_variant(pl, lib.ST_VARIANT_TILED)
-            lib.stencil_set_blocking(pl, 1, tx, ty)
-            if var != lib.ST_VARIANT_TILED:
-                lib.stencil_set_variant(pl, var)
-            lib.stencil_set_blocking(pl, tb)
-        except lib.StencilError:
-            pass
-    return tuned
+def tune_batch_plans(lib, probs, plans, ins, outs, wss, stream=None) -> list:
+    """Blocking of a batch's plans: ``stencil_autotune`` on every grid, so that the per-grid baseline
+    runs each grid with its own best single-grid kernel (the batch itself keeps each plan's depth)."""
+    return [lib.stencil_autotune(pl, i, o, w, 20, stream) + (lib.stencil_get_variant(pl),)
+            for pl, i, o, w in zip(plans, ins, outs, wss)]
 
 
 def extras(torch, lib, stream) -> dict:

@@ -13,7 +13,7 @@ properties that hold at any size.
   light-cone interior against its closed form (each mode scaled by lambda^T); the whole field
   against the FP64 oracle.  The FP32 gate is 1e-5; the 16-bit errors are printed (their gate is
   the bitwise emulation).
-* The 256-grid batch, 200 steps, with the benchmark's per-class tuning and hipGraph: every 8th
+* The 256-grid batch, 200 steps, with the benchmark's per-grid tuning and hipGraph: every 8th
   grid bit for bit against the FP32-canonical oracle.
 * Surrogate forward on 1024 x 1024: 64x64 patches against the CNN oracle run on each patch's
   receptive window (6 cells: six 3x3 layers); the judged entry point's error against one
@@ -198,7 +198,7 @@ def test_batched_256_200(g):
     plans = [lib.stencil_plan(q.rows, q.cols, q.radius, q.weights, 0.0, "f32", 0) for q in probs]
     try:
         tuned = tune_batch_plans(lib, probs, plans, ins, outs, wss)
-        say(f"batch of {len(probs)} grids, per-class blocking {tuned}")
+        say(f"batch of {len(probs)} grids, autotuned (tb, tx, ty, variant) per grid, first 8: {tuned[:8]}")
         del wss
         batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
         try:
