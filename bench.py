@@ -146,41 +146,57 @@ def tune_batch_plans(lib, probs, plans, ins, outs, wss, stream=None) -> list:
             for pl, i, o, w in zip(plans, ins, outs, wss)]
 
 
-def extras(torch, lib, stream) -> dict:
-    ex = {}
-    # heat 512^2, 100 steps (launch-bound, L2-resident)
+def _roofs(flop: float, bytes_per_update: float, gst: float) -> dict:
+    hbm = HBM_PEAK / bytes_per_update / 1e9
+    alu = VALU_FP32_PEAK / flop / 1e9
+    return {"alg_bytes_per_update": bytes_per_update, "hbm_roof_gstencil": hbm, "alu_roof_gstencil": alu,
+            "bound": "hbm" if hbm < alu else "alu", "frac_of_roof": gst / min(hbm, alu)}
+
+
+def extra_heat2d(torch, lib, stream) -> dict:
+    """Heat 512^2, 100 steps: L2-resident and launch-bound, so no roofline (the grid never leaves L2)."""
     p = wl.heat2d()
     x = torch.from_numpy(p.u0).to("cuda")
     out = torch.empty_like(x)
     ws = torch.empty_like(x)
     plan = lib.stencil_plan(p.rows, p.cols, 1, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
     tb, _, _ = lib.stencil_autotune(plan, x, out, ws, 20, stream)
+    var = lib.stencil_get_variant(plan)
     run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
     run()
     t = time_runs(run, 20, stream) / 20
-    ex["heat2d_512_100"] = {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "us": t * 1e6, "tb": tb}
     lib.stencil_destroy(plan)
-    # 16-bit storage: Star-2D9P 8192^2, 500 steps
+    return {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "us": t * 1e6, "tb": tb,
+            "variant": VARIANT_NAMES[var], "launches": math.ceil(p.steps / tb)}
+
+
+def extra_star9(torch, lib, stream) -> dict:
+    """Star-2D9P 8192^2, 500 steps, FP32 / BF16 / FP16 storage (17 FLOP per update)."""
     p = wl.star9_precision(rows=8192, cols=8192, steps=500)
     res = {}
     for st in ("f32", "bf16", "f16"):
-        if st == "f32":
-            xh = torch.from_numpy(p.u0).to("cuda")
-        else:
-            xh = torch.from_numpy(p.u0).to("cuda").to(torch.bfloat16 if st == "bf16" else torch.float16).view(torch.int16)
+        xh = torch.from_numpy(p.u0).to("cuda")
+        if st != "f32":
+            xh = xh.to(torch.bfloat16 if st == "bf16" else torch.float16).view(torch.int16)
         o = torch.empty_like(xh)
         w2 = torch.empty_like(xh)
         plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, st, 0)
         tb, _, _ = lib.stencil_autotune(plan, xh, o, w2, 20, stream)
+        var = lib.stencil_get_variant(plan)
         run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
         run()
-        t = time_runs(run, 2, stream) / 2
-        res[st] = {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "ms": t * 1e3, "tb": tb}
+        t = time_runs(run, 3, stream) / 3
+        gst = p.steps * p.rows * p.cols / t / 1e9
+        res[st] = {"gstencil_s": gst, "ms": t * 1e3, "tb": tb, "variant": VARIANT_NAMES[var],
+                   **_roofs(17.0, 2.0 * xh.element_size() / tb, gst)}
         lib.stencil_destroy(plan)
         del xh, o, w2
-    ex["star9_8192_500"] = res
     torch.cuda.empty_cache()
-    # batched: 256 grids, one graph launch vs per-grid launches
+    return res
+
+
+def extra_batched(torch, lib, stream) -> dict:
+    """256 grids, one hipGraph launch of the batched kernels vs per-grid launches (each grid autotuned)."""
     probs = wl.batch_problems()
     ins = [torch.from_numpy(q.u0).to("cuda") for q in probs]
     outs = [torch.empty_like(i) for i in ins]
@@ -190,21 +206,25 @@ def extras(torch, lib, stream) -> dict:
     per_grid = lambda: [lib.stencil_run(pl, i, o, q.steps, w, stream)  # noqa: E731
                         for q, pl, i, o, w in zip(probs, plans, ins, outs, wss)]
     per_grid()
-    t_per = time_runs(per_grid, 1, stream)
+    t_per = time_runs(per_grid, 3, stream) / 3
     batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
     bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
     runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
     runb()
-    t_b = time_runs(runb, 3, stream) / 3
+    t_b = time_runs(runb, 5, stream) / 5
     cells = sum(q.rows * q.cols * q.steps for q in probs)
-    ex["batched_256"] = {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "per_grid_ms": t_per * 1e3,
-                         "speedup_vs_per_grid": t_per / t_b}
     lib.stencil_batch_destroy(batch)
     for pl in plans:
         lib.stencil_destroy(pl)
     del ins, outs, wss, bws
     torch.cuda.empty_cache()
-    # surrogate inference vs 16 plain varcoef steps on 1024^2 (timing only; accuracy is in the tests)
+    return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "per_grid_ms": t_per * 1e3,
+            "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
+
+
+def extra_surrogate(torch, lib, stream) -> dict:
+    """Surrogate inference on 1024^2 (75,456 FLOP per cell on the MFMA path) vs the fastest plain 16
+    varcoef steps; timing only, the accuracy of a trained network is measured by the training driver."""
     u0, kap = wl.varcoef_problem(1024, 1024, seed=0)
     u = torch.from_numpy(u0).to("cuda")
     k = torch.from_numpy(kap).to("cuda")
@@ -229,11 +249,18 @@ def extras(torch, lib, stream) -> dict:
     run = lambda: lib.surrogate_forward(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
     run()
     ts = time_runs(run, 10, stream) / 10
-    ex["surrogate_1024_K16"] = {"plain_16_steps_us": best * 1e6, "cnn_infer_us": ts * 1e6,
-                                "speedup_vs_plain": best / ts, "cnn_tflops": 75456.0 * 1024 * 1024 / ts / 1e12}
     lib.surrogate_destroy(m)
     lib.stencil_destroy(vplan)
-    return ex
+    return {"plain_16_steps_us": best * 1e6, "cnn_infer_us": ts * 1e6, "speedup_vs_plain": best / ts,
+            "cnn_tflops": 75456.0 * 1024 * 1024 / ts / 1e12, "cnn_frac_of_bf16_mfma_peak": 75456.0 * 1024 * 1024 / ts / 2.5e15}
+
+
+EXTRAS = {"heat2d": ("heat2d_512_100", extra_heat2d), "star9": ("star9_8192_500", extra_star9),
+          "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate)}
+
+
+def extras(torch, lib, stream) -> dict:
+    return {key: fn(torch, lib, stream) for key, fn in EXTRAS.values()}
 
 
 def main():
@@ -246,6 +273,8 @@ def main():
     ap.add_argument("--tb", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=None)
     ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching")
+    ap.add_argument("--workload", default="box49", choices=["box49"] + sorted(EXTRAS),
+                    help="box49: the benchmark line; any other: only that workload's figures (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer once (reference for the HBM byte counters) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,6 +296,10 @@ def main():
         return
     import paper_2605_07954_amd as lib
     stream = torch.cuda.current_stream()
+    if args.workload != "box49":
+        key, fn = EXTRAS[args.workload]
+        print(json.dumps({"workload": key, **fn(torch, lib, stream)}), flush=True)
+        return
     p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)
     line = {"metric": "GStencil/s", "value": value, "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

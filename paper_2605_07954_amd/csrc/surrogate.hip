@@ -47,34 +47,48 @@ constexpr float KMID = 0.125f, KHALF = 0.075f;
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
-// GELU(z) = z Phi(z) with the normal CDF Phi(z) = (1 + erf(z / sqrt 2)) / 2, and GELU'(z) = Phi(z) +
-// z phi(z).  erf uses the rational approximation of Abramowitz & Stegun, Handbook of Mathematical
-// Functions, formula 7.1.26 (after Hastings): for x >= 0, 1 - erf(x) = (a1 t + a2 t^2 + a3 t^3 +
-// a4 t^4 + a5 t^5) exp(-x^2) with t = 1 / (1 + p x), absolute error <= 1.5e-7 -- four orders of
-// magnitude below the BF16 rounding every activation goes through next.  The same exp(-z^2 / 2)
-// serves phi(z), and Phi(z) of negative z comes out without cancellation.
+// GELU(z) = z Phi(z) with the normal CDF Phi(z) = erfc(-z / sqrt 2) / 2, and GELU'(z) = Phi(z) +
+// z phi(z).  erfc comes from the Chebyshev-fitted formula of Press, Teukolsky, Vetterling and
+// Flannery, Numerical Recipes (2nd ed.), Sec. 6.2: for x >= 0, erfc(x) = t exp(-x^2 + c0 + t (c1 +
+// t (c2 + ... + t c9))) with t = 1 / (1 + x / 2), fractional error below 1.2e-7 everywhere -- so
+// Phi(z) keeps its relative accuracy far into the negative tail, where GELU is small and its BF16
+// rounding is still done relative to its own size.
 struct NormalCdf {
     float cdf;  // Phi(z)
     float pdf;  // phi(z)
 };
 
-__device__ __forceinline__ NormalCdf normal_cdf(float z) {
-    constexpr float P = 0.3275911f;
-    constexpr float A1 = 0.254829592f, A2 = -0.284496736f, A3 = 1.421413741f, A4 = -1.453152027f,
-                    A5 = 1.061405429f;
-    constexpr float INV_SQRT2 = 0.70710678118654752f, INV_SQRT_2PI = 0.39894228040143268f;
-    constexpr float HALF_LOG2E = 0.72134752044448170f;  // log2(e) / 2
-    const float ax = fabsf(z) * INV_SQRT2;
-    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(P, ax, 1.0f));
-    const float poly = t * __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(__builtin_fmaf(A5, t, A4), t, A3), t, A2), t, A1);
-    const float e = __builtin_amdgcn_exp2f(-(z * z) * HALF_LOG2E);  // exp(-z^2 / 2) = exp(-x^2)
-    const float tail = 0.5f * poly * e;                                // 1 - Phi(|z|)
-    return {z >= 0.0f ? 1.0f - tail : tail, INV_SQRT_2PI * e};
+__device__ __forceinline__ float horner9(float t) {
+    constexpr float C1 = 1.00002368f, C2 = 0.37409196f, C3 = 0.09678418f, C4 = -0.18628806f, C5 = 0.27886807f,
+                    C6 = -1.13520398f, C7 = 1.48851587f, C8 = -0.82215223f, C9 = 0.17087277f;
+    float p = __builtin_fmaf(C9, t, C8);
+    p = __builtin_fmaf(p, t, C7);
+    p = __builtin_fmaf(p, t, C6);
+    p = __builtin_fmaf(p, t, C5);
+    p = __builtin_fmaf(p, t, C4);
+    p = __builtin_fmaf(p, t, C3);
+    p = __builtin_fmaf(p, t, C2);
+    return __builtin_fmaf(p, t, C1);
 }
 
-__device__ __forceinline__ float gelu(float z) { return z * normal_cdf(z).cdf; }
+template <bool WITH_PDF>
+__device__ __forceinline__ NormalCdf normal_cdf(float z) {
+    constexpr float C0 = -1.26551223f;
+    constexpr float INV_SQRT2 = 0.70710678118654752f, INV_SQRT_2PI = 0.39894228040143268f;
+    constexpr float LOG2E = 1.44269504088896341f;
+    const float x = fabsf(z) * INV_SQRT2;
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.5f, x, 1.0f));
+    const float arg = __builtin_fmaf(-x, x, __builtin_fmaf(horner9(t), t, C0));
+    const float tail = 0.5f * t * __builtin_amdgcn_exp2f(arg * LOG2E);  // erfc(x) / 2 = 1 - Phi(|z|)
+    NormalCdf r;
+    r.cdf = z >= 0.0f ? 1.0f - tail : tail;
+    r.pdf = WITH_PDF ? INV_SQRT_2PI * __builtin_amdgcn_exp2f(-(x * x) * LOG2E) : 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ float gelu(float z) { return z * normal_cdf<false>(z).cdf; }
 __device__ __forceinline__ float gelu_grad(float z) {
-    const NormalCdf n = normal_cdf(z);
+    const NormalCdf n = normal_cdf<true>(z);
     return __builtin_fmaf(z, n.pdf, n.cdf);
 }
 
