@@ -209,6 +209,7 @@ def extra_batched(torch, lib, stream) -> dict:
     t_per = time_runs(per_grid, 3, stream) / 3
     batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
     bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+    caps = lib.stencil_batch_autotune(batch, ins, outs, bws, stream)
     runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
     runb()
     t_b = time_runs(runb, 5, stream) / 5
@@ -218,7 +219,8 @@ def extra_batched(torch, lib, stream) -> dict:
         lib.stencil_destroy(pl)
     del ins, outs, wss, bws
     torch.cuda.empty_cache()
-    return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "per_grid_ms": t_per * 1e3,
+    return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "depth_caps": {f"{k[0]}{k[1]}": v for k, v in caps.items()},
+            "per_grid_ms": t_per * 1e3,
             "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
 
 
@@ -246,7 +248,7 @@ def extra_surrogate(torch, lib, stream) -> dict:
     pd = torch.from_numpy(init_params(0)).to("cuda")  # timing only: the weights' values do not matter
     sws = torch.empty(lib.surrogate_workspace_bytes(m, 1, 1024, 1024), dtype=torch.uint8, device="cuda")
     uh = torch.empty((1, 1024, 1024), device="cuda")
-    run = lambda: lib.surrogate_forward(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
+    run = lambda: lib.surrogate_infer(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
     run()
     ts = time_runs(run, 10, stream) / 10
     lib.surrogate_destroy(m)

@@ -200,7 +200,7 @@ int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, i
 int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int64_t* steps, uint32_t flags);
 
 /* stencil_batch_workspace_bytes -- workspace for the batch: descriptor and queue tables and
- * one ping-pong field per grid that takes two or more passes. */
+ * one ping-pong field per tiled grid with two or more steps. */
 int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
 
 /* stencil_run_batched -- outs[g] = S_g^{steps[g]}(ins[g]) for every grid g.
@@ -208,6 +208,16 @@ int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
  * bitwise those of stencil_run on each grid.  Asynchronous on `stream`. */
 int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
                         size_t ws_bytes, void* stream);
+
+/* stencil_batch_autotune -- pick the temporal depth of the batch's tiled grids: for each stencil
+ * class (shape, radius) in turn, run the whole batch with the class's depth capped at 1, 2, 3, 4,
+ * 6, 8, 12 and 16 passes' worth of steps (each grid also capped by what its 128 x 64 tile fits in
+ * LDS), keep the fastest cap, then tune the next class.  Runs the batch twice per candidate on
+ * the caller's buffers (outs are overwritten; results are bitwise those of any other depth).
+ * Writes the chosen cap per class to tb_out[6] when non-NULL (star r = 1, 2, 3, then box r = 1,
+ * 2, 3; 0 = class absent).  Synchronises the stream.  Errors: as stencil_run_batched. */
+int stencil_batch_autotune(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
+                           size_t ws_bytes, int* tb_out, void* stream);
 
 /* stencil_batch_destroy -- free the batch (graph, pinned table).  NULL is a no-op. */
 int stencil_batch_destroy(st_batch* batch);
@@ -232,10 +242,10 @@ int surrogate_destroy(sg_model* m);
  * of rows x cols: activations, pre-activations, gradients and partial sums. */
 int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_t cols, size_t* bytes);
 
-/* surrogate_forward -- u_hat[b] = surrogate(u0[b], kappa[b]) for `batch`
+/* surrogate_infer -- u_hat[b] = surrogate(u0[b], kappa[b]) for `batch`
  * fields of rows x cols (device FP32, contiguous one after another).
  * Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
-int surrogate_forward(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat,
+int surrogate_infer(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat,
                       int batch, int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream);
 
 /* surrogate_loss_grad -- forward, masked MSE loss against `target`, and the
@@ -267,6 +277,37 @@ int surrogate_synth_fields(const float* coef, int n, int64_t rows, int64_t cols,
  * int32 pairs) from fields of rows x cols: src -> dst.  Asynchronous. */
 int surrogate_crop(const float* src, float* dst, const int* yx, int n, int64_t rows, int64_t cols,
                    int64_t h, int64_t w, void* stream);
+
+/* surrogate_train -- the whole training loop on the device: the network learns to replace K
+ * plain steps of the variable-coefficient heat stencil on trajectories that stencil generates.
+ * For optimiser step s = 0 .. cfg->steps-1 and trajectory b = 0 .. cfg->batch-1 (index
+ * i = s*batch + b):
+ *   1. (u0, kappa) of rows x cols from coefficient row coef[i] (as surrogate_synth_fields);
+ *   2. the target u_K = K steps of the plain varcoef stencil from u0 (an internal varcoef plan);
+ *   3. crop x crop windows of u0, kappa and u_K at crop_yx[2i], crop_yx[2i+1] (row, col);
+ *   4. masked MSE loss and gradient on the crops (surrogate_loss_grad); the mask drops the 6 cells
+ *      next to a crop edge that cuts the grid (the network's receptive field), keeps domain edges;
+ *      the step's loss goes to losses[s] (device doubles);
+ *   5. one Adam step with t = step0 + s + 1 and the cosine schedule
+ *      lr_s = lr (1 + cos(pi (step0 + s) / total_steps)) / 2.
+ * The random numbers (coefficients, crop offsets) are inputs, and every reduction has a fixed
+ * order, so training is deterministic: steps [0, a) then [a, n) in two calls (step0 = a in the
+ * second) give bitwise the same params, optim and losses as one call over [0, n).
+ * coef: device FP32, steps*batch rows of 96; crop_yx: HOST int32, 2*steps*batch.  Asynchronous
+ * (the host only enqueues).  Errors: ST_EINVAL (bad config or offsets), ST_ENOWS, ST_EHIP. */
+typedef struct sg_train_cfg {
+    int64_t rows, cols;   /* trajectory grid */
+    int64_t crop;         /* square crop side, <= rows and cols */
+    int batch;            /* trajectories per optimiser step, 1 .. 64 */
+    int K;                /* plain steps the network replaces, >= 1 */
+    int64_t steps;        /* optimiser steps in this call */
+    int64_t step0;        /* global index of the first of them */
+    int64_t total_steps;  /* length of the cosine schedule, >= step0 + steps */
+    float lr, beta1, beta2, eps;
+} sg_train_cfg;
+int surrogate_train_ws_bytes(const sg_model* m, const sg_train_cfg* cfg, size_t* bytes);
+int surrogate_train(sg_model* m, float* params, float* optim, const float* coef, const int* crop_yx,
+                    const sg_train_cfg* cfg, double* losses, void* workspace, size_t ws_bytes, void* stream);
 
 /* surrogate_infer_checked -- the surrogate with the plain stencil as judge and
  * fallback: computes u_hat = surrogate(u0, kappa), then the judge plan

@@ -64,15 +64,18 @@ _SIGS = {
     "stencil_batch_workspace_bytes": [_p, ctypes.POINTER(_sz)],
     "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
     "stencil_batch_destroy": [_p],
+    "stencil_batch_autotune": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, ctypes.POINTER(_int), _p],
     "surrogate_create": [ctypes.POINTER(_p), _u32],
     "surrogate_destroy": [_p],
     "surrogate_workspace_bytes": [_p, _int, _i64, _i64, ctypes.POINTER(_sz)],
-    "surrogate_forward": [_p, _p, _p, _p, _p, _int, _i64, _i64, _p, _sz, _p],
+    "surrogate_infer": [_p, _p, _p, _p, _p, _int, _i64, _i64, _p, _sz, _p],
     "surrogate_loss_grad": [_p, _p, _p, _p, _p, _p, _int, _i64, _i64, _p, _p, _p, _sz, _p],
     "surrogate_adam": [_p, _p, _p, _p, _int, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _p],
     "surrogate_synth_fields": [_p, _int, _i64, _i64, _p, _p, _p],
     "surrogate_crop": [_p, _p, _p, _int, _i64, _i64, _i64, _i64, _p],
     "surrogate_checked_ws_bytes": [_p, _i64, _i64, ctypes.POINTER(_sz)],
+    "surrogate_train_ws_bytes": [_p, _p, ctypes.POINTER(_sz)],
+    "surrogate_train": [_p, _p, _p, _p, _p, _p, _p, _p, _sz, _p],
     "surrogate_infer_checked": [_p, _p, _p, _p, _p, _i64, _i64, _p, _i64, ctypes.c_double,
                                 ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _p, _sz, _p],
     "stencil_strerror": [_int],
@@ -281,6 +284,18 @@ def stencil_run_batched(batch, ins, outs, workspace, stream=None) -> None:
                                   _stream(stream)), "stencil_run_batched")
 
 
+def stencil_batch_autotune(batch, ins, outs, workspace, stream=None) -> dict:
+    """Returns the chosen depth cap per stencil class present: {("star", 1): 8, ("box", 1): 4, ...}."""
+    n = len(ins)
+    pi = (_p * n)(*[_dptr(t, "in").value for t in ins])
+    po = (_p * n)(*[_dptr(t, "out").value for t in outs])
+    caps = (_int * 6)()
+    _ck(lib().stencil_batch_autotune(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace), caps,
+                                     _stream(stream)), "stencil_batch_autotune")
+    names = [("star", 1), ("star", 2), ("star", 3), ("box", 1), ("box", 2), ("box", 3)]
+    return {names[k]: caps[k] for k in range(6) if caps[k]}
+
+
 def stencil_batch_destroy(batch) -> None:
     _ck(lib().stencil_batch_destroy(batch), "stencil_batch_destroy")
 
@@ -288,6 +303,36 @@ def stencil_batch_destroy(batch) -> None:
 # ---------------------------------------------------------------------------
 # surrogate
 # ---------------------------------------------------------------------------
+
+class SgTrainCfg(ctypes.Structure):
+    """Mirror of ``sg_train_cfg``."""
+    _fields_ = [("rows", _i64), ("cols", _i64), ("crop", _i64), ("batch", _int), ("K", _int), ("steps", _i64),
+                ("step0", _i64), ("total_steps", _i64), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+def _train_cfg(rows, cols, crop, batch, K, steps, step0, total_steps, lr, beta1, beta2, eps) -> SgTrainCfg:
+    return SgTrainCfg(rows, cols, crop, batch, K, steps, step0, total_steps, lr, beta1, beta2, eps)
+
+
+def surrogate_train_ws_bytes(model, rows: int, cols: int, crop: int, batch: int, K: int, steps: int) -> int:
+    cfg = _train_cfg(rows, cols, crop, batch, K, steps, 0, max(steps, 1), 1e-3, 0.9, 0.999, 1e-8)
+    n = _sz()
+    _ck(lib().surrogate_train_ws_bytes(model, ctypes.byref(cfg), ctypes.byref(n)), "surrogate_train_ws_bytes")
+    return n.value
+
+
+def surrogate_train(model, params, optim, coef, crop_yx, losses, workspace, rows: int, cols: int, crop: int,
+                    batch: int, K: int, steps: int, step0: int, total_steps: int, lr: float, beta1: float = 0.9,
+                    beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    """crop_yx: host int32 array of 2*steps*batch offsets; coef, losses: device tensors."""
+    yx = np.ascontiguousarray(np.asarray(crop_yx, dtype=np.int32).reshape(-1))
+    if yx.size != 2 * steps * batch:
+        raise ValueError("crop_yx must hold 2 * steps * batch offsets")
+    cfg = _train_cfg(rows, cols, crop, batch, K, steps, step0, total_steps, lr, beta1, beta2, eps)
+    _ck(lib().surrogate_train(model, _dptr(params, "params"), _dptr(optim, "optim"), _dptr(coef, "coef"),
+                              yx.ctypes.data_as(_p), ctypes.byref(cfg), _dptr(losses, "losses"),
+                              _dptr(workspace, "workspace"), _nbytes(workspace), _stream(stream)), "surrogate_train")
 
 def surrogate_create(flags: int = 0):
     h = _p()
@@ -305,11 +350,11 @@ def surrogate_workspace_bytes(model, batch: int, rows: int, cols: int) -> int:
     return n.value
 
 
-def surrogate_forward(model, params, u0, kappa, u_hat, batch: int, rows: int, cols: int, workspace,
+def surrogate_infer(model, params, u0, kappa, u_hat, batch: int, rows: int, cols: int, workspace,
                       stream=None) -> None:
-    _ck(lib().surrogate_forward(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
+    _ck(lib().surrogate_infer(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
                                 _dptr(u_hat, "u_hat"), batch, rows, cols, _dptr(workspace, "workspace"),
-                                _nbytes(workspace), _stream(stream)), "surrogate_forward")
+                                _nbytes(workspace), _stream(stream)), "surrogate_infer")
 
 
 def surrogate_loss_grad(model, params, u0, kappa, target, lo_hi, batch: int, rows: int, cols: int, grad, loss,

@@ -136,6 +136,8 @@ struct st_batch {
     std::vector<int> res;              // LDS-resident grids
     std::vector<int> zero_steps;       // grids with steps == 0 (copied, not computed)
     std::vector<int> active;           // active[p]: tiled grids with more than p passes
+    std::vector<int> tiled;            // tiled grids, in input order
+    std::vector<int> tb_max;           // per grid: deepest pass the batch tile's LDS budget allows
     int max_passes;
     size_t off_desc, off_tprefix, off_order, off_res, off_fields, ws_bytes;
     std::vector<size_t> field_off;     // per grid: workspace offset of its ping-pong field (0 = none)
@@ -160,6 +162,31 @@ size_t batch_lds_budget() { return std::min<size_t>(80 * 1024, lds_limit()); }
 
 }  // namespace
 
+// Pass structure of the tiled grids from their current depths: passes per grid, the queue order
+// (by pass count, descending, so that the grids still active at pass p are a prefix), the tile
+// prefix sums over that order and the LDS of the deepest pass.
+static void build_passes(st_batch* B) {
+    std::vector<int> order = B->tiled;
+    size_t lds = 0;
+    for (int g : order) {
+        BatchDesc& d = B->desc[g];
+        d.passes = (d.steps + d.tb - 1) / d.tb;
+        lds = std::max(lds, tiled_lds_bytes(d.r, d.tb, kTX, kTY));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->desc[a].passes > B->desc[b].passes; });
+    B->order = order;
+    B->tile_prefix.assign(1, 0);
+    for (int g : order) B->tile_prefix.push_back(B->tile_prefix.back() + B->desc[g].tiles_x * B->desc[g].tiles_y);
+    B->max_passes = order.empty() ? 0 : B->desc[order[0]].passes;
+    B->active.clear();
+    for (int p = 0; p < B->max_passes; ++p) {
+        int a = 0;
+        while (a < int(order.size()) && B->desc[order[a]].passes > p) ++a;
+        B->active.push_back(a);
+    }
+    B->lds_pass = lds;
+}
+
 extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int64_t* steps,
                                     uint32_t flags) {
     if (!out) return fail(ST_EINVAL, "out is NULL");
@@ -172,8 +199,9 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->flags = flags;
     B->desc.resize(n);
     B->field_off.assign(n, 0);
+    B->tb_max.assign(n, 0);
     std::vector<int> tiled;
-    size_t lds_pass = 0, lds_res = 0;
+    size_t lds_res = 0;
     for (int g = 0; g < n; ++g) {
         const st_plan* p = plans[g];
         if (!p || p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3 || steps[g] < 0 ||
@@ -203,28 +231,19 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
             B->res.push_back(g);
             continue;
         }
-        // the plan's temporal depth, lowered until the batch tile fits the LDS budget
-        int tb = std::max(1, p->tb);
-        while (tb > 1 && tiled_lds_bytes(p->radius, tb, kTX, kTY) > batch_lds_budget()) --tb;
-        d.tb = tb;
+        // deepest pass the batch tile allows; the plan's depth, capped by it, is the starting point
+        int tbm = 16;
+        while (tbm > 1 && tiled_lds_bytes(p->radius, tbm, kTX, kTY) > batch_lds_budget()) --tbm;
+        B->tb_max[g] = tbm;
+        d.tb = std::min(std::max(1, p->tb), tbm);
         d.tiles_x = (p->cols + kTX - 1) / kTX;
         d.tiles_y = (p->rows + kTY - 1) / kTY;
-        d.passes = (d.steps + tb - 1) / tb;
-        lds_pass = std::max(lds_pass, tiled_lds_bytes(p->radius, tb, kTX, kTY));
         tiled.push_back(g);
     }
-    std::stable_sort(tiled.begin(), tiled.end(),
-                     [&](int a, int b) { return B->desc[a].passes > B->desc[b].passes; });
-    B->order = tiled;
-    B->tile_prefix.assign(1, 0);
-    for (int g : tiled) B->tile_prefix.push_back(B->tile_prefix.back() + B->desc[g].tiles_x * B->desc[g].tiles_y);
-    B->max_passes = tiled.empty() ? 0 : B->desc[tiled[0]].passes;
-    for (int p = 0; p < B->max_passes; ++p) {
-        int a = 0;
-        while (a < int(tiled.size()) && B->desc[tiled[a]].passes > p) ++a;
-        B->active.push_back(a);
-    }
-    // workspace: descriptor table, queue tables, one ping-pong field per multi-pass grid
+    B->tiled = tiled;
+    build_passes(B);
+    // workspace: descriptor table, queue tables, one ping-pong field per tiled grid with two or more
+    // steps (any depth the autotuner may pick below the step count needs it)
     size_t off = 0;
     B->off_desc = off;
     off = align256(off + size_t(n) * sizeof(BatchDesc));
@@ -236,13 +255,12 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     off = align256(off + std::max<size_t>(B->res.size(), 1) * sizeof(int));
     B->off_fields = off;
     for (int g : tiled) {
-        if (B->desc[g].passes >= 2) {
+        if (B->desc[g].steps >= 2) {
             B->field_off[g] = off;
             off = align256(off + size_t(B->desc[g].rows * B->desc[g].cols) * sizeof(float));
         }
     }
     B->ws_bytes = std::max<size_t>(off, 256);
-    B->lds_pass = lds_pass;
     B->lds_res = lds_res;
     B->pinned = nullptr;
     B->pinned_bytes = B->off_fields - B->off_desc;
@@ -395,4 +413,73 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
     }
     ST_HIP_CHECK(hipGraphLaunch(B->exec, s));
     return ST_OK;
+}
+
+// Coordinate descent over the stencil classes (shape, radius) of the tiled grids: for each class
+// in turn, time the whole batch (direct launches) with the class's depth capped at each candidate,
+// keep the fastest, then move to the next class.
+extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void* const* outs, void* workspace,
+                                      size_t ws_bytes, int* tb_out, void* stream) {
+    if (!B || !ins || !outs) return fail(ST_EINVAL, "NULL argument");
+    if (!workspace || ws_bytes < B->ws_bytes) return fail(ST_ENOWS, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (tb_out) std::fill(tb_out, tb_out + 6, 0);
+    const uint32_t flags = B->flags;
+    B->flags &= ~ST_FLAG_GRAPH;
+    std::vector<int> classes;  // shape * 8 + r
+    for (int g : B->tiled) {
+        const int c = B->desc[g].shape * 8 + B->desc[g].r;
+        if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ST_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(ST_EHIP, "hipEventCreate");
+    static const int kCaps[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    auto apply = [&](int cls, int cap) {
+        for (int g : B->tiled)
+            if (B->desc[g].shape * 8 + B->desc[g].r == cls) B->desc[g].tb = std::min(cap, B->tb_max[g]);
+        build_passes(B);
+        B->staged_valid = false;  // descriptor tables changed
+    };
+    auto timed = [&](float* ms) -> int {
+        for (int rep = 0; rep < 2; ++rep) {  // the first run warms up and stages the tables
+            if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) return fail(ST_EHIP, "hipEventRecord");
+            if (int r = stencil_run_batched(B, ins, outs, workspace, ws_bytes, stream)) return r;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(ST_EHIP, "hipEventRecord/Synchronize");
+        return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? ST_OK : fail(ST_EHIP, "hipEventElapsedTime");
+    };
+    for (int cls : classes) {
+        if (rc) break;
+        int deepest = 1;
+        for (int g : B->tiled)
+            if (B->desc[g].shape * 8 + B->desc[g].r == cls) deepest = std::max(deepest, B->tb_max[g]);
+        int best_cap = 0;
+        float best = 1e30f;
+        for (int cap : kCaps) {
+            if (cap > deepest) break;
+            apply(cls, cap);
+            float ms = 0.0f;
+            if ((rc = timed(&ms))) break;
+            if (ms < best) {
+                best = ms;
+                best_cap = cap;
+            }
+        }
+        if (!rc && best_cap) apply(cls, best_cap);
+        if (tb_out && !rc) {
+            // report the cap chosen for each class in class order: star r=1..3 then box r=1..3
+            const int slot = (cls / 8) * 3 + (cls % 8) - 1;
+            if (slot >= 0 && slot < 6) tb_out[slot] = best_cap;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    B->flags = flags;
+    if (B->exec) {  // the captured graph holds the old pass structure
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    return rc;
 }

@@ -780,7 +780,7 @@ int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_
     return ST_OK;
 }
 
-int surrogate_forward(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat, int batch,
+int surrogate_infer(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat, int batch,
                       int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream) {
     if (!m || !params || !u0 || !kappa || !u_hat) return fail(ST_EINVAL, "NULL argument");
     if (int rc = check_dims(batch, rows, cols)) return rc;
@@ -915,6 +915,119 @@ int surrogate_checked_ws_bytes(const sg_model* m, int64_t rows, int64_t cols, si
     const size_t field = a256(size_t(rows * cols) * 4);
     *bytes = layout(1, rows, cols, false).total + 3 * field + a256(1024 * 16) + 256;
     return ST_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int COEF_ROW = 4 * (16 + 8);  // floats per trajectory's coefficient row
+constexpr int RFIELD = 6;               // receptive-field radius of six 3x3 layers
+
+struct TrainWs {
+    size_t u0, kp, uk, cu0, ckp, cuk, grad, jws, yx, sg, total;
+    size_t field, crop, jws_bytes;
+};
+
+int train_layout(const sg_train_cfg* c, TrainWs* T) {
+    if (!c) return fail(ST_EINVAL, "cfg is NULL");
+    if (c->rows < 1 || c->cols < 1 || c->crop < 1 || c->crop > c->rows || c->crop > c->cols || c->batch < 1 ||
+        c->batch > MAXB || c->K < 1 || c->steps < 0 || c->step0 < 0 || c->total_steps < c->step0 + c->steps ||
+        !(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f) ||
+        !(c->eps > 0.0f))
+        return fail(ST_EINVAL, "bad training configuration");
+    if (int rc = check_dims(c->batch, c->rows, c->cols)) return rc;
+    const int64_t B = c->batch;
+    T->field = a256(size_t(B * c->rows * c->cols) * 4);
+    T->crop = a256(size_t(B * c->crop * c->crop) * 4);
+    T->jws_bytes = a256(size_t(c->rows * c->cols) * 4);
+    size_t off = 0;
+    T->u0 = off; off += T->field;
+    T->kp = off; off += T->field;
+    T->uk = off; off += T->field;
+    T->cu0 = off; off += T->crop;
+    T->ckp = off; off += T->crop;
+    T->cuk = off; off += T->crop;
+    T->grad = off; off += a256(size_t(SG_PARAM_COUNT) * 4);
+    T->jws = off; off += T->jws_bytes;
+    T->yx = off; off += a256(size_t(std::max<int64_t>(c->steps, 1) * B) * 8);
+    T->sg = off; off += layout(c->batch, c->crop, c->crop, true).total;
+    T->total = off;
+    return ST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int surrogate_train_ws_bytes(const sg_model* m, const sg_train_cfg* cfg, size_t* bytes) {
+    if (!m || !bytes) return fail(ST_EINVAL, "NULL argument");
+    TrainWs T;
+    if (int rc = train_layout(cfg, &T)) return rc;
+    *bytes = T.total;
+    return ST_OK;
+}
+
+int surrogate_train(sg_model* m, float* params, float* optim, const float* coef, const int* crop_yx,
+                    const sg_train_cfg* cfg, double* losses, void* workspace, size_t ws_bytes, void* stream) {
+    if (!m || !params || !optim || !coef || !crop_yx || !losses) return fail(ST_EINVAL, "NULL argument");
+    TrainWs T;
+    if (int rc = train_layout(cfg, &T)) return rc;
+    if (!workspace || ws_bytes < T.total) return fail(ST_ENOWS, "workspace too small");
+    const sg_train_cfg c = *cfg;
+    const int B = c.batch;
+    const int64_t n = c.steps * B;
+    for (int64_t i = 0; i < n; ++i) {
+        const int y = crop_yx[2 * i], x = crop_yx[2 * i + 1];
+        if (y < 0 || x < 0 || y + c.crop > c.rows || x + c.crop > c.cols) return fail(ST_EINVAL, "crop outside the grid");
+    }
+    if (c.steps == 0) return ST_OK;
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* U0 = reinterpret_cast<float*>(ws + T.u0);
+    float* KP = reinterpret_cast<float*>(ws + T.kp);
+    float* UK = reinterpret_cast<float*>(ws + T.uk);
+    float* cu0 = reinterpret_cast<float*>(ws + T.cu0);
+    float* ckp = reinterpret_cast<float*>(ws + T.ckp);
+    float* cuk = reinterpret_cast<float*>(ws + T.cuk);
+    float* grad = reinterpret_cast<float*>(ws + T.grad);
+    int* yx = reinterpret_cast<int*>(ws + T.yx);
+    ST_HIP_CHECK(hipMemcpyAsync(yx, crop_yx, size_t(n) * 8, hipMemcpyHostToDevice, s));
+    // the judge: the plain stencil, as deep per pass as this device's LDS allows
+    st_plan* judge = nullptr;
+    if (int rc = stencil_plan_varcoef(&judge, c.rows, c.cols, 0.0, 0)) return rc;
+    for (int tb : {8, 4, 2, 1})
+        if (stencil_set_blocking(judge, tb, 0, 0) == ST_OK) break;
+    int rc = ST_OK;
+    const int64_t field = c.rows * c.cols;
+    for (int64_t st = 0; st < c.steps && rc == ST_OK; ++st) {
+        if ((rc = surrogate_synth_fields(coef + st * B * COEF_ROW, B, c.rows, c.cols, U0, KP, stream))) break;
+        for (int b = 0; b < B && rc == ST_OK; ++b)
+            rc = stencil_run_varcoef(judge, U0 + b * field, KP + b * field, UK + b * field, c.K, ws + T.jws,
+                                     T.jws_bytes, stream);
+        if (rc) break;
+        const int* yx_s = yx + 2 * st * B;
+        if ((rc = surrogate_crop(U0, cu0, yx_s, B, c.rows, c.cols, c.crop, c.crop, stream))) break;
+        if ((rc = surrogate_crop(KP, ckp, yx_s, B, c.rows, c.cols, c.crop, c.crop, stream))) break;
+        if ((rc = surrogate_crop(UK, cuk, yx_s, B, c.rows, c.cols, c.crop, c.crop, stream))) break;
+        int lohi[4 * MAXB];
+        for (int b = 0; b < B; ++b) {
+            const int y = crop_yx[2 * (st * B + b)], x = crop_yx[2 * (st * B + b) + 1];
+            lohi[4 * b] = y > 0 ? RFIELD : 0;
+            lohi[4 * b + 1] = int(c.crop) - (y + c.crop < c.rows ? RFIELD : 0);
+            lohi[4 * b + 2] = x > 0 ? RFIELD : 0;
+            lohi[4 * b + 3] = int(c.crop) - (x + c.crop < c.cols ? RFIELD : 0);
+        }
+        if ((rc = surrogate_loss_grad(m, params, cu0, ckp, cuk, lohi, B, c.crop, c.crop, grad, losses + st, ws + T.sg,
+                                      ws_bytes - T.sg, stream)))
+            break;
+        const int64_t g = c.step0 + st;
+        const double lr = double(c.lr) * 0.5 * (1.0 + std::cos(3.14159265358979323846 * double(g) / double(c.total_steps)));
+        rc = surrogate_adam(m, params, grad, optim, int(g + 1), float(lr), c.beta1, c.beta2, c.eps, stream);
+    }
+    // the judge's kernels are enqueued: destroying the host-side plan does not wait for them
+    stencil_destroy(judge);
+    return rc;
 }
 
 int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, const float* kappa, float* out,

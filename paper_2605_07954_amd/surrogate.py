@@ -1,11 +1,12 @@
 """Training and evaluation driver of the CNN surrogate.
 
-Host-side sequencing only: every arithmetic step runs in the library's kernels (field synthesis,
-the plain variable-coefficient stencil that generates the targets, crops, the MFMA forward and
-backward passes, Adam).  The host draws the random numbers -- field coefficients and crop
-offsets -- and passes them in.
+Host-side sequencing only: training is one C-ABI call per chunk of optimiser steps
+(``surrogate_train``: field synthesis, the plain variable-coefficient stencil that generates the
+targets, crops, the MFMA forward and backward passes and Adam all run in the library's kernels),
+and evaluation is ``surrogate_infer_checked``, whose judge is the plain stencil.  The host draws
+the random numbers -- field coefficients and crop offsets -- and passes them in.
 
-One training step on a batch of B trajectories:
+One optimiser step on a batch of B trajectories:
   1. synthesise (u0, kappa) on the full grid from per-trajectory coefficient rows;
   2. target u_K = K plain steps of the varcoef stencil (the generator is the method itself);
   3. crop a random window of each field (u0, kappa, u_K);
@@ -13,9 +14,6 @@ One training step on a batch of B trajectories:
   5. Adam step with a cosine learning-rate schedule.
 Cells closer than the receptive-field radius (6) to a crop edge that is not a grid edge are left
 out of the loss: their true inputs lie outside the crop.
-
-The plain stencil stays the judge: ``evaluate`` reports the held-out rel-L2 of the surrogate
-against K plain steps, and ``surrogate_infer_checked`` (C ABI) falls back to the plain result.
 """
 from __future__ import annotations
 
@@ -26,13 +24,11 @@ import time
 
 import numpy as np
 
-from . import (SG_PARAM_COUNT, ST_FLAG_GRAPH, stencil_destroy, stencil_plan_varcoef, stencil_run_varcoef,
-               stencil_set_blocking, stencil_workspace_bytes, surrogate_adam, surrogate_create, surrogate_crop,
-               surrogate_destroy, surrogate_forward, surrogate_loss_grad, surrogate_synth_fields,
-               surrogate_workspace_bytes)
+from . import (SG_PARAM_COUNT, stencil_destroy, stencil_plan_varcoef, stencil_set_blocking, surrogate_checked_ws_bytes,
+               surrogate_create, surrogate_destroy, surrogate_infer_checked, surrogate_synth_fields, surrogate_train,
+               surrogate_train_ws_bytes)
 
 CHANNELS = (2, 32, 32, 32, 32, 32, 1)
-RF = 6  # receptive-field radius of six 3x3 layers
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -50,102 +46,84 @@ def init_params(seed: int) -> np.ndarray:
     return v
 
 
-def crop_lohi(y0: int, x0: int, crop: int, grid: int) -> list[int]:
-    return [RF if y0 > 0 else 0, crop - (RF if y0 + crop < grid else 0),
-            RF if x0 > 0 else 0, crop - (RF if x0 + crop < grid else 0)]
-
-
 class Trainer:
     def __init__(self, grid: int = 1024, crop: int = 256, batch: int = 8, K: int = 16, seed: int = 0,
-                 device: str = "cuda"):
+                 device: str = "cuda", chunk: int = 50):
         import torch
         self.torch = torch
-        self.grid, self.crop, self.batch, self.K, self.seed = grid, crop, batch, K, seed
-        dev = self.dev = device
-        f32 = torch.float32
+        self.grid, self.crop, self.batch, self.K, self.seed, self.chunk = grid, crop, batch, K, seed, chunk
+        self.dev = device
         self.model = surrogate_create()
-        self.judge = stencil_plan_varcoef(grid, grid, 0.0, ST_FLAG_GRAPH)
-        for tb in (8, 4, 2, 1):
-            try:
-                stencil_set_blocking(self.judge, tb)
-                break
-            except Exception:  # noqa: BLE001 - deeper blocks may not fit this device's LDS
-                continue
-        self.U0 = torch.empty((batch, grid, grid), dtype=f32, device=dev)
-        self.KP = torch.empty_like(self.U0)
-        self.UK = torch.empty_like(self.U0)
-        self.jws = torch.empty(max(stencil_workspace_bytes(self.judge, K), 4), dtype=torch.uint8, device=dev)
-        self.cu0 = torch.empty((batch, crop, crop), dtype=f32, device=dev)
-        self.ckp = torch.empty_like(self.cu0)
-        self.cuk = torch.empty_like(self.cu0)
-        self.ws = torch.empty(surrogate_workspace_bytes(self.model, batch, crop, crop), dtype=torch.uint8,
-                              device=dev)
-        self.params = torch.from_numpy(init_params(seed)).to(dev)
-        self.grad = torch.zeros(SG_PARAM_COUNT, dtype=f32, device=dev)
-        self.optim = torch.zeros(2 * SG_PARAM_COUNT, dtype=f32, device=dev)
-        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.t = 0
+        self.params = torch.from_numpy(init_params(seed)).to(device)
+        self.optim = torch.zeros(2 * SG_PARAM_COUNT, dtype=torch.float32, device=device)
+        self.ws = torch.empty(surrogate_train_ws_bytes(self.model, grid, grid, crop, batch, K, chunk),
+                              dtype=torch.uint8, device=device)
+        self.rng = np.random.default_rng(seed + 12345)
+        self.judge = None
 
     def close(self):
-        stencil_destroy(self.judge)
+        if self.judge is not None:
+            stencil_destroy(self.judge)
         surrogate_destroy(self.model)
 
-    def make_targets(self, coef: np.ndarray):
-        """Synthesise B trajectories' (u0, kappa) on the full grid and advance them K plain steps."""
-        torch = self.torch
-        n = coef.shape[0]
-        surrogate_synth_fields(torch.from_numpy(np.ascontiguousarray(coef, np.float32)).to(self.dev), n,
-                               self.grid, self.grid, self.U0, self.KP)
-        for b in range(n):
-            stencil_run_varcoef(self.judge, self.U0[b], self.KP[b], self.UK[b], self.K, self.jws)
+    def draws(self, k0: int, n: int):
+        """Coefficient rows and crop offsets of optimiser steps k0 .. k0+n-1 (host random numbers)."""
+        coef = np.concatenate([_coefficients(self.batch, 100_000 + self.seed * 1_000_003 + k) for k in range(k0, k0 + n)])
+        yx = self.rng.integers(0, self.grid - self.crop + 1, size=(n * self.batch, 2)).astype(np.int32)
+        return coef, yx
 
-    def step(self, coef: np.ndarray, offsets: np.ndarray, lr: float) -> None:
+    def train(self, n_traj: int, lr: float = 1e-3, log_every: int | None = None, log=print):
         torch = self.torch
-        self.make_targets(coef)
-        yx = torch.from_numpy(np.ascontiguousarray(offsets, np.int32)).to(self.dev)
-        B, G, C = self.batch, self.grid, self.crop
-        for src, dst in ((self.U0, self.cu0), (self.KP, self.ckp), (self.UK, self.cuk)):
-            surrogate_crop(src, dst, yx, B, G, G, C, C)
-        lohi = [v for (y0, x0) in offsets for v in crop_lohi(int(y0), int(x0), C, G)]
-        surrogate_loss_grad(self.model, self.params, self.cu0, self.ckp, self.cuk, lohi, B, C, C, self.grad,
-                            self.loss, self.ws)
-        self.t += 1
-        surrogate_adam(self.model, self.params, self.grad, self.optim, self.t, lr)
-
-    def train(self, n_traj: int, lr: float = 1e-3, log_every: int = 50, log=print):
         steps = max(1, n_traj // self.batch)
-        rng = np.random.default_rng(self.seed + 12345)
-        losses = []
+        chunk = min(self.chunk, log_every or self.chunk)
+        history = []
         t0 = time.perf_counter()
-        for k in range(steps):
-            coef = _coefficients(self.batch, 100_000 + self.seed * 1_000_003 + k)
-            offs = rng.integers(0, self.grid - self.crop + 1, size=(self.batch, 2))
-            lr_k = lr * 0.5 * (1.0 + math.cos(math.pi * k / steps))
-            self.step(coef, offs, lr_k)
-            if (k + 1) % log_every == 0 or k == steps - 1:
-                lv = float(self.loss.cpu()[0])
-                losses.append((k + 1, lv))
-                log(f"step {k + 1}/{steps}  trajectories {(k + 1) * self.batch}  loss {lv:.4e}  "
-                    f"{time.perf_counter() - t0:.1f} s", flush=True) if log is print else log(k + 1, lv)
-        return losses
+        for k0 in range(0, steps, chunk):
+            n = min(chunk, steps - k0)
+            coef, yx = self.draws(k0, n)
+            losses = torch.zeros(n, dtype=torch.float64, device=self.dev)
+            surrogate_train(self.model, self.params, self.optim, torch.from_numpy(coef).to(self.dev), yx, losses, self.ws,
+                            self.grid, self.grid, self.crop, self.batch, self.K, n, k0, steps, lr)
+            lv = float(losses[-1].cpu())
+            history.append((k0 + n, lv))
+            if log is print:
+                print(f"step {k0 + n}/{steps}  trajectories {(k0 + n) * self.batch}  loss {lv:.4e}  "
+                      f"{time.perf_counter() - t0:.1f} s", flush=True)
+            elif log is not None:
+                log(k0 + n, lv)
+        return history
 
     def evaluate(self, params, n: int, seed: int = 7):
-        """Held-out rel-L2 of the surrogate, of the identity predictor (u_hat = u0), against K plain steps."""
+        """Held-out rel-L2 against K plain steps (from the library's judged entry point) of the surrogate
+        with `params` and of the identity predictor u_hat = u0 (all-zero parameters)."""
         torch = self.torch
         G = self.grid
-        fws = torch.empty(surrogate_workspace_bytes(self.model, 1, G, G), dtype=torch.uint8, device=self.dev)
-        uh = torch.empty((1, G, G), dtype=torch.float32, device=self.dev)
+        if self.judge is None:
+            self.judge = stencil_plan_varcoef(G, G, 0.0, 0)
+            for tb in (8, 4, 2, 1):
+                try:
+                    stencil_set_blocking(self.judge, tb)
+                    break
+                except Exception:  # noqa: BLE001 - deeper blocks may not fit this device's LDS
+                    continue
+        cws = torch.empty(surrogate_checked_ws_bytes(self.model, G, G), dtype=torch.uint8, device=self.dev)
+        zero = torch.zeros(SG_PARAM_COUNT, dtype=torch.float32, device=self.dev)
+        U0 = torch.empty((self.batch, G, G), dtype=torch.float32, device=self.dev)
+        KP = torch.empty_like(U0)
+        out = torch.empty((G, G), dtype=torch.float32, device=self.dev)
         errs, ident = [], []
         coef_all = _coefficients(n, seed)
         for k in range(0, n, self.batch):
             coef = coef_all[k:k + self.batch]
-            self.make_targets(coef)
+            surrogate_synth_fields(torch.from_numpy(np.ascontiguousarray(coef, np.float32)).to(self.dev), coef.shape[0],
+                                   G, G, U0, KP)
             for b in range(coef.shape[0]):
-                surrogate_forward(self.model, params, self.U0[b], self.KP[b], uh, 1, G, G, fws)
-                d = (uh[0].double() - self.UK[b].double()).norm() / self.UK[b].double().norm()
-                i = (self.U0[b].double() - self.UK[b].double()).norm() / self.UK[b].double().norm()
-                errs.append(float(d))
-                ident.append(float(i))
+                _, e = surrogate_infer_checked(self.model, params, U0[b], KP[b], out, G, G, self.judge, self.K,
+                                               float("inf"), cws)
+                _, i = surrogate_infer_checked(self.model, zero, U0[b], KP[b], out, G, G, self.judge, self.K,
+                                               float("inf"), cws)
+                errs.append(e)
+                ident.append(i)
         return np.array(errs), np.array(ident)
 
 
@@ -167,7 +145,7 @@ def main(argv=None):
     ap.add_argument("--heldout", type=int, default=1000)
     ap.add_argument("--out", default=None, help="write the trained parameters (.npy) and a JSON summary here")
     args = ap.parse_args(argv)
-    tr = Trainer(grid=args.grid, crop=args.crop, batch=args.batch)
+    tr = Trainer(grid=args.grid, crop=args.crop, batch=args.batch, chunk=50)
     try:
         p0 = tr.params.clone()
         t0 = time.perf_counter()

@@ -113,3 +113,22 @@ def test_binding_constants_match_header():
     for n in names:
         assert n in defs, n
         assert getattr(lib, n) == defs[n], (n, getattr(lib, n), defs[n])
+
+
+def test_train_cfg_layout_matches_header(tmp_path):
+    """The binding's ctypes mirror of sg_train_cfg has the C compiler's size and field offsets."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    fields = [f[0] for f in lib.SgTrainCfg._fields_]
+    src = tmp_path / "cfg.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mi355stencil.h"\nint main(void) {\n'
+                   '    printf("%zu", sizeof(sg_train_cfg));\n'
+                   + "".join(f'    printf(" %zu", offsetof(sg_train_cfg, {f}));\n' for f in fields)
+                   + "    return 0;\n}\n")
+    exe = tmp_path / "cfg"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(lib.HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(lib.SgTrainCfg)
+    assert got[1:] == [getattr(lib.SgTrainCfg, f).offset for f in fields]

@@ -112,3 +112,35 @@ def test_batched_config_sample(g):
         np.testing.assert_array_equal(got, ref, err_msg=p.name)
         e = oracle.rel_l2(got, oracle.stencil_f64(p.u0, p.weights, 0.0, p.steps))
         assert e <= 1e-5, (p.name, e)
+
+
+def test_batched_autotune_bitwise(g):
+    """The batch autotuner changes only the depth of each class's passes: results stay bitwise equal
+    to the oracle, before and after tuning, with and without the graph."""
+    import torch
+    import paper_2605_07954_amd as lib
+    problems = _mixed(20, 11)
+    refs = [oracle.stencil_f32(p.u0, p.weights, p.boundary, p.steps) for p in problems]
+    plans = [lib.stencil_plan(p.rows, p.cols, p.radius, p.weights, p.boundary, "f32", 0) for p in problems]
+    try:
+        batch = lib.stencil_batch_create(plans, [p.steps for p in problems], lib.ST_FLAG_GRAPH)
+        try:
+            ins = [g.to_dev(p.u0) for p in problems]
+            outs = [torch.empty_like(x) for x in ins]
+            ws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device=g.DEV)
+            lib.stencil_run_batched(batch, ins, outs, ws)  # builds the graph with the plans' depths
+            caps = lib.stencil_batch_autotune(batch, ins, outs, ws)
+            say("chosen caps", caps)
+            assert caps and all(1 <= v <= 16 for v in caps.values())
+            for rep in range(2):
+                for o in outs:
+                    o.fill_(float("nan"))
+                lib.stencil_run_batched(batch, ins, outs, ws)
+                torch.cuda.synchronize()
+                for p, o, ref in zip(problems, outs, refs):
+                    np.testing.assert_array_equal(g.to_host(o), ref, err_msg=f"{p.name} rep {rep}")
+        finally:
+            lib.stencil_batch_destroy(batch)
+    finally:
+        for h in plans:
+            lib.stencil_destroy(h)

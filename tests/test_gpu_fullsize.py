@@ -237,7 +237,7 @@ def test_surrogate_1024(g):
     try:
         ws = torch.empty(lib.surrogate_workspace_bytes(m, 1, n, n), dtype=torch.uint8, device=g.DEV)
         out = torch.empty((1, n, n), dtype=torch.float32, device=g.DEV)
-        lib.surrogate_forward(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, 1, n, n, ws)
+        lib.surrogate_infer(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, 1, n, n, ws)
         got = g.to_host(out[0])
         cws = torch.empty(lib.surrogate_checked_ws_bytes(m, n, n), dtype=torch.uint8, device=g.DEV)
         chk = torch.empty((n, n), dtype=torch.float32, device=g.DEV)
