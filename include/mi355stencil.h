@@ -106,15 +106,16 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
                                  while the current one computes (FP32, cols % 4 == 0)          */
 #define ST_VARIANT_MARCH   2  /* each wavefront walks a column band down the grid, rows in a
                                  register ring, side columns by lane shifts; tb up to 4 (r = 1),
-                                 3 (r = 2) or 2 (r >= 3); the tile is ignored (any storage,
-                                 cols % 4 == 0)                                                 */
+                                 3 (r = 2) or 2 (r >= 3); the tile is ignored; any storage and
+                                 width (four columns per lane when cols % 4 == 0 and the
+                                 buffers are 16-byte aligned, else one)                         */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
- * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage; both streaming
- * and marching need cols % 4 == 0 and a constant-weight plan; or the current tb is deeper than the variant
+ * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage and cols % 4 == 0;
+ * both need a constant-weight plan; or the current tb is deeper than the variant
  * allows: its LDS budget when streaming, 4/3/2 for r = 1/2/>=3 when marching -- lower tb
- * first).  A run whose
- * buffers are not 16-byte aligned falls back to the tiled kernels. */
+ * first).  A streaming run whose buffers are not 16-byte aligned falls back to the tiled
+ * kernels; a marching run takes one column per lane instead. */
 int stencil_set_variant(st_plan* plan, int variant);
 int stencil_get_variant(const st_plan* plan, int* variant);
 

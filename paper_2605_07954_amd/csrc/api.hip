@@ -236,7 +236,7 @@ int stencil_set_variant(st_plan* plan, int variant) {
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
         return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
     if (variant == ST_VARIANT_MARCH && !march_usable(plan))
-        return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan with cols % 4 == 0");
+        return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan");
     const int old = plan->variant;
     plan->variant = variant;
     if (plan->tb > max_tb(plan, plan->tile_x, plan->tile_y)) {  // keep the plan launchable

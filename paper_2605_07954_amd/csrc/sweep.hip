@@ -393,11 +393,10 @@ int launch_pass(const st_plan* p, const void* src, void* dst, const float* kappa
         return fail(ST_EUNSUPPORTED, "launch_pass called on a naive plan");
     }
     const int ti = tile_index(p->tile_x, p->tile_y);
-    const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
-    if (p->variant == VARIANT_MARCH && march_usable(p) && aligned && levels <= march_max_tb(p->radius))
+    if (p->variant == VARIANT_MARCH && march_usable(p) && levels <= march_max_tb(p->radius))
         return launch_march(p, src, dst, levels, s);
-    if (p->variant == VARIANT_STREAM && stream_usable(p) && (reinterpret_cast<uintptr_t>(src) % 16) == 0 &&
-        (reinterpret_cast<uintptr_t>(dst) % 16) == 0) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
+    if (p->variant == VARIANT_STREAM && stream_usable(p) && aligned) {
         KernelFn fn = stream_lookup(p->shape, p->radius, ti);
         if (!fn) return fail(ST_EUNSUPPORTED, "no streaming kernel for this shape/radius/tile");
         const size_t lds = stream_lds_bytes(p->radius, levels, p->tile_x, p->tile_y);
