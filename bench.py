@@ -219,7 +219,8 @@ def extra_batched(torch, lib, stream) -> dict:
         lib.stencil_destroy(pl)
     del ins, outs, wss, bws
     torch.cuda.empty_cache()
-    return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3, "depth_caps": {f"{k[0]}{k[1]}": v for k, v in caps.items()},
+    return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3,
+            "classes": {f"{k[0]}{k[1]}": f"{v[0]} x{v[1]}" for k, v in caps.items()},
             "per_grid_ms": t_per * 1e3,
             "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
 

@@ -210,15 +210,26 @@ int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
 int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
                         size_t ws_bytes, void* stream);
 
-/* stencil_batch_autotune -- pick the temporal depth of the batch's tiled grids: for each stencil
- * class (shape, radius) in turn, run the whole batch with the class's depth capped at 1, 2, 3, 4,
- * 6, 8, 12 and 16 passes' worth of steps (each grid also capped by what its 128 x 64 tile fits in
- * LDS), keep the fastest cap, then tune the next class.  Runs the batch twice per candidate on
- * the caller's buffers (outs are overwritten; results are bitwise those of any other depth).
- * Writes the chosen cap per class to tb_out[6] when non-NULL (star r = 1, 2, 3, then box r = 1,
- * 2, 3; 0 = class absent).  Synchronises the stream.  Errors: as stencil_run_batched. */
+/* stencil_batch_set_class -- set the engine (0 = LDS tiles, 1 = marching) and pass depth of one
+ * stencil class (shape 0 = star, 1 = box; radius 1..3) of the batch by hand; results are bitwise
+ * the same for every choice.  Tiles: depth 1..16, further capped per grid by what its tile fits
+ * in LDS.  Marching: depth up to 4 (r = 1), 3 (r = 2) or 2 (r = 3).  Errors: ST_EINVAL,
+ * ST_EUNSUPPORTED (depth out of range). */
+int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, int depth);
+
+/* stencil_batch_autotune -- pick, for each stencil class (shape, radius) of the grids that are
+ * not LDS-resident, the engine and the depth of its passes: LDS tiles of 128 x 64 (one multi-grid
+ * launch per pass for all tiled classes) with the depth capped at 1, 2, 3, 4, 6, 8, 12 or 16
+ * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, one
+ * column per lane, any width; one chain of launches per class, the classes on parallel branches
+ * of the graph) with 1 .. 4 (r = 1), 3 (r = 2) or 2 (r = 3) levels.  Coordinate descent: each
+ * class in turn, every candidate timed on the whole batch run twice on the caller's buffers (outs
+ * are overwritten; results are bitwise those of any other choice).  Writes the chosen depth and
+ * engine (0 = tiles, 1 = marching) per class to tb_out[6] / engine_out[6] when non-NULL (star
+ * r = 1, 2, 3, then box r = 1, 2, 3; 0 = class absent).  Synchronises the stream.  Errors: as
+ * stencil_run_batched.  A new batch starts with every class on tiles at its plans' depths. */
 int stencil_batch_autotune(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
-                           size_t ws_bytes, int* tb_out, void* stream);
+                           size_t ws_bytes, int* tb_out, int* engine_out, void* stream);
 
 /* stencil_batch_destroy -- free the batch (graph, pinned table).  NULL is a no-op. */
 int stencil_batch_destroy(st_batch* batch);

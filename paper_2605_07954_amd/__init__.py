@@ -64,7 +64,9 @@ _SIGS = {
     "stencil_batch_workspace_bytes": [_p, ctypes.POINTER(_sz)],
     "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
     "stencil_batch_destroy": [_p],
-    "stencil_batch_autotune": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, ctypes.POINTER(_int), _p],
+    "stencil_batch_set_class": [_p, _int, _int, _int, _int],
+    "stencil_batch_autotune": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, ctypes.POINTER(_int),
+                               ctypes.POINTER(_int), _p],
     "surrogate_create": [ctypes.POINTER(_p), _u32],
     "surrogate_destroy": [_p],
     "surrogate_workspace_bytes": [_p, _int, _i64, _i64, ctypes.POINTER(_sz)],
@@ -284,16 +286,22 @@ def stencil_run_batched(batch, ins, outs, workspace, stream=None) -> None:
                                   _stream(stream)), "stencil_run_batched")
 
 
+def stencil_batch_set_class(batch, shape: str, radius: int, engine: str, depth: int) -> None:
+    _ck(lib().stencil_batch_set_class(batch, {"star": 0, "box": 1}[shape], radius, {"tiles": 0, "march": 1}[engine],
+                                      depth), "stencil_batch_set_class")
+
+
 def stencil_batch_autotune(batch, ins, outs, workspace, stream=None) -> dict:
-    """Returns the chosen depth cap per stencil class present: {("star", 1): 8, ("box", 1): 4, ...}."""
+    """Returns the choice per stencil class present: {("star", 1): ("march", 2), ("box", 3): ("tiles", 1), ...}."""
     n = len(ins)
     pi = (_p * n)(*[_dptr(t, "in").value for t in ins])
     po = (_p * n)(*[_dptr(t, "out").value for t in outs])
-    caps = (_int * 6)()
-    _ck(lib().stencil_batch_autotune(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace), caps,
-                                     _stream(stream)), "stencil_batch_autotune")
+    depth = (_int * 6)()
+    engine = (_int * 6)()
+    _ck(lib().stencil_batch_autotune(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace), depth,
+                                     engine, _stream(stream)), "stencil_batch_autotune")
     names = [("star", 1), ("star", 2), ("star", 3), ("box", 1), ("box", 2), ("box", 3)]
-    return {names[k]: caps[k] for k in range(6) if caps[k]}
+    return {names[k]: (("tiles", "march")[engine[k]], depth[k]) for k in range(6) if depth[k]}
 
 
 def stencil_batch_destroy(batch) -> None:

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "march_body.h"
 #include "sweep_body.h"
 
 namespace st {
@@ -27,7 +28,8 @@ struct BatchDesc {
     float* out;
     float* ws;
     int64_t rows, cols;
-    int64_t tiles_x, tiles_y;
+    int64_t tiles_x, tiles_y;  // tiled engine: tiles; marching engine: bands and segments
+    int64_t seg;               // marching engine: output rows per task
     int r, shape, tb, steps, passes, resident;
     float b;
     float w[MAXK];
@@ -118,6 +120,57 @@ __global__ __launch_bounds__(NT) void batched_resident(const BatchDesc* desc, co
     dispatch_resident(desc[res[blockIdx.x]], reinterpret_cast<float*>(lds4));
 }
 
+// Marching engine: one launch runs `levels` (the template TB) levels of pass p for the grids
+// order[s0 .. s0+n) of one stencil class; wavefront task -> (grid, band, segment) through the class's
+// task prefix sums.  One column per lane, so any width and alignment.
+struct MarchPassArgs {
+    const BatchDesc* desc;
+    const int* order;            // the class's grids, ordered by passes then last-pass depth, descending
+    const int64_t* task_prefix;  // prefix sums of tasks over `order`
+    int s0, n;                   // the slice of `order` this launch covers
+    int p;                       // pass index
+};
+
+constexpr int MW = 4;  // wavefronts per workgroup of the marching engine
+
+template <int R, int SH, int TB>
+__global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
+    const int lane = int(threadIdx.x & 63);
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t* pre = a.task_prefix + a.s0;
+    const int64_t task = pre[0] + int64_t(blockIdx.x) * MW + wave;
+    if (task >= pre[a.n]) return;
+    const int k = upper_index(pre, a.n + 1, task);
+    const BatchDesc& d = a.desc[a.order[a.s0 + k]];
+    const int64_t t = task - pre[k];
+    const int64_t band = t % d.tiles_x, segi = t / d.tiles_x;
+    constexpr int H = march::halo_lanes(R, TB, 1);
+    const int64_t y0 = segi * d.seg;
+    const int64_t y1 = y0 + d.seg < d.rows ? y0 + d.seg : d.rows;
+    const int P = d.passes, p = a.p;
+    const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
+    float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
+    const march::MarchView v{src, dst, d.rows, d.cols, d.b};
+    march::march_task<ST_F32, R, 1, SH, TB>(v, d.w, lane, y0, y1, band * (64 - 2 * H) - H);
+}
+
+using MarchPassFn = void (*)(MarchPassArgs);
+
+template <int SH>
+MarchPassFn batched_march_fn(int r, int levels) {
+#define ST_BMARCH(R, TB) \
+    if (r == R && levels == TB) return batched_march<R, SH, TB>;
+    ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4)
+    ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3)
+    ST_BMARCH(3, 1) ST_BMARCH(3, 2)
+#undef ST_BMARCH
+    return nullptr;
+}
+
+MarchPassFn batched_march_lookup(int shape, int r, int levels) {
+    return shape == SHAPE_BOX ? batched_march_fn<SHAPE_BOX>(r, levels) : batched_march_fn<SHAPE_STAR>(r, levels);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 
@@ -136,10 +189,21 @@ struct st_batch {
     std::vector<int> res;              // LDS-resident grids
     std::vector<int> zero_steps;       // grids with steps == 0 (copied, not computed)
     std::vector<int> active;           // active[p]: tiled grids with more than p passes
-    std::vector<int> tiled;            // tiled grids, in input order
+    std::vector<int> tiled;            // grids that are neither resident nor zero-step, in input order
     std::vector<int> tb_max;           // per grid: deepest pass the batch tile's LDS budget allows
     int max_passes;
-    size_t off_desc, off_tprefix, off_order, off_res, off_fields, ws_bytes;
+    // per stencil class (slot = shape * 3 + r - 1): engine (0 = LDS tiles, 1 = marching) and depth
+    int engine[6], depth[6];
+    struct MLaunch {
+        int s0, n, p, levels;
+        int64_t tasks;
+    };
+    struct MClass {
+        std::vector<int> order;        // the class's marching grids by passes, then last-pass depth
+        std::vector<int64_t> prefix;   // task prefix sums over `order`
+        std::vector<MLaunch> launches; // in pass order
+    } mclass[6];
+    size_t off_desc, off_tprefix, off_order, off_res, off_morder[6], off_mprefix[6], off_fields, ws_bytes;
     std::vector<size_t> field_off;     // per grid: workspace offset of its ping-pong field (0 = none)
     size_t lds_pass, lds_res;
     // staging + graph
@@ -162,16 +226,42 @@ size_t batch_lds_budget() { return std::min<size_t>(80 * 1024, lds_limit()); }
 
 }  // namespace
 
-// Pass structure of the tiled grids from their current depths: passes per grid, the queue order
-// (by pass count, descending, so that the grids still active at pass p are a prefix), the tile
-// prefix sums over that order and the LDS of the deepest pass.
+static int class_slot(const BatchDesc& d) { return d.shape * 3 + d.r - 1; }
+
+// Marching engine: output rows per task for a class, so that its tasks about fill the device once.
+static int64_t march_segment(int64_t band_rows) {
+    constexpr int64_t kWaves = 4096;  // resident wavefronts the segments are sized for
+    const int64_t seg = (band_rows + kWaves - 1) / kWaves;
+    return std::min<int64_t>(2048, std::max<int64_t>(8, seg));
+}
+
+// Pass structure from each class's engine and depth.  Tiled engine: passes per grid, the queue
+// order (by pass count, descending, so that the grids still active at pass p are a prefix), the tile
+// prefix sums over that order and the LDS of the deepest pass.  Marching engine, per class: bands
+// and segments per grid, the order by (passes, depth of the last pass) descending, the task prefix
+// sums, and the launches -- at pass p the full-depth grids are a prefix of the order and the grids
+// finishing with a shallower pass follow in groups of equal depth.
 static void build_passes(st_batch* B) {
-    std::vector<int> order = B->tiled;
+    std::vector<int> order;
     size_t lds = 0;
-    for (int g : order) {
+    for (int c = 0; c < 6; ++c) B->mclass[c] = st_batch::MClass();
+    for (int g : B->tiled) {
         BatchDesc& d = B->desc[g];
-        d.passes = (d.steps + d.tb - 1) / d.tb;
-        lds = std::max(lds, tiled_lds_bytes(d.r, d.tb, kTX, kTY));
+        const int c = class_slot(d);
+        if (B->engine[c] == 0) {
+            d.tb = std::min(B->depth[c] > 0 ? B->depth[c] : d.tb, B->tb_max[g]);
+            d.tiles_x = (d.cols + kTX - 1) / kTX;
+            d.tiles_y = (d.rows + kTY - 1) / kTY;
+            d.passes = (d.steps + d.tb - 1) / d.tb;
+            lds = std::max(lds, tiled_lds_bytes(d.r, d.tb, kTX, kTY));
+            order.push_back(g);
+        } else {
+            d.tb = B->depth[c];
+            d.passes = (d.steps + d.tb - 1) / d.tb;
+            d.tiles_x = (d.cols + (64 - 2 * march::halo_lanes(d.r, d.tb, 1)) - 1) /
+                        (64 - 2 * march::halo_lanes(d.r, d.tb, 1));  // bands
+            B->mclass[c].order.push_back(g);
+        }
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->desc[a].passes > B->desc[b].passes; });
     B->order = order;
@@ -185,6 +275,46 @@ static void build_passes(st_batch* B) {
         B->active.push_back(a);
     }
     B->lds_pass = lds;
+    for (int c = 0; c < 6; ++c) {
+        st_batch::MClass& M = B->mclass[c];
+        if (M.order.empty()) continue;
+        const int tb = B->depth[c];
+        auto last_depth = [&](int g) { return B->desc[g].steps - (B->desc[g].passes - 1) * tb; };
+        std::stable_sort(M.order.begin(), M.order.end(), [&](int a, int b) {
+            const BatchDesc &da = B->desc[a], &db = B->desc[b];
+            return da.passes != db.passes ? da.passes > db.passes : last_depth(a) > last_depth(b);
+        });
+        int64_t band_rows = 0;
+        for (int g : M.order) band_rows += B->desc[g].tiles_x * B->desc[g].rows;
+        const int64_t seg = march_segment(band_rows);
+        M.prefix.assign(1, 0);
+        for (int g : M.order) {
+            BatchDesc& d = B->desc[g];
+            d.seg = std::min<int64_t>(seg, d.rows);
+            d.tiles_y = (d.rows + d.seg - 1) / d.seg;  // segments
+            M.prefix.push_back(M.prefix.back() + d.tiles_x * d.tiles_y);
+        }
+        const int P = B->desc[M.order[0]].passes;
+        const int n = int(M.order.size());
+        for (int p = 0; p < P; ++p) {
+            // grids at pass p: passes > p (a prefix); those with passes == p + 1 run their last depth
+            int a = 0;
+            while (a < n && B->desc[M.order[a]].passes > p) ++a;
+            int full = 0;
+            while (full < a && (B->desc[M.order[full]].passes > p + 1 || last_depth(M.order[full]) == tb)) ++full;
+            auto push = [&](int s0, int e, int levels) {
+                if (e > s0) M.launches.push_back({s0, e - s0, p, levels, M.prefix[e] - M.prefix[s0]});
+            };
+            push(0, full, tb);
+            for (int s0 = full; s0 < a;) {
+                const int lv = last_depth(M.order[s0]);
+                int e = s0;
+                while (e < a && last_depth(M.order[e]) == lv) ++e;
+                push(s0, e, lv);
+                s0 = e;
+            }
+        }
+    }
 }
 
 extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int64_t* steps,
@@ -241,6 +371,10 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
         tiled.push_back(g);
     }
     B->tiled = tiled;
+    for (int c = 0; c < 6; ++c) {
+        B->engine[c] = 0;
+        B->depth[c] = 0;  // 0: each grid keeps its plan's depth (capped by the tile's LDS)
+    }
     build_passes(B);
     // workspace: descriptor table, queue tables, one ping-pong field per tiled grid with two or more
     // steps (any depth the autotuner may pick below the step count needs it)
@@ -248,11 +382,17 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     B->off_desc = off;
     off = align256(off + size_t(n) * sizeof(BatchDesc));
     B->off_tprefix = off;
-    off = align256(off + B->tile_prefix.size() * sizeof(int64_t));
+    off = align256(off + (tiled.size() + 1) * sizeof(int64_t));
     B->off_order = off;
-    off = align256(off + std::max<size_t>(B->order.size(), 1) * sizeof(int));
+    off = align256(off + std::max<size_t>(tiled.size(), 1) * sizeof(int));
     B->off_res = off;
     off = align256(off + std::max<size_t>(B->res.size(), 1) * sizeof(int));
+    for (int c = 0; c < 6; ++c) {  // room for every tiled grid in any class's marching tables
+        B->off_morder[c] = off;
+        off = align256(off + std::max<size_t>(tiled.size(), 1) * sizeof(int));
+        B->off_mprefix[c] = off;
+        off = align256(off + (tiled.size() + 1) * sizeof(int64_t));
+    }
     B->off_fields = off;
     for (int g : tiled) {
         if (B->desc[g].steps >= 2) {
@@ -291,15 +431,50 @@ extern "C" int stencil_batch_destroy(st_batch* batch) {
     return ST_OK;
 }
 
-// Enqueue the batch's kernels: the resident grids on `side` (joined back into `s` at the end when
-// side != s), the pass levels of the tiled grids on `s`.
-static int enqueue_batch(st_batch* B, char* ws, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+// The marching launches of class c, in pass order, on stream `s`.
+static int enqueue_march_class(st_batch* B, int c, char* ws, hipStream_t s) {
+    const st_batch::MClass& M = B->mclass[c];
+    const BatchDesc& d0 = B->desc[M.order[0]];
+    for (const st_batch::MLaunch& L : M.launches) {
+        MarchPassFn fn = batched_march_lookup(d0.shape, d0.r, L.levels);
+        if (!fn) return fail(ST_EUNSUPPORTED, "no batched marching kernel for this class/depth");
+        MarchPassArgs a;
+        a.desc = reinterpret_cast<const BatchDesc*>(ws + B->off_desc);
+        a.order = reinterpret_cast<const int*>(ws + B->off_morder[c]);
+        a.task_prefix = reinterpret_cast<const int64_t*>(ws + B->off_mprefix[c]);
+        a.s0 = L.s0;
+        a.n = L.n;
+        a.p = L.p;
+        const int64_t blocks = (L.tasks + MW - 1) / MW;
+        clear_stale_error();
+        hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(64 * MW), 0, s, a);
+        ST_LAUNCH_CHECK("batched_march");
+    }
+    return ST_OK;
+}
+
+// Enqueue the batch's kernels: the resident grids on `side`, the marching classes on `mside[c]`
+// (each joined back into `s` at the end when it differs from s), the pass levels of the tiled grids
+// on `s`.
+static int enqueue_batch(st_batch* B, char* ws, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join,
+                         const hipStream_t* mside, const hipEvent_t* mjoin) {
     const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + B->off_desc);
     const bool branch = side != s;
+    if (branch) {
+        ST_HIP_CHECK(hipEventRecord(fork, s));
+        for (int c = 0; c < 6; ++c)
+            if (!B->mclass[c].order.empty()) ST_HIP_CHECK(hipStreamWaitEvent(mside[c], fork, 0));
+    }
+    for (int c = 0; c < 6; ++c) {
+        if (B->mclass[c].order.empty()) continue;
+        if (int rc = enqueue_march_class(B, c, ws, branch ? mside[c] : s)) return rc;
+        if (branch) {
+            ST_HIP_CHECK(hipEventRecord(mjoin[c], mside[c]));
+        }
+    }
     if (!B->res.empty()) {
         if (int rc = prepare_lds(reinterpret_cast<const void*>(batched_resident), B->lds_res)) return rc;
         if (branch) {
-            ST_HIP_CHECK(hipEventRecord(fork, s));
             ST_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
         }
         clear_stale_error();
@@ -326,6 +501,9 @@ static int enqueue_batch(st_batch* B, char* ws, hipStream_t s, hipStream_t side,
         ST_HIP_CHECK(hipEventRecord(join, side));
         ST_HIP_CHECK(hipStreamWaitEvent(s, join, 0));
     }
+    if (branch)
+        for (int c = 0; c < 6; ++c)
+            if (!B->mclass[c].order.empty()) ST_HIP_CHECK(hipStreamWaitEvent(s, mjoin[c], 0));
     return ST_OK;
 }
 
@@ -364,6 +542,12 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
         if (!B->order.empty())
             std::memcpy(h + (B->off_order - B->off_desc), B->order.data(), B->order.size() * sizeof(int));
         if (!B->res.empty()) std::memcpy(h + (B->off_res - B->off_desc), B->res.data(), B->res.size() * sizeof(int));
+        for (int c = 0; c < 6; ++c) {
+            const st_batch::MClass& M = B->mclass[c];
+            if (M.order.empty()) continue;
+            std::memcpy(h + (B->off_morder[c] - B->off_desc), M.order.data(), M.order.size() * sizeof(int));
+            std::memcpy(h + (B->off_mprefix[c] - B->off_desc), M.prefix.data(), M.prefix.size() * sizeof(int64_t));
+        }
         ST_HIP_CHECK(hipMemcpyAsync(ws + B->off_desc, h, B->pinned_bytes, hipMemcpyHostToDevice, s));
         ST_HIP_CHECK(hipEventRecord(B->staged, s));
         B->staged_valid = true;
@@ -374,8 +558,10 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
     for (int g : B->zero_steps)
         ST_HIP_CHECK(hipMemcpyAsync(outs[g], ins[g], size_t(B->desc[g].rows * B->desc[g].cols) * sizeof(float),
                                     hipMemcpyDeviceToDevice, s));
-    if (B->res.empty() && B->max_passes == 0) return ST_OK;
-    if (!(B->flags & ST_FLAG_GRAPH)) return enqueue_batch(B, ws, s, s, nullptr, nullptr);
+    bool any_march = false;
+    for (int c = 0; c < 6; ++c) any_march = any_march || !B->mclass[c].order.empty();
+    if (B->res.empty() && B->max_passes == 0 && !any_march) return ST_OK;
+    if (!(B->flags & ST_FLAG_GRAPH)) return enqueue_batch(B, ws, s, s, nullptr, nullptr, nullptr, nullptr);
     if (!(B->exec && B->g_ws == workspace)) {
         if (B->exec) {
             (void)hipGraphExecDestroy(B->exec);
@@ -384,17 +570,23 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
         // capture: the resident grids on a side branch forked from and joined back into the main one
         hipStream_t cap = nullptr, side = nullptr;
         hipEvent_t fork = nullptr, join = nullptr;
+        hipStream_t mside[6] = {};
+        hipEvent_t mjoin[6] = {};
         int rc = ST_OK;
         hipGraph_t graph = nullptr;
-        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        bool made = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess &&
+                    hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+                    hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+        for (int c = 0; c < 6 && made; ++c)
+            made = hipStreamCreateWithFlags(&mside[c], hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&mjoin[c], hipEventDisableTiming) == hipSuccess;
+        if (!made) {
             rc = fail(ST_EHIP, "stream/event creation for graph capture failed");
         } else if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(ST_EHIP, "hipStreamBeginCapture failed");
         } else {
-            rc = enqueue_batch(B, ws, cap, side, fork, join);
+            rc = enqueue_batch(B, ws, cap, side, fork, join, mside, mjoin);
             const hipError_t e = hipStreamEndCapture(cap, &graph);
             if (!rc && e != hipSuccess) rc = fail(ST_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
@@ -406,6 +598,10 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
         if (side) (void)hipStreamDestroy(side);
+        for (int c = 0; c < 6; ++c) {
+            if (mjoin[c]) (void)hipEventDestroy(mjoin[c]);
+            if (mside[c]) (void)hipStreamDestroy(mside[c]);
+        }
         if (cap) (void)hipStreamDestroy(cap);
         (void)hipGetLastError();
         if (rc) return rc;
@@ -415,29 +611,50 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
     return ST_OK;
 }
 
-// Coordinate descent over the stencil classes (shape, radius) of the tiled grids: for each class
-// in turn, time the whole batch (direct launches) with the class's depth capped at each candidate,
-// keep the fastest, then move to the next class.
+extern "C" int stencil_batch_set_class(st_batch* B, int shape, int radius, int engine, int depth) {
+    if (!B) return fail(ST_EINVAL, "batch is NULL");
+    if ((shape != SHAPE_STAR && shape != SHAPE_BOX) || radius < 1 || radius > 3 || (engine != 0 && engine != 1))
+        return fail(ST_EINVAL, "bad class or engine");
+    if (depth < 1 || depth > 16 || (engine == 1 && depth > march_max_tb(radius)))
+        return fail(ST_EUNSUPPORTED, "depth out of range for this engine");
+    const int c = shape * 3 + radius - 1;
+    B->engine[c] = engine;
+    B->depth[c] = depth;
+    build_passes(B);
+    B->staged_valid = false;
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    return ST_OK;
+}
+
+// Coordinate descent over the stencil classes (shape, radius) of the non-resident grids: for each
+// class in turn, time the whole batch (direct launches) with every candidate engine and depth -- LDS
+// tiles with the class's depth capped at 1, 2, 3, 4, 6, 8, 12 or 16, or marching with 1 .. the
+// deepest its radius allows -- keep the fastest, then move to the next class.
 extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void* const* outs, void* workspace,
-                                      size_t ws_bytes, int* tb_out, void* stream) {
+                                      size_t ws_bytes, int* tb_out, int* engine_out, void* stream) {
     if (!B || !ins || !outs) return fail(ST_EINVAL, "NULL argument");
     if (!workspace || ws_bytes < B->ws_bytes) return fail(ST_ENOWS, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (tb_out) std::fill(tb_out, tb_out + 6, 0);
+    if (engine_out) std::fill(engine_out, engine_out + 6, 0);
     const uint32_t flags = B->flags;
     B->flags &= ~ST_FLAG_GRAPH;
-    std::vector<int> classes;  // shape * 8 + r
+    bool present[6] = {};
+    int deepest[6] = {};
     for (int g : B->tiled) {
-        const int c = B->desc[g].shape * 8 + B->desc[g].r;
-        if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+        const int c = class_slot(B->desc[g]);
+        present[c] = true;
+        deepest[c] = std::max(deepest[c], B->tb_max[g]);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ST_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(ST_EHIP, "hipEventCreate");
-    static const int kCaps[] = {1, 2, 3, 4, 6, 8, 12, 16};
-    auto apply = [&](int cls, int cap) {
-        for (int g : B->tiled)
-            if (B->desc[g].shape * 8 + B->desc[g].r == cls) B->desc[g].tb = std::min(cap, B->tb_max[g]);
+    auto apply = [&](int c, int engine, int depth) {
+        B->engine[c] = engine;
+        B->depth[c] = depth;
         build_passes(B);
         B->staged_valid = false;  // descriptor tables changed
     };
@@ -450,29 +667,29 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
             return fail(ST_EHIP, "hipEventRecord/Synchronize");
         return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? ST_OK : fail(ST_EHIP, "hipEventElapsedTime");
     };
-    for (int cls : classes) {
-        if (rc) break;
-        int deepest = 1;
-        for (int g : B->tiled)
-            if (B->desc[g].shape * 8 + B->desc[g].r == cls) deepest = std::max(deepest, B->tb_max[g]);
-        int best_cap = 0;
-        float best = 1e30f;
-        for (int cap : kCaps) {
-            if (cap > deepest) break;
-            apply(cls, cap);
+    static const int kCaps[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int c = 0; c < 6 && rc == ST_OK; ++c) {
+        if (!present[c]) continue;
+        const int r = c % 3 + 1;
+        std::vector<std::pair<int, int>> cands;
+        for (int cap : kCaps)
+            if (cap <= deepest[c]) cands.push_back({0, cap});
+        for (int t = 1; t <= march_max_tb(r); ++t) cands.push_back({1, t});
+        std::pair<int, int> best = cands[0];
+        float best_ms = 1e30f;
+        for (const auto& cd : cands) {
+            apply(c, cd.first, cd.second);
             float ms = 0.0f;
             if ((rc = timed(&ms))) break;
-            if (ms < best) {
-                best = ms;
-                best_cap = cap;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cd;
             }
         }
-        if (!rc && best_cap) apply(cls, best_cap);
-        if (tb_out && !rc) {
-            // report the cap chosen for each class in class order: star r=1..3 then box r=1..3
-            const int slot = (cls / 8) * 3 + (cls % 8) - 1;
-            if (slot >= 0 && slot < 6) tb_out[slot] = best_cap;
-        }
+        if (rc) break;
+        apply(c, best.first, best.second);
+        if (tb_out) tb_out[c] = best.second;
+        if (engine_out) engine_out[c] = best.first;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

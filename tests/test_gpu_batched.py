@@ -131,7 +131,7 @@ def test_batched_autotune_bitwise(g):
             lib.stencil_run_batched(batch, ins, outs, ws)  # builds the graph with the plans' depths
             caps = lib.stencil_batch_autotune(batch, ins, outs, ws)
             say("chosen caps", caps)
-            assert caps and all(1 <= v <= 16 for v in caps.values())
+            assert caps and all(e in ("tiles", "march") and 1 <= d <= 16 for (e, d) in caps.values())
             for rep in range(2):
                 for o in outs:
                     o.fill_(float("nan"))
@@ -139,6 +139,48 @@ def test_batched_autotune_bitwise(g):
                 torch.cuda.synchronize()
                 for p, o, ref in zip(problems, outs, refs):
                     np.testing.assert_array_equal(g.to_host(o), ref, err_msg=f"{p.name} rep {rep}")
+        finally:
+            lib.stencil_batch_destroy(batch)
+    finally:
+        for h in plans:
+            lib.stencil_destroy(h)
+
+
+@pytest.mark.parametrize("graph", [0, 2])
+def test_batched_engines_every_class_bitwise(g, graph):
+    """Every stencil class on LDS tiles and on the marching engine (one column per lane) at every
+    depth, with a shallower last pass (step counts not divisible by the depth): bitwise equal to the
+    FP32-canonical oracle, directly and through the graph."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rng = np.random.default_rng(21)
+    problems = []
+    for k, (shape, r) in enumerate([(wl.STAR, 1), (wl.BOX, 1), (wl.STAR, 2), (wl.BOX, 2), (wl.STAR, 3), (wl.BOX, 3)]):
+        for j, (rows, cols, steps) in enumerate([(150 + 37 * k, 301 + 11 * j, 7 + j), (233, 130 + 16 * k, 5)]):
+            w = wl.random_footprint_weights(np.random.default_rng(700 + 10 * k + j), shape, r)
+            problems.append(wl.Problem(f"{shape}{r}-{j}", rows, cols, r, shape, w, 0.0 if j else 0.5, steps,
+                                       rng.random((rows, cols), dtype=np.float32)))
+    refs = [oracle.stencil_f32(p.u0, p.weights, p.boundary, p.steps) for p in problems]
+    plans = [lib.stencil_plan(p.rows, p.cols, p.radius, p.weights, p.boundary, "f32", 0) for p in problems]
+    try:
+        batch = lib.stencil_batch_create(plans, [p.steps for p in problems], graph)
+        try:
+            ins = [g.to_dev(p.u0) for p in problems]
+            outs = [torch.empty_like(x) for x in ins]
+            ws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device=g.DEV)
+            for engine, depths in (("march", {1: 4, 2: 3, 3: 2}), ("tiles", {1: 4, 2: 3, 3: 2})):
+                for r in (1, 2, 3):
+                    for depth in range(1, depths[r] + 1):
+                        for shape in ("star", "box"):
+                            lib.stencil_batch_set_class(batch, shape, r, engine, depth)
+                        for o in outs:
+                            o.fill_(float("nan"))
+                        lib.stencil_run_batched(batch, ins, outs, ws)
+                        torch.cuda.synchronize()
+                        for p, o, ref in zip(problems, outs, refs):
+                            np.testing.assert_array_equal(g.to_host(o), ref, err_msg=f"{p.name} {engine} r{r} x{depth}")
+            with pytest.raises(lib.StencilError):
+                lib.stencil_batch_set_class(batch, "star", 3, "march", 3)
         finally:
             lib.stencil_batch_destroy(batch)
     finally:
