@@ -156,7 +156,8 @@ def test_batched_engines_every_class_bitwise(g, graph):
     rng = np.random.default_rng(21)
     problems = []
     for k, (shape, r) in enumerate([(wl.STAR, 1), (wl.BOX, 1), (wl.STAR, 2), (wl.BOX, 2), (wl.STAR, 3), (wl.BOX, 3)]):
-        for j, (rows, cols, steps) in enumerate([(150 + 37 * k, 301 + 11 * j, 7 + j), (233, 130 + 16 * k, 5)]):
+        for j in range(2):
+            rows, cols, steps = [(150 + 37 * k, 301 + 11 * k, 7 + k % 2), (233, 130 + 16 * k, 5)][j]
             w = wl.random_footprint_weights(np.random.default_rng(700 + 10 * k + j), shape, r)
             problems.append(wl.Problem(f"{shape}{r}-{j}", rows, cols, r, shape, w, 0.0 if j else 0.5, steps,
                                        rng.random((rows, cols), dtype=np.float32)))
