@@ -45,7 +45,7 @@ VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march"}
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip"):
+    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip", "march_body.h"):
         with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
