@@ -105,15 +105,16 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
 #define ST_VARIANT_STREAM  1  /* persistent workgroups; the next tile is copied into LDS by DMA
                                  while the current one computes (FP32, cols % 4 == 0)          */
 #define ST_VARIANT_MARCH   2  /* each wavefront walks a column band down the grid, rows in a
-                                 register ring, side columns by lane shifts; tb up to 4 (r = 1),
-                                 3 (r = 2) or 2 (r >= 3); the tile is ignored; any storage and
+                                 register ring, side columns by lane shifts; tb up to 8 / 6 /
+                                 4 / 3 (star, r = 1 / 2 / 3 / 4) or 4 / 3 / 2 / 2 (box); the
+                                 tile is ignored; any storage and
                                  width (four columns per lane when cols % 4 == 0 and the
                                  buffers are 16-byte aligned, else one)                         */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
  * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage and cols % 4 == 0;
  * both need a constant-weight plan; or the current tb is deeper than the variant
- * allows: its LDS budget when streaming, 4/3/2 for r = 1/2/>=3 when marching -- lower tb
+ * allows: its LDS budget when streaming, the depths listed above when marching -- lower tb
  * first).  A streaming run whose buffers are not 16-byte aligned falls back to the tiled
  * kernels; a marching run takes one column per lane instead. */
 int stencil_set_variant(st_plan* plan, int variant);
@@ -163,7 +164,8 @@ int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes);
 int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
                   size_t ws_bytes, void* stream);
 
-/* stencil_autotune -- time every supported (variant, tb, tile) candidate on the
+/* stencil_autotune -- time every supported (variant, tb, tile) candidate (LDS tiles with tb in
+ * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with every depth it offers) on the
  * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
@@ -213,7 +215,7 @@ int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* ou
 /* stencil_batch_set_class -- set the engine (0 = LDS tiles, 1 = marching) and pass depth of one
  * stencil class (shape 0 = star, 1 = box; radius 1..3) of the batch by hand; results are bitwise
  * the same for every choice.  Tiles: depth 1..16, further capped per grid by what its tile fits
- * in LDS.  Marching: depth up to 4 (r = 1), 3 (r = 2) or 2 (r = 3).  Errors: ST_EINVAL,
+ * in LDS.  Marching: depth up to 8 / 6 / 4 (star, r = 1 / 2 / 3) or 4 / 3 / 2 (box).  Errors: ST_EINVAL,
  * ST_EUNSUPPORTED (depth out of range). */
 int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, int depth);
 
@@ -222,7 +224,8 @@ int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, 
  * launch per pass for all tiled classes) with the depth capped at 1, 2, 3, 4, 6, 8, 12 or 16
  * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, one
  * column per lane, any width; one chain of launches per class, the classes on parallel branches
- * of the graph) with 1 .. 4 (r = 1), 3 (r = 2) or 2 (r = 3) levels.  Coordinate descent: each
+ * of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star r = 1 / 2 / 3, 4 / 3 / 2
+ * for box).  Coordinate descent: each
  * class in turn, every candidate timed on the whole batch run twice on the caller's buffers (outs
  * are overwritten; results are bitwise those of any other choice).  Writes the chosen depth and
  * engine (0 = tiles, 1 = marching) per class to tb_out[6] / engine_out[6] when non-NULL (star

@@ -399,7 +399,15 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
         if (var == VARIANT_MARCH && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
         plan->variant = var;
-        for (int tb : kTb) {
+        // LDS tiles: the depths of kTb; marching: every depth it offers
+        int cands[16], nc = 0;
+        if (var == VARIANT_MARCH) {
+            for (int tb = 1; tb <= max_tb(plan, tx, ty) && nc < 16; ++tb) cands[nc++] = tb;
+        } else {
+            for (int tb : kTb) cands[nc++] = tb;
+        }
+        for (int k = 0; k < nc; ++k) {
+            const int tb = cands[k];
             if (plan->kind == KIND_CONST && tb > max_tb(plan, tx, ty)) continue;
             if (tb > sample_steps) continue;
             plan->tb = tb;

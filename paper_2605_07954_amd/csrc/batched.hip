@@ -151,7 +151,8 @@ __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
     const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
     float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
     const march::MarchView v{src, dst, d.rows, d.cols, d.b};
-    march::march_task<ST_F32, R, 1, SH, TB>(v, d.w, lane, y0, y1, band * (64 - 2 * H) - H);
+    // one register per row in flight: every class keeps a ring length of input rows loading
+    march::march_task<ST_F32, R, 1, SH, TB, 2 * R + 1>(v, d.w, lane, y0, y1, band * (64 - 2 * H) - H);
 }
 
 using MarchPassFn = void (*)(MarchPassArgs);
@@ -160,9 +161,16 @@ template <int SH>
 MarchPassFn batched_march_fn(int r, int levels) {
 #define ST_BMARCH(R, TB) \
     if (r == R && levels == TB) return batched_march<R, SH, TB>;
-    ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4)
-    ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3)
-    ST_BMARCH(3, 1) ST_BMARCH(3, 2)
+    if constexpr (SH == SHAPE_STAR) {
+        ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4) ST_BMARCH(1, 5) ST_BMARCH(1, 6)
+        ST_BMARCH(1, 7) ST_BMARCH(1, 8)
+        ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3) ST_BMARCH(2, 4) ST_BMARCH(2, 5) ST_BMARCH(2, 6)
+        ST_BMARCH(3, 1) ST_BMARCH(3, 2) ST_BMARCH(3, 3) ST_BMARCH(3, 4)
+    } else {
+        ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4)
+        ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3)
+        ST_BMARCH(3, 1) ST_BMARCH(3, 2)
+    }
 #undef ST_BMARCH
     return nullptr;
 }
@@ -615,7 +623,7 @@ extern "C" int stencil_batch_set_class(st_batch* B, int shape, int radius, int e
     if (!B) return fail(ST_EINVAL, "batch is NULL");
     if ((shape != SHAPE_STAR && shape != SHAPE_BOX) || radius < 1 || radius > 3 || (engine != 0 && engine != 1))
         return fail(ST_EINVAL, "bad class or engine");
-    if (depth < 1 || depth > 16 || (engine == 1 && depth > march_max_tb(radius)))
+    if (depth < 1 || depth > 16 || (engine == 1 && depth > march_max_tb(shape, radius)))
         return fail(ST_EUNSUPPORTED, "depth out of range for this engine");
     const int c = shape * 3 + radius - 1;
     B->engine[c] = engine;
@@ -674,7 +682,7 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
         std::vector<std::pair<int, int>> cands;
         for (int cap : kCaps)
             if (cap <= deepest[c]) cands.push_back({0, cap});
-        for (int t = 1; t <= march_max_tb(r); ++t) cands.push_back({1, t});
+        for (int t = 1; t <= march_max_tb(c / 3, r); ++t) cands.push_back({1, t});
         std::pair<int, int> best = cands[0];
         float best_ms = 1e30f;
         for (const auto& cd : cands) {

@@ -97,9 +97,10 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
-// Row-marching pass (march.hip): FP32 constant-weight plans with cols % 4 == 0; up to
-// march_max_tb(radius) levels per pass (4 for r = 1, 3 for r = 2, else 2).
-int march_max_tb(int radius);
+// Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment; up to
+// march_max_tb(shape, radius) levels per pass (star: 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4; box:
+// 4 / 3 / 2 / 2).
+int march_max_tb(int shape, int radius);
 bool march_usable(const st_plan* p);
 int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s);
 // Drop a stale runtime error left by earlier API calls so that the check after our next

@@ -39,6 +39,11 @@ struct MarchArgs {
     float w[MAXK];
 };
 
+// Input rows a wavefront keeps in flight: one ring length (2r+1 rows, loaded that many iterations
+// before use) wherever the registers allow; box r >= 3 needs them for its rings and its long
+// per-row arithmetic hides a one-row lead anyway.
+constexpr int fifo_rows(int R, int SHAPE) { return SHAPE == SHAPE_STAR || R <= 2 ? 2 * R + 1 : 0; }
+
 template <int S, int R, int V, int SHAPE, int TB>
 __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int lane = int(threadIdx.x & 63);
@@ -52,7 +57,7 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
     const int64_t X0 = band * OUTW - V * H;
     const MarchView v{a.src, a.dst, a.rows, a.cols, a.b};
-    march_task<S, R, V, SHAPE, TB>(v, a.w, lane, y0, y1, X0);
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE)>(v, a.w, lane, y0, y1, X0);
 }
 
 template <int S, int R, int V, int SHAPE, int TB>
@@ -77,15 +82,23 @@ MarchFn march_kernel() {
     else return sweep_march<S, R, V, SH, TB>;
 }
 
-// Depths per radius: the rings of TB levels must fit the register file next to each other.
+// Depths per shape and radius: the rings of TB levels must fit the register file next to each
+// other (a star ring row holds V values, a box ring row V + 2r).
 template <int S, int V, int SH>
 MarchFn march_fn(int r, int levels) {
 #define ST_MARCH(R, TB) \
     if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB>();
-    ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4)
-    ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3)
-    ST_MARCH(3, 1) ST_MARCH(3, 2)
-    ST_MARCH(4, 1) ST_MARCH(4, 2)
+    if constexpr (SH == SHAPE_STAR) {
+        ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4) ST_MARCH(1, 5) ST_MARCH(1, 6) ST_MARCH(1, 7) ST_MARCH(1, 8)
+        ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3) ST_MARCH(2, 4) ST_MARCH(2, 5) ST_MARCH(2, 6)
+        ST_MARCH(3, 1) ST_MARCH(3, 2) ST_MARCH(3, 3) ST_MARCH(3, 4)
+        ST_MARCH(4, 1) ST_MARCH(4, 2) ST_MARCH(4, 3)
+    } else {
+        ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4)
+        ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3)
+        ST_MARCH(3, 1) ST_MARCH(3, 2)
+        ST_MARCH(4, 1) ST_MARCH(4, 2)
+    }
 #undef ST_MARCH
     return nullptr;
 }
@@ -110,7 +123,10 @@ MarchFn march_lookup(int storage, int V, int shape, int r, int levels) {
 
 }  // namespace
 
-int march_max_tb(int radius) { return radius == 1 ? 4 : radius == 2 ? 3 : 2; }
+int march_max_tb(int shape, int radius) {
+    if (shape == SHAPE_STAR) return radius == 1 ? 8 : radius == 2 ? 6 : radius == 3 ? 4 : 3;
+    return radius == 1 ? 4 : radius == 2 ? 3 : 2;
+}
 
 bool march_usable(const st_plan* p) { return p->kind == KIND_CONST && p->radius <= 4; }
 

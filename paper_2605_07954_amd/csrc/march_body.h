@@ -1,8 +1,7 @@
 // Device body of the row-marching Jacobi pass (paper Sec. II-C update with the fixed halo of
 // Sec. IV-A; per cell the FP32 order of Sec. IV-E), shared by the single-grid kernel and the batched
 // multi-grid kernel.  See march.hip for the design; this file holds the per-wavefront task:
-// march_one (one level) and march_levels (TB >= 2 levels) walk one band of columns over a
-// segment of rows.
+// march_levels walks one band of columns over a segment of rows, TB levels per pass.
 #pragma once
 
 #include "internal.h"
@@ -52,43 +51,45 @@ struct Cells {
     float c[V];
 };
 
-// The V outputs of a lane for one row; `ring[(base + R + dy) % N]` holds input row dy.
-template <int R, int V, int SHAPE, int N>
-__device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const float* w) {
-    constexpr int K = 2 * R + 1;
-    Cells<V> o;
-    const Row<R, V>& mid = ring[(base + R) % N];
-#pragma unroll
-    for (int c = 0; c < V; ++c) o.c[c] = w[R * K + R] * mid.v[R + c];
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
-        const Row<R, V>& x = ring[(base + R + dy) % N];
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-            if ((dy == 0 && dx == 0) || !tap_on(SHAPE, dy, dx)) continue;
-            const float wt = w[(dy + R) * K + dx + R];
-#pragma unroll
-            for (int c = 0; c < V; ++c) o.c[c] = __builtin_fmaf(wt, x.v[R + c + dx], o.c[c]);
-        }
-    }
-    return o;
+// What one load of V cells returns, still in the storage type: a prefetched row is widened to FP32
+// only when it enters the window, so the load need not complete before that.
+template <int S, int V>
+struct RawSel {
+    using type = typename Fmt<S>::T;
+};
+template <>
+struct RawSel<ST_F32, 4> {
+    using type = float4;
+};
+template <>
+struct RawSel<ST_BF16, 4> {
+    using type = uint2;
+};
+template <>
+struct RawSel<ST_F16, 4> {
+    using type = uint2;
+};
+template <int S, int V>
+using Raw = typename RawSel<S, V>::type;
+
+template <int S, int V>
+__device__ __forceinline__ Raw<S, V> load_raw(const void* src, int64_t off) {
+    return *reinterpret_cast<const Raw<S, V>*>(static_cast<const typename Fmt<S>::T*>(src) + off);
 }
 
-// V consecutive cells of the storage type from element offset `off`, widened to FP32 (exact).
+// Exact widening to FP32.
 template <int S, int V>
-__device__ __forceinline__ Cells<V> load_cells(const void* src, int64_t off) {
+__device__ __forceinline__ Cells<V> widen(Raw<S, V> r) {
     Cells<V> q;
     if constexpr (V == 1) {
-        q.c[0] = Fmt<S>::ld(static_cast<const typename Fmt<S>::T*>(src)[off]);
+        q.c[0] = Fmt<S>::ld(r);
     } else if constexpr (S == ST_F32) {
-        const float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(src) + off);
-        q.c[0] = f.x; q.c[1] = f.y; q.c[2] = f.z; q.c[3] = f.w;
+        q.c[0] = r.x; q.c[1] = r.y; q.c[2] = r.z; q.c[3] = r.w;
     } else {
-        const uint2 h = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(src) + off);
-        q.c[0] = Fmt<S>::ld(uint16_t(h.x & 0xffffu));
-        q.c[1] = Fmt<S>::ld(uint16_t(h.x >> 16));
-        q.c[2] = Fmt<S>::ld(uint16_t(h.y & 0xffffu));
-        q.c[3] = Fmt<S>::ld(uint16_t(h.y >> 16));
+        q.c[0] = Fmt<S>::ld(uint16_t(r.x & 0xffffu));
+        q.c[1] = Fmt<S>::ld(uint16_t(r.x >> 16));
+        q.c[2] = Fmt<S>::ld(uint16_t(r.y & 0xffffu));
+        q.c[3] = Fmt<S>::ld(uint16_t(r.y >> 16));
     }
     return q;
 }
@@ -109,84 +110,103 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
     for (int c = 0; c < V; ++c) x.v[R + c] = q.c[c];
 }
 
-// Loads one input row into `x` (own columns).  EDGE tasks may touch rows or columns outside the
-// grid: those cells hold b.  Interior tasks only clamp the row of a prefetch past the grid's end.
-template <int S, int R, int V, bool EDGE>
-__device__ __forceinline__ void load_row(Row<R, V>& x, const void* src, int64_t gy, int64_t rows, int64_t cols,
-                                         int64_t gx, bool col_in, float b) {
-    Cells<V> q;
-    if (EDGE) {
-        if (gy >= 0 && gy < rows && col_in) {
-            q = load_cells<S, V>(src, gy * cols + gx);
-        } else {
-#pragma unroll
-            for (int c = 0; c < V; ++c) q.c[c] = b;
-        }
-    } else {
-        const int64_t g = gy < rows ? gy : rows - 1;
-        q = load_cells<S, V>(src, g * cols + gx);
-    }
-    set_own<R, V>(x, q);
+// Where a lane reads input row gy: EDGE tasks clamp row and column into the grid (the cells they
+// stand for are replaced by b when the row is used, see `cells_of`); interior tasks only clamp a
+// prefetch past the grid's last row.
+template <bool EDGE>
+__device__ __forceinline__ int64_t src_offset(int64_t gy, int64_t rows, int64_t cols, int64_t gx, bool col_in) {
+    int64_t g = gy < rows ? gy : rows - 1;
+    if (EDGE) g = g < 0 ? 0 : g;
+    return g * cols + (EDGE && !col_in ? 0 : gx);
 }
 
-// One level: output rows [y0, y1) of the band whose first loaded column is X0.
-template <int S, int R, int V, int SHAPE, bool EDGE>
-__device__ __forceinline__ void march_one(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                          int64_t X0) {
-    constexpr int N = 2 * R + 2;  // window of 2R+1 rows plus one row in flight
-    constexpr int H = halo_lanes(R, 1, V);
+template <int S, int V, bool EDGE>
+__device__ __forceinline__ Cells<V> cells_of(Raw<S, V> r, int64_t gy, int64_t rows, bool col_in, float b) {
+    Cells<V> q = widen<S, V>(r);
+    if (EDGE && !(gy >= 0 && gy < rows && col_in)) {
+#pragma unroll
+        for (int c = 0; c < V; ++c) q.c[c] = b;
+    }
+    return q;
+}
+
+// The V outputs of a lane for one row; `ring[(base + R + dy) % N]` holds input row dy.  A box
+// footprint reads the side columns of every row, which each ring row therefore carries from the
+// moment it enters; a star footprint reads them on the centre row only, so ring rows hold their own
+// columns and the centre row's sides are produced here, once per row and level as well.
+template <int R, int V, int SHAPE, int N>
+__device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const float* w) {
+    constexpr int K = 2 * R + 1;
+    Row<R, V> mid = ring[(base + R) % N];
+    if constexpr (SHAPE == SHAPE_STAR) fill_sides<R, V>(mid);
+    Cells<V> o;
+#pragma unroll
+    for (int c = 0; c < V; ++c) o.c[c] = w[R * K + R] * mid.v[R + c];
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        const Row<R, V>& x = dy == 0 ? mid : ring[(base + R + dy) % N];
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            if ((dy == 0 && dx == 0) || !tap_on(SHAPE, dy, dx)) continue;
+            const float wt = w[(dy + R) * K + dx + R];
+#pragma unroll
+            for (int c = 0; c < V; ++c) o.c[c] = __builtin_fmaf(wt, x.v[R + c + dx], o.c[c]);
+        }
+    }
+    return o;
+}
+
+// TB levels over output rows [y0, y1) of the band whose first loaded column is X0.  Level l (0 =
+// input, TB = output) keeps its own ring of N = 2R+1 rows.  Iteration i computes level-1 row
+// m1 = y0 - R(TB-1) + i from the input rows m1-R .. m1+R, then, once enough rows of the level below
+// exist, level-l row m1 - (l-1)R for l = 2 .. TB.  Within level l the row of iteration i sits in slot
+// (i + l - 1) % N (because -2R = 1 mod N), so with the loop unrolled a multiple of N times every
+// slot index is a compile-time constant.
+//
+// Input rows are loaded D iterations before they enter the window, into a FIFO of D raw rows (D a
+// multiple of N; the loop is unrolled D times).  With D = 0 a row is loaded into the ring slot that
+// level 1 has just released, one iteration ahead.
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE>
+__device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
+                                             int64_t X0) {
+    constexpr int N = 2 * R + 1;
+    static_assert(D % N == 0, "the FIFO length must be a multiple of the ring length");
+    constexpr int U = D > 0 ? D : N;  // unroll
+    constexpr int H = halo_lanes(R, TB, V);
+    constexpr bool SIDES = SHAPE != SHAPE_STAR;  // ring rows carry side columns
     const int64_t rows = a.rows, cols = a.cols;
     const int64_t gx = X0 + V * lane;
     const bool col_in = gx >= 0 && gx + V <= cols;  // V = 4 only with cols % 4 == 0: all or none
     const bool writer = lane >= H && lane < 64 - H && (!EDGE || col_in);
     const float b = a.b;
-    Row<R, V> ring[N];
-    const int64_t j0 = y0 - R;  // input row held by slot 0 at the start; row j lives in slot (j - j0) % N
-#pragma unroll
-    for (int t = 0; t < N; ++t) load_row<S, R, V, EDGE>(ring[t], a.src, j0 + t, rows, cols, gx, col_in, b);
-#pragma unroll
-    for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(ring[t]);
-    for (int64_t k0 = y0; k0 < y1; k0 += N) {
-#pragma unroll
-        for (int u = 0; u < N; ++u) {
-            const int64_t k = k0 + u;
-            if (k >= y1) break;
-            fill_sides<R, V>(ring[(u + 2 * R) % N]);  // row k+R enters the window
-            const Cells<V> o = apply<R, V, SHAPE, N>(ring, u, w);
-            if (writer) store_cells<S, V>(a.dst, k * cols + gx, o);
-            load_row<S, R, V, EDGE>(ring[u], a.src, k - R + N, rows, cols, gx, col_in, b);  // row k-R is done
-        }
-    }
-}
-
-// TB >= 2 levels.  Level l (0 = input, TB = output) keeps its own ring of N = 2R+1 rows.  Iteration i
-// computes level-1 row m1 = y0 - R(TB-1) + i from the input rows m1-R .. m1+R, then, once enough rows
-// of the level below exist, level-l row m1 - (l-1)R for l = 2 .. TB.  Within level l the row of
-// iteration i sits in slot (i + l - 1) % N (because -2R = 1 mod N), so every slot index is a
-// compile-time constant of the loop unrolled N times.
-template <int S, int R, int V, int SHAPE, int TB, bool EDGE>
-__device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                             int64_t X0) {
-    constexpr int N = 2 * R + 1;
-    constexpr int H = halo_lanes(R, TB, V);
-    const int64_t rows = a.rows, cols = a.cols;
-    const int64_t gx = X0 + V * lane;
-    const bool col_in = gx >= 0 && gx + V <= cols;
-    const bool writer = lane >= H && lane < 64 - H && (!EDGE || col_in);
-    const float b = a.b;
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
-    const int64_t j0 = y0 - R * TB;  // input row in slot 0 at the start
+    Raw<S, V> fifo[D > 0 ? D : 1];
+    const int64_t j0 = y0 - R * TB;  // input row j lives in ring slot (j - j0) % N, FIFO slot (j - j0) % D
+    auto fetch = [&](int64_t j) { return load_raw<S, V>(a.src, src_offset<EDGE>(j, rows, cols, gx, col_in)); };
+    constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
-    for (int t = 0; t < N; ++t) load_row<S, R, V, EDGE>(lv[0][t], a.src, j0 + t, rows, cols, gx, col_in, b);
+    for (int t = 0; t < FIRST; ++t) {
+        set_own<R, V>(lv[0][t], cells_of<S, V, EDGE>(fetch(j0 + t), j0 + t, rows, col_in, b));
+        if (SIDES && t < 2 * R) fill_sides<R, V>(lv[0][t]);
+    }
+    if constexpr (D > 0) {
 #pragma unroll
-    for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
+        for (int t = 0; t < D; ++t) fifo[(2 * R + t) % D] = fetch(j0 + 2 * R + t);
+    }
     const int64_t iters = (y1 - y0) + 2 * R * (TB - 1);
-    for (int64_t i0 = 0; i0 < iters; i0 += N) {
+    for (int64_t i0 = 0; i0 < iters; i0 += U) {
 #pragma unroll
-        for (int u = 0; u < N; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + u;
             if (i >= iters) break;
-            fill_sides<R, V>(lv[0][(u + 2 * R) % N]);  // input row m1 + R enters the window
+            Row<R, V>& in = lv[0][(u + 2 * R) % N];  // input row j0 + i + 2R enters the window
+            if constexpr (D > 0) {
+                const int f = (u + 2 * R) % D;
+                const int64_t j = j0 + i + 2 * R;
+                set_own<R, V>(in, cells_of<S, V, EDGE>(fifo[f], j, rows, col_in, b));
+                fifo[f] = fetch(j + D);
+            }
+            if (SIDES) fill_sides<R, V>(in);
 #pragma unroll
             for (int l = 1; l <= TB; ++l) {
                 if (i < 2 * R * (l - 1)) break;  // level l - 1 does not have 2R+1 rows yet
@@ -201,10 +221,12 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
 #pragma unroll
                     for (int c = 0; c < V; ++c) q.c[c] = inside ? Fmt<S>::rnd(q.c[c]) : b;
                     set_own<R, V>(x, q);
-                    fill_sides<R, V>(x);
+                    if (SIDES) fill_sides<R, V>(x);
                 }
-                if (l == 1)  // input row m1 - R is no longer needed: fetch the row N further down
-                    load_row<S, R, V, EDGE>(lv[0][u], a.src, j0 + i + N, rows, cols, gx, col_in, b);
+                if (D == 0 && l == 1) {  // input row m1 - R is no longer needed: fetch the row N further down
+                    const int64_t j = j0 + i + N;
+                    set_own<R, V>(lv[0][u % N], cells_of<S, V, EDGE>(fetch(j), j, rows, col_in, b));
+                }
             }
         }
     }
@@ -227,20 +249,16 @@ __device__ __forceinline__ void load_weights(const float* w, float* wv) {
     }
 }
 
-// One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels.
-template <int S, int R, int V, int SHAPE, int TB>
+// One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels, input rows
+// loaded D iterations ahead (0: one).
+template <int S, int R, int V, int SHAPE, int TB, int D>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                            int64_t X0) {
     const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 64 * V > a.cols;
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    if constexpr (TB == 1) {
-        if (edge) march_one<S, R, V, SHAPE, true>(a, wv, lane, y0, y1, X0);
-        else march_one<S, R, V, SHAPE, false>(a, wv, lane, y0, y1, X0);
-    } else {
-        if (edge) march_levels<S, R, V, SHAPE, TB, true>(a, wv, lane, y0, y1, X0);
-        else march_levels<S, R, V, SHAPE, TB, false>(a, wv, lane, y0, y1, X0);
-    }
+    if (edge) march_levels<S, R, V, SHAPE, TB, D, true>(a, wv, lane, y0, y1, X0);
+    else march_levels<S, R, V, SHAPE, TB, D, false>(a, wv, lane, y0, y1, X0);
 }
 
 }  // namespace march

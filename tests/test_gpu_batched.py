@@ -157,7 +157,7 @@ def test_batched_engines_every_class_bitwise(g, graph):
     problems = []
     for k, (shape, r) in enumerate([(wl.STAR, 1), (wl.BOX, 1), (wl.STAR, 2), (wl.BOX, 2), (wl.STAR, 3), (wl.BOX, 3)]):
         for j in range(2):
-            rows, cols, steps = [(150 + 37 * k, 301 + 11 * k, 7 + k % 2), (233, 130 + 16 * k, 5)][j]
+            rows, cols, steps = [(150 + 37 * k, 301 + 11 * k, 7 + k % 2), (233, 130 + 16 * k, 13)][j]
             w = wl.random_footprint_weights(np.random.default_rng(700 + 10 * k + j), shape, r)
             problems.append(wl.Problem(f"{shape}{r}-{j}", rows, cols, r, shape, w, 0.0 if j else 0.5, steps,
                                        rng.random((rows, cols), dtype=np.float32)))
@@ -169,11 +169,12 @@ def test_batched_engines_every_class_bitwise(g, graph):
             ins = [g.to_dev(p.u0) for p in problems]
             outs = [torch.empty_like(x) for x in ins]
             ws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device=g.DEV)
-            for engine, depths in (("march", {1: 4, 2: 3, 3: 2}), ("tiles", {1: 4, 2: 3, 3: 2})):
+            deepest = {"star": {1: 8, 2: 6, 3: 4}, "box": {1: 4, 2: 3, 3: 2}}  # marching
+            for engine in ("march", "tiles"):
                 for r in (1, 2, 3):
-                    for depth in range(1, depths[r] + 1):
-                        for shape in ("star", "box"):
-                            lib.stencil_batch_set_class(batch, shape, r, engine, depth)
+                    for depth in range(1, deepest["star"][r] + 1):
+                        for shape in ("star", "box"):  # the box classes stay at their deepest
+                            lib.stencil_batch_set_class(batch, shape, r, engine, min(depth, deepest[shape][r]))
                         for o in outs:
                             o.fill_(float("nan"))
                         lib.stencil_run_batched(batch, ins, outs, ws)
@@ -181,7 +182,9 @@ def test_batched_engines_every_class_bitwise(g, graph):
                         for p, o, ref in zip(problems, outs, refs):
                             np.testing.assert_array_equal(g.to_host(o), ref, err_msg=f"{p.name} {engine} r{r} x{depth}")
             with pytest.raises(lib.StencilError):
-                lib.stencil_batch_set_class(batch, "star", 3, "march", 3)
+                lib.stencil_batch_set_class(batch, "star", 3, "march", 5)
+            with pytest.raises(lib.StencilError):
+                lib.stencil_batch_set_class(batch, "box", 3, "march", 3)
         finally:
             lib.stencil_batch_destroy(batch)
     finally:

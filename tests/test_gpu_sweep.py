@@ -257,12 +257,17 @@ def test_stream_variant_bitwise(g, rows, cols, shape, r, b, steps):
         lib.stencil_destroy(plan)
 
 
+def march_depth(shape, r):
+    """Deepest pass the marching variant offers: star rings hold only their own columns."""
+    return {1: 8, 2: 6, 3: 4, 4: 3}[r] if shape == wl.STAR else {1: 4, 2: 3}.get(r, 2)
+
+
 MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exactly one band (tb 1: 248
     # columns, tb 2: 240), one column group past it, many bands; segments with ragged ends; b != 0;
     # grids shorter than the radius; odd step counts (the last two-level pass has one level)
     (1, 4, wl.BOX, 3, 0.0, 3), (5, 8, wl.STAR, 4, 0.5, 4), (37, 248, wl.BOX, 3, 0.0, 5), (40, 240, wl.BOX, 2, 0.25, 5),
-    (33, 252, wl.STAR, 1, -1.0, 7), (300, 516, wl.BOX, 1, 0.0, 9), (257, 1000, wl.STAR, 2, 0.0, 6),
-    (1024, 1024, wl.BOX, 3, 0.0, 7), (700, 1200, wl.STAR, 3, 0.5, 5), (129, 996, wl.BOX, 4, 0.0, 3),
+    (33, 252, wl.STAR, 1, -1.0, 17), (300, 516, wl.BOX, 1, 0.0, 9), (257, 1000, wl.STAR, 2, 0.0, 13),
+    (1024, 1024, wl.BOX, 3, 0.0, 7), (700, 1200, wl.STAR, 3, 0.5, 9), (129, 996, wl.BOX, 4, 0.0, 3),
     (2050, 64, wl.STAR, 4, 0.0, 4),
     # widths that are not a multiple of 4 (one column per lane): narrower than a band, one band
     # plus one column, many bands with a ragged end
@@ -273,8 +278,8 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
 @pytest.mark.parametrize("case", MARCH_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in MARCH_CASES])
 def test_march_variant_bitwise(g, case):
     """The row-marching variant (one wavefront per column band, lane-shifted side columns) equals the
-    FP32-canonical oracle bit for bit at every depth it offers for the radius (r = 1: up to 4 levels,
-    r = 2: 3, else 2), with four columns per lane (width a multiple of 4, aligned buffers) and with one
+    FP32-canonical oracle bit for bit at every depth it offers for the shape and radius (star r = 1 /
+    2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 4 / 3 / 2 / 2), with four columns per lane (width a multiple of 4, aligned buffers) and with one
     (any other width, or buffers off a 16-byte boundary)."""
     import torch
     import paper_2605_07954_amd as lib
@@ -283,7 +288,7 @@ def test_march_variant_bitwise(g, case):
     u0 = np.random.default_rng(rows * cols + 7).random((rows, cols), dtype=np.float32)
     ref = oracle.stencil_f32(u0, W, b, steps)
     x = g.to_dev(u0)
-    deepest = {1: 4, 2: 3}.get(r, 2)
+    deepest = march_depth(shape, r)
     for tb in range(1, deepest + 1):
         plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
         try:
@@ -319,7 +324,7 @@ def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
     W = _weights(shape, r, rows + 5 * cols + r)
     bits = oracle.to_bits(np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32), storage)
     ref = oracle.stencil_lowp(bits, W, b, steps, storage)
-    for tb in range(1, {1: 4, 2: 3}.get(r, 2) + 1):
+    for tb in range(1, march_depth(shape, r) + 1):
         plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
         try:
             lib.stencil_set_blocking(plan, 1)
