@@ -2,10 +2,10 @@
 // padding), channels 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias everywhere, exact-erf GELU after
 // layers 1-5, residual output u_hat = u0 + f(u0, (kappa - 0.125) / 0.075).
 //
-//   layer 1 (2 -> 32)   vector ALU, FP32
+//   layer 1 (2 -> 32)   FP32 MFMA (v_mfma_f32_16x16x4_f32), K = 9 taps x 2 inputs
 //   layers 2-5 (32->32) BF16 MFMA implicit GEMM (v_mfma_f32_16x16x32_bf16), FP32 accumulate:
-//                       M = 16 consecutive pixels of a row, N = 16 output channels, K = the 32
-//                       input channels of one tap; 9 taps x 2 N-halves per 16 pixels
+//                       M = 16 output channels, N = 16 consecutive pixels of a row, K = the 32
+//                       input channels of one tap; 9 taps x 2 M-halves per 16 pixels
 //   layer 6 (32 -> 1)   vector ALU, FP32 over BF16 activations
 // Backward: dA = the same MFMA convolution with the taps flipped and the channel roles swapped,
 // times GELU'(Z) in the epilogue; dW of layers 2-5 is an MFMA GEMM whose reduction runs over
@@ -53,48 +53,55 @@ __device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(ui
 // t (c2 + ... + t c9))) with t = 1 / (1 + x / 2), fractional error below 1.2e-7 everywhere -- so
 // Phi(z) keeps its relative accuracy far into the negative tail, where GELU is small and its BF16
 // rounding is still done relative to its own size.
-struct NormalCdf {
-    float cdf;  // Phi(z)
-    float pdf;  // phi(z)
+//
+// Evaluated as a power of two: with L = log2(e) and s = x sqrt(L) = |z| sqrt(L / 2),
+//   tail = erfc(x) / 2 = 1 - Phi(|z|) = t 2^(-s^2 + (L c0 - 1) + t (L c1 + t (L c2 + ...))),
+//   t = 1 / (1 + s / (2 sqrt L)),   phi(z) = 2^(-s^2 + log2(1 / sqrt(2 pi))),
+// so the scale factors fold into the constants, and GELU(z) = max(z, 0) - |z| tail for either sign.
+struct ErfcTail {
+    float s;     // |z| sqrt(L / 2)
+    float tail;  // 1 - Phi(|z|)
 };
 
-__device__ __forceinline__ float horner9(float t) {
-    constexpr float C1 = 1.00002368f, C2 = 0.37409196f, C3 = 0.09678418f, C4 = -0.18628806f, C5 = 0.27886807f,
-                    C6 = -1.13520398f, C7 = 1.48851587f, C8 = -0.82215223f, C9 = 0.17087277f;
-    float p = __builtin_fmaf(C9, t, C8);
-    p = __builtin_fmaf(p, t, C7);
-    p = __builtin_fmaf(p, t, C6);
-    p = __builtin_fmaf(p, t, C5);
-    p = __builtin_fmaf(p, t, C4);
-    p = __builtin_fmaf(p, t, C3);
-    p = __builtin_fmaf(p, t, C2);
-    return __builtin_fmaf(p, t, C1);
-}
-
-template <bool WITH_PDF>
-__device__ __forceinline__ NormalCdf normal_cdf(float z) {
-    constexpr float C0 = -1.26551223f;
-    constexpr float INV_SQRT2 = 0.70710678118654752f, INV_SQRT_2PI = 0.39894228040143268f;
-    constexpr float LOG2E = 1.44269504088896341f;
-    const float x = fabsf(z) * INV_SQRT2;
-    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.5f, x, 1.0f));
-    const float arg = __builtin_fmaf(-x, x, __builtin_fmaf(horner9(t), t, C0));
-    const float tail = 0.5f * t * __builtin_amdgcn_exp2f(arg * LOG2E);  // erfc(x) / 2 = 1 - Phi(|z|)
-    NormalCdf r;
-    r.cdf = z >= 0.0f ? 1.0f - tail : tail;
-    r.pdf = WITH_PDF ? INV_SQRT_2PI * __builtin_amdgcn_exp2f(-(x * x) * LOG2E) : 0.0f;
+__device__ __forceinline__ ErfcTail erfc_tail(float z) {
+    constexpr float KS = 0.849321782588958740f;  // sqrt(L / 2)
+    constexpr float KT = 0.416277319192886353f;  // 1 / (2 sqrt L)
+    constexpr float D0 = -2.82574820518493652f, D1 = 1.44272923469543457f, D2 = 0.539700627326965332f,
+                    D3 = 0.139630049467086792f, D4 = -0.268756866455078125f, D5 = 0.402321577072143555f,
+                    D6 = -1.63775312900543213f, D7 = 2.14747452735900879f, D8 = -1.18611490726470947f,
+                    D9 = 0.246517300605773926f;  // L c_k, and L c0 - 1
+    ErfcTail r;
+    r.s = fabsf(z) * KS;
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(KT, r.s, 1.0f));
+    float p = __builtin_fmaf(D9, t, D8);
+    p = __builtin_fmaf(p, t, D7);
+    p = __builtin_fmaf(p, t, D6);
+    p = __builtin_fmaf(p, t, D5);
+    p = __builtin_fmaf(p, t, D4);
+    p = __builtin_fmaf(p, t, D3);
+    p = __builtin_fmaf(p, t, D2);
+    p = __builtin_fmaf(p, t, D1);
+    p = __builtin_fmaf(p, t, D0);
+    r.tail = t * __builtin_amdgcn_exp2f(__builtin_fmaf(-r.s, r.s, p));
     return r;
 }
 
-__device__ __forceinline__ float gelu(float z) { return z * normal_cdf<false>(z).cdf; }
+__device__ __forceinline__ float gelu(float z) {
+    return __builtin_fmaf(-fabsf(z), erfc_tail(z).tail, fmaxf(z, 0.0f));
+}
+
 __device__ __forceinline__ float gelu_grad(float z) {
-    const NormalCdf n = normal_cdf<true>(z);
-    return __builtin_fmaf(z, n.pdf, n.cdf);
+    constexpr float LOG2_INV_SQRT_2PI = -1.32574808597564697f;
+    const ErfcTail e = erfc_tail(z);
+    const float cdf = z >= 0.0f ? 1.0f - e.tail : e.tail;
+    const float pdf = __builtin_amdgcn_exp2f(__builtin_fmaf(-e.s, e.s, LOG2_INV_SQRT_2PI));
+    return __builtin_fmaf(z, pdf, cdf);
 }
 
 // ---------------------------------------------------------------------------
-// weight preparation: FP32 master -> BF16 MFMA B-operand fragments
-// frag[tap][nt][lane][8]: lane holds W'[tap][k = 8*(lane/16) + i][n = 16*nt + lane%16]
+// weight preparation: FP32 master -> BF16 MFMA A-operand fragments
+// frag[tap][nt][lane][8]: lane holds W'[tap][k = 8*(lane/16) + i][n = 16*nt + lane%16], i.e. the
+// 16 x 32 (output channel x input channel) A operand with row n - 16 nt = lane % 16
 // forward:   W'[tap][ci][co]  = W[tap][ci][co]
 // backward:  W'[tap][co][ci]  = W[8 - tap][ci][co]   (flipped taps, swapped channel roles)
 // ---------------------------------------------------------------------------
@@ -115,53 +122,67 @@ __global__ void prep_frags(const float* params, uint16_t* frags) {
 }
 
 // ---------------------------------------------------------------------------
-// layer 1: 2 -> 32, vector ALU
+// Tiles of TH x TW output pixels; their input is the haloed (TH+2) x (TW+2) patch of NHWC BF16
+// activations (4 chunks of 8 channels per pixel).  The persistent kernels below walk tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...: the next tile's patch is loaded into registers while
+// the current one computes from LDS (two LDS buffers, one barrier per tile).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* u0, const float* kappa, int nb,
-                                              int H, int W, float* Z, uint16_t* A) {
-    __shared__ float w[9 * 2 * C + C];
-    for (int k = threadIdx.x; k < 9 * 2 * C + C; k += 256) w[k] = params[k];
-    __syncthreads();
-    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (p >= int64_t(nb) * H * W) return;
-    const int64_t b = p / (int64_t(H) * W);
-    const int y = int((p / W) % H), x = int(p % W);
-    float in[9][2];
+constexpr int TH = 8, TW = 32;
+constexpr int TPIX = (TH + 2) * (TW + 2);      // haloed patch pixels
+constexpr int TCHUNK = TPIX * 4;               // 16-byte chunks in the patch
+constexpr int SPT = (TCHUNK + 255) / 256;      // chunks per thread
+
+// LDS slot of chunk c of patch pixel p: the chunk index is XOR-ed with bits 2-3 of the pixel, so
+// that the same chunk of 16 consecutive pixels lands in 16 distinct 16-byte bank groups.
+__device__ __forceinline__ int slot(int p, int c) { return p * 4 + (c ^ ((p >> 2) & 3)); }
+
+struct Tile {
+    int b, y0, x0;
+};
+
+__device__ __forceinline__ Tile tile_at(int64_t t, int H, int W) {
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int64_t per = int64_t(tiles_x) * tiles_y;
+    const int r = int(t % per);
+    return Tile{int(t / per), (r / tiles_x) * TH, (r % tiles_x) * TW};
+}
+
+__host__ __device__ inline int64_t tile_count(int nb, int H, int W) {
+    return int64_t(nb) * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+}
+
+// Global loads of a tile's patch (zero outside the field) into registers.  Offsets within the
+// patch are 32-bit (9 rows of W * C < 2^31 elements); a tile whose patch lies inside the field
+// loads without per-pixel checks.
+__device__ __forceinline__ void patch_fetch(const uint16_t* X, Tile tc, int H, int W, uint4 (&r)[SPT]) {
+    const int64_t base = ((int64_t(tc.b) * H + (tc.y0 - 1)) * W + (tc.x0 - 1)) * C;  // patch pixel (0, 0)
+    const bool inside = tc.y0 >= 1 && tc.y0 + TH + 1 <= H && tc.x0 >= 1 && tc.x0 + TW + 1 <= W;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-            const int64_t q = (b * H + yy) * W + xx;
-            in[t][0] = u0[q];
-            in[t][1] = (kappa[q] - KMID) / KHALF;
-        } else {
-            in[t][0] = in[t][1] = 0.0f;
-        }
+    for (int j = 0; j < SPT; ++j) {
+        const int k = int(threadIdx.x) + 256 * j;
+        const int pix = k >> 2, ch = k & 3;
+        const int py = pix / (TW + 2), px = pix % (TW + 2);
+        const int yy = tc.y0 - 1 + py, xx = tc.x0 - 1 + px;
+        r[j] = make_uint4(0, 0, 0, 0);
+        if (k < TCHUNK && (inside || (yy >= 0 && yy < H && xx >= 0 && xx < W)))
+            r[j] = *reinterpret_cast<const uint4*>(X + (base + ((py * W + px) * C + ch * 8)));
     }
-    uint32_t packed[C / 2];
+}
+
+__device__ __forceinline__ void patch_store(uint4* lds, const uint4 (&r)[SPT]) {
 #pragma unroll
-    for (int co = 0; co < C; ++co) {
-        float acc = w[9 * 2 * C + co];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            acc = __builtin_fmaf(w[(t * 2 + 0) * C + co], in[t][0], acc);
-            acc = __builtin_fmaf(w[(t * 2 + 1) * C + co], in[t][1], acc);
-        }
-        if (Z) Z[p * C + co] = acc;
-        const uint32_t h = f2bf(gelu(acc));
-        if (co & 1) packed[co / 2] |= h << 16; else packed[co / 2] = h;
+    for (int j = 0; j < SPT; ++j) {
+        const int k = int(threadIdx.x) + 256 * j;
+        if (k < TCHUNK) lds[slot(k >> 2, k & 3)] = r[j];
     }
-    uint4* dst = reinterpret_cast<uint4*>(A + p * C);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
 }
 
 // ---------------------------------------------------------------------------
-// 32 -> 32 MFMA convolution (forward, or backward-data with flipped fragments)
-// Tile: TH x TW pixels per 256-thread workgroup; each wave owns TH/4 rows x TW pixels.
+// 32 -> 32 MFMA convolution (forward, or backward-data with flipped fragments).  Each wave owns
+// TH/4 rows x TW pixels of a tile.  The weights are the A operand (M = 16 output channels, K = 32
+// input channels of one tap) and the activations the B operand (N = 16 pixels), so a lane's result
+// is 4 consecutive channels of one pixel and the epilogue writes 8- or 16-byte vectors.
 // ---------------------------------------------------------------------------
-constexpr int TH = 8, TW = 32;
-
 enum Epi { EPI_FWD = 0, EPI_BWD_BF16 = 1, EPI_BWD_F32 = 2 };
 
 struct ConvArgs {
@@ -173,125 +194,249 @@ struct ConvArgs {
     uint16_t* Aout;         // fwd: GELU(Z) bf16; bwd: dZ bf16
     float* Fout;            // bwd: dZ fp32 (layer-1 target)
     int nb, H, W;
-    int epi;
 };
 
-__global__ __launch_bounds__(256) void conv_mfma(ConvArgs a) {
-    __shared__ uint4 tile[(TH + 2) * (TW + 2) * 4];  // pixels x 4 chunks of 8 channels
-    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
-    const int64_t bt = blockIdx.x;
-    const int b = int(bt / (int64_t(tiles_x) * tiles_y));
-    const int tr = int(bt % (int64_t(tiles_x) * tiles_y));
-    const int y0 = (tr / tiles_x) * TH, x0 = (tr % tiles_x) * TW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    return uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
+}
 
-    // stage the haloed input tile (zero outside the field)
-    for (int k = threadIdx.x; k < (TH + 2) * (TW + 2) * 4; k += 256) {
-        const int pix = k >> 2, ch = k & 3;
-        const int yy = y0 - 1 + pix / (TW + 2), xx = x0 - 1 + pix % (TW + 2);
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-            v = reinterpret_cast<const uint4*>(a.X + ((int64_t(b) * a.H + yy) * a.W + xx) * C)[ch];
-        tile[k] = v;
-    }
-    // B fragments of all taps into registers
-    bf16x8_t bfr[9][2];
+template <int EPI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv_mfma(ConvArgs a) {
+    __shared__ uint4 patch[2][TCHUNK];
+    const int64_t ntiles = tile_count(a.nb, a.H, a.W);
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // A fragments of all taps, loaded once per workgroup
+    bf16x8_t wf[9][2];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int k = 0; k < 9; ++k)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
-            bfr[t][nt] = *reinterpret_cast<const bf16x8_t*>(a.frags + ((t * 2 + nt) * 64 + lane) * 8);
-    __syncthreads();
-
-    constexpr int ROWS = TH / 4;   // rows per wave
-    constexpr int MT = TW / 16;    // M-tiles per row
-    f32x4_t acc[ROWS][MT][2];
+            wf[k][nt] = *reinterpret_cast<const bf16x8_t*>(a.frags + ((k * 2 + nt) * 64 + lane) * 8);
+    const int lane_px = lane & 15, ch0 = 4 * (lane >> 4);  // result: channels 16 nt + ch0 + i of pixel lane_px
+    float bias[2][4];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r)
+    for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+        for (int i = 0; i < 4; ++i) bias[nt][i] = EPI == EPI_FWD ? a.bias[16 * nt + ch0 + i] : 0.0f;
+    constexpr int ROWS = TH / 4;  // rows per wave
+    constexpr int MT = TW / 16;   // 16-pixel groups per row
+    uint4 pre[SPT];
+    patch_fetch(a.X, tile_at(t, a.H, a.W), a.H, a.W, pre);
+    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+        const Tile tc = tile_at(t, a.H, a.W);
+        uint4* lds = patch[buf];
+        patch_store(lds, pre);
+        __syncthreads();
+        if (t + gridDim.x < ntiles) patch_fetch(a.X, tile_at(t + gridDim.x, a.H, a.W), a.H, a.W, pre);
+        f32x4_t acc[ROWS][MT][2];
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) acc[r][m][nt] = f32x4_t{0, 0, 0, 0};
+        for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int ty = wave * ROWS + r;
+            for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
+                for (int nt = 0; nt < 2; ++nt) acc[r][m][nt] = f32x4_t{0, 0, 0, 0};
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int py = ty + t / 3, px = m * 16 + (lane & 15) + t % 3;
-                const uint4 q = tile[(py * (TW + 2) + px) * 4 + (lane >> 4)];
-                const bf16x8_t av = __builtin_bit_cast(bf16x8_t, q);
-                acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bfr[t][0], acc[r][m][0], 0, 0, 0);
-                acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bfr[t][1], acc[r][m][1], 0, 0, 0);
+        for (int r = 0; r < ROWS; ++r) {
+            const int ty = wave * ROWS + r;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const int p = (ty + k / 3) * (TW + 2) + m * 16 + lane_px + k % 3;
+                    const bf16x8_t xv = __builtin_bit_cast(bf16x8_t, lds[slot(p, lane >> 4)]);
+                    acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][0], xv, acc[r][m][0], 0, 0, 0);
+                    acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][1], xv, acc[r][m][1], 0, 0, 0);
+                }
             }
         }
-    }
-    // epilogue: lane holds D[pixel m = 4*(lane/16) + i][channel 16*nt + lane%16].  Offsets inside a
-    // row are 32-bit (W * C < 2^31 is checked on the host); one 64-bit row base per row.
-    const int lane_px = 4 * (lane >> 4), lane_ch = lane & 15;
-    float bias[2];
+        // epilogue; offsets inside a row are 32-bit (W * C < 2^31 is checked on the host)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) bias[nt] = a.epi == EPI_FWD ? a.bias[16 * nt + lane_ch] : 0.0f;
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = tc.y0 + wave * ROWS + r;
+            if (y >= a.H) continue;
+            const int64_t row = (int64_t(tc.b) * a.H + y) * a.W * C;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int y = y0 + wave * ROWS + r;
-        if (y >= a.H) continue;
-        const int64_t row = (int64_t(b) * a.H + y) * a.W * C;
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + m * 16 + lane_px + i;
+            for (int m = 0; m < MT; ++m) {
+                const int x = tc.x0 + m * 16 + lane_px;
                 if (x >= a.W) continue;
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
-                    const int64_t o = row + (x * C + 16 * nt + lane_ch);
-                    float v = acc[r][m][nt][i];
-                    if (a.epi == EPI_FWD) {
-                        v += bias[nt];
-                        if (a.Zout) a.Zout[o] = v;
-                        a.Aout[o] = f2bf(gelu(v));
+                    const int64_t o = row + (x * C + 16 * nt + ch0);
+                    float v[4];
+                    if (EPI == EPI_FWD) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = acc[r][m][nt][i] + bias[nt][i];
+                        if (a.Zout) *reinterpret_cast<float4*>(a.Zout + o) = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = gelu(v[i]);
                     } else {
-                        v *= gelu_grad(a.Zprev[o]);
-                        if (a.epi == EPI_BWD_BF16) a.Aout[o] = f2bf(v);
-                        else a.Fout[o] = v;
+                        const float4 z = *reinterpret_cast<const float4*>(a.Zprev + o);
+                        v[0] = acc[r][m][nt][0] * gelu_grad(z.x);
+                        v[1] = acc[r][m][nt][1] * gelu_grad(z.y);
+                        v[2] = acc[r][m][nt][2] * gelu_grad(z.z);
+                        v[3] = acc[r][m][nt][3] * gelu_grad(z.w);
                     }
+                    if (EPI == EPI_BWD_F32)
+                        *reinterpret_cast<float4*>(a.Fout + o) = make_float4(v[0], v[1], v[2], v[3]);
+                    else
+                        *reinterpret_cast<uint2*>(a.Aout + o) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
                 }
             }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// layer 6: 32 -> 1 (forward with residual; backward data)
+// layer 1: 2 -> 32 in FP32 on MFMA (v_mfma_f32_16x16x4_f32): M = 16 output channels, N = 16 pixels
+// of a row, K = the 18 (tap, input channel) pairs k = 2 tap + c, padded to 20.  The patch holds
+// (u0, (kappa - 0.125) / 0.075) per pixel in FP32, normalised once per patch pixel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void l6_fwd(const float* params, const uint16_t* A5, const float* u0, int nb, int H,
-                                              int W, float* uhat) {
-    __shared__ float w[9 * C + 1];
-    for (int k = threadIdx.x; k < 9 * C + 1; k += 256) w[k] = params[woff(5) + k];
-    __syncthreads();
-    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (p >= int64_t(nb) * H * W) return;
-    const int64_t b = p / (int64_t(H) * W);
-    const int y = int((p / W) % H), x = int(p % W);
-    float acc = w[9 * C];
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-        const uint4* src = reinterpret_cast<const uint4*>(A5 + ((b * H + yy) * W + xx) * C);
+constexpr int SPT1 = (TPIX + 255) / 256;  // patch pixels per thread
+
+__device__ __forceinline__ void input_fetch(const float* u0, const float* kappa, Tile tc, int H, int W,
+                                            float2 (&r)[SPT1]) {
+    const int64_t base = (int64_t(tc.b) * H + (tc.y0 - 1)) * W + (tc.x0 - 1);  // patch pixel (0, 0)
+    const bool inside = tc.y0 >= 1 && tc.y0 + TH + 1 <= H && tc.x0 >= 1 && tc.x0 + TW + 1 <= W;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 v = src[q];
-            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+    for (int j = 0; j < SPT1; ++j) {
+        const int k = int(threadIdx.x) + 256 * j;
+        const int py = k / (TW + 2), px = k % (TW + 2);
+        const int yy = tc.y0 - 1 + py, xx = tc.x0 - 1 + px;
+        r[j] = make_float2(0.0f, KMID);  // zero padding of both input channels
+        if (k < TPIX && (inside || (yy >= 0 && yy < H && xx >= 0 && xx < W))) {
+            const int64_t q = base + (py * W + px);
+            r[j] = make_float2(u0[q], kappa[q]);
+        }
+    }
+}
+
+__device__ __forceinline__ void input_store(float* lds, const float2 (&r)[SPT1]) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ci = q * 8 + 2 * e;
-                acc = __builtin_fmaf(w[t * C + ci], bf2f(uint16_t(wd[e] & 0xffffu)), acc);
-                acc = __builtin_fmaf(w[t * C + ci + 1], bf2f(uint16_t(wd[e] >> 16)), acc);
+    for (int j = 0; j < SPT1; ++j) {
+        const int k = int(threadIdx.x) + 256 * j;
+        if (k < TPIX) {
+            lds[2 * k] = r[j].x;
+            lds[2 * k + 1] = (r[j].y - KMID) / KHALF;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* u0, const float* kappa, int nb,
+                                              int H, int W, float* Z, uint16_t* A) {
+    __shared__ float patch[2][2 * TPIX];
+    const int64_t ntiles = tile_count(nb, H, W);
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane_px = lane & 15, ch0 = 4 * (lane >> 4);
+    // per K step s this lane supplies k = 4 s + lane / 16: weight W1[k][co] (A) and the patch value
+    // at tap k / 2, channel k % 2 (B), found at `koff[s]` floats from its pixel's first channel
+    float wa[5][2];
+    int koff[5];
+#pragma unroll
+    for (int s5 = 0; s5 < 5; ++s5) {
+        const int k = 4 * s5 + (lane >> 4);
+        const int tap = k >> 1;
+        koff[s5] = k < 18 ? 2 * ((tap / 3) * (TW + 2) + tap % 3) + (k & 1) : -1;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) wa[s5][mt] = k < 18 ? params[k * C + 16 * mt + lane_px] : 0.0f;
+    }
+    float bias[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[mt][i] = params[9 * 2 * C + 16 * mt + ch0 + i];
+    constexpr int ROWS = TH / 4, MT = TW / 16;
+    float2 pre[SPT1];
+    input_fetch(u0, kappa, tile_at(t, H, W), H, W, pre);
+    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+        const Tile tc = tile_at(t, H, W);
+        float* lds = patch[buf];
+        input_store(lds, pre);
+        __syncthreads();
+        if (t + gridDim.x < ntiles) input_fetch(u0, kappa, tile_at(t + gridDim.x, H, W), H, W, pre);
+        f32x4_t acc[ROWS][MT][2];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                acc[r][m][0] = acc[r][m][1] = f32x4_t{0, 0, 0, 0};
+                const int pix = (wave * ROWS + r) * (TW + 2) + m * 16 + lane_px;
+#pragma unroll
+                for (int s5 = 0; s5 < 5; ++s5) {
+                    const float bv = koff[s5] >= 0 ? lds[2 * pix + koff[s5]] : 0.0f;
+                    acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s5][0], bv, acc[r][m][0], 0, 0, 0);
+                    acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s5][1], bv, acc[r][m][1], 0, 0, 0);
+                }
+            }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int y = tc.y0 + wave * ROWS + r;
+            if (y >= H) continue;
+            const int64_t row = (int64_t(tc.b) * H + y) * W * C;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int x = tc.x0 + m * 16 + lane_px;
+                if (x >= W) continue;
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    const int64_t o = row + (x * C + 16 * mt + ch0);
+                    float v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = acc[r][m][mt][i] + bias[mt][i];
+                    if (Z) *reinterpret_cast<float4*>(Z + o) = make_float4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<uint2*>(A + o) =
+                        make_uint2(pack_bf16(gelu(v[0]), gelu(v[1])), pack_bf16(gelu(v[2]), gelu(v[3])));
+                }
             }
         }
     }
-    uhat[p] = u0[p] + acc;
+}
+
+// ---------------------------------------------------------------------------
+// layer 6: 32 -> 1 with the residual, FP32 over BF16 activations; one output pixel per thread of
+// the tile, weights read as uniform (scalar) values.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void l6_fwd(const float* __restrict__ params, const uint16_t* A5,
+                                              const float* u0, int nb, int H, int W, float* uhat) {
+    __shared__ uint4 patch[2][TCHUNK];
+    const int64_t ntiles = tile_count(nb, H, W);
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    const float* __restrict__ w6 = params + woff(5);
+    const int ty = int(threadIdx.x) / TW, tx = int(threadIdx.x) % TW;
+    uint4 pre[SPT];
+    patch_fetch(A5, tile_at(t, H, W), H, W, pre);
+    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+        const Tile tc = tile_at(t, H, W);
+        uint4* lds = patch[buf];
+        patch_store(lds, pre);
+        __syncthreads();
+        if (t + gridDim.x < ntiles) patch_fetch(A5, tile_at(t + gridDim.x, H, W), H, W, pre);
+        float acc = w6[9 * C];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int p = (ty + k / 3) * (TW + 2) + tx + k % 3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 v = lds[slot(p, q)];
+                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ci = q * 8 + 2 * e;
+                    acc = __builtin_fmaf(w6[k * C + ci], bf2f(uint16_t(wd[e] & 0xffffu)), acc);
+                    acc = __builtin_fmaf(w6[k * C + ci + 1], bf2f(uint16_t(wd[e] >> 16)), acc);
+                }
+            }
+        }
+        const int y = tc.y0 + ty, x = tc.x0 + tx;
+        if (y < H && x < W) {
+            const int64_t o = (int64_t(tc.b) * H + y) * W + x;
+            uhat[o] = u0[o] + acc;
+        }
+    }
 }
 
 constexpr int MAXB = 64;  // largest training batch (per-sample loss masks travel in the kernel arguments)
@@ -713,18 +858,35 @@ int check_dims(int nb, int64_t H, int64_t W) {
     return ST_OK;
 }
 
+// Grid of a persistent tile kernel: one workgroup per resident slot, at most one per tile.
+int tile_grid(const void* fn, int nb, int H, int W, unsigned* grid) {
+    int blocks = 0;
+    if (int rc = resident_blocks(fn, 0, &blocks)) return rc;
+    *grid = unsigned(std::min<int64_t>(tile_count(nb, H, W), blocks));
+    return ST_OK;
+}
+
+template <int EPI>
+int launch_conv(const ConvArgs& a, hipStream_t s) {
+    unsigned grid = 0;
+    if (int rc = tile_grid(reinterpret_cast<const void*>(conv_mfma<EPI>), a.nb, a.H, a.W, &grid)) return rc;
+    hipLaunchKernelGGL(conv_mfma<EPI>, dim3(grid), dim3(256), 0, s, a);
+    ST_LAUNCH_CHECK("conv_mfma");
+    return ST_OK;
+}
+
 int forward_impl(const float* params, const float* u0, const float* kappa, float* uhat, int nb, int H, int W,
                  char* ws, const WsLayout& L, bool train, hipStream_t s) {
     uint16_t* frags = reinterpret_cast<uint16_t*>(ws + L.frags);
     clear_stale_error();
     hipLaunchKernelGGL(prep_frags, dim3((4 * 2 * FRAG + 255) / 256), dim3(256), 0, s, params, frags);
     ST_LAUNCH_CHECK("prep_frags");
-    const unsigned gpx = unsigned(L.nblk_px);
     auto act = [&](int l) { return reinterpret_cast<uint16_t*>(ws + L.act[l]); };
     auto zz = [&](int l) { return train ? reinterpret_cast<float*>(ws + L.z[l]) : nullptr; };
-    hipLaunchKernelGGL(l1_fwd, dim3(gpx), dim3(256), 0, s, params, u0, kappa, nb, H, W, zz(0), act(0));
+    unsigned g1 = 0;
+    if (int rc = tile_grid(reinterpret_cast<const void*>(l1_fwd), nb, H, W, &g1)) return rc;
+    hipLaunchKernelGGL(l1_fwd, dim3(g1), dim3(256), 0, s, params, u0, kappa, nb, H, W, zz(0), act(0));
     ST_LAUNCH_CHECK("l1_fwd");
-    const unsigned gt = unsigned(int64_t(nb) * ((H + TH - 1) / TH) * ((W + TW - 1) / TW));
     for (int l = 1; l <= 4; ++l) {
         ConvArgs a;
         a.X = act(l - 1);
@@ -737,11 +899,11 @@ int forward_impl(const float* params, const float* u0, const float* kappa, float
         a.nb = nb;
         a.H = H;
         a.W = W;
-        a.epi = EPI_FWD;
-        hipLaunchKernelGGL(conv_mfma, dim3(gt), dim3(256), 0, s, a);
-        ST_LAUNCH_CHECK("conv_mfma fwd");
+        if (int rc = launch_conv<EPI_FWD>(a, s)) return rc;
     }
-    hipLaunchKernelGGL(l6_fwd, dim3(gpx), dim3(256), 0, s, params, act(4), u0, nb, H, W, uhat);
+    unsigned g6 = 0;
+    if (int rc = tile_grid(reinterpret_cast<const void*>(l6_fwd), nb, H, W, &g6)) return rc;
+    hipLaunchKernelGGL(l6_fwd, dim3(g6), dim3(256), 0, s, params, act(4), u0, nb, H, W, uhat);
     ST_LAUNCH_CHECK("l6_fwd");
     return ST_OK;
 }
@@ -838,7 +1000,6 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
     ST_LAUNCH_CHECK("l6_bwd_data");
     // layers 5 .. 2 (index l = 4 .. 1): dZ_l in dzb[cur]
     const uint16_t* frags = reinterpret_cast<const uint16_t*>(ws + L.frags);
-    const unsigned gt = unsigned(int64_t(nb) * ((H + TH - 1) / TH) * ((W + TW - 1) / TW));
     int cur = 0;
     float* dz1 = reinterpret_cast<float*>(ws + L.dz1);
     for (int l = 4; l >= 1; --l) {
@@ -858,9 +1019,7 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
         a.nb = nb;
         a.H = H;
         a.W = W;
-        a.epi = l > 1 ? EPI_BWD_BF16 : EPI_BWD_F32;
-        hipLaunchKernelGGL(conv_mfma, dim3(gt), dim3(256), 0, s, a);
-        ST_LAUNCH_CHECK("conv_mfma bwd");
+        if (int rc = l > 1 ? launch_conv<EPI_BWD_BF16>(a, s) : launch_conv<EPI_BWD_F32>(a, s)) return rc;
         cur ^= 1;
     }
     // layer 1
