@@ -6,7 +6,8 @@
 //   layers 2-5 (32->32) BF16 MFMA implicit GEMM (v_mfma_f32_16x16x32_bf16), FP32 accumulate:
 //                       M = 16 output channels, N = 16 consecutive pixels of a row, K = the 32
 //                       input channels of one tap; 9 taps x 2 M-halves per 16 pixels
-//   layer 6 (32 -> 1)   vector ALU, FP32 over BF16 activations
+//   layer 6 (32 -> 1)   BF16 MFMA over the BF16 activations with each FP32 weight split into a
+//                       BF16 pair (high + low part, 16 significant bits), FP32 accumulate
 // Backward: dA = the same MFMA convolution with the taps flipped and the channel roles swapped,
 // times GELU'(Z) in the epilogue; dW of layers 2-5 is an MFMA GEMM whose reduction runs over
 // pixels (activation and gradient tiles are staged channel-major in LDS so that 8 consecutive
@@ -106,11 +107,25 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // backward:  W'[tap][co][ci]  = W[8 - tap][ci][co]   (flipped taps, swapped channel roles)
 // ---------------------------------------------------------------------------
 constexpr int FRAG = 9 * 2 * 64 * 8;  // bf16 per layer and direction
+// Layer 6 (32 -> 1, forward): frag6[tap][lane][8] is the A operand whose row 0 holds bf16(W6) and
+// row 1 bf16(W6 - bf16(W6)), every other row zero: one MFMA per tap yields both partial sums,
+// which together carry 16 significant bits of every FP32 weight (relative error <= 2^-18).
+constexpr int FRAG6 = 9 * 64 * 8;
+constexpr int NFRAG = 4 * 2 * FRAG + FRAG6;  // bf16 in the fragment area
 
 __global__ void prep_frags(const float* params, uint16_t* frags) {
-    // frags: [4 layers][2 directions][FRAG]
+    // frags: [4 layers][2 directions][FRAG], then [FRAG6]
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 4 * 2 * FRAG) return;
+    if (idx >= NFRAG) return;
+    if (idx >= 4 * 2 * FRAG) {
+        const int r = idx - 4 * 2 * FRAG;
+        const int tap = r / (64 * 8), lane = (r / 8) % 64, i = r % 8;
+        const int m = lane % 16, k = 8 * (lane / 16) + i;
+        const float w = params[woff(5) + tap * C + k];
+        const uint16_t hi = f2bf(w);
+        frags[idx] = m == 0 ? hi : m == 1 ? f2bf(w - bf2f(hi)) : uint16_t(0);
+        return;
+    }
     const int l = idx / (2 * FRAG), dir = (idx / FRAG) % 2, r = idx % FRAG;
     const int tap = r / (2 * 64 * 8), nt = (r / (64 * 8)) % 2, lane = (r / 8) % 64, i = r % 8;
     const int k = 8 * (lane / 16) + i, n = 16 * nt + lane % 16;
@@ -132,9 +147,12 @@ constexpr int TPIX = (TH + 2) * (TW + 2);      // haloed patch pixels
 constexpr int TCHUNK = TPIX * 4;               // 16-byte chunks in the patch
 constexpr int SPT = (TCHUNK + 255) / 256;      // chunks per thread
 
-// LDS slot of chunk c of patch pixel p: the chunk index is XOR-ed with bits 2-3 of the pixel, so
-// that the same chunk of 16 consecutive pixels lands in 16 distinct 16-byte bank groups.
-__device__ __forceinline__ int slot(int p, int c) { return p * 4 + (c ^ ((p >> 2) & 3)); }
+// LDS slot of chunk c of patch pixel p: pixels are 5 slots apart (one 16-byte slot of padding), so
+// the same chunk of 8 or 16 consecutive pixels falls in distinct 16-byte bank groups (5 is odd),
+// and an operand's address is a per-lane base plus a compile-time offset.
+constexpr int PSTRIDE = 5;
+constexpr int PSLOTS = TPIX * PSTRIDE;  // uint4 slots per patch buffer
+__device__ __forceinline__ int slot(int p, int c) { return p * PSTRIDE + c; }
 
 struct Tile {
     int b, y0, x0;
@@ -202,7 +220,7 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 
 template <int EPI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv_mfma(ConvArgs a) {
-    __shared__ uint4 patch[2][TCHUNK];
+    __shared__ uint4 patch[2][PSLOTS];
     const int64_t ntiles = tile_count(a.nb, a.H, a.W);
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
@@ -230,27 +248,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         patch_store(lds, pre);
         __syncthreads();
         if (t + gridDim.x < ntiles) patch_fetch(a.X, tile_at(t + gridDim.x, a.H, a.W), a.H, a.W, pre);
+        // accumulators start from the bias (forward) or zero; the taps run in the outer loop so
+        // that consecutive MFMAs feed independent accumulators
         f32x4_t acc[ROWS][MT][2];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r)
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) acc[r][m][nt] = f32x4_t{0, 0, 0, 0};
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[r][m][nt] = f32x4_t{bias[nt][0], bias[nt][1], bias[nt][2], bias[nt][3]};
+        const uint4* opnd = lds + slot((wave * ROWS) * (TW + 2) + lane_px, lane >> 4);
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int ty = wave * ROWS + r;
+        for (int k = 0; k < 9; ++k)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
+            for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const int p = (ty + k / 3) * (TW + 2) + m * 16 + lane_px + k % 3;
-                    const bf16x8_t xv = __builtin_bit_cast(bf16x8_t, lds[slot(p, lane >> 4)]);
+                for (int m = 0; m < MT; ++m) {
+                    const bf16x8_t xv =
+                        __builtin_bit_cast(bf16x8_t, opnd[PSTRIDE * ((r + k / 3) * (TW + 2) + m * 16 + k % 3)]);
                     acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][0], xv, acc[r][m][0], 0, 0, 0);
                     acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][1], xv, acc[r][m][1], 0, 0, 0);
                 }
-            }
-        }
         // epilogue; offsets inside a row are 32-bit (W * C < 2^31 is checked on the host)
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
@@ -267,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
                     float v[4];
                     if (EPI == EPI_FWD) {
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] = acc[r][m][nt][i] + bias[nt][i];
+                        for (int i = 0; i < 4; ++i) v[i] = acc[r][m][nt][i];
                         if (a.Zout) *reinterpret_cast<float4*>(a.Zout + o) = make_float4(v[0], v[1], v[2], v[3]);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) v[i] = gelu(v[i]);
@@ -357,20 +376,27 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
         input_store(lds, pre);
         __syncthreads();
         if (t + gridDim.x < ntiles) input_fetch(u0, kappa, tile_at(t + gridDim.x, H, W), H, W, pre);
+        // accumulators start from the bias; K steps outermost so that consecutive MFMAs feed
+        // independent accumulators
         f32x4_t acc[ROWS][MT][2];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                acc[r][m][0] = acc[r][m][1] = f32x4_t{0, 0, 0, 0};
-                const int pix = (wave * ROWS + r) * (TW + 2) + m * 16 + lane_px;
+            for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int s5 = 0; s5 < 5; ++s5) {
-                    const float bv = koff[s5] >= 0 ? lds[2 * pix + koff[s5]] : 0.0f;
+                for (int mt = 0; mt < 2; ++mt)
+                    acc[r][m][mt] = f32x4_t{bias[mt][0], bias[mt][1], bias[mt][2], bias[mt][3]};
+        const float* opnd = lds + 2 * ((wave * ROWS) * (TW + 2) + lane_px);
+#pragma unroll
+        for (int s5 = 0; s5 < 5; ++s5)
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    const float bv = koff[s5] >= 0 ? opnd[2 * (r * (TW + 2) + m * 16) + koff[s5]] : 0.0f;
                     acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s5][0], bv, acc[r][m][0], 0, 0, 0);
                     acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s5][1], bv, acc[r][m][1], 0, 0, 0);
                 }
-            }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int y = tc.y0 + wave * ROWS + r;
@@ -385,7 +411,7 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
                     const int64_t o = row + (x * C + 16 * mt + ch0);
                     float v[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = acc[r][m][mt][i] + bias[mt][i];
+                    for (int i = 0; i < 4; ++i) v[i] = acc[r][m][mt][i];
                     if (Z) *reinterpret_cast<float4*>(Z + o) = make_float4(v[0], v[1], v[2], v[3]);
                     *reinterpret_cast<uint2*>(A + o) =
                         make_uint2(pack_bf16(gelu(v[0]), gelu(v[1])), pack_bf16(gelu(v[2]), gelu(v[3])));
@@ -396,17 +422,23 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
 }
 
 // ---------------------------------------------------------------------------
-// layer 6: 32 -> 1 with the residual, FP32 over BF16 activations; one output pixel per thread of
-// the tile, weights read as uniform (scalar) values.
+// layer 6: 32 -> 1 with the residual, on MFMA with the split weights of frag6 (M row 0: high
+// parts, row 1: low parts), N = 16 pixels, K = 32 channels of one tap; the bias starts row 0.
+// Lanes 0-15 hold rows 0-3 of their pixel: f = row 0 + row 1.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void l6_fwd(const float* __restrict__ params, const uint16_t* A5,
-                                              const float* u0, int nb, int H, int W, float* uhat) {
-    __shared__ uint4 patch[2][TCHUNK];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l6_fwd(
+    const float* params, const uint16_t* frag6, const uint16_t* A5, const float* u0, int nb, int H, int W,
+    float* uhat) {
+    __shared__ uint4 patch[2][PSLOTS];
     const int64_t ntiles = tile_count(nb, H, W);
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    const float* __restrict__ w6 = params + woff(5);
-    const int ty = int(threadIdx.x) / TW, tx = int(threadIdx.x) % TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lane_px = lane & 15;
+    bf16x8_t wf[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wf[k] = *reinterpret_cast<const bf16x8_t*>(frag6 + (k * 64 + lane) * 8);
+    const float b0 = lane < 16 ? params[woff(5) + 9 * C] : 0.0f;
+    constexpr int ROWS = TH / 4, MT = TW / 16;
     uint4 pre[SPT];
     patch_fetch(A5, tile_at(t, H, W), H, W, pre);
     for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
@@ -415,26 +447,35 @@ __global__ __launch_bounds__(256) void l6_fwd(const float* __restrict__ params, 
         patch_store(lds, pre);
         __syncthreads();
         if (t + gridDim.x < ntiles) patch_fetch(A5, tile_at(t + gridDim.x, H, W), H, W, pre);
-        float acc = w6[9 * C];
+        f32x4_t acc[ROWS][MT];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int p = (ty + k / 3) * (TW + 2) + tx + k % 3;
+        for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = lds[slot(p, q)];
-                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            for (int m = 0; m < MT; ++m) acc[r][m] = f32x4_t{b0, 0, 0, 0};
+        const uint4* opnd = lds + slot((wave * ROWS) * (TW + 2) + lane_px, lane >> 4);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ci = q * 8 + 2 * e;
-                    acc = __builtin_fmaf(w6[k * C + ci], bf2f(uint16_t(wd[e] & 0xffffu)), acc);
-                    acc = __builtin_fmaf(w6[k * C + ci + 1], bf2f(uint16_t(wd[e] >> 16)), acc);
+        for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    const bf16x8_t xv =
+                        __builtin_bit_cast(bf16x8_t, opnd[PSTRIDE * ((r + k / 3) * (TW + 2) + m * 16 + k % 3)]);
+                    acc[r][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k], xv, acc[r][m], 0, 0, 0);
+                }
+        if (lane < 16) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int y = tc.y0 + wave * ROWS + r;
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    const int x = tc.x0 + m * 16 + lane_px;
+                    if (y < H && x < W) {
+                        const int64_t o = (int64_t(tc.b) * H + y) * W + x;
+                        uhat[o] = u0[o] + (acc[r][m][0] + acc[r][m][1]);
+                    }
                 }
             }
-        }
-        const int y = tc.y0 + ty, x = tc.x0 + tx;
-        if (y < H && x < W) {
-            const int64_t o = (int64_t(tc.b) * H + y) * W + x;
-            uhat[o] = u0[o] + acc;
         }
     }
 }
@@ -814,7 +855,7 @@ WsLayout layout(int nb, int64_t H, int64_t W, bool train) {
     L.nblk_rg = int(nb * ((H + RH - 1) / RH) * ((W + RW - 1) / RW));
     size_t off = 0;
     L.frags = off;
-    off = a256(off + size_t(4) * 2 * FRAG * 2);
+    off = a256(off + size_t(NFRAG) * 2);
     const size_t actb = size_t(L.npix) * C * 2, zb = size_t(L.npix) * C * 4;
     for (int l = 0; l < 5; ++l) {
         if (train || l < 2) {
@@ -879,7 +920,7 @@ int forward_impl(const float* params, const float* u0, const float* kappa, float
                  char* ws, const WsLayout& L, bool train, hipStream_t s) {
     uint16_t* frags = reinterpret_cast<uint16_t*>(ws + L.frags);
     clear_stale_error();
-    hipLaunchKernelGGL(prep_frags, dim3((4 * 2 * FRAG + 255) / 256), dim3(256), 0, s, params, frags);
+    hipLaunchKernelGGL(prep_frags, dim3((NFRAG + 255) / 256), dim3(256), 0, s, params, frags);
     ST_LAUNCH_CHECK("prep_frags");
     auto act = [&](int l) { return reinterpret_cast<uint16_t*>(ws + L.act[l]); };
     auto zz = [&](int l) { return train ? reinterpret_cast<float*>(ws + L.z[l]) : nullptr; };
@@ -903,7 +944,7 @@ int forward_impl(const float* params, const float* u0, const float* kappa, float
     }
     unsigned g6 = 0;
     if (int rc = tile_grid(reinterpret_cast<const void*>(l6_fwd), nb, H, W, &g6)) return rc;
-    hipLaunchKernelGGL(l6_fwd, dim3(g6), dim3(256), 0, s, params, act(4), u0, nb, H, W, uhat);
+    hipLaunchKernelGGL(l6_fwd, dim3(g6), dim3(256), 0, s, params, frags + 4 * 2 * FRAG, act(4), u0, nb, H, W, uhat);
     ST_LAUNCH_CHECK("l6_fwd");
     return ST_OK;
 }
