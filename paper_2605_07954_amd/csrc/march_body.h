@@ -130,6 +130,26 @@ __device__ __forceinline__ Cells<V> cells_of(Raw<S, V> r, int64_t gy, int64_t ro
     return q;
 }
 
+// Input row gy loaded and widened at once (the ring rows and the one-row lead): EDGE tasks skip
+// the load for cells outside the grid, which hold b; interior tasks only clamp a load past the
+// grid's last row.
+template <int S, int V, bool EDGE>
+__device__ __forceinline__ Cells<V> load_now(const void* src, int64_t gy, int64_t rows, int64_t cols, int64_t gx,
+                                             bool col_in, float b) {
+    Cells<V> q;
+    if (EDGE) {
+        if (gy >= 0 && gy < rows && col_in) {
+            q = widen<S, V>(load_raw<S, V>(src, gy * cols + gx));
+        } else {
+#pragma unroll
+            for (int c = 0; c < V; ++c) q.c[c] = b;
+        }
+    } else {
+        q = widen<S, V>(load_raw<S, V>(src, (gy < rows ? gy : rows - 1) * cols + gx));
+    }
+    return q;
+}
+
 // The V outputs of a lane for one row; `ring[(base + R + dy) % N]` holds input row dy.  A box
 // footprint reads the side columns of every row, which each ring row therefore carries from the
 // moment it enters; a star footprint reads them on the centre row only, so ring rows hold their own
@@ -185,9 +205,11 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     auto fetch = [&](int64_t j) { return load_raw<S, V>(a.src, src_offset<EDGE>(j, rows, cols, gx, col_in)); };
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
-    for (int t = 0; t < FIRST; ++t) {
-        set_own<R, V>(lv[0][t], cells_of<S, V, EDGE>(fetch(j0 + t), j0 + t, rows, col_in, b));
-        if (SIDES && t < 2 * R) fill_sides<R, V>(lv[0][t]);
+    for (int t = 0; t < FIRST; ++t)
+        set_own<R, V>(lv[0][t], load_now<S, V, EDGE>(a.src, j0 + t, rows, cols, gx, col_in, b));
+    if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
     }
     if constexpr (D > 0) {
 #pragma unroll
@@ -224,8 +246,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     if (SIDES) fill_sides<R, V>(x);
                 }
                 if (D == 0 && l == 1) {  // input row m1 - R is no longer needed: fetch the row N further down
-                    const int64_t j = j0 + i + N;
-                    set_own<R, V>(lv[0][u % N], cells_of<S, V, EDGE>(fetch(j), j, rows, col_in, b));
+                    set_own<R, V>(lv[0][u % N], load_now<S, V, EDGE>(a.src, j0 + i + N, rows, cols, gx, col_in, b));
                 }
             }
         }
