@@ -40,9 +40,11 @@ struct MarchArgs {
 };
 
 // Input rows a wavefront keeps in flight: one ring length (2r+1 rows, loaded that many iterations
-// before use) wherever the registers allow; box r >= 3 needs them for its rings and its long
-// per-row arithmetic hides a one-row lead anyway.
-constexpr int fifo_rows(int R, int SHAPE) { return SHAPE == SHAPE_STAR || R <= 2 ? 2 * R + 1 : 0; }
+// before use) wherever the registers allow; box r >= 3 with several levels needs them for its
+// rings, and its long per-row arithmetic hides a one-row lead.
+constexpr int fifo_rows(int R, int SHAPE, int TB) {
+    return SHAPE == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
+}
 
 template <int S, int R, int V, int SHAPE, int TB>
 __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
@@ -57,7 +59,7 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
     const int64_t X0 = band * OUTW - V * H;
     const MarchView v{a.src, a.dst, a.rows, a.cols, a.b};
-    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE)>(v, a.w, lane, y0, y1, X0);
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB)>(v, a.w, lane, y0, y1, X0);
 }
 
 template <int S, int R, int V, int SHAPE, int TB>
