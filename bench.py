@@ -39,13 +39,14 @@ VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP
 HBM_PEAK = 8.0e12
 
 
-KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march"}
-VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march"}
+KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march"}
+VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8"}
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip", "march_body.h"):
+    for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip", "march_body.h", "march_kern.h",
+              "march_f32.hip"):
         with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -126,7 +127,8 @@ def main_line(args, torch, lib, stream):
     traffic = measured_traffic(tb, (tx, ty), variant)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": achieved / VALU_FP32_PEAK, "traffic": traffic,
-            "kernel": KERNEL_NAMES[variant] + f"<f32, r=3, box, tb={tb}>", "launches": launches,
+            "kernel": KERNEL_NAMES[variant] + f"<f32, r=3, box{', 8 columns per lane' if variant == 3 else ''}, tb={tb}>",
+            "launches": launches,
             "avg_launch_us": t / launches * 1e6,
             "alg_flop_per_launch": 97.0 * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
             "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
@@ -275,7 +277,7 @@ def main():
     ap.add_argument("--jacobi-steps", type=int, default=1000)
     ap.add_argument("--tb", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=None)
-    ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching")
+    ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching, 3 = marching with eight columns per lane")
     ap.add_argument("--workload", default="box49", choices=["box49"] + sorted(EXTRAS),
                     help="box49: the benchmark line; any other: only that workload's figures (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -110,6 +110,10 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
                                  tile is ignored; any storage and
                                  width (four columns per lane when cols % 4 == 0 and the
                                  buffers are 16-byte aligned, else one)                         */
+#define ST_VARIANT_MARCH8  3  /* the same marching pass with eight columns per lane when
+                                 cols % 8 == 0 and the buffers are 16-byte aligned (else as
+                                 ST_VARIANT_MARCH); tb up to 8 / 4 / 3 / 2 (star) or
+                                 3 / 2 / 2 / 1 (box)                                            */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
  * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage and cols % 4 == 0;
@@ -165,7 +169,8 @@ int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double
                   size_t ws_bytes, void* stream);
 
 /* stencil_autotune -- time every supported (variant, tb, tile) candidate (LDS tiles with tb in
- * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with every depth it offers) on the
+ * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with four and, when cols % 8 == 0, eight
+ * columns per lane at every depth each offers) on the
  * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.

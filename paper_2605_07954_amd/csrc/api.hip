@@ -231,11 +231,12 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
 
 int stencil_set_variant(st_plan* plan, int variant) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
-    if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM && variant != ST_VARIANT_MARCH)
+    if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM && variant != ST_VARIANT_MARCH &&
+        variant != ST_VARIANT_MARCH8)
         return fail(ST_EINVAL, "unknown variant");
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
         return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
-    if (variant == ST_VARIANT_MARCH && !march_usable(plan))
+    if ((variant == ST_VARIANT_MARCH || variant == ST_VARIANT_MARCH8) && !march_usable(plan))
         return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan");
     const int old = plan->variant;
     plan->variant = variant;
@@ -392,16 +393,17 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
-    const int nvar = plan->kind == KIND_CONST ? 3 : 1;
+    const int nvar = plan->kind == KIND_CONST ? 4 : 1;
     for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
         if (var == VARIANT_STREAM && !stream_usable(plan)) break;
-        if (var == VARIANT_MARCH && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
+        if (is_march(var) && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
+        if (var == VARIANT_MARCH8 && plan->cols % 8 != 0) break;  // would run the four-column kernels
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
         plan->variant = var;
         // LDS tiles: the depths of kTb; marching: every depth it offers
         int cands[16], nc = 0;
-        if (var == VARIANT_MARCH) {
+        if (is_march(var)) {
             for (int tb = 1; tb <= max_tb(plan, tx, ty) && nc < 16; ++tb) cands[nc++] = tb;
         } else {
             for (int tb : kTb) cands[nc++] = tb;

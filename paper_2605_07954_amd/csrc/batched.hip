@@ -623,7 +623,7 @@ extern "C" int stencil_batch_set_class(st_batch* B, int shape, int radius, int e
     if (!B) return fail(ST_EINVAL, "batch is NULL");
     if ((shape != SHAPE_STAR && shape != SHAPE_BOX) || radius < 1 || radius > 3 || (engine != 0 && engine != 1))
         return fail(ST_EINVAL, "bad class or engine");
-    if (depth < 1 || depth > 16 || (engine == 1 && depth > march_max_tb(shape, radius)))
+    if (depth < 1 || depth > 16 || (engine == 1 && depth > march_max_tb(shape, radius, 1)))
         return fail(ST_EUNSUPPORTED, "depth out of range for this engine");
     const int c = shape * 3 + radius - 1;
     B->engine[c] = engine;
@@ -682,7 +682,7 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
         std::vector<std::pair<int, int>> cands;
         for (int cap : kCaps)
             if (cap <= deepest[c]) cands.push_back({0, cap});
-        for (int t = 1; t <= march_max_tb(c / 3, r); ++t) cands.push_back({1, t});
+        for (int t = 1; t <= march_max_tb(c / 3, r, 1); ++t) cands.push_back({1, t});
         std::pair<int, int> best = cands[0];
         float best_ms = 1e30f;
         for (const auto& cd : cands) {

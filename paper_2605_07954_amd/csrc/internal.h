@@ -35,7 +35,12 @@ int fail(int code, const std::string& msg);
 
 enum Shape { SHAPE_STAR = 0, SHAPE_BOX = 1 };
 enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1 };
-enum Variant { VARIANT_TILED = ST_VARIANT_TILED, VARIANT_STREAM = ST_VARIANT_STREAM, VARIANT_MARCH = ST_VARIANT_MARCH };
+enum Variant {
+    VARIANT_TILED = ST_VARIANT_TILED,
+    VARIANT_STREAM = ST_VARIANT_STREAM,
+    VARIANT_MARCH = ST_VARIANT_MARCH,
+    VARIANT_MARCH8 = ST_VARIANT_MARCH8
+};
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
 
@@ -97,12 +102,15 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
-// Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment; up to
-// march_max_tb(shape, radius) levels per pass (star: 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4; box:
-// 4 / 3 / 2 / 2).
-int march_max_tb(int shape, int radius);
+// Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment, up to
+// vmax (4 or 8) columns per lane; up to march_max_tb(shape, radius, vmax) levels per pass (vmax 4:
+// star 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4, box 4 / 3 / 2 / 2; vmax 8: star 8 / 4 / 3 / 2, box
+// 3 / 2 / 2 / 1).
+int march_max_tb(int shape, int radius, int vmax);
 bool march_usable(const st_plan* p);
-int launch_march(const st_plan* p, const void* src, void* dst, int levels, hipStream_t s);
+int launch_march(const st_plan* p, const void* src, void* dst, int levels, int vmax, hipStream_t s);
+inline bool is_march(int variant) { return variant == VARIANT_MARCH || variant == VARIANT_MARCH8; }
+inline int march_vmax(int variant) { return variant == VARIANT_MARCH8 ? 8 : 4; }
 // Drop a stale runtime error left by earlier API calls so that the check after our next
 // launch reports that launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }

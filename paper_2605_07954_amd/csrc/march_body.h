@@ -69,6 +69,21 @@ template <>
 struct RawSel<ST_F16, 4> {
     using type = uint2;
 };
+struct F32x8 {
+    float4 a, b;
+};
+template <>
+struct RawSel<ST_F32, 8> {
+    using type = F32x8;
+};
+template <>
+struct RawSel<ST_BF16, 8> {
+    using type = uint4;
+};
+template <>
+struct RawSel<ST_F16, 8> {
+    using type = uint4;
+};
 template <int S, int V>
 using Raw = typename RawSel<S, V>::type;
 
@@ -83,8 +98,18 @@ __device__ __forceinline__ Cells<V> widen(Raw<S, V> r) {
     Cells<V> q;
     if constexpr (V == 1) {
         q.c[0] = Fmt<S>::ld(r);
+    } else if constexpr (S == ST_F32 && V == 8) {
+        q.c[0] = r.a.x; q.c[1] = r.a.y; q.c[2] = r.a.z; q.c[3] = r.a.w;
+        q.c[4] = r.b.x; q.c[5] = r.b.y; q.c[6] = r.b.z; q.c[7] = r.b.w;
     } else if constexpr (S == ST_F32) {
         q.c[0] = r.x; q.c[1] = r.y; q.c[2] = r.z; q.c[3] = r.w;
+    } else if constexpr (V == 8) {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            q.c[2 * k] = Fmt<S>::ld(uint16_t(w[k] & 0xffffu));
+            q.c[2 * k + 1] = Fmt<S>::ld(uint16_t(w[k] >> 16));
+        }
     } else {
         q.c[0] = Fmt<S>::ld(uint16_t(r.x & 0xffffu));
         q.c[1] = Fmt<S>::ld(uint16_t(r.x >> 16));
@@ -99,8 +124,15 @@ __device__ __forceinline__ void store_cells(void* dst, int64_t off, const Cells<
     using T = typename Fmt<S>::T;
     if constexpr (V == 1) {
         static_cast<T*>(dst)[off] = Fmt<S>::st(q.c[0]);
+    } else if constexpr (V == 8 && S != ST_F32) {  // eight 16-bit cells: one 16-byte store
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            w[k] = uint32_t(Fmt<S>::st(q.c[2 * k])) | (uint32_t(Fmt<S>::st(q.c[2 * k + 1])) << 16);
+        *reinterpret_cast<uint4*>(static_cast<T*>(dst) + off) = make_uint4(w[0], w[1], w[2], w[3]);
     } else {
-        store4<S>(static_cast<T*>(dst) + off, q.c);
+#pragma unroll
+        for (int k = 0; k < V; k += 4) store4<S>(static_cast<T*>(dst) + off + k, q.c + k);
     }
 }
 
@@ -196,7 +228,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     constexpr bool SIDES = SHAPE != SHAPE_STAR;  // ring rows carry side columns
     const int64_t rows = a.rows, cols = a.cols;
     const int64_t gx = X0 + V * lane;
-    const bool col_in = gx >= 0 && gx + V <= cols;  // V = 4 only with cols % 4 == 0: all or none
+    const bool col_in = gx >= 0 && gx + V <= cols;  // V > 1 only with cols % V == 0: all or none
     const bool writer = lane >= H && lane < 64 - H && (!EDGE || col_in);
     const float b = a.b;
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)

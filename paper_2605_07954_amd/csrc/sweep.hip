@@ -359,7 +359,7 @@ int supported_tiles(int* xy, int cap) {
 
 int max_tb(const st_plan* p, int tx, int ty) {
     int tb = 1;
-    if (p->variant == VARIANT_MARCH) return march_max_tb(p->shape, p->radius);
+    if (is_march(p->variant)) return march_max_tb(p->shape, p->radius, march_vmax(p->variant));
     if (p->variant == VARIANT_STREAM) {
         while (tb < 16 && stream_lds_bytes(p->radius, tb + 1, tx, ty) <= lds_limit()) ++tb;
     } else {
@@ -393,8 +393,9 @@ int launch_pass(const st_plan* p, const void* src, void* dst, const float* kappa
         return fail(ST_EUNSUPPORTED, "launch_pass called on a naive plan");
     }
     const int ti = tile_index(p->tile_x, p->tile_y);
-    if (p->variant == VARIANT_MARCH && march_usable(p) && levels <= march_max_tb(p->shape, p->radius))
-        return launch_march(p, src, dst, levels, s);
+    if (is_march(p->variant) && march_usable(p) &&
+        levels <= march_max_tb(p->shape, p->radius, march_vmax(p->variant)))
+        return launch_march(p, src, dst, levels, march_vmax(p->variant), s);
     const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
     if (p->variant == VARIANT_STREAM && stream_usable(p) && aligned) {
         KernelFn fn = stream_lookup(p->shape, p->radius, ti);

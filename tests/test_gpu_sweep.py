@@ -257,8 +257,12 @@ def test_stream_variant_bitwise(g, rows, cols, shape, r, b, steps):
         lib.stencil_destroy(plan)
 
 
-def march_depth(shape, r):
-    """Deepest pass the marching variant offers: star rings hold only their own columns."""
+def march_depth(shape, r, variant=None):
+    """Deepest pass a marching variant offers: star rings hold only their own columns; eight
+    columns per lane need twice the ring registers."""
+    import paper_2605_07954_amd as lib
+    if variant == lib.ST_VARIANT_MARCH8:
+        return {1: 8, 2: 4, 3: 3, 4: 2}[r] if shape == wl.STAR else {1: 3, 2: 2, 3: 2, 4: 1}[r]
     return {1: 8, 2: 6, 3: 4, 4: 3}[r] if shape == wl.STAR else {1: 4, 2: 3}.get(r, 2)
 
 
@@ -268,7 +272,7 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
     (1, 4, wl.BOX, 3, 0.0, 3), (5, 8, wl.STAR, 4, 0.5, 4), (37, 248, wl.BOX, 3, 0.0, 5), (40, 240, wl.BOX, 2, 0.25, 5),
     (33, 252, wl.STAR, 1, -1.0, 17), (300, 516, wl.BOX, 1, 0.0, 9), (257, 1000, wl.STAR, 2, 0.0, 13),
     (1024, 1024, wl.BOX, 3, 0.0, 7), (700, 1200, wl.STAR, 3, 0.5, 9), (129, 996, wl.BOX, 4, 0.0, 3),
-    (2050, 64, wl.STAR, 4, 0.0, 4),
+    (2050, 64, wl.STAR, 4, 0.0, 4), (200, 328, wl.BOX, 1, 0.5, 11), (96, 136, wl.BOX, 4, 0.0, 3),
     # widths that are not a multiple of 4 (one column per lane): narrower than a band, one band
     # plus one column, many bands with a ragged end
     (3, 5, wl.BOX, 2, 0.0, 3), (70, 63, wl.STAR, 1, 0.5, 9), (41, 58, wl.BOX, 3, 0.0, 4), (300, 517, wl.BOX, 1, -0.5, 7),
@@ -277,10 +281,11 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
 
 @pytest.mark.parametrize("case", MARCH_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in MARCH_CASES])
 def test_march_variant_bitwise(g, case):
-    """The row-marching variant (one wavefront per column band, lane-shifted side columns) equals the
-    FP32-canonical oracle bit for bit at every depth it offers for the shape and radius (star r = 1 /
-    2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 4 / 3 / 2 / 2), with four columns per lane (width a multiple of 4, aligned buffers) and with one
-    (any other width, or buffers off a 16-byte boundary)."""
+    """The row-marching variants (one wavefront per column band, lane-shifted side columns) equal the
+    FP32-canonical oracle bit for bit at every depth they offer for the shape and radius (star r = 1
+    / 2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 4 / 3 / 2 / 2; with eight columns per lane star
+    8 / 4 / 3 / 2, box 3 / 2 / 2 / 1), with eight columns per lane (width a multiple of 8), four
+    (width a multiple of 4) and one (any other width, or buffers off a 16-byte boundary)."""
     import torch
     import paper_2605_07954_amd as lib
     rows, cols, shape, r, b, steps = case
@@ -288,12 +293,17 @@ def test_march_variant_bitwise(g, case):
     u0 = np.random.default_rng(rows * cols + 7).random((rows, cols), dtype=np.float32)
     ref = oracle.stencil_f32(u0, W, b, steps)
     x = g.to_dev(u0)
-    deepest = march_depth(shape, r)
+    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8):
+        _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, steps, variant)
+
+
+def _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, steps, variant):
+    deepest = march_depth(shape, r, variant)
     for tb in range(1, deepest + 1):
         plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
         try:
             lib.stencil_set_blocking(plan, 1)
-            lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
+            lib.stencil_set_variant(plan, variant)
             lib.stencil_set_blocking(plan, tb)
             with pytest.raises(lib.StencilError):
                 lib.stencil_set_blocking(plan, deepest + 1)
@@ -301,14 +311,14 @@ def test_march_variant_bitwise(g, case):
             ws = torch.empty_like(x)
             lib.stencil_run(plan, x, out, steps, ws)
             torch.cuda.synchronize()
-            np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"tb {tb}")
+            np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"variant {variant} tb {tb}")
             # a buffer 4 bytes past a 16-byte boundary takes one column per lane
             xb = torch.empty(rows * cols + 1, dtype=torch.float32, device=g.DEV)
             xb[1:].copy_(x.reshape(-1))
             ob = torch.full_like(xb, float("nan"))
             lib.stencil_run(plan, xb[1:], ob[1:], steps, ws)
             torch.cuda.synchronize()
-            np.testing.assert_array_equal(g.to_host(ob[1:]).reshape(rows, cols), ref, err_msg=f"unaligned tb {tb}")
+            np.testing.assert_array_equal(g.to_host(ob[1:]).reshape(rows, cols), ref, err_msg=f"variant {variant} unaligned tb {tb}")
         finally:
             lib.stencil_destroy(plan)
 
@@ -316,24 +326,27 @@ def test_march_variant_bitwise(g, case):
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 @pytest.mark.parametrize("rows,cols,shape,r,b,steps", [(300, 260, wl.STAR, 2, 0.0, 23), (129, 500, wl.BOX, 1, 0.5, 11),
                                                       (40, 996, wl.BOX, 3, 0.0, 5), (7, 8, wl.STAR, 4, -0.25, 4),
-                                                      (97, 301, wl.STAR, 2, 0.0, 9), (33, 70, wl.BOX, 3, 0.0, 4)])
+                                                      (97, 301, wl.STAR, 2, 0.0, 9), (33, 70, wl.BOX, 3, 0.0, 4),
+                                                      (150, 264, wl.STAR, 2, 0.0, 13), (61, 96, wl.BOX, 3, 0.5, 5),
+                                                      (77, 200, wl.BOX, 1, 0.0, 8)])
 def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
-    """Marching with BF16/FP16 storage (8-byte loads, FP32 arithmetic, every level rounded to the
-    storage type) equals the emulating oracle bit for bit at every depth."""
+    """Marching with BF16/FP16 storage (8- or 16-byte loads, FP32 arithmetic, every level rounded to
+    the storage type) equals the emulating oracle bit for bit at every depth of both variants."""
     import paper_2605_07954_amd as lib
     W = _weights(shape, r, rows + 5 * cols + r)
     bits = oracle.to_bits(np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32), storage)
     ref = oracle.stencil_lowp(bits, W, b, steps, storage)
-    for tb in range(1, march_depth(shape, r) + 1):
-        plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
-        try:
-            lib.stencil_set_blocking(plan, 1)
-            lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH)
-            lib.stencil_set_blocking(plan, tb)
-            got = g.run(plan, g.to_dev(bits), steps, rows, cols, storage)
-            np.testing.assert_array_equal(g.to_host(got), ref, err_msg=f"tb {tb}")
-        finally:
-            lib.stencil_destroy(plan)
+    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8):
+        for tb in range(1, march_depth(shape, r, variant) + 1):
+            plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
+            try:
+                lib.stencil_set_blocking(plan, 1)
+                lib.stencil_set_variant(plan, variant)
+                lib.stencil_set_blocking(plan, tb)
+                got = g.run(plan, g.to_dev(bits), steps, rows, cols, storage)
+                np.testing.assert_array_equal(g.to_host(got), ref, err_msg=f"variant {variant} tb {tb}")
+            finally:
+                lib.stencil_destroy(plan)
 
 
 def test_solve_until_converged(g):
