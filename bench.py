@@ -94,6 +94,51 @@ def cpu_baseline(p) -> dict:
             "sample": f"box2d49p FP32-canonical oracle on the 1024x1024 top-left crop, {steps} steps ({dt:.1f} s)"}
 
 
+def cpu_oracle_timings() -> dict:
+    """The oracle as written, timed on this host for every configuration (all threads, and one
+    thread for the small ones): a reported CPU baseline, never the target."""
+    import oracle
+    nthreads = oracle.num_threads()
+
+    def timed(fn, *a):
+        t0 = time.perf_counter()
+        fn(*a)
+        return time.perf_counter() - t0
+
+    out = {"threads": nthreads}
+    p = wl.heat2d()
+    for mode, fn in (("f64", oracle.stencil_f64), ("f32", oracle.stencil_f32)):
+        dt = timed(fn, p.u0, p.weights, 0.0, p.steps)
+        oracle.set_threads(1)
+        dt1 = timed(fn, p.u0, p.weights, 0.0, p.steps)
+        oracle.set_threads(nthreads)
+        upd = p.steps * p.rows * p.cols
+        out[f"heat2d_512_100_{mode}"] = {"s": dt, "gstencil_s": upd / dt / 1e9, "s_1thread": dt1,
+                                         "gstencil_s_1thread": upd / dt1 / 1e9}
+    p = wl.box49(rows=1024, cols=1024, steps=200)
+    for mode, fn in (("f64", oracle.stencil_f64), ("f32", oracle.stencil_f32)):
+        dt = timed(fn, p.u0, p.weights, 0.0, p.steps)
+        out[f"box49_1024crop_200_{mode}"] = {"s": dt, "gstencil_s": p.steps * p.rows * p.cols / dt / 1e9}
+    probs = wl.batch_problems(n_grids=256, steps=200)
+    t0 = time.perf_counter()
+    for q in probs:
+        oracle.stencil_f32(q.u0, q.weights, 0.0, q.steps)
+    dt = time.perf_counter() - t0
+    upd = sum(q.steps * q.rows * q.cols for q in probs)
+    out["batched_256_200_f32"] = {"s": dt, "gstencil_s": upd / dt / 1e9}
+    p = wl.star9_precision()
+    dt = timed(oracle.stencil_f64, p.u0, p.weights, 0.0, p.steps)
+    out["star9_8192_500_f64"] = {"s": dt, "gstencil_s": p.steps * p.rows * p.cols / dt / 1e9}
+    bits = oracle.to_bits(p.u0[:2048, :2048], "bf16")
+    dt = timed(oracle.stencil_lowp, bits, p.weights, 0.0, 100, "bf16")
+    out["star9_2048crop_100_bf16_emulated"] = {"s": dt, "gstencil_s": 100 * 2048 * 2048 / dt / 1e9}
+    u0, kappa = wl.varcoef_problem()[:2]
+    for mode, fn in (("f64", oracle.varcoef_f64), ("f32", oracle.varcoef_f32)):
+        dt = timed(fn, u0, kappa, 0.0, 16)
+        out[f"varcoef_1024_16_{mode}"] = {"s": dt, "gstencil_s": 16 * u0.size / dt / 1e9}
+    return out
+
+
 def main_line(args, torch, lib, stream):
     p = wl.box49(rows=args.size, cols=args.size, steps=args.jacobi_steps)
     rows, cols = p.rows, p.cols
@@ -283,12 +328,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer once (reference for the HBM byte counters) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-oracle-timings", action="store_true",
+                    help="only time the CPU oracle on every configuration (host cores; no GPU work)")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "row-slab decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_oracle_timings:  # host cores only: nothing below touches the GPU
+        print(json.dumps({"cpu_oracle_timings": cpu_oracle_timings()}), flush=True)
+        return
     import torch
     torch.cuda.set_device(0)
     if args.copy_calibration:

@@ -87,9 +87,11 @@ __device__ __forceinline__ ErfcTail erfc_tail(float z) {
     return r;
 }
 
-__device__ __forceinline__ float gelu(float z) {
-    return __builtin_fmaf(-fabsf(z), erfc_tail(z).tail, fmaxf(z, 0.0f));
-}
+// max(z, 0) in one integer max on the bit pattern: a negative float (or -0) is a negative integer
+// (fmaxf would first quiet a signalling NaN: two instructions)
+__device__ __forceinline__ float relu(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
+
+__device__ __forceinline__ float gelu(float z) { return __builtin_fmaf(-fabsf(z), erfc_tail(z).tail, relu(z)); }
 
 __device__ __forceinline__ float gelu_grad(float z) {
     constexpr float LOG2_INV_SQRT_2PI = -1.32574808597564697f;
@@ -214,8 +216,11 @@ struct ConvArgs {
     int nb, H, W;
 };
 
+// Two values rounded to BF16 (nearest even) and packed low-first: one v_cvt_pk_bf16_f32.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
-    return uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
 template <int EPI>
@@ -233,11 +238,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         for (int nt = 0; nt < 2; ++nt)
             wf[k][nt] = *reinterpret_cast<const bf16x8_t*>(a.frags + ((k * 2 + nt) * 64 + lane) * 8);
     const int lane_px = lane & 15, ch0 = 4 * (lane >> 4);  // result: channels 16 nt + ch0 + i of pixel lane_px
-    float bias[2][4];
+    f32x4_t bias4[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bias[nt][i] = EPI == EPI_FWD ? a.bias[16 * nt + ch0 + i] : 0.0f;
+        for (int i = 0; i < 4; ++i) bias4[nt][i] = EPI == EPI_FWD ? a.bias[16 * nt + ch0 + i] : 0.0f;
     constexpr int ROWS = TH / 4;  // rows per wave
     constexpr int MT = TW / 16;   // 16-pixel groups per row
     uint4 pre[SPT];
@@ -248,16 +253,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         patch_store(lds, pre);
         __syncthreads();
         if (t + gridDim.x < ntiles) patch_fetch(a.X, tile_at(t + gridDim.x, a.H, a.W), a.H, a.W, pre);
-        // accumulators start from the bias (forward) or zero; the taps run in the outer loop so
-        // that consecutive MFMAs feed independent accumulators
+        // the first tap's MFMAs start from the bias (forward) or zero, read straight from `bias4`; the
+        // taps run in the outer loop so that consecutive MFMAs feed independent accumulators
         f32x4_t acc[ROWS][MT][2];
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r)
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-                    acc[r][m][nt] = f32x4_t{bias[nt][0], bias[nt][1], bias[nt][2], bias[nt][3]};
         const uint4* opnd = lds + slot((wave * ROWS) * (TW + 2) + lane_px, lane >> 4);
 #pragma unroll
         for (int k = 0; k < 9; ++k)
@@ -267,8 +265,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
                 for (int m = 0; m < MT; ++m) {
                     const bf16x8_t xv =
                         __builtin_bit_cast(bf16x8_t, opnd[PSTRIDE * ((r + k / 3) * (TW + 2) + m * 16 + k % 3)]);
-                    acc[r][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][0], xv, acc[r][m][0], 0, 0, 0);
-                    acc[r][m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][1], xv, acc[r][m][1], 0, 0, 0);
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt)
+                        acc[r][m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k][nt], xv,
+                                                                                k == 0 ? bias4[nt] : acc[r][m][nt], 0, 0, 0);
                 }
         // epilogue; offsets inside a row are 32-bit (W * C < 2^31 is checked on the host)
 #pragma unroll
