@@ -424,12 +424,14 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
 // ---------------------------------------------------------------------------
 // layer 6: 32 -> 1 with the residual, on MFMA with the split weights of frag6 (M row 0: high
 // parts, row 1: low parts), N = 16 pixels, K = 32 channels of one tap; the bias starts row 0.
-// Lanes 0-15 hold rows 0-3 of their pixel: f = row 0 + row 1.
+// Lanes 0-15 hold rows 0-3 of their pixel: f = row 0 + row 1.  Its arithmetic per tile is short,
+// so it runs one patch buffer (two barriers per tile) to fit three workgroups per CU and keep
+// more loads in flight.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l6_fwd(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l6_fwd(
     const float* params, const uint16_t* frag6, const uint16_t* A5, const float* u0, int nb, int H, int W,
     float* uhat) {
-    __shared__ uint4 patch[2][PSLOTS];
+    __shared__ uint4 patch[PSLOTS];  // one buffer (two barriers per tile): three workgroups per CU
     const int64_t ntiles = tile_count(nb, H, W);
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
@@ -441,9 +443,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     constexpr int ROWS = TH / 4, MT = TW / 16;
     uint4 pre[SPT];
     patch_fetch(A5, tile_at(t, H, W), H, W, pre);
-    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+    for (; t < ntiles; t += gridDim.x) {
         const Tile tc = tile_at(t, H, W);
-        uint4* lds = patch[buf];
+        uint4* lds = patch;
+        __syncthreads();  // every wave is done reading the previous tile
         patch_store(lds, pre);
         __syncthreads();
         if (t + gridDim.x < ntiles) patch_fetch(A5, tile_at(t + gridDim.x, H, W), H, W, pre);
