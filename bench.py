@@ -207,7 +207,7 @@ def extra_heat2d(torch, lib, stream) -> dict:
     out = torch.empty_like(x)
     ws = torch.empty_like(x)
     plan = lib.stencil_plan(p.rows, p.cols, 1, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
-    tb, _, _ = lib.stencil_autotune(plan, x, out, ws, 20, stream)
+    tb, _, _ = lib.stencil_autotune(plan, x, out, ws, p.steps, stream)  # the whole run: a few ms
     var = lib.stencil_get_variant(plan)
     run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
     run()
@@ -228,7 +228,9 @@ def extra_star9(torch, lib, stream) -> dict:
         o = torch.empty_like(xh)
         w2 = torch.empty_like(xh)
         plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, st, 0)
-        tb, _, _ = lib.stencil_autotune(plan, xh, o, w2, 20, stream)
+        # 120 sample steps: a whole number of passes at every depth up to 6 and at 8, so that no
+        # candidate is timed with a shallower last pass than the real run has
+        tb, _, _ = lib.stencil_autotune(plan, xh, o, w2, 120, stream)
         var = lib.stencil_get_variant(plan)
         run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
         run()
