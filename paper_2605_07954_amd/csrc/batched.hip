@@ -31,6 +31,7 @@ struct BatchDesc {
     int64_t tiles_x, tiles_y;  // tiled engine: tiles; marching engine: bands and segments
     int64_t seg;               // marching engine: output rows per task
     int r, shape, tb, steps, passes, resident;
+    int vec;  // marching engine: rows 16-byte aligned in every buffer (cols % 4 == 0): vector accesses
     float b;
     float w[MAXK];
 };
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(NT) void batched_resident(const BatchDesc* desc, co
 
 // Marching engine: one launch runs `levels` (the template TB) levels of pass p for the grids
 // order[s0 .. s0+n) of one stencil class; wavefront task -> (grid, band, segment) through the class's
-// task prefix sums.  One column per lane, so any width and alignment.
+// task prefix sums.  Four columns per lane: one vector access per lane and row for grids whose rows
+// are 16-byte aligned in every buffer, four element accesses otherwise (any width and alignment).
 struct MarchPassArgs {
     const BatchDesc* desc;
     const int* order;            // the class's grids, ordered by passes then last-pass depth, descending
@@ -132,6 +134,7 @@ struct MarchPassArgs {
 };
 
 constexpr int MW = 4;  // wavefronts per workgroup of the marching engine
+constexpr int MV = 4;  // columns per lane of the marching engine (vector or element accesses per grid)
 
 template <int R, int SH, int TB>
 __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
@@ -144,15 +147,18 @@ __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
     const BatchDesc& d = a.desc[a.order[a.s0 + k]];
     const int64_t t = task - pre[k];
     const int64_t band = t % d.tiles_x, segi = t / d.tiles_x;
-    constexpr int H = march::halo_lanes(R, TB, 1);
+    constexpr int H = march::halo_lanes(R, TB, MV);
     const int64_t y0 = segi * d.seg;
     const int64_t y1 = y0 + d.seg < d.rows ? y0 + d.seg : d.rows;
     const int P = d.passes, p = a.p;
     const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
     float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
     const march::MarchView v{src, dst, d.rows, d.cols, d.b};
-    // one register per row in flight: every class keeps a ring length of input rows loading
-    march::march_task<ST_F32, R, 1, SH, TB, 2 * R + 1>(v, d.w, lane, y0, y1, band * (64 - 2 * H) - H);
+    const int64_t X0 = band * (MV * (64 - 2 * H)) - MV * H;
+    // input rows in flight: one ring length, except box r >= 3 with several levels (registers)
+    constexpr int D = SH == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
+    if (d.vec) march::march_task<ST_F32, R, MV, SH, TB, D, true>(v, d.w, lane, y0, y1, X0);
+    else march::march_task<ST_F32, R, MV, SH, TB, D, false>(v, d.w, lane, y0, y1, X0);
 }
 
 using MarchPassFn = void (*)(MarchPassArgs);
@@ -236,11 +242,22 @@ size_t batch_lds_budget() { return std::min<size_t>(80 * 1024, lds_limit()); }
 
 static int class_slot(const BatchDesc& d) { return d.shape * 3 + d.r - 1; }
 
-// Marching engine: output rows per task for a class, so that its tasks about fill the device once.
-static int64_t march_segment(int64_t band_rows) {
-    constexpr int64_t kWaves = 4096;  // resident wavefronts the segments are sized for
-    const int64_t seg = (band_rows + kWaves - 1) / kWaves;
+// Marching engine: output rows per task for a class, so that its tasks about fill the device once
+// (`waves`: the wavefronts of the class's kernel the device holds at once).
+static int64_t march_segment(int64_t band_rows, int64_t waves) {
+    const int64_t seg = (band_rows + waves - 1) / waves;
     return std::min<int64_t>(2048, std::max<int64_t>(8, seg));
+}
+
+// Wavefronts of the marching kernel for (shape, radius, depth) resident at once (4096 if unknown).
+static int64_t march_waves(int shape, int r, int tb) {
+    MarchPassFn fn = batched_march_lookup(shape, r, tb);
+    int blocks = 0;
+    if (!fn || resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks) != ST_OK || blocks < 1) {
+        (void)hipGetLastError();
+        return 4096;
+    }
+    return int64_t(blocks) * MW;
 }
 
 // Pass structure from each class's engine and depth.  Tiled engine: passes per grid, the queue
@@ -266,8 +283,8 @@ static void build_passes(st_batch* B) {
         } else {
             d.tb = B->depth[c];
             d.passes = (d.steps + d.tb - 1) / d.tb;
-            d.tiles_x = (d.cols + (64 - 2 * march::halo_lanes(d.r, d.tb, 1)) - 1) /
-                        (64 - 2 * march::halo_lanes(d.r, d.tb, 1));  // bands
+            const int64_t band_w = MV * (64 - 2 * march::halo_lanes(d.r, d.tb, MV));
+            d.tiles_x = (d.cols + band_w - 1) / band_w;  // bands
             B->mclass[c].order.push_back(g);
         }
     }
@@ -294,7 +311,7 @@ static void build_passes(st_batch* B) {
         });
         int64_t band_rows = 0;
         for (int g : M.order) band_rows += B->desc[g].tiles_x * B->desc[g].rows;
-        const int64_t seg = march_segment(band_rows);
+        const int64_t seg = march_segment(band_rows, march_waves(c / 3, c % 3 + 1, tb));
         M.prefix.assign(1, 0);
         for (int g : M.order) {
             BatchDesc& d = B->desc[g];
@@ -544,6 +561,8 @@ extern "C" int stencil_run_batched(st_batch* B, const void* const* ins, void* co
             d.in = static_cast<const float*>(ins[g]);
             d.out = static_cast<float*>(outs[g]);
             d.ws = B->field_off[g] ? reinterpret_cast<float*>(ws + B->field_off[g]) : nullptr;
+            auto a16 = [](const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+            d.vec = d.cols % MV == 0 && a16(d.in) && a16(d.out) && (!d.ws || a16(d.ws));
             std::memcpy(h + g * sizeof(BatchDesc), &d, sizeof(d));
         }
         std::memcpy(h + (B->off_tprefix - B->off_desc), B->tile_prefix.data(), B->tile_prefix.size() * sizeof(int64_t));

@@ -87,6 +87,46 @@ struct RawSel<ST_F16, 8> {
 template <int S, int V>
 using Raw = typename RawSel<S, V>::type;
 
+// A lane's V cells loaded one element at a time (any width and alignment).
+template <int S, int V>
+struct Elems {
+    typename Fmt<S>::T v[V];
+};
+// VEC: one vector access per lane and row (cols % V == 0, 16-byte aligned rows); otherwise V
+// element accesses.  V = 1 is the same either way.
+template <int S, int V, bool VEC>
+struct RawTSel {
+    using type = Elems<S, V>;
+};
+template <int S, int V>
+struct RawTSel<S, V, true> {
+    using type = Raw<S, V>;
+};
+template <int S>
+struct RawTSel<S, 1, false> {
+    using type = Raw<S, 1>;
+};
+template <int S, int V, bool VEC>
+using RawT = typename RawTSel<S, V, VEC>::type;
+
+// Which of a lane's V columns lie inside the grid.  With vector accesses (and V = 1) all or none,
+// since cols % V == 0; with element accesses each column on its own.
+template <int V>
+struct ColMask {
+    bool ok[V];
+    bool any;
+};
+
+template <int V, bool VEC>
+__device__ __forceinline__ ColMask<V> col_mask(int64_t gx, int64_t cols) {
+    ColMask<V> m;
+    const bool all = gx >= 0 && gx + V <= cols;
+#pragma unroll
+    for (int c = 0; c < V; ++c) m.ok[c] = (VEC || V == 1) ? all : (gx + c >= 0 && gx + c < cols);
+    m.any = (VEC || V == 1) ? all : (gx + V > 0 && gx < cols);
+    return m;
+}
+
 template <int S, int V>
 __device__ __forceinline__ Raw<S, V> load_raw(const void* src, int64_t off) {
     return *reinterpret_cast<const Raw<S, V>*>(static_cast<const typename Fmt<S>::T*>(src) + off);
@@ -120,6 +160,14 @@ __device__ __forceinline__ Cells<V> widen(Raw<S, V> r) {
 }
 
 template <int S, int V>
+__device__ __forceinline__ Cells<V> widen(const Elems<S, V>& r) {
+    Cells<V> q;
+#pragma unroll
+    for (int c = 0; c < V; ++c) q.c[c] = Fmt<S>::ld(r.v[c]);
+    return q;
+}
+
+template <int S, int V>
 __device__ __forceinline__ void store_cells(void* dst, int64_t off, const Cells<V>& q) {
     using T = typename Fmt<S>::T;
     if constexpr (V == 1) {
@@ -142,44 +190,74 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
     for (int c = 0; c < V; ++c) x.v[R + c] = q.c[c];
 }
 
-// Where a lane reads input row gy: EDGE tasks clamp row and column into the grid (the cells they
-// stand for are replaced by b when the row is used, see `cells_of`); interior tasks only clamp a
-// prefetch past the grid's last row.
-template <bool EDGE>
-__device__ __forceinline__ int64_t src_offset(int64_t gy, int64_t rows, int64_t cols, int64_t gx, bool col_in) {
+// Input row gy as raw storage values, for the FIFO: EDGE tasks clamp row and columns into the grid
+// (the cells they stand for are replaced by b when the row is used, see `cells_of`); interior tasks
+// only clamp a prefetch past the grid's last row.
+template <int S, int V, bool VEC, bool EDGE>
+__device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const void* src, int64_t gy, int64_t rows, int64_t cols,
+                                                     int64_t gx, const ColMask<V>& m) {
     int64_t g = gy < rows ? gy : rows - 1;
     if (EDGE) g = g < 0 ? 0 : g;
-    return g * cols + (EDGE && !col_in ? 0 : gx);
-}
-
-template <int S, int V, bool EDGE>
-__device__ __forceinline__ Cells<V> cells_of(Raw<S, V> r, int64_t gy, int64_t rows, bool col_in, float b) {
-    Cells<V> q = widen<S, V>(r);
-    if (EDGE && !(gy >= 0 && gy < rows && col_in)) {
-#pragma unroll
-        for (int c = 0; c < V; ++c) q.c[c] = b;
-    }
-    return q;
-}
-
-// Input row gy loaded and widened at once (the ring rows and the one-row lead): EDGE tasks skip
-// the load for cells outside the grid, which hold b; interior tasks only clamp a load past the
-// grid's last row.
-template <int S, int V, bool EDGE>
-__device__ __forceinline__ Cells<V> load_now(const void* src, int64_t gy, int64_t rows, int64_t cols, int64_t gx,
-                                             bool col_in, float b) {
-    Cells<V> q;
-    if (EDGE) {
-        if (gy >= 0 && gy < rows && col_in) {
-            q = widen<S, V>(load_raw<S, V>(src, gy * cols + gx));
-        } else {
-#pragma unroll
-            for (int c = 0; c < V; ++c) q.c[c] = b;
-        }
+    if constexpr (VEC || V == 1) {
+        return load_raw<S, V>(src, g * cols + (EDGE && !m.ok[0] ? 0 : gx));
     } else {
-        q = widen<S, V>(load_raw<S, V>(src, (gy < rows ? gy : rows - 1) * cols + gx));
+        RawT<S, V, VEC> r;
+        const typename Fmt<S>::T* row = static_cast<const typename Fmt<S>::T*>(src) + g * cols;
+#pragma unroll
+        for (int c = 0; c < V; ++c) r.v[c] = row[EDGE && !m.ok[c] ? 0 : gx + c];
+        return r;
+    }
+}
+
+template <int S, int V, bool EDGE, typename RawRow>
+__device__ __forceinline__ Cells<V> cells_of(const RawRow& r, int64_t gy, int64_t rows, const ColMask<V>& m,
+                                             float b) {
+    Cells<V> q = widen<S, V>(r);
+    if (EDGE) {
+        const bool row_ok = gy >= 0 && gy < rows;
+#pragma unroll
+        for (int c = 0; c < V; ++c) q.c[c] = row_ok && m.ok[c] ? q.c[c] : b;
     }
     return q;
+}
+
+// Input row gy loaded and widened at once (the ring rows and the one-row lead).  With vector
+// accesses EDGE tasks skip the load for cells outside the grid, which hold b; with element accesses
+// they load clamped addresses and substitute b.  Interior tasks only clamp a load past the grid's
+// last row.
+template <int S, int V, bool VEC, bool EDGE>
+__device__ __forceinline__ Cells<V> load_now(const void* src, int64_t gy, int64_t rows, int64_t cols, int64_t gx,
+                                             const ColMask<V>& m, float b) {
+    if constexpr (VEC || V == 1) {
+        Cells<V> q;
+        if (EDGE) {
+            if (gy >= 0 && gy < rows && m.ok[0]) {
+                q = widen<S, V>(load_raw<S, V>(src, gy * cols + gx));
+            } else {
+#pragma unroll
+                for (int c = 0; c < V; ++c) q.c[c] = b;
+            }
+        } else {
+            q = widen<S, V>(load_raw<S, V>(src, (gy < rows ? gy : rows - 1) * cols + gx));
+        }
+        return q;
+    } else {
+        return cells_of<S, V, EDGE>(fetch_raw<S, V, VEC, EDGE>(src, gy, rows, cols, gx, m), gy, rows, m, b);
+    }
+}
+
+// A lane's V outputs of one row: one vector store, or one element store per column inside the grid.
+template <int S, int V, bool VEC, bool EDGE>
+__device__ __forceinline__ void store_row(void* dst, int64_t row_off, int64_t gx, const Cells<V>& q,
+                                          const ColMask<V>& m) {
+    if constexpr (VEC || V == 1) {
+        store_cells<S, V>(dst, row_off + gx, q);
+    } else {
+        typename Fmt<S>::T* row = static_cast<typename Fmt<S>::T*>(dst) + row_off;
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+            if (!EDGE || m.ok[c]) row[gx + c] = Fmt<S>::st(q.c[c]);
+    }
 }
 
 // The V outputs of a lane for one row; `ring[(base + R + dy) % N]` holds input row dy.  A box
@@ -218,7 +296,7 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 // Input rows are loaded D iterations before they enter the window, into a FIFO of D raw rows (D a
 // multiple of N; the loop is unrolled D times).  With D = 0 a row is loaded into the ring slot that
 // level 1 has just released, one iteration ahead.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE>
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                              int64_t X0) {
     constexpr int N = 2 * R + 1;
@@ -228,17 +306,17 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     constexpr bool SIDES = SHAPE != SHAPE_STAR;  // ring rows carry side columns
     const int64_t rows = a.rows, cols = a.cols;
     const int64_t gx = X0 + V * lane;
-    const bool col_in = gx >= 0 && gx + V <= cols;  // V > 1 only with cols % V == 0: all or none
-    const bool writer = lane >= H && lane < 64 - H && (!EDGE || col_in);
+    const ColMask<V> cm = col_mask<V, VEC>(gx, cols);
+    const bool writer = lane >= H && lane < 64 - H && (!EDGE || cm.any);
     const float b = a.b;
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
-    Raw<S, V> fifo[D > 0 ? D : 1];
+    RawT<S, V, VEC> fifo[D > 0 ? D : 1];
     const int64_t j0 = y0 - R * TB;  // input row j lives in ring slot (j - j0) % N, FIFO slot (j - j0) % D
-    auto fetch = [&](int64_t j) { return load_raw<S, V>(a.src, src_offset<EDGE>(j, rows, cols, gx, col_in)); };
+    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE>(a.src, j, rows, cols, gx, cm); };
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
     for (int t = 0; t < FIRST; ++t)
-        set_own<R, V>(lv[0][t], load_now<S, V, EDGE>(a.src, j0 + t, rows, cols, gx, col_in, b));
+        set_own<R, V>(lv[0][t], load_now<S, V, VEC, EDGE>(a.src, j0 + t, rows, cols, gx, cm, b));
     if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
 #pragma unroll
         for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
@@ -257,7 +335,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
             if constexpr (D > 0) {
                 const int f = (u + 2 * R) % D;
                 const int64_t j = j0 + i + 2 * R;
-                set_own<R, V>(in, cells_of<S, V, EDGE>(fifo[f], j, rows, col_in, b));
+                set_own<R, V>(in, cells_of<S, V, EDGE>(fifo[f], j, rows, cm, b));
                 fifo[f] = fetch(j + D);
             }
             if (SIDES) fill_sides<R, V>(in);
@@ -267,18 +345,18 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                 const int64_t m = y0 - R * (TB - 1) + i - int64_t(l - 1) * R;  // row of level l
                 Cells<V> q = apply<R, V, SHAPE, N>(lv[l - 1], u + l - 1, w);
                 if (l == TB) {
-                    if (writer) store_cells<S, V>(a.dst, m * cols + gx, q);
+                    if (writer) store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm);
                 } else {
                     Row<R, V>& x = lv[l][(u + l - 1) % N];
                     // every level is rounded to the storage type; cells outside the grid keep b
-                    const bool inside = !EDGE || (m >= 0 && m < rows && col_in);
+                    const bool row_in = !EDGE || (m >= 0 && m < rows);
 #pragma unroll
-                    for (int c = 0; c < V; ++c) q.c[c] = inside ? Fmt<S>::rnd(q.c[c]) : b;
+                    for (int c = 0; c < V; ++c) q.c[c] = row_in && (!EDGE || cm.ok[c]) ? Fmt<S>::rnd(q.c[c]) : b;
                     set_own<R, V>(x, q);
                     if (SIDES) fill_sides<R, V>(x);
                 }
                 if (D == 0 && l == 1) {  // input row m1 - R is no longer needed: fetch the row N further down
-                    set_own<R, V>(lv[0][u % N], load_now<S, V, EDGE>(a.src, j0 + i + N, rows, cols, gx, col_in, b));
+                    set_own<R, V>(lv[0][u % N], load_now<S, V, VEC, EDGE>(a.src, j0 + i + N, rows, cols, gx, cm, b));
                 }
             }
         }
@@ -303,15 +381,15 @@ __device__ __forceinline__ void load_weights(const float* w, float* wv) {
 }
 
 // One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels, input rows
-// loaded D iterations ahead (0: one).
-template <int S, int R, int V, int SHAPE, int TB, int D>
+// loaded D iterations ahead (0: one); VEC selects vector or element accesses (see RawT).
+template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                            int64_t X0) {
     const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 64 * V > a.cols;
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    if (edge) march_levels<S, R, V, SHAPE, TB, D, true>(a, wv, lane, y0, y1, X0);
-    else march_levels<S, R, V, SHAPE, TB, D, false>(a, wv, lane, y0, y1, X0);
+    if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC>(a, wv, lane, y0, y1, X0);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC>(a, wv, lane, y0, y1, X0);
 }
 
 }  // namespace march
