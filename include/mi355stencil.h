@@ -227,8 +227,8 @@ int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, 
 /* stencil_batch_autotune -- pick, for each stencil class (shape, radius) of the grids that are
  * not LDS-resident, the engine and the depth of its passes: LDS tiles of 128 x 64 (one multi-grid
  * launch per pass for all tiled classes) with the depth capped at 1, 2, 3, 4, 6, 8, 12 or 16
- * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, one
- * column per lane, any width; one chain of launches per class, the classes on parallel branches
+ * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, four
+ * columns per lane, any width and alignment; one chain of launches per class, the classes on parallel branches
  * of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star r = 1 / 2 / 3, 4 / 3 / 2
  * for box).  Coordinate descent: each
  * class in turn, every candidate timed on the whole batch run twice on the caller's buffers (outs

@@ -148,7 +148,8 @@ def test_batched_autotune_bitwise(g):
 
 @pytest.mark.parametrize("graph", [0, 2])
 def test_batched_engines_every_class_bitwise(g, graph):
-    """Every stencil class on LDS tiles and on the marching engine (one column per lane) at every
+    """Every stencil class on LDS tiles and on the marching engine (four columns per lane: vector
+    accesses for widths divisible by 4, element accesses otherwise) at every
     depth, with a shallower last pass (step counts not divisible by the depth): bitwise equal to the
     FP32-canonical oracle, directly and through the graph."""
     import torch
