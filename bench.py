@@ -39,14 +39,14 @@ VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP
 HBM_PEAK = 8.0e12
 
 
-KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march"}
-VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8"}
+KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march", 4: "sweep_march"}
+VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1"}
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip", "march_body.h", "march_kern.h",
-              "march_f32.hip"):
+              "march_f32_box.hip"):
         with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -324,7 +324,7 @@ def main():
     ap.add_argument("--jacobi-steps", type=int, default=1000)
     ap.add_argument("--tb", type=int, default=0)
     ap.add_argument("--tile", type=int, nargs=2, default=None)
-    ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching, 3 = marching with eight columns per lane")
+    ap.add_argument("--variant", type=int, default=0, help="with --tb: 0 = tiled, 1 = streaming, 2 = marching, 3 = marching with eight columns per lane, 4 = marching with one column per lane")
     ap.add_argument("--workload", default="box49", choices=["box49"] + sorted(EXTRAS),
                     help="box49: the benchmark line; any other: only that workload's figures (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",

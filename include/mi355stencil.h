@@ -107,20 +107,23 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
 #define ST_VARIANT_MARCH   2  /* each wavefront walks a column band down the grid, rows in a
                                  register ring, side columns by lane shifts; tb up to 8 / 6 /
                                  4 / 3 (star, r = 1 / 2 / 3 / 4) or 4 / 3 / 2 / 2 (box); the
-                                 tile is ignored; any storage and
-                                 width (four columns per lane when cols % 4 == 0 and the
-                                 buffers are 16-byte aligned, else one)                         */
+                                 tile is ignored; any storage, width and alignment (four
+                                 columns per lane: one vector access per lane and row when
+                                 cols % 4 == 0 and the buffers are 16-byte aligned, else one
+                                 element access per column)                                     */
 #define ST_VARIANT_MARCH8  3  /* the same marching pass with eight columns per lane when
                                  cols % 8 == 0 and the buffers are 16-byte aligned (else as
                                  ST_VARIANT_MARCH); tb up to 8 / 4 / 3 / 2 (star) or
                                  3 / 2 / 2 / 1 (box)                                            */
+#define ST_VARIANT_MARCH1  4  /* the marching pass with one column per lane (more, shorter
+                                 tasks: for small grids); depths as ST_VARIANT_MARCH            */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
  * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage and cols % 4 == 0;
  * both need a constant-weight plan; or the current tb is deeper than the variant
  * allows: its LDS budget when streaming, the depths listed above when marching -- lower tb
  * first).  A streaming run whose buffers are not 16-byte aligned falls back to the tiled
- * kernels; a marching run takes one column per lane instead. */
+ * kernels. */
 int stencil_set_variant(st_plan* plan, int variant);
 int stencil_get_variant(const st_plan* plan, int* variant);
 
@@ -169,8 +172,8 @@ int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double
                   size_t ws_bytes, void* stream);
 
 /* stencil_autotune -- time every supported (variant, tb, tile) candidate (LDS tiles with tb in
- * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with four and, when cols % 8 == 0, eight
- * columns per lane at every depth each offers) on the
+ * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with one, four and, when cols % 8 == 0,
+ * eight columns per lane at every depth each offers) on the
  * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.

@@ -23,7 +23,7 @@ ST_OK = 0
 ST_EINVAL, ST_EALIAS, ST_EUNSUPPORTED, ST_EHIP, ST_ENOWS, ST_ENOMEM, ST_ESTATE = -1, -2, -3, -4, -5, -6, -7
 ST_F32, ST_BF16, ST_F16 = 0, 1, 2
 ST_FLAG_NAIVE, ST_FLAG_GRAPH = 0x1, 0x2
-ST_VARIANT_TILED, ST_VARIANT_STREAM, ST_VARIANT_MARCH, ST_VARIANT_MARCH8 = 0, 1, 2, 3
+ST_VARIANT_TILED, ST_VARIANT_STREAM, ST_VARIANT_MARCH, ST_VARIANT_MARCH8, ST_VARIANT_MARCH1 = 0, 1, 2, 3, 4
 SG_PARAM_COUNT = 37889
 STORAGE = {"f32": ST_F32, "bf16": ST_BF16, "f16": ST_F16}
 

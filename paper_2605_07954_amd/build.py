@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmi355stencil.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["march_f32.hip", "march_bf16.hip", "march_f16.hip", "surrogate.hip", "batched.hip", "sweep.hip", "api.hip",
-           "march.hip", "varcoef.hip", "norms.hip"]
+SOURCES = ["march_f32_star.hip", "march_bf16_star.hip", "march_f16_star.hip", "march_f32_box.hip", "march_bf16_box.hip",
+           "march_f16_box.hip", "surrogate.hip", "batched.hip", "sweep.hip", "api.hip", "march.hip", "varcoef.hip",
+           "norms.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -232,11 +232,12 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
 int stencil_set_variant(st_plan* plan, int variant) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
     if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM && variant != ST_VARIANT_MARCH &&
-        variant != ST_VARIANT_MARCH8)
+        variant != ST_VARIANT_MARCH8 && variant != ST_VARIANT_MARCH1)
         return fail(ST_EINVAL, "unknown variant");
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
         return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
-    if ((variant == ST_VARIANT_MARCH || variant == ST_VARIANT_MARCH8) && !march_usable(plan))
+    if ((variant == ST_VARIANT_MARCH || variant == ST_VARIANT_MARCH8 || variant == ST_VARIANT_MARCH1) &&
+        !march_usable(plan))
         return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan");
     const int old = plan->variant;
     plan->variant = variant;
@@ -393,7 +394,7 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
-    const int nvar = plan->kind == KIND_CONST ? 4 : 1;
+    const int nvar = plan->kind == KIND_CONST ? 5 : 1;
     for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
         if (var == VARIANT_STREAM && !stream_usable(plan)) break;

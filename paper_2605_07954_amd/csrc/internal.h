@@ -39,7 +39,8 @@ enum Variant {
     VARIANT_TILED = ST_VARIANT_TILED,
     VARIANT_STREAM = ST_VARIANT_STREAM,
     VARIANT_MARCH = ST_VARIANT_MARCH,
-    VARIANT_MARCH8 = ST_VARIANT_MARCH8
+    VARIANT_MARCH8 = ST_VARIANT_MARCH8,
+    VARIANT_MARCH1 = ST_VARIANT_MARCH1
 };
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
@@ -103,14 +104,16 @@ int prepare_lds(const void* fn, size_t bytes);
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
 // Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment, up to
-// vmax (4 or 8) columns per lane; up to march_max_tb(shape, radius, vmax) levels per pass (vmax 4:
+// vmax (1, 4 or 8) columns per lane; up to march_max_tb(shape, radius, vmax) levels per pass (vmax 4:
 // star 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4, box 4 / 3 / 2 / 2; vmax 8: star 8 / 4 / 3 / 2, box
 // 3 / 2 / 2 / 1).
 int march_max_tb(int shape, int radius, int vmax);
 bool march_usable(const st_plan* p);
 int launch_march(const st_plan* p, const void* src, void* dst, int levels, int vmax, hipStream_t s);
-inline bool is_march(int variant) { return variant == VARIANT_MARCH || variant == VARIANT_MARCH8; }
-inline int march_vmax(int variant) { return variant == VARIANT_MARCH8 ? 8 : 4; }
+inline bool is_march(int variant) {
+    return variant == VARIANT_MARCH || variant == VARIANT_MARCH8 || variant == VARIANT_MARCH1;
+}
+inline int march_vmax(int variant) { return variant == VARIANT_MARCH8 ? 8 : variant == VARIANT_MARCH1 ? 1 : 4; }
 // Drop a stale runtime error left by earlier API calls so that the check after our next
 // launch reports that launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }

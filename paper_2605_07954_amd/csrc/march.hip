@@ -4,8 +4,8 @@
 // BF16 or FP16; arithmetic is FP32 and every level is rounded to the storage type.
 //
 // One wavefront owns a band of columns, V per lane (V = 8 or 4 with one or two 16-byte loads, or one
-// 8-byte load, per lane and row; V = 1 with one element per lane, for any width and alignment), and
-// walks down a segment of rows.  Each input row is read from HBM once per band; the r columns a lane needs on either side
+// 8-byte load, per lane and row; for any other width or alignment V = 4 with one element access
+// per column; or V = 1, many short tasks for small grids), and walks down a segment of rows.  Each input row is read from HBM once per band; the r columns a lane needs on either side
 // come from neighbouring lanes through DPP wave shifts (the value at column c < 0 is the previous
 // lane's value at column c + V, so the side columns are produced nearest first, one shift each),
 // and the pass uses neither LDS nor barriers.  The rows a lane needs sit in a register ring whose
@@ -29,17 +29,18 @@ using march_k::MWAVES;
 
 namespace {
 
-MarchFn march_lookup(int storage, int V, int shape, int r, int levels) {
-    if (storage == ST_F32) return march_lookup_f32(V, shape, r, levels);
-    if (storage == ST_BF16) return march_lookup_bf16(V, shape, r, levels);
-    if (storage == ST_F16) return march_lookup_f16(V, shape, r, levels);
+MarchFn march_lookup(int storage, int mode, int shape, int r, int levels) {
+    const bool box = shape == SHAPE_BOX;
+    if (storage == ST_F32) return box ? march_lookup_f32_box(mode, r, levels) : march_lookup_f32_star(mode, r, levels);
+    if (storage == ST_BF16) return box ? march_lookup_bf16_box(mode, r, levels) : march_lookup_bf16_star(mode, r, levels);
+    if (storage == ST_F16) return box ? march_lookup_f16_box(mode, r, levels) : march_lookup_f16_star(mode, r, levels);
     return nullptr;
 }
 
 }  // namespace
 
 int march_max_tb(int shape, int radius, int vmax) {
-    if (vmax == 8) {  // never deeper than the four- and one-column kernels it falls back to
+    if (vmax == 8) {  // never deeper than the four-column kernels it falls back to
         if (shape == SHAPE_STAR) return radius == 1 ? 8 : radius == 2 ? 4 : radius == 3 ? 3 : 2;
         return radius == 1 ? 3 : radius == 2 ? 2 : radius == 3 ? 2 : 1;
     }
@@ -50,12 +51,14 @@ int march_max_tb(int shape, int radius, int vmax) {
 bool march_usable(const st_plan* p) { return p->kind == KIND_CONST && p->radius <= 4; }
 
 int launch_march(const st_plan* p, const void* src, void* dst, int levels, int vmax, hipStream_t s) {
-    // V columns per lane with one vector load per lane and row when every row starts on a 16-byte
-    // boundary (cols % V == 0 and aligned buffers; four 16-bit cells are 8 bytes, which the same
-    // condition covers); else one column per lane
+    // V columns per lane with one vector access per lane and row when every row starts on a
+    // 16-byte boundary (cols % V == 0 and aligned buffers; four 16-bit cells are 8 bytes, which the
+    // same condition covers); else four columns per lane with element accesses (mode 0); vmax 1:
+    // one column per lane, any width and alignment
     const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
-    const int V = aligned && vmax == 8 && p->cols % 8 == 0 ? 8 : aligned && p->cols % 4 == 0 ? 4 : 1;
-    MarchFn fn = march_lookup(p->storage, V, p->shape, p->radius, levels);
+    const int mode = vmax == 1 ? 1 : aligned && vmax == 8 && p->cols % 8 == 0 ? 8 : aligned && p->cols % 4 == 0 ? 4 : 0;
+    const int V = mode == 8 ? 8 : mode == 1 ? 1 : 4;
+    MarchFn fn = march_lookup(p->storage, mode, p->shape, p->radius, levels);
     if (!fn) return fail(ST_EUNSUPPORTED, "no row-marching kernel for this shape/radius/depth");
     MarchArgs a;
     a.src = src;

@@ -1,0 +1,10 @@
+// Row-marching kernels, F32 storage, star footprints (see march.hip).
+#include "march_kern.h"
+
+namespace st {
+
+march_k::MarchFn march_lookup_f32_star(int mode, int r, int levels) {
+    return march_k::march_lookup_shape<ST_F32, SHAPE_STAR>(mode, r, levels);
+}
+
+}  // namespace st

@@ -1,5 +1,5 @@
 // Row-marching kernels and their instantiation tables; included by one translation unit per
-// storage type (march_f32.hip, march_bf16.hip, march_f16.hip), which instantiate that type's
+// storage type and shape (march_f32_star.hip, march_f32_box.hip, ...), which instantiate those
 // kernels, and by march.hip for the launch arguments.  The design is described in march.hip.
 #pragma once
 
@@ -33,7 +33,7 @@ constexpr int fifo_rows(int R, int SHAPE, int TB) {
     return SHAPE == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
 }
 
-template <int S, int R, int V, int SHAPE, int TB>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC>
 __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -46,37 +46,37 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
     const int64_t X0 = band * OUTW - V * H;
     const MarchView v{a.src, a.dst, a.rows, a.cols, a.b};
-    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB)>(v, a.w, lane, y0, y1, X0);
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC>(v, a.w, lane, y0, y1, X0);
 }
 
-template <int S, int R, int V, int SHAPE, int TB>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC>
 __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
-    sweep_march_body<S, R, V, SHAPE, TB>(a);
+    sweep_march_body<S, R, V, SHAPE, TB, VEC>(a);
 }
 
 // r = 3 with two levels and four columns per lane needs about 174 registers, just over the 168
 // that let three wavefronts share a SIMD; held to 168, the compiler keeps six values in scratch (one
 // access per 192 FMAs), and the third wavefront hides more load latency than that costs (measured
 // +2 % on box49).
-template <int S, int R, int V, int SHAPE, int TB>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC>
 __global__ __launch_bounds__(64 * MWAVES) __attribute__((amdgpu_waves_per_eu(3))) void sweep_march_w3(MarchArgs a) {
-    sweep_march_body<S, R, V, SHAPE, TB>(a);
+    sweep_march_body<S, R, V, SHAPE, TB, VEC>(a);
 }
 
 using MarchFn = void (*)(MarchArgs);
 
-template <int S, int R, int V, int SH, int TB>
+template <int S, int R, int V, int SH, int TB, bool VEC = true>
 MarchFn march_kernel() {
-    if constexpr (V == 4 && R == 3 && TB == 2) return sweep_march_w3<S, R, V, SH, TB>;
-    else return sweep_march<S, R, V, SH, TB>;
+    if constexpr (V == 4 && R == 3 && TB == 2 && VEC) return sweep_march_w3<S, R, V, SH, TB, VEC>;
+    else return sweep_march<S, R, V, SH, TB, VEC>;
 }
 
 // Depths per shape and radius: the rings of TB levels must fit the register file next to each
 // other (a star ring row holds V values, a box ring row V + 2r).
-template <int S, int V, int SH>
+template <int S, int V, int SH, bool VEC>
 MarchFn march_fn(int r, int levels) {
 #define ST_MARCH(R, TB) \
-    if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB>();
+    if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB, VEC>();
     if constexpr (SH == SHAPE_STAR) {
         ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4) ST_MARCH(1, 5) ST_MARCH(1, 6) ST_MARCH(1, 7) ST_MARCH(1, 8)
         ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3) ST_MARCH(2, 4) ST_MARCH(2, 5) ST_MARCH(2, 6)
@@ -90,11 +90,6 @@ MarchFn march_fn(int r, int levels) {
     }
 #undef ST_MARCH
     return nullptr;
-}
-
-template <int S, int V>
-MarchFn march_lookup_s(int shape, int r, int levels) {
-    return shape == SHAPE_BOX ? march_fn<S, V, SHAPE_BOX>(r, levels) : march_fn<S, V, SHAPE_STAR>(r, levels);
 }
 
 // Eight columns per lane: twice the arithmetic per lane shift, load and halo lane, and twice the
@@ -119,25 +114,25 @@ MarchFn march8_fn(int r, int levels) {
     return nullptr;
 }
 
-template <int S>
-MarchFn march8_lookup_s(int shape, int r, int levels) {
-    return shape == SHAPE_BOX ? march8_fn<S, SHAPE_BOX>(r, levels) : march8_fn<S, SHAPE_STAR>(r, levels);
+// The kernel of storage type S and shape SH for `mode` (8 or 4: that many columns per lane with
+// vector accesses; 0: four columns per lane with element accesses; 1: one column per lane), radius
+// and depth (nullptr if none).
+template <int S, int SH>
+MarchFn march_lookup_shape(int mode, int r, int levels) {
+    if (mode == 8) return march8_fn<S, SH>(r, levels);
+    if (mode == 4) return march_fn<S, 4, SH, true>(r, levels);
+    if (mode == 1) return march_fn<S, 1, SH, true>(r, levels);
+    return march_fn<S, 4, SH, false>(r, levels);
 }
-
-// The kernel of storage type S for V columns per lane, shape, radius and depth (nullptr if none).
-template <int S>
-MarchFn march_lookup_storage(int V, int shape, int r, int levels) {
-    if (V == 8) return march8_lookup_s<S>(shape, r, levels);
-    if (V == 4) return march_lookup_s<S, 4>(shape, r, levels);
-    return march_lookup_s<S, 1>(shape, r, levels);
-}
-
 
 }  // namespace march_k
 
-// Per-storage lookups, one per translation unit.
-march_k::MarchFn march_lookup_f32(int V, int shape, int r, int levels);
-march_k::MarchFn march_lookup_bf16(int V, int shape, int r, int levels);
-march_k::MarchFn march_lookup_f16(int V, int shape, int r, int levels);
+// Lookups per storage type and shape, one per translation unit.
+march_k::MarchFn march_lookup_f32_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_f32_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_bf16_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_bf16_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_f16_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_f16_box(int mode, int r, int levels);
 
 }  // namespace st

@@ -273,7 +273,7 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
     (33, 252, wl.STAR, 1, -1.0, 17), (300, 516, wl.BOX, 1, 0.0, 9), (257, 1000, wl.STAR, 2, 0.0, 13),
     (1024, 1024, wl.BOX, 3, 0.0, 7), (700, 1200, wl.STAR, 3, 0.5, 9), (129, 996, wl.BOX, 4, 0.0, 3),
     (2050, 64, wl.STAR, 4, 0.0, 4), (200, 328, wl.BOX, 1, 0.5, 11), (96, 136, wl.BOX, 4, 0.0, 3),
-    # widths that are not a multiple of 4 (one column per lane): narrower than a band, one band
+    # widths that are not a multiple of 4 (element accesses): narrower than a band, one band
     # plus one column, many bands with a ragged end
     (3, 5, wl.BOX, 2, 0.0, 3), (70, 63, wl.STAR, 1, 0.5, 9), (41, 58, wl.BOX, 3, 0.0, 4), (300, 517, wl.BOX, 1, -0.5, 7),
     (257, 1001, wl.STAR, 2, 0.0, 6), (130, 263, wl.BOX, 3, 0.25, 5), (90, 301, wl.STAR, 4, 0.0, 3)]
@@ -284,8 +284,9 @@ def test_march_variant_bitwise(g, case):
     """The row-marching variants (one wavefront per column band, lane-shifted side columns) equal the
     FP32-canonical oracle bit for bit at every depth they offer for the shape and radius (star r = 1
     / 2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 4 / 3 / 2 / 2; with eight columns per lane star
-    8 / 4 / 3 / 2, box 3 / 2 / 2 / 1), with eight columns per lane (width a multiple of 8), four
-    (width a multiple of 4) and one (any other width, or buffers off a 16-byte boundary)."""
+    8 / 4 / 3 / 2, box 3 / 2 / 2 / 1), with vector accesses (eight or four columns per lane, width a
+    multiple of 8 or 4), element accesses (four columns per lane: any other width, or buffers off a
+    16-byte boundary) and one column per lane."""
     import torch
     import paper_2605_07954_amd as lib
     rows, cols, shape, r, b, steps = case
@@ -293,7 +294,7 @@ def test_march_variant_bitwise(g, case):
     u0 = np.random.default_rng(rows * cols + 7).random((rows, cols), dtype=np.float32)
     ref = oracle.stencil_f32(u0, W, b, steps)
     x = g.to_dev(u0)
-    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8):
+    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8, lib.ST_VARIANT_MARCH1):
         _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, steps, variant)
 
 
@@ -312,7 +313,7 @@ def _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, ste
             lib.stencil_run(plan, x, out, steps, ws)
             torch.cuda.synchronize()
             np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"variant {variant} tb {tb}")
-            # a buffer 4 bytes past a 16-byte boundary takes one column per lane
+            # a buffer 4 bytes past a 16-byte boundary takes element accesses
             xb = torch.empty(rows * cols + 1, dtype=torch.float32, device=g.DEV)
             xb[1:].copy_(x.reshape(-1))
             ob = torch.full_like(xb, float("nan"))
@@ -336,7 +337,7 @@ def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
     W = _weights(shape, r, rows + 5 * cols + r)
     bits = oracle.to_bits(np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32), storage)
     ref = oracle.stencil_lowp(bits, W, b, steps, storage)
-    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8):
+    for variant in (lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8, lib.ST_VARIANT_MARCH1):
         for tb in range(1, march_depth(shape, r, variant) + 1):
             plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
             try:
