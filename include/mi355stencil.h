@@ -174,7 +174,8 @@ int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double
 /* stencil_autotune -- time every supported (variant, tb, tile) candidate (LDS tiles with tb in
  * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with one, four and, when cols % 8 == 0,
  * eight columns per lane at every depth each offers) on the
- * caller's buffers for `sample_steps` steps and keep the fastest in the plan.
+ * caller's buffers for `sample_steps` steps (one warm-up run, then the better of two timed runs)
+ * and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
  * Synchronises the stream.  Errors: as stencil_run. */
