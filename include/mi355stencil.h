@@ -106,7 +106,7 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
                                  while the current one computes (FP32, cols % 4 == 0)          */
 #define ST_VARIANT_MARCH   2  /* each wavefront walks a column band down the grid, rows in a
                                  register ring, side columns by lane shifts; tb up to 8 / 6 /
-                                 4 / 3 (star, r = 1 / 2 / 3 / 4) or 4 / 3 / 2 / 2 (box); the
+                                 4 / 3 (star, r = 1 / 2 / 3 / 4) or 6 / 3 / 2 / 2 (box); the
                                  tile is ignored; any storage, width and alignment (four
                                  columns per lane: one vector access per lane and row when
                                  cols % 4 == 0 and the buffers are 16-byte aligned, else one
@@ -224,7 +224,7 @@ int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* ou
 /* stencil_batch_set_class -- set the engine (0 = LDS tiles, 1 = marching) and pass depth of one
  * stencil class (shape 0 = star, 1 = box; radius 1..3) of the batch by hand; results are bitwise
  * the same for every choice.  Tiles: depth 1..16, further capped per grid by what its tile fits
- * in LDS.  Marching: depth up to 8 / 6 / 4 (star, r = 1 / 2 / 3) or 4 / 3 / 2 (box).  Errors: ST_EINVAL,
+ * in LDS.  Marching: depth up to 8 / 6 / 4 (star, r = 1 / 2 / 3) or 6 / 3 / 2 (box).  Errors: ST_EINVAL,
  * ST_EUNSUPPORTED (depth out of range). */
 int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, int depth);
 
@@ -233,7 +233,7 @@ int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, 
  * launch per pass for all tiled classes) with the depth capped at 1, 2, 3, 4, 6, 8, 12 or 16
  * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, four
  * columns per lane, any width and alignment; one chain of launches per class, the classes on parallel branches
- * of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star r = 1 / 2 / 3, 4 / 3 / 2
+ * of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star r = 1 / 2 / 3, 6 / 3 / 2
  * for box).  Coordinate descent: each
  * class in turn, every candidate timed on the whole batch run twice on the caller's buffers (outs
  * are overwritten; results are bitwise those of any other choice).  Writes the chosen depth and

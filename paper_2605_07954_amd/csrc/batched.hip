@@ -173,7 +173,7 @@ MarchPassFn batched_march_fn(int r, int levels) {
         ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3) ST_BMARCH(2, 4) ST_BMARCH(2, 5) ST_BMARCH(2, 6)
         ST_BMARCH(3, 1) ST_BMARCH(3, 2) ST_BMARCH(3, 3) ST_BMARCH(3, 4)
     } else {
-        ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4)
+        ST_BMARCH(1, 1) ST_BMARCH(1, 2) ST_BMARCH(1, 3) ST_BMARCH(1, 4) ST_BMARCH(1, 5) ST_BMARCH(1, 6)
         ST_BMARCH(2, 1) ST_BMARCH(2, 2) ST_BMARCH(2, 3)
         ST_BMARCH(3, 1) ST_BMARCH(3, 2)
     }

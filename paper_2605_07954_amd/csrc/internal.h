@@ -105,7 +105,7 @@ int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
 // Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment, up to
 // vmax (1, 4 or 8) columns per lane; up to march_max_tb(shape, radius, vmax) levels per pass (vmax 4:
-// star 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4, box 4 / 3 / 2 / 2; vmax 8: star 8 / 4 / 3 / 2, box
+// star 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4, box 6 / 3 / 2 / 2; vmax 8: star 8 / 4 / 3 / 2, box
 // 3 / 2 / 2 / 1).
 int march_max_tb(int shape, int radius, int vmax);
 bool march_usable(const st_plan* p);

@@ -45,7 +45,7 @@ int march_max_tb(int shape, int radius, int vmax) {
         return radius == 1 ? 3 : radius == 2 ? 2 : radius == 3 ? 2 : 1;
     }
     if (shape == SHAPE_STAR) return radius == 1 ? 8 : radius == 2 ? 6 : radius == 3 ? 4 : 3;
-    return radius == 1 ? 4 : radius == 2 ? 3 : 2;
+    return radius == 1 ? 6 : radius == 2 ? 3 : 2;
 }
 
 bool march_usable(const st_plan* p) { return p->kind == KIND_CONST && p->radius <= 4; }

@@ -83,7 +83,7 @@ MarchFn march_fn(int r, int levels) {
         ST_MARCH(3, 1) ST_MARCH(3, 2) ST_MARCH(3, 3) ST_MARCH(3, 4)
         ST_MARCH(4, 1) ST_MARCH(4, 2) ST_MARCH(4, 3)
     } else {
-        ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4)
+        ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4) ST_MARCH(1, 5) ST_MARCH(1, 6)
         ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3)
         ST_MARCH(3, 1) ST_MARCH(3, 2)
         ST_MARCH(4, 1) ST_MARCH(4, 2)

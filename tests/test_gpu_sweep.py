@@ -263,7 +263,7 @@ def march_depth(shape, r, variant=None):
     import paper_2605_07954_amd as lib
     if variant == lib.ST_VARIANT_MARCH8:
         return {1: 8, 2: 4, 3: 3, 4: 2}[r] if shape == wl.STAR else {1: 3, 2: 2, 3: 2, 4: 1}[r]
-    return {1: 8, 2: 6, 3: 4, 4: 3}[r] if shape == wl.STAR else {1: 4, 2: 3}.get(r, 2)
+    return {1: 8, 2: 6, 3: 4, 4: 3}[r] if shape == wl.STAR else {1: 6, 2: 3}.get(r, 2)
 
 
 MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exactly one band (tb 1: 248
@@ -283,7 +283,7 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
 def test_march_variant_bitwise(g, case):
     """The row-marching variants (one wavefront per column band, lane-shifted side columns) equal the
     FP32-canonical oracle bit for bit at every depth they offer for the shape and radius (star r = 1
-    / 2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 4 / 3 / 2 / 2; with eight columns per lane star
+    / 2 / 3 / 4: up to 8 / 6 / 4 / 3 levels; box: 6 / 3 / 2 / 2; with eight columns per lane star
     8 / 4 / 3 / 2, box 3 / 2 / 2 / 1), with vector accesses (eight or four columns per lane, width a
     multiple of 8 or 4), element accesses (four columns per lane: any other width, or buffers off a
     16-byte boundary) and one column per lane."""
