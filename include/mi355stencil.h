@@ -178,9 +178,18 @@ int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double
  * and keep the fastest in the plan.
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
- * Synchronises the stream.  Errors: as stencil_run. */
+ * Synchronises the stream.  Errors: as stencil_run; ST_EINVAL for a varcoef plan (see
+ * stencil_autotune_varcoef). */
 int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
                      int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream);
+
+/* stencil_autotune_varcoef -- the same for a varcoef plan (the conservative heat step with the
+ * diffusivity field `kappa`, device FP32 rows x cols, only read): times its LDS-tile kernel at
+ * every tile of stencil_tiles() and tb in {1, 2, 3, 4, 6, 8} within the LDS budget and keeps the
+ * fastest.  Errors: as stencil_run_varcoef; ST_EINVAL for a constant-weight plan. */
+int stencil_autotune_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, void* workspace,
+                             size_t ws_bytes, int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out,
+                             void* stream);
 
 /* stencil_solve_ws_bytes -- workspace stencil_solve needs for this check interval. */
 int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* bytes);

@@ -57,6 +57,8 @@ _SIGS = {
     "stencil_norms": [_p, _p, _p, _p, _p, _sz, _p],
     "stencil_autotune": [_p, _p, _p, _p, _sz, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
                          ctypes.POINTER(_int), _p],
+    "stencil_autotune_varcoef": [_p, _p, _p, _p, _p, _sz, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                 ctypes.POINTER(_int), _p],
     "stencil_solve_ws_bytes": [_p, _i64, ctypes.POINTER(_sz)],
     "stencil_solve": [_p, _p, _p, _i64, _i64, ctypes.c_double, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                       _p, _sz, _p],
@@ -240,6 +242,15 @@ def stencil_autotune(plan, inp, out, workspace, sample_steps: int, stream=None):
     _ck(lib().stencil_autotune(plan, _dptr(inp, "in"), _dptr(out, "out"), _dptr(workspace, "workspace"),
                                _nbytes(workspace), sample_steps, ctypes.byref(tb), ctypes.byref(tx),
                                ctypes.byref(ty), _stream(stream)), "stencil_autotune")
+    return tb.value, tx.value, ty.value
+
+
+def stencil_autotune_varcoef(plan, inp, kappa, out, workspace, sample_steps: int, stream=None):
+    tb, tx, ty = _int(), _int(), _int()
+    _ck(lib().stencil_autotune_varcoef(plan, _dptr(inp, "in"), _dptr(kappa, "kappa"), _dptr(out, "out"),
+                                       _dptr(workspace, "workspace"), _nbytes(workspace), sample_steps,
+                                       ctypes.byref(tb), ctypes.byref(tx), ctypes.byref(ty), _stream(stream)),
+        "stencil_autotune_varcoef")
     return tb.value, tx.value, ty.value
 
 

@@ -190,10 +190,10 @@ int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double bound
     p->flags = flags;
     p->b = boundary;
     p->bq = float(boundary);
-    p->tb = 4;
-    while (p->tb > 1 && varcoef_lds_bytes(p->tb) > lds_limit()) --p->tb;
     p->tile_x = 128;
     p->tile_y = 64;
+    p->tb = 4;
+    while (p->tb > 1 && varcoef_lds_bytes(p->tb, p->tile_x, p->tile_y) > lds_limit()) --p->tb;
     *out = p;
     return ST_OK;
 }
@@ -220,7 +220,7 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
     const int t = tb ? tb : plan->tb;
     if (plan->kind == KIND_CONST && t > max_tb(plan, tx, ty))
         return fail(ST_EUNSUPPORTED, "temporal block too deep for this tile's LDS budget");
-    if (plan->kind == KIND_VARCOEF && varcoef_lds_bytes(t) > lds_limit())
+    if (plan->kind == KIND_VARCOEF && varcoef_lds_bytes(t, tx, ty) > lds_limit())
         return fail(ST_EUNSUPPORTED, "temporal block too deep for the LDS budget");
     plan->tb = t;
     plan->tile_x = tx;
@@ -377,9 +377,13 @@ int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, floa
     return run_common(plan, in, out, kappa, steps, workspace, ws_bytes, stream);
 }
 
-int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
-                     int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream) {
-    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+}  // extern "C"
+
+// Times every candidate blocking of `plan` on the caller's buffers (kappa: varcoef plans only) and
+// keeps the fastest; see stencil_autotune.
+static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void* out, void* workspace,
+                         size_t ws_bytes, int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out,
+                         void* stream) {
     if (plan->flags & ST_FLAG_NAIVE) return fail(ST_ESTATE, "naive plans have nothing to tune");
     if (sample_steps < 1) return fail(ST_EINVAL, "sample_steps must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -412,6 +416,7 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
         for (int k = 0; k < nc; ++k) {
             const int tb = cands[k];
             if (plan->kind == KIND_CONST && tb > max_tb(plan, tx, ty)) continue;
+            if (plan->kind == KIND_VARCOEF && varcoef_lds_bytes(tb, tx, ty) > lds_limit()) continue;
             if (tb > sample_steps) continue;
             plan->tb = tb;
             plan->tile_x = tx;
@@ -419,11 +424,11 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
             size_t need = 0;
             stencil_workspace_bytes(plan, sample_steps, &need);
             if (need > ws_bytes) continue;
-            if ((rc = run_common(plan, in, out, nullptr, sample_steps, workspace, ws_bytes, stream))) break;  // warm-up
+            if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;  // warm-up
             float ms = 1e30f;  // the better of two timed runs
             for (int rep = 0; rep < 2 && rc == ST_OK; ++rep) {
                 if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
-                if ((rc = run_common(plan, in, out, nullptr, sample_steps, workspace, ws_bytes, stream))) break;
+                if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;
                 if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
                 if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ST_EHIP, "hipEventSynchronize"); break; }
                 float t = 0;
@@ -453,6 +458,29 @@ int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, 
     if (tile_x_out) *tile_x_out = best_tx;
     if (tile_y_out) *tile_y_out = best_ty;
     return ST_OK;
+}
+
+extern "C" {
+
+int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
+                     int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "varcoef plans are tuned by stencil_autotune_varcoef");
+    return autotune_impl(plan, in, nullptr, out, workspace, ws_bytes, sample_steps, tb_out, tile_x_out, tile_y_out,
+                         stream);
+}
+
+int stencil_autotune_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, void* workspace,
+                             size_t ws_bytes, int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out,
+                             void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind != KIND_VARCOEF) return fail(ST_EINVAL, "not a varcoef plan");
+    if (!kappa) return fail(ST_EINVAL, "kappa is NULL");
+    if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
+    const size_t bytes = size_t(plan->rows * plan->cols) * 4;
+    if (overlap(kappa, out, bytes)) return fail(ST_EALIAS, "kappa and out overlap");
+    return autotune_impl(plan, in, kappa, out, workspace, ws_bytes, sample_steps, tb_out, tile_x_out, tile_y_out,
+                         stream);
 }
 
 }  // extern "C"

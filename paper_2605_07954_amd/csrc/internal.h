@@ -93,7 +93,7 @@ int supported_tiles(int* xy, int cap);
 int max_tb(const st_plan* p, int tx, int ty);
 int varcoef_launch(const st_plan* p, const float* src, float* dst, const float* kappa, int levels, hipStream_t s);
 size_t tiled_lds_bytes(int r, int tb, int tx, int ty);
-size_t varcoef_lds_bytes(int tb);
+size_t varcoef_lds_bytes(int tb, int tile_x, int tile_y);
 
 // Largest dynamic LDS allocation one workgroup may request on the current device (bytes);
 // 64 KiB when no device is visible.

@@ -153,11 +153,22 @@ __global__ __launch_bounds__(NT) void varcoef_tiled(SweepArgs a) {
     }
 }
 
-constexpr int VTX = 128, VTY = 64, VRS = 8;
+constexpr int VRS = 8;
+
+using VcFn = void (*)(SweepArgs);
+
+// The tiles of the constant-weight sweep's set: small ones give a small grid enough workgroups.
+VcFn varcoef_lookup(int tx, int ty) {
+    if (tx == 64 && ty == 64) return varcoef_tiled<64, 64, VRS>;
+    if (tx == 128 && ty == 32) return varcoef_tiled<128, 32, VRS>;
+    if (tx == 128 && ty == 64) return varcoef_tiled<128, 64, VRS>;
+    if (tx == 256 && ty == 32) return varcoef_tiled<256, 32, VRS>;
+    return nullptr;
+}
 
 }  // namespace
 
-size_t varcoef_lds_bytes(int tb) { return vlds_bytes(tb, VTX, VTY); }
+size_t varcoef_lds_bytes(int tb, int tx, int ty) { return vlds_bytes(tb, tx, ty); }
 
 int varcoef_launch(const st_plan* p, const float* src, float* dst, const float* kappa, int levels, hipStream_t s) {
     SweepArgs a;
@@ -175,11 +186,13 @@ int varcoef_launch(const st_plan* p, const float* src, float* dst, const float* 
         ST_LAUNCH_CHECK("varcoef_naive");
         return ST_OK;
     }
-    const size_t lds = vlds_bytes(levels, VTX, VTY);
+    const int tx = p->tile_x, ty = p->tile_y;
+    VcFn fn = varcoef_lookup(tx, ty);
+    if (!fn) return fail(ST_EUNSUPPORTED, "no varcoef kernel for this tile");
+    const size_t lds = vlds_bytes(levels, tx, ty);
     a.tb = levels;
-    a.tiles_x = (p->cols + VTX - 1) / VTX;
-    a.tiles_y = (p->rows + VTY - 1) / VTY;
-    auto fn = varcoef_tiled<VTX, VTY, VRS>;
+    a.tiles_x = (p->cols + tx - 1) / tx;
+    a.tiles_y = (p->rows + ty - 1) / ty;
     if (int rc = prepare_lds(reinterpret_cast<const void*>(fn), lds)) return rc;
     clear_stale_error();
     hipLaunchKernelGGL(fn, dim3(unsigned(a.tiles_x * a.tiles_y)), dim3(NT), lds, s, a);

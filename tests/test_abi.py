@@ -65,8 +65,16 @@ def test_host_validation_codes():
             lib.stencil_set_blocking(h, 0, 100, 100)   # tile not instantiated
         with pytest.raises(lib.StencilError):
             lib.stencil_set_blocking(h, 17)
+        # a varcoef tuner call on a constant-weight plan is rejected before any device work
+        assert lib.lib().stencil_autotune_varcoef(h, None, None, None, None, 0, 1, None, None, None, None) == -1
     finally:
         lib.stencil_destroy(h)
+    v = lib.stencil_plan_varcoef(8, 8, 0.0, 0)
+    try:  # and a constant-weight tuner call on a varcoef plan (it has no kappa to run with)
+        assert lib.lib().stencil_autotune(v, None, None, None, 0, 1, None, None, None, None) == -1
+        assert "stencil_autotune_varcoef" in lib.lib().stencil_last_error().decode()
+    finally:
+        lib.stencil_destroy(v)
 
 
 def test_strerror():

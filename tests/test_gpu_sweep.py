@@ -198,6 +198,45 @@ def test_varcoef(g):
             np.testing.assert_array_equal(got, ref32)
 
 
+def test_varcoef_tiles_and_autotune(g):
+    """The varcoef kernel at every tile and depth, and the blocking stencil_autotune_varcoef keeps,
+    bitwise equal to the FP32 oracle (ragged tiles, b != 0)."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, b, steps = 150, 203, 0.25, 11
+    u0, kap = wl.varcoef_problem(rows, cols, seed=5)
+    ref32 = oracle.varcoef_f32(u0, kap, b, steps)
+    x, k = g.to_dev(u0), g.to_dev(kap)
+    out = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    for tx, ty in lib.stencil_tiles():
+        for tb in (1, 2, 3, 4, 6, 8):
+            plan = lib.stencil_plan_varcoef(rows, cols, b, 0)
+            try:
+                try:
+                    lib.stencil_set_blocking(plan, tb, tx, ty)
+                except lib.StencilError as e:  # too deep for this tile's LDS
+                    assert e.code == lib.ST_EUNSUPPORTED
+                    continue
+                out.fill_(float("nan"))
+                lib.stencil_run_varcoef(plan, x, k, out, steps, ws)
+                np.testing.assert_array_equal(g.to_host(out), ref32, err_msg=f"tile {tx}x{ty} tb {tb}")
+            finally:
+                lib.stencil_destroy(plan)
+    plan = lib.stencil_plan_varcoef(rows, cols, b, lib.ST_FLAG_GRAPH)
+    try:
+        cfg = lib.stencil_autotune_varcoef(plan, x, k, out, ws, steps)
+        say(f"varcoef {rows}x{cols}: autotuned (tb, tile_x, tile_y) = {cfg}")
+        with pytest.raises(lib.StencilError):  # a constant-weight tuner call on a varcoef plan
+            lib.stencil_autotune(plan, x, out, ws, steps)
+        out.fill_(float("nan"))
+        lib.stencil_run_varcoef(plan, x, k, out, steps, ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(g.to_host(out), ref32)
+    finally:
+        lib.stencil_destroy(plan)
+
+
 def test_error_paths(g):
     import torch
     import paper_2605_07954_amd as lib
