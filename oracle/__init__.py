@@ -31,7 +31,9 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIBPATH):
-            raise RuntimeError(f"{_LIBPATH} is missing; run `python oracle/build.py` first")
+            # compile the checker where it is used (gcc only; nothing of the GPU library is involved)
+            from . import build as _build
+            _build.build()
         L = ctypes.CDLL(_LIBPATH)
         L.oracle_stencil_f64.argtypes = [_i64, _i64, ctypes.c_int, _p, ctypes.c_double, _i64, _p, _p]
         L.oracle_stencil_f32.argtypes = [_i64, _i64, ctypes.c_int, _p, ctypes.c_float, _i64, _p, _p]
