@@ -76,8 +76,9 @@ typedef struct sg_model sg_model;
  * Per-cell FP32 order: acc = W_c * u_c, then acc = fma(W_k, u_k, acc) over the
  * footprint taps in row-major (dy, dx) order (star footprint when every weight
  * off the two axes is zero, else the full box).
- * Errors: ST_EINVAL (rows or cols < 1, bad radius, non-finite weight or b,
- * NULL out/weights, unknown storage or flag bits), ST_ENOMEM. */
+ * Errors: ST_EINVAL (rows or cols < 1 or > 2^31, more than 2^46 cells, bad
+ * radius, non-finite weight or b, NULL out/weights, unknown storage or flag
+ * bits), ST_ENOMEM. */
 int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const float* weights,
                  double boundary, int storage, uint32_t flags);
 

@@ -142,6 +142,7 @@ int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const fl
     *out = nullptr;
     if (rows < 1 || cols < 1) return fail(ST_EINVAL, "rows and cols must be >= 1");
     if (rows > (int64_t(1) << 31) || cols > (int64_t(1) << 31)) return fail(ST_EINVAL, "grid side too large");
+    if (rows * cols > (int64_t(1) << 46)) return fail(ST_EINVAL, "grid has more cells than device memory can hold");
     if (radius < 1 || radius > ST_MAX_RADIUS) return fail(ST_EINVAL, "radius must be in [1, 4]");
     if (!weights) return fail(ST_EINVAL, "weights is NULL");
     if (storage != ST_F32 && storage != ST_BF16 && storage != ST_F16) return fail(ST_EINVAL, "unknown storage type");
@@ -176,6 +177,7 @@ int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double bound
     *out = nullptr;
     if (rows < 1 || cols < 1) return fail(ST_EINVAL, "rows and cols must be >= 1");
     if (rows > (int64_t(1) << 31) || cols > (int64_t(1) << 31)) return fail(ST_EINVAL, "grid side too large");
+    if (rows * cols > (int64_t(1) << 46)) return fail(ST_EINVAL, "grid has more cells than device memory can hold");
     if (!std::isfinite(boundary)) return fail(ST_EINVAL, "boundary value must be finite");
     if (int rc = check_flags(flags)) return rc;
     st_plan* p = new (std::nothrow) st_plan;
@@ -326,9 +328,9 @@ static int run_common(st_plan* plan, const void* in, void* out, const float* kap
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!(plan->flags & ST_FLAG_GRAPH) || steps == 0) return enqueue_run(plan, in, out, kappa, steps, workspace, s);
 
-    // graph path: capture the passes once per (in, out, workspace, steps, stream)
-    if (!(plan->graph_exec && plan->g_in == in && plan->g_out == out && plan->g_ws == workspace &&
-          plan->g_steps == steps && plan->g_stream == stream)) {
+    // graph path: capture the passes once per (in, kappa, out, workspace, steps, stream)
+    if (!(plan->graph_exec && plan->g_in == in && plan->g_kappa == kappa && plan->g_out == out &&
+          plan->g_ws == workspace && plan->g_steps == steps && plan->g_stream == stream)) {
         drop_graph(plan);
         hipStream_t cap;
         ST_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -351,6 +353,7 @@ static int run_common(st_plan* plan, const void* in, void* out, const float* kap
         if (e != hipSuccess) return fail(ST_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         plan->graph_exec = exec;
         plan->g_in = in;
+        plan->g_kappa = kappa;
         plan->g_out = out;
         plan->g_ws = workspace;
         plan->g_steps = steps;

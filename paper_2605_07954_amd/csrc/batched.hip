@@ -359,10 +359,13 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     size_t lds_res = 0;
     for (int g = 0; g < n; ++g) {
         const st_plan* p = plans[g];
-        if (!p || p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3 || steps[g] < 0 ||
-            steps[g] > (int64_t(1) << 30)) {
+        if (!p || steps[g] < 0 || steps[g] > (int64_t(1) << 30)) {
             delete B;
-            return fail(p ? ST_EUNSUPPORTED : ST_EINVAL, "batched grids must be FP32 constant-weight plans, r <= 3");
+            return fail(ST_EINVAL, "NULL plan, or steps outside [0, 2^30]");
+        }
+        if (p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3) {
+            delete B;
+            return fail(ST_EUNSUPPORTED, "batched grids must be FP32 constant-weight plans, r <= 3");
         }
         BatchDesc& d = B->desc[g];
         std::memset(&d, 0, sizeof(d));

@@ -75,6 +75,7 @@ struct st_plan {
     // cached hipGraph of a full run (ST_FLAG_GRAPH)
     void* graph_exec;
     const void* g_in;
+    const float* g_kappa;  // varcoef plans: the diffusivity field the graph reads
     void* g_out;
     void* g_ws;
     int64_t g_steps;

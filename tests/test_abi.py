@@ -43,6 +43,11 @@ def test_host_validation_codes():
     W[1, 1] = 1
     wp = W.ctypes.data_as(ctypes.c_void_p)
     assert _plan(0, 5, 1, wp, 0.0, 0, 0)[0] == -1           # rows < 1
+    assert _plan(2**31 + 1, 5, 1, wp, 0.0, 0, 0)[0] == -1   # side > 2^31
+    assert _plan(2**31, 2**31, 1, wp, 0.0, 0, 0)[0] == -1   # 2^62 cells: byte counts would wrap
+    rc, h = _plan(2**23, 2**23, 1, wp, 0.0, 0, 0)            # 2^46 cells: the largest accepted
+    assert rc == 0
+    lib.stencil_destroy(h)
     assert _plan(5, 5, 0, wp, 0.0, 0, 0)[0] == -1           # radius 0
     assert _plan(5, 5, 5, wp, 0.0, 0, 0)[0] == -1           # radius > 4
     assert _plan(5, 5, 1, None, 0.0, 0, 0)[0] == -1         # NULL weights
@@ -102,10 +107,13 @@ def test_batch_create_validation_on_host():
             with pytest.raises(lib.StencilError) as ei:
                 lib.stencil_batch_create(ok + [p], [1, 1, 1, 1], 0)
             assert ei.value.code == -3
-        with pytest.raises(lib.StencilError):
-            lib.stencil_batch_create(ok, [1, -1, 1], 0)
-        with pytest.raises(lib.StencilError):
+        for steps in ([1, -1, 1], [1, 2**30 + 1, 1]):
+            with pytest.raises(lib.StencilError) as ei:
+                lib.stencil_batch_create(ok, steps, 0)
+            assert ei.value.code == lib.ST_EINVAL
+        with pytest.raises(lib.StencilError) as ei:
             lib.stencil_batch_create(ok, [1, 1, 1], 0x80)
+        assert ei.value.code == lib.ST_EINVAL
     finally:
         for p in ok + bad:
             lib.stencil_destroy(p)

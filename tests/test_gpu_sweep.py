@@ -233,6 +233,15 @@ def test_varcoef_tiles_and_autotune(g):
         lib.stencil_run_varcoef(plan, x, k, out, steps, ws)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(g.to_host(out), ref32)
+        # same buffers, another diffusivity field: the cached graph must not replay the old one
+        _, kap2 = wl.varcoef_problem(rows, cols, seed=6)
+        ref2 = oracle.varcoef_f32(u0, kap2, b, steps)
+        k2 = g.to_dev(kap2)
+        for kk, want in ((k2, ref2), (k, ref32), (k2, ref2)):
+            out.fill_(float("nan"))
+            lib.stencil_run_varcoef(plan, x, kk, out, steps, ws)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.to_host(out), want)
     finally:
         lib.stencil_destroy(plan)
 
