@@ -45,6 +45,10 @@ enum Variant {
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
 
+// Workgroups of a one-cell-per-thread reference launch; beyond it the kernels stride over the grid
+// (a launch may hold at most 2^32 threads).
+constexpr int64_t kNaiveMaxBlocks = int64_t(1) << 20;
+
 // Kernel argument block of one sweep pass (passed by value; weights live in kernargs).
 struct SweepArgs {
     const void* src;

@@ -5,7 +5,8 @@
 //
 // One wavefront owns a band of columns, V per lane (V = 8 or 4 with one or two 16-byte loads, or one
 // 8-byte load, per lane and row; for any other width or alignment V = 4 with one element access
-// per column; or V = 1, many short tasks for small grids), and walks down a segment of rows.  Each input row is read from HBM once per band; the r columns a lane needs on either side
+// per column; or V = 1, many short tasks for small grids), and walks down a segment of rows.  Each
+// input row is read from HBM once per band; the r columns a lane needs on either side
 // come from neighbouring lanes through DPP wave shifts (the value at column c < 0 is the previous
 // lane's value at column c + V, so the side columns are produced nearest first, one shift each),
 // and the pass uses neither LDS nor barriers.  The rows a lane needs sit in a register ring whose

@@ -10,9 +10,6 @@ namespace march_k {
 
 using namespace march;
 
-
-using namespace march;
-
 constexpr int MWAVES = 4;  // wavefronts per workgroup, each with its own task
 
 struct MarchArgs {

@@ -34,23 +34,24 @@ __global__ __launch_bounds__(256) void sweep_naive(SweepArgs a) {
     using F = Fmt<S>;
     using T = typename F::T;
     const int64_t n = a.rows * a.cols;
-    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (idx >= n) return;
-    const int64_t i = idx / a.cols, j = idx - i * a.cols;
     const T* src = static_cast<const T*>(a.src);
     auto at = [&](int64_t y, int64_t x) -> float {
         return (y < 0 || y >= a.rows || x < 0 || x >= a.cols) ? a.b : F::ld(src[y * a.cols + x]);
     };
     constexpr int K = 2 * R + 1;
-    float acc = a.w[R * K + R] * at(i, j);
+    // grid-stride: the grid is capped on the host, so any cell count fits one launch
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < n; idx += int64_t(gridDim.x) * 256) {
+        const int64_t i = idx / a.cols, j = idx - i * a.cols;
+        float acc = a.w[R * K + R] * at(i, j);
 #pragma unroll
-    for (int dy = -R; dy <= R; ++dy)
+        for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-            if ((dy == 0 && dx == 0) || !tap_in(SHAPE, dy, dx)) continue;
-            acc = __builtin_fmaf(a.w[(dy + R) * K + dx + R], at(i + dy, j + dx), acc);
-        }
-    static_cast<T*>(a.dst)[idx] = F::st(acc);
+            for (int dx = -R; dx <= R; ++dx) {
+                if ((dy == 0 && dx == 0) || !tap_in(SHAPE, dy, dx)) continue;
+                acc = __builtin_fmaf(a.w[(dy + R) * K + dx + R], at(i + dy, j + dx), acc);
+            }
+        static_cast<T*>(a.dst)[idx] = F::st(acc);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +381,7 @@ int launch_naive(const st_plan* p, const void* src, void* dst, const float* kapp
     a.tb = 1;
     a.tiles_x = a.tiles_y = 0;
     const int64_t n = p->rows * p->cols;
-    const int64_t blocks = (n + 255) / 256;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, kNaiveMaxBlocks);
     clear_stale_error();
     hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(256), 0, s, a);
     ST_LAUNCH_CHECK("sweep_naive");

@@ -29,18 +29,19 @@ __device__ __forceinline__ float vc_update(float uc, float kc, float un, float k
 
 __global__ __launch_bounds__(NT) void varcoef_naive(SweepArgs a) {
     const int64_t n = a.rows * a.cols;
-    const int64_t idx = int64_t(blockIdx.x) * NT + threadIdx.x;
-    if (idx >= n) return;
-    const int64_t i = idx / a.cols, j = idx - i * a.cols;
     const float* u = static_cast<const float*>(a.src);
     const float* k = a.kappa;
-    const float uc = u[idx], kc = k[idx];
-    const bool hn = i > 0, hw = j > 0, he = j + 1 < a.cols, hs = i + 1 < a.rows;
-    const float un = hn ? u[idx - a.cols] : a.b, kn = hn ? k[idx - a.cols] : kc;
-    const float uw = hw ? u[idx - 1] : a.b, kw = hw ? k[idx - 1] : kc;
-    const float ue = he ? u[idx + 1] : a.b, ke = he ? k[idx + 1] : kc;
-    const float us = hs ? u[idx + a.cols] : a.b, ks = hs ? k[idx + a.cols] : kc;
-    static_cast<float*>(a.dst)[idx] = vc_update(uc, kc, un, kn, uw, kw, ue, ke, us, ks);
+    // grid-stride: the grid is capped on the host, so any cell count fits one launch
+    for (int64_t idx = int64_t(blockIdx.x) * NT + threadIdx.x; idx < n; idx += int64_t(gridDim.x) * NT) {
+        const int64_t i = idx / a.cols, j = idx - i * a.cols;
+        const float uc = u[idx], kc = k[idx];
+        const bool hn = i > 0, hw = j > 0, he = j + 1 < a.cols, hs = i + 1 < a.rows;
+        const float un = hn ? u[idx - a.cols] : a.b, kn = hn ? k[idx - a.cols] : kc;
+        const float uw = hw ? u[idx - 1] : a.b, kw = hw ? k[idx - 1] : kc;
+        const float ue = he ? u[idx + 1] : a.b, ke = he ? k[idx + 1] : kc;
+        const float us = hs ? u[idx + a.cols] : a.b, ks = hs ? k[idx + a.cols] : kc;
+        static_cast<float*>(a.dst)[idx] = vc_update(uc, kc, un, kn, uw, kw, ue, ke, us, ks);
+    }
 }
 
 struct VGeo {
@@ -182,7 +183,8 @@ int varcoef_launch(const st_plan* p, const float* src, float* dst, const float* 
         a.tb = 1;
         const int64_t n = p->rows * p->cols;
         clear_stale_error();
-        hipLaunchKernelGGL(varcoef_naive, dim3(unsigned((n + NT - 1) / NT)), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL(varcoef_naive, dim3(unsigned(std::min<int64_t>((n + NT - 1) / NT, kNaiveMaxBlocks))),
+                           dim3(NT), 0, s, a);
         ST_LAUNCH_CHECK("varcoef_naive");
         return ST_OK;
     }

@@ -48,6 +48,56 @@ def test_heat2d_512_100(g):
         np.testing.assert_array_equal(got, ref32)
 
 
+
+def test_naive_paths_beyond_one_cell_per_thread(g):
+    """The one-cell-per-thread reference kernels (ST_FLAG_NAIVE) stride once the grid has more cells
+    than their capped launch has threads (2^20 workgroups x 256 = 2^28): a 16400^2 grid, one step, for
+    the constant-weight and the varcoef path.  The first and last rows are checked bit for bit
+    against the FP32 oracle on a crop (one step: every crop row but the one at the cut is exact), the
+    whole field against the tiled kernels bit for bit."""
+    import torch
+    import paper_2605_07954_amd as lib
+    n, b, h = 16400, 0.3, 8
+    assert n * n > (1 << 28)
+    rng = np.random.default_rng(11)
+    u0 = rng.random((n, n), dtype=np.float32)
+    W = wl.heat5_weights()
+    x = g.to_dev(u0)
+    outs = {}
+    for flags in (lib.ST_FLAG_NAIVE, 0):
+        plan = lib.stencil_plan(n, n, 1, W, b, "f32", flags)
+        try:
+            outs[flags] = g.run(plan, x, 1, n, n)
+            torch.cuda.synchronize()
+        finally:
+            lib.stencil_destroy(plan)
+    assert torch.equal(outs[lib.ST_FLAG_NAIVE], outs[0])
+    got = outs[lib.ST_FLAG_NAIVE]
+    top = oracle.stencil_f32(u0[:h], W, b, 1)
+    bot = oracle.stencil_f32(u0[-h:], W, b, 1)
+    np.testing.assert_array_equal(g.to_host(got[: h - 1]), top[: h - 1])
+    np.testing.assert_array_equal(g.to_host(got[-(h - 1):]), bot[1:])
+    del outs, got
+    kap = (0.05 + 0.15 * rng.random((n, n), dtype=np.float32)).astype(np.float32)
+    k = g.to_dev(kap)
+    vo = {}
+    for flags in (lib.ST_FLAG_NAIVE, 0):
+        plan = lib.stencil_plan_varcoef(n, n, b, flags)
+        try:
+            out = torch.empty_like(x)
+            lib.stencil_run_varcoef(plan, x, k, out, 1, None)
+            torch.cuda.synchronize()
+            vo[flags] = out
+        finally:
+            lib.stencil_destroy(plan)
+    assert torch.equal(vo[lib.ST_FLAG_NAIVE], vo[0])
+    got = vo[lib.ST_FLAG_NAIVE]
+    top = oracle.varcoef_f32(u0[:h], kap[:h], b, 1)
+    bot = oracle.varcoef_f32(u0[-h:], kap[-h:], b, 1)
+    np.testing.assert_array_equal(g.to_host(got[: h - 1]), top[: h - 1])
+    np.testing.assert_array_equal(g.to_host(got[-(h - 1):]), bot[1:])
+    say(f"naive paths at {n}x{n}: bitwise equal to the tiled kernels and the oracle crops")
+
 CASES = [
     # rows, cols, shape, r, b, steps
     (1, 1, wl.STAR, 1, 0.0, 3),
