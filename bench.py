@@ -209,12 +209,13 @@ def extra_heat2d(torch, lib, stream) -> dict:
     plan = lib.stencil_plan(p.rows, p.cols, 1, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
     tb, _, _ = lib.stencil_autotune(plan, x, out, ws, p.steps, stream)  # the whole run: a few ms
     var = lib.stencil_get_variant(plan)
+    seg = lib.stencil_get_march_segment(plan)
     run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
     run()
     t = time_runs(run, 20, stream) / 20
     lib.stencil_destroy(plan)
     return {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "us": t * 1e6, "tb": tb,
-            "variant": VARIANT_NAMES[var], "launches": math.ceil(p.steps / tb)}
+            "variant": VARIANT_NAMES[var], "march_seg_min": seg, "launches": math.ceil(p.steps / tb)}
 
 
 def extra_star9(torch, lib, stream) -> dict:
@@ -232,11 +233,12 @@ def extra_star9(torch, lib, stream) -> dict:
         # candidate is timed with a shallower last pass than the real run has
         tb, _, _ = lib.stencil_autotune(plan, xh, o, w2, 120, stream)
         var = lib.stencil_get_variant(plan)
+        seg = lib.stencil_get_march_segment(plan)
         run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
         run()
         t = time_runs(run, 3, stream) / 3
         gst = p.steps * p.rows * p.cols / t / 1e9
-        res[st] = {"gstencil_s": gst, "ms": t * 1e3, "tb": tb, "variant": VARIANT_NAMES[var],
+        res[st] = {"gstencil_s": gst, "ms": t * 1e3, "tb": tb, "variant": VARIANT_NAMES[var], "march_seg_min": seg,
                    **_roofs(17.0, 2.0 * xh.element_size() / tb, gst)}
         lib.stencil_destroy(plan)
         del xh, o, w2

@@ -128,6 +128,16 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
 int stencil_set_variant(st_plan* plan, int variant);
 int stencil_get_variant(const st_plan* plan, int* variant);
 
+/* stencil_set_march_segment -- marching variants: each wavefront computes at
+ * least `min_rows` output rows of its column band (0, the default: as many
+ * (band, segment) tasks as the device holds wavefronts at once).  A segment
+ * recomputes r (tb - 1) rows of the lower levels at either end, which on
+ * small grids costs more than the idle SIMDs of fewer, longer tasks.  Bitwise
+ * the same results; values above rows act as rows.  stencil_autotune sets it.
+ * Errors: ST_EINVAL (NULL plan, negative min_rows). */
+int stencil_set_march_segment(st_plan* plan, int64_t min_rows);
+int stencil_get_march_segment(const st_plan* plan, int64_t* min_rows);
+
 /* stencil_get_blocking -- read back the current (tb, tile_x, tile_y). */
 int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y);
 
@@ -172,11 +182,13 @@ int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes);
 int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
                   size_t ws_bytes, void* stream);
 
-/* stencil_autotune -- time every supported (variant, tb, tile) candidate (LDS tiles with tb in
- * {1, 2, 3, 4, 6, 8} within their LDS budget, marching with one, four and, when cols % 8 == 0,
- * eight columns per lane at every depth each offers) on the
- * caller's buffers for `sample_steps` steps (one warm-up run, then the better of two timed runs)
- * and keep the fastest in the plan.
+/* stencil_autotune -- time every supported (variant, tb, tile) candidate on the caller's buffers
+ * for `sample_steps` steps (one warm-up run, then the better of two timed runs) and keep the
+ * fastest in the plan (variant, blocking and segment length).  Candidates: LDS tiles with tb in
+ * {1, 2, 3, 4, 6, 8} within their LDS budget; marching with one, four and, when cols % 8 == 0,
+ * eight columns per lane at every depth each offers, each depth above 1 also with segments of
+ * at least 1/2 (when that is 2 rows or more), 1, 2, 4 and 8 x r (tb - 1) rows
+ * (stencil_set_march_segment).
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
  * Synchronises the stream.  Errors: as stencil_run; ST_EINVAL for a varcoef plan (see

@@ -49,6 +49,8 @@ _SIGS = {
     "stencil_get_blocking": [_p, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
     "stencil_set_variant": [_p, _int],
     "stencil_get_variant": [_p, ctypes.POINTER(_int)],
+    "stencil_set_march_segment": [_p, _i64],
+    "stencil_get_march_segment": [_p, ctypes.POINTER(_i64)],
     "stencil_tiles": [ctypes.POINTER(_int), _int, ctypes.POINTER(_int)],
     "stencil_workspace_bytes": [_p, _i64, ctypes.POINTER(_sz)],
     "stencil_run": [_p, _p, _p, _i64, _p, _sz, _p],
@@ -192,6 +194,16 @@ def stencil_set_variant(plan, variant: int) -> None:
 def stencil_get_variant(plan) -> int:
     v = _int()
     _ck(lib().stencil_get_variant(plan, ctypes.byref(v)), "stencil_get_variant")
+    return v.value
+
+
+def stencil_set_march_segment(plan, min_rows: int) -> None:
+    _ck(lib().stencil_set_march_segment(plan, int(min_rows)), "stencil_set_march_segment")
+
+
+def stencil_get_march_segment(plan) -> int:
+    v = _i64()
+    _ck(lib().stencil_get_march_segment(plan, ctypes.byref(v)), "stencil_get_march_segment")
     return v.value
 
 

@@ -251,6 +251,20 @@ int stencil_set_variant(st_plan* plan, int variant) {
     return ST_OK;
 }
 
+int stencil_set_march_segment(st_plan* plan, int64_t min_rows) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (min_rows < 0) return fail(ST_EINVAL, "min_rows must be >= 0");
+    plan->seg_min = min_rows;
+    drop_graph(plan);
+    return ST_OK;
+}
+
+int stencil_get_march_segment(const st_plan* plan, int64_t* min_rows) {
+    if (!plan || !min_rows) return fail(ST_EINVAL, "NULL argument");
+    *min_rows = plan->seg_min;
+    return ST_OK;
+}
+
 int stencil_get_variant(const st_plan* plan, int* variant) {
     if (!plan || !variant) return fail(ST_EINVAL, "NULL argument");
     *variant = plan->variant;
@@ -393,6 +407,7 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
     const uint32_t saved_flags = plan->flags;
     plan->flags &= ~ST_FLAG_GRAPH;
     int best_tb = plan->tb, best_tx = plan->tile_x, best_ty = plan->tile_y, best_var = plan->variant;
+    int64_t best_seg = plan->seg_min;
     float best_ms = 1e30f;
     int tiles[32];
     const int nt = supported_tiles(tiles, 16);
@@ -416,7 +431,7 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
         } else {
             for (int tb : kTb) cands[nc++] = tb;
         }
-        for (int k = 0; k < nc; ++k) {
+        for (int k = 0; k < nc && rc == ST_OK; ++k) {
             const int tb = cands[k];
             if (plan->kind == KIND_CONST && tb > max_tb(plan, tx, ty)) continue;
             if (plan->kind == KIND_VARCOEF && varcoef_lds_bytes(tb, tx, ty) > lds_limit()) continue;
@@ -427,24 +442,36 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
             size_t need = 0;
             stencil_workspace_bytes(plan, sample_steps, &need);
             if (need > ws_bytes) continue;
-            if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;  // warm-up
-            float ms = 1e30f;  // the better of two timed runs
-            for (int rep = 0; rep < 2 && rc == ST_OK; ++rep) {
-                if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
-                if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;
-                if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
-                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ST_EHIP, "hipEventSynchronize"); break; }
-                float t = 0;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                ms = std::min(ms, t);
+            // marching with several levels: also segments of at least 1/2, 1, 2, 4, 8 x r (tb - 1) rows
+            int64_t segs[6] = {0}, ns = 1;
+            if (is_march(var) && tb > 1) {
+                const int64_t unit = int64_t(plan->radius) * (tb - 1);
+                if (unit >= 4 && unit / 2 < plan->rows) segs[ns++] = unit / 2;
+                for (int64_t f = 1; f <= 8; f *= 2)
+                    if (f * unit < plan->rows) segs[ns++] = f * unit;
             }
-            if (rc) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_tb = tb;
-                best_tx = tx;
-                best_ty = ty;
-                best_var = var;
+            for (int64_t si = 0; si < ns && rc == ST_OK; ++si) {
+                plan->seg_min = segs[si];
+                if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;  // warm-up
+                float ms = 1e30f;  // the better of two timed runs
+                for (int rep = 0; rep < 2 && rc == ST_OK; ++rep) {
+                    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
+                    if ((rc = run_common(plan, in, out, kappa, sample_steps, workspace, ws_bytes, stream))) break;
+                    if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(ST_EHIP, "hipEventRecord"); break; }
+                    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(ST_EHIP, "hipEventSynchronize"); break; }
+                    float t = 0;
+                    (void)hipEventElapsedTime(&t, e0, e1);
+                    ms = std::min(ms, t);
+                }
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_tb = tb;
+                    best_tx = tx;
+                    best_ty = ty;
+                    best_var = var;
+                    best_seg = segs[si];
+                }
             }
         }
     }
@@ -455,6 +482,7 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
     plan->tb = best_tb;
     plan->tile_x = best_tx;
     plan->tile_y = best_ty;
+    plan->seg_min = best_seg;
     drop_graph(plan);
     if (rc) return rc;
     if (tb_out) *tb_out = best_tb;

@@ -76,6 +76,7 @@ struct st_plan {
     double wsum;      // sum of the FP32 weights in FP64
     int tb, tile_x, tile_y;
     int variant;      // st::Variant (FP32 grids with cols % 4 == 0 may stream)
+    int64_t seg_min;  // marching: least output rows per task (0: one task per resident wavefront)
     // cached hipGraph of a full run (ST_FLAG_GRAPH)
     void* graph_exec;
     const void* g_in;

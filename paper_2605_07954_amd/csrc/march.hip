@@ -16,7 +16,8 @@
 // H = ceil(r tb / V) halo lanes per side.
 //
 // Segments are sized on the host so that the number of (band, segment) tasks is close to the number
-// of wavefronts the device holds at once: every wavefront runs one task of equal length.
+// of wavefronts the device holds at once: every wavefront runs one task of equal length.  A plan may
+// ask for longer segments (stencil_set_march_segment), which the autotuner does for small grids.
 
 #include <algorithm>
 
@@ -75,6 +76,9 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     const int64_t waves = int64_t(blocks) * MWAVES;
     const int64_t per_band = std::max<int64_t>(1, waves / a.bands);  // segments per band
     a.seg = (p->rows + per_band - 1) / per_band;
+    // a segment recomputes r (levels - 1) rows of the lower levels at either end: on small grids
+    // longer segments (fewer tasks than wavefronts) cost less than the recomputation they avoid
+    a.seg = std::max<int64_t>(a.seg, std::min<int64_t>(p->seg_min, p->rows));
     const int64_t segs = (p->rows + a.seg - 1) / a.seg;
     a.tasks = segs * a.bands;
     const int64_t grid = (a.tasks + MWAVES - 1) / MWAVES;

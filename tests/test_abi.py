@@ -70,6 +70,13 @@ def test_host_validation_codes():
             lib.stencil_set_blocking(h, 0, 100, 100)   # tile not instantiated
         with pytest.raises(lib.StencilError):
             lib.stencil_set_blocking(h, 17)
+        assert lib.stencil_get_march_segment(h) == 0        # default: one task per resident wavefront
+        lib.stencil_set_march_segment(h, 12)
+        assert lib.stencil_get_march_segment(h) == 12
+        with pytest.raises(lib.StencilError) as ei:
+            lib.stencil_set_march_segment(h, -1)
+        assert ei.value.code == lib.ST_EINVAL
+        assert lib.stencil_get_march_segment(h) == 12
         # a varcoef tuner call on a constant-weight plan is rejected before any device work
         assert lib.lib().stencil_autotune_varcoef(h, None, None, None, None, 0, 1, None, None, None, None) == -1
     finally:
