@@ -261,6 +261,7 @@ def extra_batched(torch, lib, stream) -> dict:
     batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
     bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
     caps = lib.stencil_batch_autotune(batch, ins, outs, bws, stream)
+    segs = {k: lib.stencil_batch_get_segment(batch, k[0], k[1]) for k in caps}
     runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
     runb()
     t_b = time_runs(runb, 5, stream) / 5
@@ -271,7 +272,8 @@ def extra_batched(torch, lib, stream) -> dict:
     del ins, outs, wss, bws
     torch.cuda.empty_cache()
     return {"gstencil_s": cells / t_b / 1e9, "ms": t_b * 1e3,
-            "classes": {f"{k[0]}{k[1]}": f"{v[0]} x{v[1]}" for k, v in caps.items()},
+            "classes": {f"{k[0]}{k[1]}": f"{v[0]} x{v[1]}" + (f", {segs[k]}-row segments" if segs[k] else "")
+                        for k, v in caps.items()},
             "per_grid_ms": t_per * 1e3,
             "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
 

@@ -250,13 +250,24 @@ int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* ou
  * ST_EUNSUPPORTED (depth out of range). */
 int stencil_batch_set_class(st_batch* batch, int shape, int radius, int engine, int depth);
 
+/* stencil_batch_set_segment -- marching engine: each wavefront of the class (shape, radius)
+ * computes at least `min_rows` output rows of its band (0, the default: segments sized so that
+ * the class's tasks about fill the device once, and at least 8 rows).  As for a single plan
+ * (stencil_set_march_segment), longer segments recompute fewer rows of the lower levels and
+ * re-read fewer input rows.  Bitwise the same results.  stencil_batch_autotune sets it.
+ * stencil_batch_get_segment reads the segment length the class's marching launches use (0 when
+ * the class runs on tiles or is absent).  Errors: ST_EINVAL (bad class, negative min_rows). */
+int stencil_batch_set_segment(st_batch* batch, int shape, int radius, int64_t min_rows);
+int stencil_batch_get_segment(const st_batch* batch, int shape, int radius, int64_t* rows);
+
 /* stencil_batch_autotune -- pick, for each stencil class (shape, radius) of the grids that are
  * not LDS-resident, the engine and the depth of its passes: LDS tiles of 128 x 64 (one multi-grid
  * launch per pass for all tiled classes) with the depth capped at 1, 2, 3, 4, 6, 8, 12 or 16
  * (and by what each grid's tile fits in LDS), or marching (one wavefront per column band, four
- * columns per lane, any width and alignment; one chain of launches per class, the classes on parallel branches
- * of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star r = 1 / 2 / 3, 6 / 3 / 2
- * for box).  Coordinate descent: each
+ * columns per lane, any width and alignment; one chain of launches per class, the classes on
+ * parallel branches of the graph) with every depth it offers (up to 8 / 6 / 4 levels for star
+ * r = 1 / 2 / 3, 6 / 3 / 2 for box), each with the default segments and with segments 2, 4 and 8
+ * times as long (stencil_batch_set_segment).  Coordinate descent: each
  * class in turn, every candidate timed on the whole batch run twice on the caller's buffers (outs
  * are overwritten; results are bitwise those of any other choice).  Writes the chosen depth and
  * engine (0 = tiles, 1 = marching) per class to tb_out[6] / engine_out[6] when non-NULL (star

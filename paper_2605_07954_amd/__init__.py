@@ -69,6 +69,8 @@ _SIGS = {
     "stencil_run_batched": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, _p],
     "stencil_batch_destroy": [_p],
     "stencil_batch_set_class": [_p, _int, _int, _int, _int],
+    "stencil_batch_set_segment": [_p, _int, _int, _i64],
+    "stencil_batch_get_segment": [_p, _int, _int, ctypes.POINTER(_i64)],
     "stencil_batch_autotune": [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), _p, _sz, ctypes.POINTER(_int),
                                ctypes.POINTER(_int), _p],
     "surrogate_create": [ctypes.POINTER(_p), _u32],
@@ -307,6 +309,18 @@ def stencil_run_batched(batch, ins, outs, workspace, stream=None) -> None:
     po = (_p * n)(*[_dptr(t, "out").value for t in outs])
     _ck(lib().stencil_run_batched(batch, pi, po, _dptr(workspace, "workspace"), _nbytes(workspace),
                                   _stream(stream)), "stencil_run_batched")
+
+
+def stencil_batch_set_segment(batch, shape: str, radius: int, min_rows: int) -> None:
+    _ck(lib().stencil_batch_set_segment(batch, {"star": 0, "box": 1}[shape], radius, int(min_rows)),
+        "stencil_batch_set_segment")
+
+
+def stencil_batch_get_segment(batch, shape: str, radius: int) -> int:
+    v = _i64()
+    _ck(lib().stencil_batch_get_segment(batch, {"star": 0, "box": 1}[shape], radius, ctypes.byref(v)),
+        "stencil_batch_get_segment")
+    return v.value
 
 
 def stencil_batch_set_class(batch, shape: str, radius: int, engine: str, depth: int) -> None:

@@ -208,11 +208,13 @@ struct st_batch {
     int max_passes;
     // per stencil class (slot = shape * 3 + r - 1): engine (0 = LDS tiles, 1 = marching) and depth
     int engine[6], depth[6];
+    int64_t seg_min[6];  // marching: least output rows per task (0: the tasks about fill the device once)
     struct MLaunch {
         int s0, n, p, levels;
         int64_t tasks;
     };
     struct MClass {
+        int64_t seg = 0;               // output rows per task (the longest a grid's segment may be)
         std::vector<int> order;        // the class's marching grids by passes, then last-pass depth
         std::vector<int64_t> prefix;   // task prefix sums over `order`
         std::vector<MLaunch> launches; // in pass order
@@ -311,7 +313,9 @@ static void build_passes(st_batch* B) {
         });
         int64_t band_rows = 0;
         for (int g : M.order) band_rows += B->desc[g].tiles_x * B->desc[g].rows;
-        const int64_t seg = march_segment(band_rows, march_waves(c / 3, c % 3 + 1, tb));
+        const int64_t seg =
+            std::max(march_segment(band_rows, march_waves(c / 3, c % 3 + 1, tb)), B->seg_min[c]);
+        M.seg = seg;
         M.prefix.assign(1, 0);
         for (int g : M.order) {
             BatchDesc& d = B->desc[g];
@@ -402,6 +406,7 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
     for (int c = 0; c < 6; ++c) {
         B->engine[c] = 0;
         B->depth[c] = 0;  // 0: each grid keeps its plan's depth (capped by the tile's LDS)
+        B->seg_min[c] = 0;
     }
     build_passes(B);
     // workspace: descriptor table, queue tables, one ping-pong field per tiled grid with two or more
@@ -659,10 +664,35 @@ extern "C" int stencil_batch_set_class(st_batch* B, int shape, int radius, int e
     return ST_OK;
 }
 
+extern "C" int stencil_batch_set_segment(st_batch* B, int shape, int radius, int64_t min_rows) {
+    if (!B) return fail(ST_EINVAL, "batch is NULL");
+    if ((shape != SHAPE_STAR && shape != SHAPE_BOX) || radius < 1 || radius > 3 || min_rows < 0)
+        return fail(ST_EINVAL, "bad class or segment length");
+    const int c = shape * 3 + radius - 1;
+    B->seg_min[c] = min_rows;
+    build_passes(B);
+    B->staged_valid = false;
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    return ST_OK;
+}
+
+extern "C" int stencil_batch_get_segment(const st_batch* B, int shape, int radius, int64_t* rows) {
+    if (!B || !rows) return fail(ST_EINVAL, "NULL argument");
+    if ((shape != SHAPE_STAR && shape != SHAPE_BOX) || radius < 1 || radius > 3)
+        return fail(ST_EINVAL, "bad class");
+    const int c = shape * 3 + radius - 1;
+    *rows = B->engine[c] == 1 && !B->mclass[c].order.empty() ? B->mclass[c].seg : 0;
+    return ST_OK;
+}
+
 // Coordinate descent over the stencil classes (shape, radius) of the non-resident grids: for each
 // class in turn, time the whole batch (direct launches) with every candidate engine and depth -- LDS
 // tiles with the class's depth capped at 1, 2, 3, 4, 6, 8, 12 or 16, or marching with 1 .. the
-// deepest its radius allows -- keep the fastest, then move to the next class.
+// deepest its radius allows, each marching depth with the default segments and with segments 2, 4
+// and 8 times as long -- keep the fastest, then move to the next class.
 extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void* const* outs, void* workspace,
                                       size_t ws_bytes, int* tb_out, int* engine_out, void* stream) {
     if (!B || !ins || !outs) return fail(ST_EINVAL, "NULL argument");
@@ -682,10 +712,15 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ST_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(ST_EHIP, "hipEventCreate");
-    auto apply = [&](int c, int engine, int depth) {
+    auto apply = [&](int c, int engine, int depth, int seg_mult) {
         B->engine[c] = engine;
         B->depth[c] = depth;
+        B->seg_min[c] = 0;
         build_passes(B);
+        if (engine == 1 && seg_mult > 1) {  // longer than the default segment of this depth
+            B->seg_min[c] = seg_mult * B->mclass[c].seg;
+            build_passes(B);
+        }
         B->staged_valid = false;  // descriptor tables changed
     };
     auto timed = [&](float* ms) -> int {
@@ -701,14 +736,18 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
     for (int c = 0; c < 6 && rc == ST_OK; ++c) {
         if (!present[c]) continue;
         const int r = c % 3 + 1;
-        std::vector<std::pair<int, int>> cands;
+        struct Cand {
+            int engine, depth, seg_mult;
+        };
+        std::vector<Cand> cands;
         for (int cap : kCaps)
-            if (cap <= deepest[c]) cands.push_back({0, cap});
-        for (int t = 1; t <= march_max_tb(c / 3, r, 1); ++t) cands.push_back({1, t});
-        std::pair<int, int> best = cands[0];
+            if (cap <= deepest[c]) cands.push_back({0, cap, 1});
+        for (int t = 1; t <= march_max_tb(c / 3, r, 1); ++t)
+            for (int m : {1, 2, 4, 8}) cands.push_back({1, t, m});
+        Cand best = cands[0];
         float best_ms = 1e30f;
-        for (const auto& cd : cands) {
-            apply(c, cd.first, cd.second);
+        for (const Cand& cd : cands) {
+            apply(c, cd.engine, cd.depth, cd.seg_mult);
             float ms = 0.0f;
             if ((rc = timed(&ms))) break;
             if (ms < best_ms) {
@@ -717,9 +756,9 @@ extern "C" int stencil_batch_autotune(st_batch* B, const void* const* ins, void*
             }
         }
         if (rc) break;
-        apply(c, best.first, best.second);
-        if (tb_out) tb_out[c] = best.second;
-        if (engine_out) engine_out[c] = best.first;
+        apply(c, best.engine, best.depth, best.seg_mult);
+        if (tb_out) tb_out[c] = best.depth;
+        if (engine_out) engine_out[c] = best.engine;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

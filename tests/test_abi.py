@@ -108,6 +108,10 @@ def test_batch_create_validation_on_host():
         b = lib.stencil_batch_create(ok, [10, 7, 0], lib.ST_FLAG_GRAPH)
         try:
             assert lib.stencil_batch_workspace_bytes(b) >= 300 * 260 * 4  # the multi-pass grid's ping-pong field
+            assert lib.stencil_batch_get_segment(b, "star", 1) == 0     # on tiles: no marching segments
+            lib.stencil_batch_set_segment(b, "box", 2, 64)
+            for args in ((0, 1, -1), (2, 1, 8), (0, 4, 8), (0, 0, 8)):
+                assert lib.lib().stencil_batch_set_segment(b, *args) == lib.ST_EINVAL
         finally:
             lib.stencil_batch_destroy(b)
         for p in bad:

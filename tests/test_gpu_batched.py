@@ -182,6 +182,24 @@ def test_batched_engines_every_class_bitwise(g, graph):
                         torch.cuda.synchronize()
                         for p, o, ref in zip(problems, outs, refs):
                             np.testing.assert_array_equal(g.to_host(o), ref, err_msg=f"{p.name} {engine} r{r} x{depth}")
+                        if engine != "march":
+                            continue
+                        # longer segments than the default sizing: bitwise the same
+                        seg0 = lib.stencil_batch_get_segment(batch, "star", r)
+                        assert seg0 >= 8
+                        for seg in (2 * seg0, 5 * seg0, 1000):
+                            lib.stencil_batch_set_segment(batch, "star", r, seg)
+                            assert lib.stencil_batch_get_segment(batch, "star", r) == max(seg, seg0)
+                            for o in outs:
+                                o.fill_(float("nan"))
+                            lib.stencil_run_batched(batch, ins, outs, ws)
+                            torch.cuda.synchronize()
+                            for p, o, ref in zip(problems, outs, refs):
+                                np.testing.assert_array_equal(g.to_host(o), ref,
+                                                              err_msg=f"{p.name} march r{r} x{depth} seg {seg}")
+                        lib.stencil_batch_set_segment(batch, "star", r, 0)
+            with pytest.raises(lib.StencilError):
+                lib.stencil_batch_set_segment(batch, "star", 1, -1)
             with pytest.raises(lib.StencilError):
                 lib.stencil_batch_set_class(batch, "star", 3, "march", 5)
             with pytest.raises(lib.StencilError):
