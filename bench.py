@@ -39,6 +39,17 @@ VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP
 HBM_PEAK = 8.0e12
 
 
+def flop_per_update(taps: int) -> float:
+    """FLOP of one cell update with `taps` footprint taps: the centre product, then one fused
+    multiply-add (2 FLOP) per other tap -- 9 for the 5-point star, as counted in Sec. VI-E."""
+    return 2.0 * taps - 1.0
+
+
+def gstencil_s(steps: int, rows: int, cols: int, seconds: float) -> float:
+    """Cell updates per second in units of 10^9 (Sec. VI-A)."""
+    return steps * rows * cols / (seconds * 1e9)
+
+
 KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march", 4: "sweep_march"}
 VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1"}
 
@@ -89,7 +100,7 @@ def cpu_baseline(p) -> dict:
     t0 = time.perf_counter()
     oracle.stencil_f32(u0, p.weights, 0.0, steps)
     dt = time.perf_counter() - t0
-    return {"value": steps * rows * cols / dt / 1e9, "unit": "GStencil/s", "cores": oracle.num_threads(),
+    return {"value": gstencil_s(steps, rows, cols, dt), "unit": "GStencil/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"box2d49p FP32-canonical oracle on the 1024x1024 top-left crop, {steps} steps ({dt:.1f} s)"}
 
@@ -165,9 +176,10 @@ def main_line(args, torch, lib, stream):
     torch.cuda.synchronize()
     t = time_runs(run, args.steps, stream)
     ms = t / args.steps * 1e3
-    value = T * rows * cols * args.steps / t / 1e9
+    value = gstencil_s(T * args.steps, rows, cols, t)
     launches = math.ceil(T / tb) * args.steps
-    flops = 97.0 * T * rows * cols * args.steps  # 1 multiply + 48 FMA per update
+    fpu = flop_per_update(49)  # 97: 1 multiply + 48 FMA
+    flops = fpu * T * rows * cols * args.steps
     achieved = flops / t
     traffic = measured_traffic(tb, (tx, ty), variant)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
@@ -175,9 +187,9 @@ def main_line(args, torch, lib, stream):
             "kernel": KERNEL_NAMES[variant] + f"<f32, r=3, box{', 8 columns per lane' if variant == 3 else ''}, tb={tb}>",
             "launches": launches,
             "avg_launch_us": t / launches * 1e6,
-            "alg_flop_per_launch": 97.0 * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
+            "alg_flop_per_launch": fpu * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
             "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
-            "alu_roof_gstencil": VALU_FP32_PEAK / 97.0 / 1e9,
+            "alu_roof_gstencil": VALU_FP32_PEAK / fpu / 1e9,
             "frac_of_packed_fp32_peak": achieved / VALU_FP32_PEAK_PACKED,
             "alg_hbm_gbps": 8.0 / tb * T * rows * cols * args.steps / t / 1e9}
     lib.stencil_destroy(plan)
@@ -214,7 +226,7 @@ def extra_heat2d(torch, lib, stream) -> dict:
     run()
     t = time_runs(run, 20, stream) / 20
     lib.stencil_destroy(plan)
-    return {"gstencil_s": p.steps * p.rows * p.cols / t / 1e9, "us": t * 1e6, "tb": tb,
+    return {"gstencil_s": gstencil_s(p.steps, p.rows, p.cols, t), "us": t * 1e6, "tb": tb,
             "variant": VARIANT_NAMES[var], "march_seg_min": seg, "launches": math.ceil(p.steps / tb)}
 
 
@@ -237,9 +249,9 @@ def extra_star9(torch, lib, stream) -> dict:
         run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
         run()
         t = time_runs(run, 3, stream) / 3
-        gst = p.steps * p.rows * p.cols / t / 1e9
+        gst = gstencil_s(p.steps, p.rows, p.cols, t)
         res[st] = {"gstencil_s": gst, "ms": t * 1e3, "tb": tb, "variant": VARIANT_NAMES[var], "march_seg_min": seg,
-                   **_roofs(17.0, 2.0 * xh.element_size() / tb, gst)}
+                   **_roofs(flop_per_update(9), 2.0 * xh.element_size() / tb, gst)}
         lib.stencil_destroy(plan)
         del xh, o, w2
     torch.cuda.empty_cache()
