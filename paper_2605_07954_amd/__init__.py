@@ -169,6 +169,9 @@ def storage_code(storage) -> int:
 def stencil_plan(rows: int, cols: int, radius: int, weights, boundary: float = 0.0, storage="f32",
                  flags: int = 0):
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    if w.size != (2 * radius + 1) ** 2:  # the library reads exactly (2r+1)^2 weights
+        raise ValueError(f"weights must hold (2r+1)^2 = {(2 * radius + 1) ** 2} values for radius {radius}, "
+                         f"got {w.size}")
     h = _p()
     _ck(lib().stencil_plan(ctypes.byref(h), rows, cols, radius, w.ctypes.data_as(_p), float(boundary),
                            storage_code(storage), flags), "stencil_plan")

@@ -89,6 +89,15 @@ def test_host_validation_codes():
         lib.stencil_destroy(v)
 
 
+def test_binding_checks_the_weight_count():
+    """The C entry point reads (2r+1)^2 weights; the binding refuses an array of another size
+    before handing it over."""
+    with pytest.raises(ValueError):
+        lib.stencil_plan(8, 8, 2, np.ones((3, 3), np.float32) / 9, 0.0, "f32", 0)
+    h = lib.stencil_plan(8, 8, 2, np.ones(25, np.float32) / 25, 0.0, "f32", 0)  # flat is fine
+    lib.stencil_destroy(h)
+
+
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.lib().stencil_strerror(code)
