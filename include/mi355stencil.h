@@ -138,6 +138,11 @@ int stencil_get_variant(const st_plan* plan, int* variant);
 int stencil_set_march_segment(st_plan* plan, int64_t min_rows);
 int stencil_get_march_segment(const st_plan* plan, int64_t* min_rows);
 
+/* stencil_get_dims -- the plan's rows, cols and storage type (ST_F32 / ST_BF16 / ST_F16); NULL
+ * outputs are skipped.  A field of the plan occupies rows * cols * (4 or 2) bytes.  Host-only.
+ * Errors: ST_EINVAL (NULL plan). */
+int stencil_get_dims(const st_plan* plan, int64_t* rows, int64_t* cols, int* storage);
+
 /* stencil_get_blocking -- read back the current (tb, tile_x, tile_y). */
 int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y);
 

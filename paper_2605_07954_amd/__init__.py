@@ -47,6 +47,7 @@ _SIGS = {
     "stencil_destroy": [_p],
     "stencil_set_blocking": [_p, _int, _int, _int],
     "stencil_get_blocking": [_p, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
+    "stencil_get_dims": [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int)],
     "stencil_set_variant": [_p, _int],
     "stencil_get_variant": [_p, ctypes.POINTER(_int)],
     "stencil_set_march_segment": [_p, _i64],
@@ -158,6 +159,29 @@ def _nbytes(t) -> int:
     return 0 if t is None else t.numel() * t.element_size()
 
 
+def stencil_get_dims(plan):
+    """(rows, cols, storage code) of a plan."""
+    r, c, st = _i64(), _i64(), _int()
+    _ck(lib().stencil_get_dims(plan, ctypes.byref(r), ctypes.byref(c), ctypes.byref(st)), "stencil_get_dims")
+    return r.value, c.value, st.value
+
+
+def _fields(plan, **tensors):
+    """Refuse GPU fields smaller than the plan's grid (the kernels would access memory past them)."""
+    rows, cols, st = stencil_get_dims(plan)
+    need = rows * cols * (4 if st == ST_F32 else 2)
+    for name, t in tensors.items():
+        if t is not None and _nbytes(t) < need:
+            raise ValueError(f"{name} holds {_nbytes(t)} bytes; the plan's {rows} x {cols} field needs {need}")
+
+
+def _batch_fields(n: int, **tensors):
+    """Refuse FP32 surrogate fields smaller than n cells."""
+    for name, t in tensors.items():
+        if t is not None and _nbytes(t) < 4 * n:
+            raise ValueError(f"{name} holds {_nbytes(t)} bytes; {n} FP32 cells need {4 * n}")
+
+
 def storage_code(storage) -> int:
     return STORAGE[storage] if isinstance(storage, str) else int(storage)
 
@@ -233,11 +257,13 @@ def stencil_workspace_bytes(plan, steps: int) -> int:
 
 
 def stencil_run(plan, inp, out, steps: int, workspace=None, stream=None) -> None:
+    _fields(plan, inp=inp, out=out)
     _ck(lib().stencil_run(plan, _dptr(inp, "in"), _dptr(out, "out"), steps, _dptr(workspace, "workspace"),
                           _nbytes(workspace), _stream(stream)), "stencil_run")
 
 
 def stencil_run_varcoef(plan, inp, kappa, out, steps: int, workspace=None, stream=None) -> None:
+    _fields(plan, inp=inp, kappa=kappa, out=out)
     _ck(lib().stencil_run_varcoef(plan, _dptr(inp, "in"), _dptr(kappa, "kappa"), _dptr(out, "out"), steps,
                                   _dptr(workspace, "workspace"), _nbytes(workspace), _stream(stream)),
         "stencil_run_varcoef")
@@ -250,11 +276,15 @@ def stencil_norms_ws_bytes(plan) -> int:
 
 
 def stencil_norms(plan, u_prev, u, out4, workspace, stream=None) -> None:
+    _fields(plan, u_prev=u_prev, u=u)
+    if out4 is not None and _nbytes(out4) < 32:
+        raise ValueError("out4 must hold 4 doubles")
     _ck(lib().stencil_norms(plan, _dptr(u_prev, "u_prev"), _dptr(u, "u"), _dptr(out4, "out4"),
                             _dptr(workspace, "workspace"), _nbytes(workspace), _stream(stream)), "stencil_norms")
 
 
 def stencil_autotune(plan, inp, out, workspace, sample_steps: int, stream=None):
+    _fields(plan, inp=inp, out=out)
     tb, tx, ty = _int(), _int(), _int()
     _ck(lib().stencil_autotune(plan, _dptr(inp, "in"), _dptr(out, "out"), _dptr(workspace, "workspace"),
                                _nbytes(workspace), sample_steps, ctypes.byref(tb), ctypes.byref(tx),
@@ -263,6 +293,7 @@ def stencil_autotune(plan, inp, out, workspace, sample_steps: int, stream=None):
 
 
 def stencil_autotune_varcoef(plan, inp, kappa, out, workspace, sample_steps: int, stream=None):
+    _fields(plan, inp=inp, kappa=kappa, out=out)
     tb, tx, ty = _int(), _int(), _int()
     _ck(lib().stencil_autotune_varcoef(plan, _dptr(inp, "in"), _dptr(kappa, "kappa"), _dptr(out, "out"),
                                        _dptr(workspace, "workspace"), _nbytes(workspace), sample_steps,
@@ -279,6 +310,7 @@ def stencil_solve_ws_bytes(plan, check_every: int) -> int:
 
 def stencil_solve(plan, inp, out, max_steps: int, check_every: int, tol: float, workspace, stream=None):
     """Returns (steps_done, relative residual of the last step)."""
+    _fields(plan, inp=inp, out=out)
     done = _i64()
     res = ctypes.c_double()
     _ck(lib().stencil_solve(plan, _dptr(inp, "in"), _dptr(out, "out"), max_steps, check_every, float(tol),
@@ -400,6 +432,7 @@ def surrogate_workspace_bytes(model, batch: int, rows: int, cols: int) -> int:
 
 def surrogate_infer(model, params, u0, kappa, u_hat, batch: int, rows: int, cols: int, workspace,
                       stream=None) -> None:
+    _batch_fields(batch * rows * cols, u0=u0, kappa=kappa, u_hat=u_hat)
     _ck(lib().surrogate_infer(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
                                 _dptr(u_hat, "u_hat"), batch, rows, cols, _dptr(workspace, "workspace"),
                                 _nbytes(workspace), _stream(stream)), "surrogate_infer")
@@ -407,6 +440,7 @@ def surrogate_infer(model, params, u0, kappa, u_hat, batch: int, rows: int, cols
 
 def surrogate_loss_grad(model, params, u0, kappa, target, lo_hi, batch: int, rows: int, cols: int, grad, loss,
                         workspace, stream=None) -> None:
+    _batch_fields(batch * rows * cols, u0=u0, kappa=kappa, target=target)
     flat = [int(v) for v in np.asarray(lo_hi).reshape(-1)]
     if len(flat) == 4 and batch > 1:  # one mask for every field
         flat = flat * batch
@@ -441,6 +475,7 @@ def surrogate_checked_ws_bytes(model, rows: int, cols: int) -> int:
 
 def surrogate_infer_checked(model, params, u0, kappa, out, rows: int, cols: int, judge, K: int, tol: float,
                             workspace, stream=None):
+    _batch_fields(rows * cols, u0=u0, kappa=kappa, out=out)
     used = _int()
     err = ctypes.c_double()
     _ck(lib().surrogate_infer_checked(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),

@@ -271,6 +271,14 @@ int stencil_get_variant(const st_plan* plan, int* variant) {
     return ST_OK;
 }
 
+int stencil_get_dims(const st_plan* plan, int64_t* rows, int64_t* cols, int* storage) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (rows) *rows = plan->rows;
+    if (cols) *cols = plan->cols;
+    if (storage) *storage = plan->storage;
+    return ST_OK;
+}
+
 int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
     if (tb) *tb = plan->tb;

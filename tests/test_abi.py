@@ -98,6 +98,24 @@ def test_binding_checks_the_weight_count():
     lib.stencil_destroy(h)
 
 
+def test_binding_refuses_fields_smaller_than_the_plan():
+    """Field tensors are checked against the plan's rows x cols (stencil_get_dims) before any call
+    that would hand their pointers to a kernel."""
+    import torch
+    h = lib.stencil_plan(8, 6, 1, np.ones((3, 3), np.float32) / 9, 0.0, "bf16", 0)
+    try:
+        assert lib.stencil_get_dims(h) == (8, 6, lib.ST_BF16)
+        small = torch.zeros(47, dtype=torch.int16)
+        with pytest.raises(ValueError, match="holds 94 bytes"):
+            lib.stencil_run(h, small, small, 1)
+        with pytest.raises(ValueError, match="holds"):
+            lib.stencil_autotune(h, small, small, None, 1)
+    finally:
+        lib.stencil_destroy(h)
+    with pytest.raises(ValueError, match="holds"):
+        lib.surrogate_infer(None, None, torch.zeros(10), None, None, 1, 4, 4, None)
+
+
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.lib().stencil_strerror(code)
