@@ -319,8 +319,29 @@ def extra_surrogate(torch, lib, stream) -> dict:
             "cnn_tflops": 75456.0 * 1024 * 1024 / ts / 1e12, "cnn_frac_of_bf16_mfma_peak": 75456.0 * 1024 * 1024 / ts / 2.5e15}
 
 
+def extra_norms(torch, lib, stream) -> dict:
+    """FP64 norms of a 16384^2 field and its predecessor (residual, energy, mass, next-step mass for
+    the box49 weights): 8 bytes read per cell, against the HBM peak."""
+    p = wl.box49(rows=16384, cols=16384)
+    u = torch.from_numpy(p.u0).to("cuda")
+    up = torch.roll(u, 1, 0).contiguous()
+    plan = lib.stencil_plan(p.rows, p.cols, 3, p.weights, 0.0, "f32", 0)
+    ws = torch.empty(lib.stencil_norms_ws_bytes(plan), dtype=torch.uint8, device="cuda")
+    o = torch.empty(4, dtype=torch.float64, device="cuda")
+    run = lambda: lib.stencil_norms(plan, up, u, o, ws, stream)  # noqa: E731
+    run()
+    t = time_runs(run, 20, stream) / 20
+    lib.stencil_destroy(plan)
+    nbytes = 8.0 * p.rows * p.cols
+    del u, up
+    torch.cuda.empty_cache()
+    return {"us": t * 1e6, "alg_bytes": nbytes, "gb_s": nbytes / t / 1e9, "hbm_peak_gb_s": HBM_PEAK / 1e9,
+            "frac_of_hbm_peak": nbytes / t / HBM_PEAK}
+
+
 EXTRAS = {"heat2d": ("heat2d_512_100", extra_heat2d), "star9": ("star9_8192_500", extra_star9),
-          "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate)}
+          "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate),
+          "norms": ("norms_16384", extra_norms)}
 
 
 def extras(torch, lib, stream) -> dict:

@@ -222,6 +222,50 @@ def test_norms(g):
             lib.stencil_destroy(plan)
 
 
+@pytest.mark.parametrize("storage,rows,cols,shape,r,b", [("bf16", 100, 64, wl.BOX, 2, 0.5), ("f16", 33, 50, wl.STAR, 3, 0.0),
+                                                      ("f16", 7, 4, wl.BOX, 1, 1.5), ("f32", 130, 68, wl.STAR, 1, 0.0)])
+def test_norms_storage_and_alignment(g, storage, rows, cols, shape, r, b):
+    """Norms of 16-bit fields (four cells per vector load when cols % 4 == 0, one per thread
+    otherwise) and of fields that do not start on a 16-byte boundary, against the FP64 oracle on
+    the widened values."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rng = np.random.default_rng(rows + cols)
+    W = _weights(shape, r, rows + 1)
+    u = rng.standard_normal((rows, cols)).astype(np.float32)
+    up = rng.standard_normal((rows, cols)).astype(np.float32)
+    if storage != "f32":
+        ub, upb = oracle.to_bits(u, storage), oracle.to_bits(up, storage)
+        u, up = oracle.from_bits(ub, storage), oracle.from_bits(upb, storage)
+        du, dup = g.to_dev(ub), g.to_dev(upb)
+    else:
+        du, dup = g.to_dev(u), g.to_dev(up)
+    ref = oracle.norms_f64(u, W, b, up)
+    plan = lib.stencil_plan(rows, cols, r, W, b, storage, 0)
+    try:
+        ws = torch.empty(lib.stencil_norms_ws_bytes(plan), dtype=torch.uint8, device=g.DEV)
+        o = torch.zeros(4, dtype=torch.float64, device=g.DEV)
+        lib.stencil_norms(plan, dup, du, o, ws)
+        np.testing.assert_allclose(o.cpu().numpy(), ref, rtol=1e-12, atol=1e-9)
+        # the same fields one element past an aligned start: the one-cell-per-thread path
+        n = rows * cols
+        xb = torch.empty(n + 1, dtype=du.dtype, device=g.DEV)
+        pb = torch.empty(n + 1, dtype=du.dtype, device=g.DEV)
+        xb[1:].copy_(du.reshape(-1))
+        pb[1:].copy_(dup.reshape(-1))
+        o2 = torch.zeros(4, dtype=torch.float64, device=g.DEV)
+        lib.stencil_norms(plan, pb[1:], xb[1:], o2, ws)
+        np.testing.assert_allclose(o2.cpu().numpy(), ref, rtol=1e-12, atol=1e-9)
+        # without the previous field the residual is not computed (reported as 0)
+        o3 = torch.full((4,), 7.0, dtype=torch.float64, device=g.DEV)
+        lib.stencil_norms(plan, None, du, o3, ws)
+        np.testing.assert_allclose(o3.cpu().numpy()[1:], ref[1:], rtol=1e-12, atol=1e-9)
+        assert o3[0].item() == 0.0
+        say(f"norms {storage} {rows}x{cols}: {o.cpu().numpy().tolist()}")
+    finally:
+        lib.stencil_destroy(plan)
+
+
 def test_varcoef(g):
     import torch
     import paper_2605_07954_amd as lib
