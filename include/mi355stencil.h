@@ -183,7 +183,9 @@ int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes);
  *             S_j = sum of the weights W_d whose source cell j - d lies in the grid.
  * Values are read in the plan's storage type and widened exactly.  The order
  * of summation is fixed (two-stage tree), so results are run-to-run bitwise
- * reproducible.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+ * reproducible; it depends only on the grid shape and on whether both fields
+ * start on a 16-byte (FP32) or 8-byte (16-bit) boundary with cols % 4 == 0
+ * (four cells per load), not on the values.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
 int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
                   size_t ws_bytes, void* stream);
 
