@@ -558,6 +558,14 @@ int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, i
     void* nscr = ws + field + scratch_bytes;           // norms partial sums
     double* sums = reinterpret_cast<double*>(static_cast<char*>(nscr) + ((nb + 255) & ~size_t(255)));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the two runs per check differ in their buffers and step counts, so a cached graph would be
+    // captured again on every call: enqueue directly for the duration of the solve
+    struct FlagsGuard {
+        st_plan* p;
+        uint32_t saved;
+        ~FlagsGuard() { p->flags = saved; }
+    } guard{plan, plan->flags};
+    plan->flags &= ~ST_FLAG_GRAPH;
     const void* cur = in;
     int64_t done = 0;
     double rel = 0.0;

@@ -500,21 +500,29 @@ def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
                 lib.stencil_destroy(plan)
 
 
-def test_solve_until_converged(g):
+@pytest.mark.parametrize("flags", [0, 2])
+def test_solve_until_converged(g, flags):
     """Periodic convergence check: stops at the first check whose relative residual is <= tol, and
-    the field equals a plain run of that many steps."""
+    the field equals a plain run of that many steps (also for a graph-flagged plan, whose cached
+    graph the solve leaves alone)."""
     import torch
     import paper_2605_07954_amd as lib
     rows, cols, b = 32, 40, 1.0
     W = wl.heat5_weights()
     u0 = np.random.default_rng(17).random((rows, cols), dtype=np.float32)
-    plan = lib.stencil_plan(rows, cols, 1, W, b, "f32", 0)
+    plan = lib.stencil_plan(rows, cols, 1, W, b, "f32", flags)
     try:
         x = g.to_dev(u0)
         out = torch.empty_like(x)
         ws = torch.empty(lib.stencil_solve_ws_bytes(plan, 100), dtype=torch.uint8, device=g.DEV)
         done, res = lib.stencil_solve(plan, x, out, 50000, 100, 1e-6, ws)
         got = g.to_host(out)
+        if flags:  # the plan still runs through its graph afterwards
+            o2 = torch.empty_like(x)
+            w2 = torch.empty_like(x)
+            lib.stencil_run(plan, x, o2, done, w2)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.to_host(o2), got)
     finally:
         lib.stencil_destroy(plan)
     say(f"solve: {done} steps, relative residual {res:.3e}")
