@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "row-slab decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
     if args.cpu_oracle_timings:  # host cores only: nothing below touches the GPU
