@@ -152,6 +152,9 @@ def test_batch_create_validation_on_host():
         with pytest.raises(lib.StencilError) as ei:
             lib.stencil_batch_create(ok, [1, 1, 1], 0x80)
         assert ei.value.code == lib.ST_EINVAL
+        with pytest.raises(lib.StencilError) as ei:  # an empty batch
+            lib.stencil_batch_create([], [], 0)
+        assert ei.value.code == lib.ST_EINVAL
     finally:
         for p in ok + bad:
             lib.stencil_destroy(p)

@@ -49,6 +49,50 @@ def test_heat2d_512_100(g):
 
 
 
+@pytest.mark.parametrize("kind", ["identity", "zero", "shift"])
+def test_degenerate_weights(g, kind):
+    """Degenerate footprints through every variant: the identity (centre weight 1: the field comes
+    back unchanged, bit for bit), all-zero weights (every cell 0 after one step), and a pure shift
+    (one off-centre tap of weight 1 and a zero centre: the field moves one cell per step and b
+    flows in from the edge).  The kernels multiply every tap of the footprint, zero weights
+    included, while the oracle takes the nonzero taps only; that can change nothing but the sign of
+    an exact zero, so signs are compared where no exact zero arises."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, r, b, steps = 70, 132, 2, 0.75, 5
+    W = np.zeros((2 * r + 1, 2 * r + 1), np.float32)
+    if kind == "identity":
+        W[r, r] = 1.0
+    elif kind == "shift":
+        W[r - 1, r] = 1.0  # u'(i, j) = u(i - 1, j)
+    u0 = (np.random.default_rng(3).random((rows, cols), dtype=np.float32) - 0.5)
+    ref = oracle.stencil_f32(u0, W, b, steps)
+    if kind == "identity":
+        np.testing.assert_array_equal(ref, u0)
+    if kind == "shift":
+        np.testing.assert_array_equal(ref[steps:], u0[:-steps])
+        assert np.all(ref[:steps] == np.float32(b))
+    x = g.to_dev(u0)
+    for variant in (lib.ST_VARIANT_TILED, lib.ST_VARIANT_STREAM, lib.ST_VARIANT_MARCH, lib.ST_VARIANT_MARCH8,
+                    lib.ST_VARIANT_MARCH1):
+        for flags in (0, lib.ST_FLAG_NAIVE):
+            plan = lib.stencil_plan(rows, cols, r, W, b, "f32", flags)
+            try:
+                lib.stencil_set_blocking(plan, 1)
+                lib.stencil_set_variant(plan, variant)
+                lib.stencil_set_blocking(plan, 2)
+                out = torch.full_like(x, float("nan"))
+                ws = torch.empty_like(x)
+                lib.stencil_run(plan, x, out, steps, ws)
+                torch.cuda.synchronize()
+                got = g.to_host(out)
+                np.testing.assert_array_equal(got, ref, err_msg=f"{kind} variant {variant} flags {flags}")
+                if kind != "zero":
+                    assert np.array_equal(np.signbit(got), np.signbit(ref)), f"{kind}: signs differ"
+            finally:
+                lib.stencil_destroy(plan)
+
+
 def test_naive_paths_beyond_one_cell_per_thread(g):
     """The one-cell-per-thread reference kernels (ST_FLAG_NAIVE) stride once the grid has more cells
     than their capped launch has threads (2^20 workgroups x 256 = 2^28): a 16400^2 grid, one step, for
