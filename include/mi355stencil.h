@@ -245,8 +245,13 @@ int stencil_batch_create(st_batch** out, int n, st_plan* const* plans, const int
 int stencil_batch_workspace_bytes(const st_batch* batch, size_t* bytes);
 
 /* stencil_run_batched -- outs[g] = S_g^{steps[g]}(ins[g]) for every grid g.
- * ins/outs are HOST arrays of n device pointers; no in/out pair may overlap.  Results are
- * bitwise those of stencil_run on each grid.  Asynchronous on `stream`. */
+ * ins/outs are HOST arrays of n device pointers; no in/out pair may overlap (ST_EALIAS for a
+ * grid's own pair; fields of different grids and the workspace must not overlap either).
+ * Results are bitwise those of stencil_run on each grid.  Asynchronous on `stream`.
+ * The descriptor tables are copied into the workspace (from a pinned host buffer the batch owns)
+ * only when a pointer differs from the previous call's, and are reused as they are otherwise: the
+ * workspace must keep its contents between calls of the same batch, or be passed at a different
+ * address. */
 int stencil_run_batched(st_batch* batch, const void* const* ins, void* const* outs, void* workspace,
                         size_t ws_bytes, void* stream);
 
