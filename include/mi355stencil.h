@@ -20,6 +20,9 @@
  *     base[i * cols + j], i = row in [0, rows), j = column in [0, cols).
  *   - Launch errors are checked right after each launch (ST_EHIP); faults
  *     inside a kernel surface at the caller's next synchronisation.
+ *   - One device per process: occupancy and LDS limits are queried once, on
+ *     the device current at the first call, and cached.  A plan or batch may
+ *     be used from one host thread at a time (it caches graphs and tables).
  */
 #ifndef MI355STENCIL_H
 #define MI355STENCIL_H
