@@ -10,9 +10,11 @@ Metric: GStencil/s = T * Nx * Ny / (t * 1e9)  (paper Sec. VI-A, Eq. 1), t = pure
 measured with HIP events on the stream the kernels run on.
 
 The JSON line also carries
-  roofline      the sweep kernel's achieved FLOP/s against the vector-ALU roof (it is the binding
-                roof for this stencil: 97 FLOP and 8/tb bytes per update), with the HBM traffic
-                measured by rocprofv3 when the committed counters match the current kernel source;
+  roofline      the sweep kernel's achieved FLOP/s against the published FP32 vector peak
+                (157.3 TFLOP/s; the vector ALU is the binding roof for this stencil: 97 FLOP and
+                8/tb bytes per update), beside the fraction of the non-packed FMA issue rate
+                (78.6 TFLOP/s) these kernels can reach, and the HBM traffic measured by rocprofv3
+                when the committed counters match the current kernel source;
   cpu_baseline  the CPU oracle (FP32-canonical mode, all host cores) timed on a bounded sample;
   extras        the other workloads (heat 512^2, batched 256 grids, 16-bit storage, surrogate) at a
                 glance -- their parity lives in the test suite.
@@ -35,7 +37,7 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 VALU_FP32_PEAK = 256 * 4 * 16 * 2 * 2.4e9   # 78.6 TFLOP/s: FP32 FMA issued one lane-op per cycle (no packed math)
-VALU_FP32_PEAK_PACKED = 157.3e12             # published figure, needs packed FP32 (not used by these kernels)
+VALU_FP32_PEAK_PACKED = 157.3e12             # published FP32 vector peak (needs packed FP32, not used here)
 HBM_PEAK = 8.0e12
 
 
@@ -79,17 +81,23 @@ def measured_traffic(tb: int, tile, variant: int) -> float | None:
     return d.get("hbm_bytes_per_launch")
 
 
-def time_runs(fn, reps: int, stream) -> float:
+def time_each(fn, reps: int, stream) -> list:
+    """Seconds of each of `reps` back-to-back calls of `fn`, from HIP events recorded on `stream`
+    (the stream the library launches on) between the calls; the host does not wait in between."""
     import torch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
+    ev[0].record(stream)
+    for k in range(reps):
         fn()
-    e1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3
+    return [ev[k].elapsed_time(ev[k + 1]) / 1e3 for k in range(reps)]
+
+
+def time_median(fn, reps: int, stream) -> float:
+    """Median over `reps` (at least 10) timed calls, in seconds."""
+    return float(np.median(time_each(fn, max(reps, 10), stream)))
 
 
 def cpu_baseline(p) -> dict:
@@ -174,7 +182,8 @@ def main_line(args, torch, lib, stream):
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
-    t = time_runs(run, args.steps, stream)
+    each = time_each(run, args.steps, stream)  # the K timed steps, synchronised before and after
+    t = float(sum(each))
     ms = t / args.steps * 1e3
     value = gstencil_s(T * args.steps, rows, cols, t)
     launches = math.ceil(T / tb) * args.steps
@@ -182,15 +191,17 @@ def main_line(args, torch, lib, stream):
     flops = fpu * T * rows * cols * args.steps
     achieved = flops / t
     traffic = measured_traffic(tb, (tx, ty), variant)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / VALU_FP32_PEAK, "traffic": traffic,
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_FP32_PEAK_PACKED / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / VALU_FP32_PEAK_PACKED, "traffic": traffic,
+            "issue_rate_peak": VALU_FP32_PEAK / 1e12, "frac_of_issue_rate": achieved / VALU_FP32_PEAK,
+            "ms_per_step_median": float(np.median(each)) * 1e3,
+            "ms_per_step_min": min(each) * 1e3, "ms_per_step_max": max(each) * 1e3,
             "kernel": KERNEL_NAMES[variant] + f"<f32, r=3, box{', 8 columns per lane' if variant == 3 else ''}, tb={tb}>",
             "launches": launches,
             "avg_launch_us": t / launches * 1e6,
             "alg_flop_per_launch": fpu * rows * cols * tb, "alg_bytes_per_update": 8.0 / tb,
             "hbm_roof_gstencil": HBM_PEAK / (8.0 / tb) / 1e9,
             "alu_roof_gstencil": VALU_FP32_PEAK / fpu / 1e9,
-            "frac_of_packed_fp32_peak": achieved / VALU_FP32_PEAK_PACKED,
             "alg_hbm_gbps": 8.0 / tb * T * rows * cols * args.steps / t / 1e9}
     lib.stencil_destroy(plan)
     del x, out, ws
@@ -224,10 +235,42 @@ def extra_heat2d(torch, lib, stream) -> dict:
     seg = lib.stencil_get_march_segment(plan)
     run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
     run()
-    t = time_runs(run, 20, stream) / 20
+    t = time_median(run, 20, stream)
     lib.stencil_destroy(plan)
     return {"gstencil_s": gstencil_s(p.steps, p.rows, p.cols, t), "us": t * 1e6, "tb": tb,
             "variant": VARIANT_NAMES[var], "march_seg_min": seg, "launches": math.ceil(p.steps / tb)}
+
+
+def extra_box49_tb1(torch, lib, stream) -> dict:
+    """Box-2D49P 16384^2 x 1000 with one level per pass (8 bytes per update, read and write once):
+    the HBM-bound form, against the HBM roof (8 TB/s / 8 B = 1000 GStencil/s) and against the rate a
+    device copy reaches.  The best of the marching kernels with four and eight columns per lane."""
+    p = wl.box49(rows=16384, cols=16384, steps=1000)
+    x = torch.from_numpy(p.u0).to("cuda")
+    out = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    res = {}
+    for var in (lib.ST_VARIANT_MARCH8, lib.ST_VARIANT_MARCH):
+        plan = lib.stencil_plan(p.rows, p.cols, 3, p.weights, 0.0, "f32", lib.ST_FLAG_GRAPH)
+        lib.stencil_set_blocking(plan, 1)
+        lib.stencil_set_variant(plan, var)
+        run = lambda: lib.stencil_run(plan, x, out, p.steps, ws, stream)  # noqa: E731
+        run()
+        t = time_median(run, 10, stream)
+        lib.stencil_destroy(plan)
+        res[VARIANT_NAMES[var]] = gstencil_s(p.steps, p.rows, p.cols, t)
+    y = torch.empty_like(x)
+    cp = lambda: y.copy_(x)  # noqa: E731
+    cp()
+    tc = time_median(cp, 10, stream)
+    copy_gbs = 2.0 * x.numel() * 4 / tc / 1e9
+    best = max(res.values())
+    del x, out, ws, y
+    torch.cuda.empty_cache()
+    return {"gstencil_s": best, "by_variant": res, "alg_bytes_per_update": 8.0,
+            "hbm_roof_gstencil": HBM_PEAK / 8.0 / 1e9, "frac_of_hbm_roof": best / (HBM_PEAK / 8.0 / 1e9),
+            "alg_hbm_gbps": best * 8.0, "device_copy_gbps": copy_gbs,
+            "frac_of_device_copy": best * 8.0 / copy_gbs}
 
 
 def extra_star9(torch, lib, stream) -> dict:
@@ -248,7 +291,7 @@ def extra_star9(torch, lib, stream) -> dict:
         seg = lib.stencil_get_march_segment(plan)
         run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
         run()
-        t = time_runs(run, 3, stream) / 3
+        t = time_median(run, 10, stream)
         gst = gstencil_s(p.steps, p.rows, p.cols, t)
         res[st] = {"gstencil_s": gst, "ms": t * 1e3, "tb": tb, "variant": VARIANT_NAMES[var], "march_seg_min": seg,
                    **_roofs(flop_per_update(9), 2.0 * xh.element_size() / tb, gst)}
@@ -269,14 +312,14 @@ def extra_batched(torch, lib, stream) -> dict:
     per_grid = lambda: [lib.stencil_run(pl, i, o, q.steps, w, stream)  # noqa: E731
                         for q, pl, i, o, w in zip(probs, plans, ins, outs, wss)]
     per_grid()
-    t_per = time_runs(per_grid, 3, stream) / 3
+    t_per = time_median(per_grid, 10, stream)
     batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
     bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
     caps = lib.stencil_batch_autotune(batch, ins, outs, bws, stream)
     segs = {k: lib.stencil_batch_get_segment(batch, k[0], k[1]) for k in caps}
     runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
     runb()
-    t_b = time_runs(runb, 5, stream) / 5
+    t_b = time_median(runb, 10, stream)
     cells = sum(q.rows * q.cols * q.steps for q in probs)
     lib.stencil_batch_destroy(batch)
     for pl in plans:
@@ -303,7 +346,7 @@ def extra_surrogate(torch, lib, stream) -> dict:
     vtb, vtx, vty = lib.stencil_autotune_varcoef(vplan, u, k, o, w, 16, stream)  # every tile and depth
     run = lambda: lib.stencil_run_varcoef(vplan, u, k, o, 16, w, stream)  # noqa: E731
     run()
-    best = time_runs(run, 20, stream) / 20
+    best = time_median(run, 20, stream)
     m = lib.surrogate_create()
     from paper_2605_07954_amd.surrogate import init_params
     pd = torch.from_numpy(init_params(0)).to("cuda")  # timing only: the weights' values do not matter
@@ -311,7 +354,7 @@ def extra_surrogate(torch, lib, stream) -> dict:
     uh = torch.empty((1, 1024, 1024), device="cuda")
     run = lambda: lib.surrogate_infer(m, pd, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
     run()
-    ts = time_runs(run, 10, stream) / 10
+    ts = time_median(run, 10, stream)
     lib.surrogate_destroy(m)
     lib.stencil_destroy(vplan)
     return {"plain_16_steps_us": best * 1e6, "plain_blocking": {"tb": vtb, "tile": [vtx, vty]},
@@ -330,7 +373,7 @@ def extra_norms(torch, lib, stream) -> dict:
     o = torch.empty(4, dtype=torch.float64, device="cuda")
     run = lambda: lib.stencil_norms(plan, up, u, o, ws, stream)  # noqa: E731
     run()
-    t = time_runs(run, 20, stream) / 20
+    t = time_median(run, 20, stream)
     lib.stencil_destroy(plan)
     nbytes = 8.0 * p.rows * p.cols
     del u, up
@@ -339,7 +382,8 @@ def extra_norms(torch, lib, stream) -> dict:
             "frac_of_hbm_peak": nbytes / t / HBM_PEAK}
 
 
-EXTRAS = {"heat2d": ("heat2d_512_100", extra_heat2d), "star9": ("star9_8192_500", extra_star9),
+EXTRAS = {"box49_tb1": ("box49_16384_tb1", extra_box49_tb1), "heat2d": ("heat2d_512_100", extra_heat2d),
+          "star9": ("star9_8192_500", extra_star9),
           "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate),
           "norms": ("norms_16384", extra_norms)}
 

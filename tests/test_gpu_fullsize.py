@@ -9,7 +9,9 @@ properties that hold at any size.
   |lambda|^T cos(k.x + phi + T arg lambda) after T steps.
 * Star-2D9P, 8192 x 8192, 500 steps, FP32 / BF16 / FP16 storage: the 8x8 corner patches bit for
   bit against the FP32-canonical / 16-bit-emulating oracle run on the (8 + r*T)^2 corner crop (a
-  cell at least r*T from the crop's cut edges cannot see them); the sine-mode sum in the
+  cell at least r*T from the crop's cut edges cannot see them), and an 8x8 patch at the centre
+  (computed only by interior tasks, which take no edge checks) against the oracle on its
+  (8 + 2 r T)^2 crop; the sine-mode sum in the
   light-cone interior against its closed form (each mode scaled by lambda^T); the whole field
   against the FP64 oracle.  The FP32 gate is 1e-5; the 16-bit errors are printed (their gate is
   the bitwise emulation).
@@ -157,6 +159,9 @@ def test_star9_8192_500(g, star9, star9_f64, storage):
         out = tp.run(x, T)
         got_tl = g.to_host(out[:8, :8])
         got_br = g.to_host(out[rows - 8:, cols - 8:])
+        # an interior patch: every task that computes it is an interior task (no edge checks)
+        ci = rows // 2
+        got_mid = g.to_host(out[ci:ci + 8, ci:ci + 8])
         inner = g.to_host(out[torch.from_numpy(sample).to(g.DEV), m:cols - m])
         whole = g.to_host(out)
     finally:
@@ -173,6 +178,9 @@ def test_star9_8192_500(g, star9, star9_f64, storage):
     say(f"  corner crops {c}x{c}: oracle ...")
     np.testing.assert_array_equal(got_tl, ref_run(u_in[:c, :c])[:8, :8])
     np.testing.assert_array_equal(got_br, ref_run(u_in[rows - c:, cols - c:])[c - 8:, c - 8:])
+    say(f"  interior crop {8 + 2 * m}x{8 + 2 * m} at ({ci}, {ci}): oracle ...")
+    mid = u_in[ci - m:ci + 8 + m, ci - m:ci + 8 + m]
+    np.testing.assert_array_equal(got_mid, ref_run(mid)[m:m + 8, m:m + 8])
     modes = wl.fourier_sine_modes(64, 32.0, 4)
     ref = _sine_interior(modes, W, rows, cols, T, sample.astype(np.float64), m, cols - m)
     vals = inner if storage == "f32" else oracle.from_bits(inner, storage)

@@ -523,10 +523,19 @@ def _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, ste
                                                       (40, 996, wl.BOX, 3, 0.0, 5), (7, 8, wl.STAR, 4, -0.25, 4),
                                                       (97, 301, wl.STAR, 2, 0.0, 9), (33, 70, wl.BOX, 3, 0.0, 4),
                                                       (150, 264, wl.STAR, 2, 0.0, 13), (61, 96, wl.BOX, 3, 0.5, 5),
-                                                      (77, 200, wl.BOX, 1, 0.0, 8)])
+                                                      (77, 200, wl.BOX, 1, 0.0, 8),
+                                                      # three or more 512-column bands with cols % 8 == 0:
+                                                      # the eight-column interior tasks (no edge checks)
+                                                      (200, 1600, wl.STAR, 2, 0.0, 9), (200, 1600, wl.BOX, 1, 0.0, 7),
+                                                      (200, 1600, wl.BOX, 2, 0.25, 5), (200, 1600, wl.BOX, 3, 0.0, 5),
+                                                      (160, 2048, wl.STAR, 1, 0.0, 17), (160, 2048, wl.STAR, 3, 0.0, 7),
+                                                      (120, 1536, wl.STAR, 4, 0.0, 5)])
 def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
     """Marching with BF16/FP16 storage (8- or 16-byte loads, FP32 arithmetic, every level rounded to
-    the storage type) equals the emulating oracle bit for bit at every depth of both variants."""
+    the storage type) equals the emulating oracle bit for bit at every depth of every variant.  Grids
+    at least three bands wide (about 512 columns each with eight columns per lane) give the
+    marching passes interior tasks, whose kernels take no edge checks; longer segments than the
+    default are run too, so that interior segments of several rows are covered."""
     import paper_2605_07954_amd as lib
     W = _weights(shape, r, rows + 5 * cols + r)
     bits = oracle.to_bits(np.random.default_rng(rows + cols).random((rows, cols), dtype=np.float32), storage)
@@ -538,8 +547,13 @@ def test_march_lowp_bitwise(g, storage, rows, cols, shape, r, b, steps):
                 lib.stencil_set_blocking(plan, 1)
                 lib.stencil_set_variant(plan, variant)
                 lib.stencil_set_blocking(plan, tb)
-                got = g.run(plan, g.to_dev(bits), steps, rows, cols, storage)
+                xd = g.to_dev(bits)
+                got = g.run(plan, xd, steps, rows, cols, storage)
                 np.testing.assert_array_equal(g.to_host(got), ref, err_msg=f"variant {variant} tb {tb}")
+                if cols >= 1536:
+                    lib.stencil_set_march_segment(plan, 24)
+                    got = g.run(plan, xd, steps, rows, cols, storage)
+                    np.testing.assert_array_equal(g.to_host(got), ref, err_msg=f"variant {variant} tb {tb} seg 24")
             finally:
                 lib.stencil_destroy(plan)
 
