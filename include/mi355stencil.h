@@ -168,6 +168,23 @@ int stencil_workspace_bytes(const st_plan* plan, int64_t steps, size_t* bytes);
 int stencil_run(st_plan* plan, const void* in, void* out, int64_t steps, void* workspace,
                 size_t ws_bytes, void* stream);
 
+/* stencil_run_noalloc -- for callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same result
+ * as stencil_run(plan, in, out, steps, ...), bitwise, with the ping-pong field taken from a static
+ * device array of the library instead of a workspace.  That array is 64 MiB
+ * (stencil_noalloc_max_bytes), enough for a grid of 16 Mi FP32 or 32 Mi 16-bit cells; each GPU the
+ * library is loaded on holds its own copy until the process ends.  This entry point allocates
+ * nothing: no hipMalloc/hipFree, no stream, no graph (a plan's ST_FLAG_GRAPH is ignored here: the
+ * passes are enqueued directly on `stream`, which the caller may be capturing).  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (different streams, or host
+ * threads) race and give undefined results -- order them on one stream.  The array needs no
+ * clearing (every pass writes every cell it later reads).  Constant-weight plans only.
+ * Errors: ST_EINVAL (NULL plan/in/out, negative steps, varcoef plan), ST_EALIAS (in/out overlap),
+ * ST_EUNSUPPORTED (the run needs a ping-pong field larger than the static array: use stencil_run),
+ * ST_EHIP. */
+int stencil_run_noalloc(st_plan* plan, const void* in, void* out, int64_t steps, void* stream);
+int stencil_noalloc_max_bytes(size_t* bytes);
+
 /* stencil_run_varcoef -- the same for a varcoef plan; kappa is a device FP32
  * rows x cols diffusivity field (only read). */
 int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, int64_t steps,

@@ -56,6 +56,8 @@ _SIGS = {
     "stencil_workspace_bytes": [_p, _i64, ctypes.POINTER(_sz)],
     "stencil_run": [_p, _p, _p, _i64, _p, _sz, _p],
     "stencil_run_varcoef": [_p, _p, _p, _p, _i64, _p, _sz, _p],
+    "stencil_run_noalloc": [_p, _p, _p, _i64, _p],
+    "stencil_noalloc_max_bytes": [ctypes.POINTER(_sz)],
     "stencil_norms_ws_bytes": [_p, ctypes.POINTER(_sz)],
     "stencil_norms": [_p, _p, _p, _p, _p, _sz, _p],
     "stencil_autotune": [_p, _p, _p, _p, _sz, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int),
@@ -260,6 +262,18 @@ def stencil_run(plan, inp, out, steps: int, workspace=None, stream=None) -> None
     _fields(plan, inp=inp, out=out)
     _ck(lib().stencil_run(plan, _dptr(inp, "in"), _dptr(out, "out"), steps, _dptr(workspace, "workspace"),
                           _nbytes(workspace), _stream(stream)), "stencil_run")
+
+
+def stencil_run_noalloc(plan, inp, out, steps: int, stream=None) -> None:
+    _fields(plan, inp=inp, out=out)
+    _ck(lib().stencil_run_noalloc(plan, _dptr(inp, "in"), _dptr(out, "out"), steps, _stream(stream)),
+        "stencil_run_noalloc")
+
+
+def stencil_noalloc_max_bytes() -> int:
+    n = _sz()
+    _ck(lib().stencil_noalloc_max_bytes(ctypes.byref(n)), "stencil_noalloc_max_bytes")
+    return n.value
 
 
 def stencil_run_varcoef(plan, inp, kappa, out, steps: int, workspace=None, stream=None) -> None:

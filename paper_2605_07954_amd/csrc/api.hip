@@ -589,3 +589,72 @@ int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, i
 }
 
 }  // extern "C"
+
+// --------------------------------------------------------------------------
+// stencil_run_noalloc: stencil_run with its ping-pong field in a static device array
+// --------------------------------------------------------------------------
+namespace st {
+namespace {
+
+constexpr size_t kNoallocBytes = size_t(64) << 20;  // 16 Mi FP32 or 32 Mi 16-bit cells
+constexpr int kMaxDevices = 64;
+
+// The library's own ping-pong field for stencil_run_noalloc.  Each device holds its copy from the
+// time the library's code object is loaded on it until the process ends.  Host code never uses
+// this name as an address: the per-device address comes from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** ptr) {
+    int dev = 0;
+    ST_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ST_EUNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(ST_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return ST_OK;
+}
+
+}  // namespace
+}  // namespace st
+
+extern "C" {
+
+int stencil_noalloc_max_bytes(size_t* bytes) {
+    if (!bytes) return fail(ST_EINVAL, "bytes is NULL");
+    *bytes = kNoallocBytes;
+    return ST_OK;
+}
+
+int stencil_run_noalloc(st_plan* plan, const void* in, void* out, int64_t steps, void* stream) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "stencil_run_noalloc takes a constant-weight plan");
+    if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
+    if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
+    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
+    size_t need = 0;
+    stencil_workspace_bytes(plan, steps, &need);
+    if (need > kNoallocBytes)
+        return fail(ST_EUNSUPPORTED, "grid larger than the static ping-pong field (64 MiB: 16 Mi FP32 or 32 Mi "
+                                     "16-bit cells); use stencil_run with a workspace");
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    if (overlap(ws, in, bytes) || overlap(ws, out, bytes)) return fail(ST_EALIAS, "in/out overlap the static field");
+    // always enqueued directly (never through the plan's cached graph, whose capture creates a
+    // stream and instantiates a graph), so that a caller may capture this call itself
+    return enqueue_run(plan, in, out, nullptr, steps, ws, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
