@@ -7,7 +7,8 @@ two share no code; they are fed the same host buffers drawn by ``workloads``.
 Contents
   * the plain stencil definition (``stencil_oracle.c``, loaded with ctypes):
     FP64, FP32-canonical and BF16/FP16-storage-emulating modes, the light-cone
-    patch, and the variable-coefficient heat step;
+    patch, the variable-coefficient heat step, periodic and caller-framed
+    boundaries, and the 3D form;
   * FP64 norms (residual, energy, mass, predicted next mass);
   * the CNN surrogate's forward / backward / Adam in FP64 (``oracle.cnn``).
 """
@@ -41,6 +42,14 @@ def lib():
                                           _i64, _p, _p]
         L.oracle_stencil_patch_f64.argtypes = [_i64, _i64, ctypes.c_int, _p, ctypes.c_double, _i64, _p,
                                                _i64, _i64, _i64, _i64, _p]
+        L.oracle_stencil_bc_f64.argtypes = [ctypes.c_int, _i64, _i64, ctypes.c_int, _p, _p, _i64, _p, _p]
+        L.oracle_stencil_bc_f32.argtypes = [ctypes.c_int, _i64, _i64, ctypes.c_int, _p, _p, _i64, _p, _p]
+        L.oracle_stencil_bc_lowp.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, ctypes.c_int, _p, _p, _i64,
+                                             _p, _p]
+        L.oracle_frame_elems.argtypes = [_i64, _i64, ctypes.c_int]
+        L.oracle_frame_elems.restype = _i64
+        L.oracle_stencil3d_f64.argtypes = [_i64, _i64, _i64, ctypes.c_int, _p, ctypes.c_double, _i64, _p, _p]
+        L.oracle_stencil3d_f32.argtypes = [_i64, _i64, _i64, ctypes.c_int, _p, ctypes.c_float, _i64, _p, _p]
         L.oracle_varcoef_f64.argtypes = [_i64, _i64, ctypes.c_double, _i64, _p, _p, _p]
         L.oracle_varcoef_f32.argtypes = [_i64, _i64, ctypes.c_float, _i64, _p, _p, _p]
         for nm in ("oracle_f32_to_bf16_array", "oracle_bf16_to_f32_array",
@@ -127,6 +136,92 @@ def stencil_patch_f64(u0: np.ndarray, W: np.ndarray, b: float, steps: int,
     _check(lib().oracle_stencil_patch_f64(u.shape[0], u.shape[1], radius_of(wt), _ptr(wt), float(b),
                                           int(steps), _ptr(u), y0, x0, h, w, _ptr(out)),
            "oracle_stencil_patch_f64")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# other boundary rules: periodic (bc = 1) and a caller-given fixed halo frame (bc = 2)
+# ---------------------------------------------------------------------------
+BC_CODE = {"periodic": 1, "frame": 2}
+
+
+def frame_elems(rows: int, cols: int, r: int) -> int:
+    """Elements of a halo frame: top and bottom strips r x (cols + 2r), left and right strips rows x r."""
+    return int(lib().oracle_frame_elems(rows, cols, r))
+
+
+def _frame_arg(frame, dtype, rows, cols, r):
+    if frame is None:
+        return None, None
+    f = np.ascontiguousarray(frame, dtype=dtype).reshape(-1)
+    if f.size != frame_elems(rows, cols, r):
+        raise ValueError("frame has the wrong number of elements")
+    return f, _ptr(f)
+
+
+def stencil_bc_f64(u0: np.ndarray, W: np.ndarray, bc: str, steps: int, frame=None) -> np.ndarray:
+    """FP64 run with a periodic or framed boundary (frame values promoted to double)."""
+    u = np.ascontiguousarray(u0, dtype=np.float64)
+    w = np.ascontiguousarray(W, dtype=np.float64)
+    r = radius_of(w)
+    f, fp = _frame_arg(frame, np.float64, u.shape[0], u.shape[1], r)
+    out = np.empty_like(u)
+    _check(lib().oracle_stencil_bc_f64(BC_CODE[bc], u.shape[0], u.shape[1], r, _ptr(w), fp, int(steps), _ptr(u),
+                                       _ptr(out)), "oracle_stencil_bc_f64")
+    return out
+
+
+def stencil_bc_f32(u0: np.ndarray, W: np.ndarray, bc: str, steps: int, frame=None) -> np.ndarray:
+    """FP32-canonical run with a periodic or framed boundary."""
+    u = np.ascontiguousarray(u0, dtype=np.float32)
+    w = np.ascontiguousarray(W, dtype=np.float32)
+    r = radius_of(w)
+    f, fp = _frame_arg(frame, np.float32, u.shape[0], u.shape[1], r)
+    out = np.empty_like(u)
+    _check(lib().oracle_stencil_bc_f32(BC_CODE[bc], u.shape[0], u.shape[1], r, _ptr(w), fp, int(steps), _ptr(u),
+                                       _ptr(out)), "oracle_stencil_bc_f32")
+    return out
+
+
+def stencil_bc_lowp(u0_bits: np.ndarray, W: np.ndarray, bc: str, steps: int, dtype: str, frame_bits=None):
+    """16-bit storage emulation with a periodic or framed boundary (frame in raw 16-bit patterns)."""
+    u = np.ascontiguousarray(u0_bits, dtype=np.uint16)
+    w = np.ascontiguousarray(W, dtype=np.float32)
+    r = radius_of(w)
+    f, fp = _frame_arg(frame_bits, np.uint16, u.shape[0], u.shape[1], r)
+    out = np.empty_like(u)
+    _check(lib().oracle_stencil_bc_lowp(LOWP_CODE[dtype], BC_CODE[bc], u.shape[0], u.shape[1], r, _ptr(w), fp,
+                                        int(steps), _ptr(u), _ptr(out)), "oracle_stencil_bc_lowp")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 3D (planes x rows x cols, (2r+1)^3 weights W[dz+r][dy+r][dx+r], constant halo b)
+# ---------------------------------------------------------------------------
+
+def _radius3(W: np.ndarray) -> int:
+    k = W.shape[0]
+    if W.ndim != 3 or W.shape != (k, k, k) or k % 2 != 1:
+        raise ValueError("3D weights must be a (2r+1)^3 array")
+    return (k - 1) // 2
+
+
+def stencil3d_f64(u0: np.ndarray, W: np.ndarray, b: float, steps: int) -> np.ndarray:
+    u = np.ascontiguousarray(u0, dtype=np.float64)
+    w = np.ascontiguousarray(W, dtype=np.float64)
+    out = np.empty_like(u)
+    _check(lib().oracle_stencil3d_f64(u.shape[0], u.shape[1], u.shape[2], _radius3(w), _ptr(w), float(b), int(steps),
+                                      _ptr(u), _ptr(out)), "oracle_stencil3d_f64")
+    return out
+
+
+def stencil3d_f32(u0: np.ndarray, W: np.ndarray, b: float, steps: int) -> np.ndarray:
+    """FP32-canonical 3D: centre product, then fmaf per nonzero tap in row-major (dz, dy, dx) order."""
+    u = np.ascontiguousarray(u0, dtype=np.float32)
+    w = np.ascontiguousarray(W, dtype=np.float32)
+    out = np.empty_like(u)
+    _check(lib().oracle_stencil3d_f32(u.shape[0], u.shape[1], u.shape[2], _radius3(w), _ptr(w), float(b), int(steps),
+                                      _ptr(u), _ptr(out)), "oracle_stencil3d_f32")
     return out
 
 

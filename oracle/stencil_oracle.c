@@ -457,3 +457,224 @@ void oracle_f32_to_f16_array(int64_t n, const float *in, uint16_t *out) {
 void oracle_f16_to_f32_array(int64_t n, const uint16_t *in, float *out) {
     for (int64_t i = 0; i < n; i++) out[i] = oracle_f16_to_f32(in[i]);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Other boundary rules for the extended field ~u (the paper uses the zero    */
+/* halo of Sec. IV-A only; these are the library's further boundary modes):   */
+/*   bc = 1  periodic: ~u(i, j) = u(i mod rows, j mod cols) -- the halo is    */
+/*           refreshed from the grid before every step;                      */
+/*   bc = 2  fixed halo frame: the r-deep ring around the grid holds values   */
+/*           given by the caller and is never updated.  Frame layout, in      */
+/*           elements: top strip r x (cols + 2r) (rows -r..-1, columns        */
+/*           -r..cols+r-1), bottom strip r x (cols + 2r) (rows rows..rows+r-1),*/
+/*           left strip rows x r (columns -r..-1), right strip rows x r        */
+/*           (columns cols..cols+r-1), each row-major, one after another.     */
+/* ------------------------------------------------------------------------ */
+static int64_t wrap_idx(int64_t i, int64_t n) { int64_t m = i % n; return m < 0 ? m + n : m; }
+
+/* index into the frame of the out-of-grid cell (i, j), |i|, |j| within r of the grid */
+static int64_t frame_index(int64_t rows, int64_t cols, int r, int64_t i, int64_t j) {
+    const int64_t wf = cols + 2 * r;
+    if (i < 0) return (i + r) * wf + (j + r);
+    if (i >= rows) return (int64_t)r * wf + (i - rows) * wf + (j + r);
+    if (j < 0) return 2 * (int64_t)r * wf + i * r + (j + r);
+    return 2 * (int64_t)r * wf + rows * r + i * r + (j - cols);
+}
+
+int64_t oracle_frame_elems(int64_t rows, int64_t cols, int r) {
+    return 2 * (int64_t)r * (cols + 2 * r) + 2 * (int64_t)r * rows;
+}
+
+#define ORC_BC_FILL(T)                                                                          \
+    static void bc_fill_##T(int bc, int64_t rows, int64_t cols, int r, const T *frame, T *e) {   \
+        int64_t ep = cols + 2 * r;                                                                \
+        for (int64_t i = -r; i < rows + r; i++)                                                   \
+            for (int64_t j = -r; j < cols + r; j++) {                                             \
+                if (i >= 0 && i < rows && j >= 0 && j < cols) continue;                           \
+                T v = bc == 1 ? e[(wrap_idx(i, rows) + r) * ep + wrap_idx(j, cols) + r]            \
+                              : frame[frame_index(rows, cols, r, i, j)];                          \
+                e[(i + r) * ep + (j + r)] = v;                                                    \
+            }                                                                                     \
+    }
+ORC_BC_FILL(double)
+ORC_BC_FILL(float)
+
+int oracle_stencil_bc_f64(int bc, int64_t rows, int64_t cols, int r, const double *W, const double *frame,
+                          int64_t steps, const double *in, double *out) {
+    if ((bc != 1 && bc != 2) || rows < 1 || cols < 1 || steps < 0 || !W || !in || !out || (bc == 2 && !frame))
+        return ORC_EINVAL;
+    taps_t t;
+    if (build_taps_f64(r, W, &t)) return ORC_EINVAL;
+    int64_t ep = cols + 2 * r, n = (rows + 2 * r) * ep;
+    double *a = (double *)calloc(n, sizeof(double)), *c = (double *)calloc(n, sizeof(double));
+    if (!a || !c) { free(a); free(c); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < rows; i++) memcpy(a + (i + r) * ep + r, in + i * cols, sizeof(double) * cols);
+    if (bc == 2) { bc_fill_double(2, rows, cols, r, frame, a); bc_fill_double(2, rows, cols, r, frame, c); }
+    for (int64_t s = 0; s < steps; s++) {
+        if (bc == 1) bc_fill_double(1, rows, cols, r, frame, a);
+        step_f64(rows, cols, r, &t, a, c);
+        double *tmp = a; a = c; c = tmp;
+    }
+    for (int64_t i = 0; i < rows; i++) memcpy(out + i * cols, a + (i + r) * ep + r, sizeof(double) * cols);
+    free(a); free(c);
+    return ORC_OK;
+}
+
+int oracle_stencil_bc_f32(int bc, int64_t rows, int64_t cols, int r, const float *W, const float *frame,
+                          int64_t steps, const float *in, float *out) {
+    if ((bc != 1 && bc != 2) || rows < 1 || cols < 1 || steps < 0 || !W || !in || !out || (bc == 2 && !frame))
+        return ORC_EINVAL;
+    taps_t t;
+    if (build_taps_f32(r, W, &t)) return ORC_EINVAL;
+    int64_t ep = cols + 2 * r, n = (rows + 2 * r) * ep;
+    float *a = (float *)calloc(n, sizeof(float)), *c = (float *)calloc(n, sizeof(float));
+    if (!a || !c) { free(a); free(c); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < rows; i++) memcpy(a + (i + r) * ep + r, in + i * cols, sizeof(float) * cols);
+    if (bc == 2) { bc_fill_float(2, rows, cols, r, frame, a); bc_fill_float(2, rows, cols, r, frame, c); }
+    for (int64_t s = 0; s < steps; s++) {
+        if (bc == 1) bc_fill_float(1, rows, cols, r, frame, a);
+        step_f32(rows, cols, r, &t, a, c);
+        float *tmp = a; a = c; c = tmp;
+    }
+    for (int64_t i = 0; i < rows; i++) memcpy(out + i * cols, a + (i + r) * ep + r, sizeof(float) * cols);
+    free(a); free(c);
+    return ORC_OK;
+}
+
+/* 16-bit storage with a periodic or framed boundary; the frame holds 16-bit values */
+int oracle_stencil_bc_lowp(int dtype, int bc, int64_t rows, int64_t cols, int r, const float *W,
+                           const uint16_t *frame, int64_t steps, const uint16_t *in, uint16_t *out) {
+    if ((dtype != 1 && dtype != 2) || (bc != 1 && bc != 2) || rows < 1 || cols < 1 || steps < 0 || !W || !in ||
+        !out || (bc == 2 && !frame))
+        return ORC_EINVAL;
+    taps_t t;
+    if (build_taps_f32(r, W, &t)) return ORC_EINVAL;
+    int64_t ep = cols + 2 * r, n = (rows + 2 * r) * ep, nf = oracle_frame_elems(rows, cols, r);
+    float *a = (float *)calloc(n, sizeof(float)), *c = (float *)calloc(n, sizeof(float));
+    float *fr = (float *)calloc(nf > 0 ? nf : 1, sizeof(float));
+    if (!a || !c || !fr) { free(a); free(c); free(fr); return ORC_ENOMEM; }
+    if (bc == 2)
+        for (int64_t k = 0; k < nf; k++) fr[k] = lowp_load(dtype, frame[k]);
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t j = 0; j < cols; j++) a[(i + r) * ep + r + j] = lowp_load(dtype, in[i * cols + j]);
+    if (bc == 2) { bc_fill_float(2, rows, cols, r, fr, a); bc_fill_float(2, rows, cols, r, fr, c); }
+    for (int64_t s = 0; s < steps; s++) {
+        if (bc == 1) bc_fill_float(1, rows, cols, r, fr, a);
+        step_f32(rows, cols, r, &t, a, c);
+        for (int64_t i = 0; i < rows; i++)
+            for (int64_t j = 0; j < cols; j++) {
+                float *p = c + (i + r) * ep + r + j;
+                *p = lowp_load(dtype, lowp_store(dtype, *p));
+            }
+        float *tmp = a; a = c; c = tmp;
+    }
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t j = 0; j < cols; j++) out[i * cols + j] = lowp_store(dtype, a[(i + r) * ep + r + j]);
+    free(a); free(c); free(fr);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D: the same Jacobi update on a planes x rows x cols grid with a constant */
+/* halo b of depth r:                                                        */
+/*   u'(k,i,j) = sum_{dz,dy,dx in [-r,r]} W[dz+r][dy+r][dx+r] ~u(k+dz,i+dy,j+dx) */
+/* Canonical FP32 order: the centre product, then one fmaf per nonzero tap in */
+/* row-major (dz, dy, dx) order.                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;                       /* off-centre taps with a nonzero weight */
+    int dz[729], dy[729], dx[729];
+    int q[729];                  /* index of each tap's weight in W */
+    int centre;
+} taps3_t;
+
+static int build_taps3(int r, const double *W, taps3_t *t) {
+    if (r < 1 || r > 4) return ORC_EINVAL;
+    int k = 2 * r + 1;
+    t->n = 0;
+    t->centre = (r * k + r) * k + r;
+    for (int dz = -r; dz <= r; dz++)
+        for (int dy = -r; dy <= r; dy++)
+            for (int dx = -r; dx <= r; dx++) {
+                int q = ((dz + r) * k + (dy + r)) * k + (dx + r);
+                if ((dz == 0 && dy == 0 && dx == 0) || W[q] == 0.0) continue;
+                t->dz[t->n] = dz; t->dy[t->n] = dy; t->dx[t->n] = dx; t->q[t->n] = q;
+                t->n++;
+            }
+    return ORC_OK;
+}
+
+/* FP64: weights promoted from the FP32 ones the caller passes as doubles; separate mul and add */
+int oracle_stencil3d_f64(int64_t planes, int64_t rows, int64_t cols, int r, const double *W, double b,
+                         int64_t steps, const double *in, double *out) {
+    if (planes < 1 || rows < 1 || cols < 1 || steps < 0 || !W || !in || !out) return ORC_EINVAL;
+    taps3_t *t = (taps3_t *)malloc(sizeof(taps3_t));
+    if (!t) return ORC_ENOMEM;
+    if (build_taps3(r, W, t)) { free(t); return ORC_EINVAL; }
+    int64_t ep = cols + 2 * r, eq = (rows + 2 * r) * ep, n = (planes + 2 * r) * eq;
+    double *a = (double *)malloc(sizeof(double) * n), *c = (double *)malloc(sizeof(double) * n);
+    if (!a || !c) { free(a); free(c); free(t); return ORC_ENOMEM; }
+    for (int64_t q = 0; q < n; q++) a[q] = c[q] = b;
+    for (int64_t k = 0; k < planes; k++)
+        for (int64_t i = 0; i < rows; i++)
+            memcpy(a + (k + r) * eq + (i + r) * ep + r, in + (k * rows + i) * cols, sizeof(double) * cols);
+    for (int64_t s = 0; s < steps; s++) {
+#pragma omp parallel for schedule(static)
+        for (int64_t ki = 0; ki < planes * rows; ki++) {
+            int64_t k = ki / rows, i = ki % rows;
+            const double *src = a + (k + r) * eq + (i + r) * ep + r;
+            double *dst = c + (k + r) * eq + (i + r) * ep + r;
+            for (int64_t j = 0; j < cols; j++) {
+                double acc = W[t->centre] * src[j];
+                for (int q = 0; q < t->n; q++)
+                    acc += W[t->q[q]] * src[(int64_t)t->dz[q] * eq + (int64_t)t->dy[q] * ep + j + t->dx[q]];
+                dst[j] = acc;
+            }
+        }
+        double *tmp = a; a = c; c = tmp;
+    }
+    for (int64_t k = 0; k < planes; k++)
+        for (int64_t i = 0; i < rows; i++)
+            memcpy(out + (k * rows + i) * cols, a + (k + r) * eq + (i + r) * ep + r, sizeof(double) * cols);
+    free(a); free(c); free(t);
+    return ORC_OK;
+}
+
+/* FP32-canonical: the centre product, then fmaf per nonzero tap in row-major (dz, dy, dx) order */
+int oracle_stencil3d_f32(int64_t planes, int64_t rows, int64_t cols, int r, const float *W, float b,
+                         int64_t steps, const float *in, float *out) {
+    if (planes < 1 || rows < 1 || cols < 1 || steps < 0 || !W || !in || !out || r < 1 || r > 4) return ORC_EINVAL;
+    int kk = 2 * r + 1;
+    double W64[729];
+    for (int q = 0; q < kk * kk * kk; q++) W64[q] = W[q];
+    taps3_t *t = (taps3_t *)malloc(sizeof(taps3_t));
+    if (!t) return ORC_ENOMEM;
+    if (build_taps3(r, W64, t)) { free(t); return ORC_EINVAL; }
+    int64_t ep = cols + 2 * r, eq = (rows + 2 * r) * ep, n = (planes + 2 * r) * eq;
+    float *a = (float *)malloc(sizeof(float) * n), *c = (float *)malloc(sizeof(float) * n);
+    if (!a || !c) { free(a); free(c); free(t); return ORC_ENOMEM; }
+    for (int64_t q = 0; q < n; q++) a[q] = c[q] = b;
+    for (int64_t k = 0; k < planes; k++)
+        for (int64_t i = 0; i < rows; i++)
+            memcpy(a + (k + r) * eq + (i + r) * ep + r, in + (k * rows + i) * cols, sizeof(float) * cols);
+    for (int64_t s = 0; s < steps; s++) {
+#pragma omp parallel for schedule(static)
+        for (int64_t ki = 0; ki < planes * rows; ki++) {
+            int64_t k = ki / rows, i = ki % rows;
+            const float *src = a + (k + r) * eq + (i + r) * ep + r;
+            float *dst = c + (k + r) * eq + (i + r) * ep + r;
+            for (int64_t j = 0; j < cols; j++) {
+                float acc = W[t->centre] * src[j];
+                for (int q = 0; q < t->n; q++)
+                    acc = fmaf(W[t->q[q]], src[(int64_t)t->dz[q] * eq + (int64_t)t->dy[q] * ep + j + t->dx[q]], acc);
+                dst[j] = acc;
+            }
+        }
+        float *tmp = a; a = c; c = tmp;
+    }
+    for (int64_t k = 0; k < planes; k++)
+        for (int64_t i = 0; i < rows; i++)
+            memcpy(out + (k * rows + i) * cols, a + (k + r) * eq + (i + r) * ep + r, sizeof(float) * cols);
+    free(a); free(c); free(t);
+    return ORC_OK;
+}
