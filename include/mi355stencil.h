@@ -54,6 +54,7 @@ extern "C" {
 #define ST_FLAG_GRAPH  0x2u  /* stencil_run replays its passes from a cached hipGraph            */
 
 #define ST_MAX_RADIUS 4
+#define ST_MAX_RADIUS_3D 2
 
 typedef struct st_plan st_plan;
 typedef struct st_batch st_batch;
@@ -85,6 +86,23 @@ typedef struct sg_model sg_model;
 int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const float* weights,
                  double boundary, int storage, uint32_t flags);
 
+/* stencil_plan3d -- the same Jacobi update on a 3D grid of planes x rows x cols cells (element
+ * (k, i, j) at base[(k * rows + i) * cols + j]):
+ *   u'(k,i,j) = sum_{dz,dy,dx in [-r, r]} W[dz+r][dy+r][dx+r] * ~u(k+dz, i+dy, j+dx),
+ * ~u = u in the grid and the constant `boundary` outside (the paper's fixed halo, Sec. IV-A, in
+ * three dimensions); weights: (2r+1)^3 floats, row-major in (dz, dy, dx).  Per-cell FP32 order: the
+ * centre product, then one FMA per footprint tap in row-major (dz, dy, dx) order (star footprint --
+ * the taps on the three axes -- when every other weight is zero, else the full box).
+ * 1 <= r <= ST_MAX_RADIUS_3D; storage ST_F32 / ST_BF16 / ST_F16 (FP32 arithmetic, rounded every
+ * step); flags: ST_FLAG_GRAPH only.  A 3D plan runs one step per pass (stencil_run, stencil_run_noalloc,
+ * stencil_workspace_bytes and stencil_norms take it; the blocking, variant, boundary, autotune and
+ * batch calls refuse it with ST_EUNSUPPORTED, and its norms' next-step mass is NaN).  Errors: as
+ * stencil_plan, and planes < 1. */
+int stencil_plan3d(st_plan** out, int64_t planes, int64_t rows, int64_t cols, int radius, const float* weights,
+                   double boundary, int storage, uint32_t flags);
+/* stencil_get_planes -- planes of a 3D plan (1 for a 2D plan): a field holds planes * rows * cols cells. */
+int stencil_get_planes(const st_plan* plan, int64_t* planes);
+
 /* stencil_plan_varcoef -- variable-coefficient (conservative) heat step, a
  * Jacobi update (Sec. II-C) whose five weights vary with position:
  *   u'(c) = u(c) + sum_{nb in N, W, E, S} kf * (u(nb) - u(c)),
@@ -98,7 +116,7 @@ int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double bound
 int stencil_destroy(st_plan* plan);
 
 /* stencil_set_blocking -- choose the temporal-blocking depth tb (steps per HBM
- * round trip, 1..16) and the output tile (tile_x, tile_y) of the tiled
+ * round trip, 1..16; up to 64 steps per halo swap for ST_VARIANT_RESIDENT) and the output tile (tile_x, tile_y) of the tiled
  * kernel; 0 keeps the current value.  The result is bitwise independent of
  * these choices.  Errors: ST_EINVAL (value out of range), ST_EUNSUPPORTED
  * (tile not instantiated; the supported set is listed by stencil_tiles()). */
@@ -121,6 +139,16 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
                                  3 / 2 / 2 / 1 (box)                                            */
 #define ST_VARIANT_MARCH1  4  /* the marching pass with one column per lane (more, shorter
                                  tasks: for small grids); depths as ST_VARIANT_MARCH            */
+#define ST_VARIANT_RESIDENT 5 /* the whole run in one cooperative launch: one workgroup per compute
+                                 unit keeps its tile in LDS for every step and swaps an r*tb-deep
+                                 halo with its eight neighbours every tb steps through global
+                                 memory, gated by per-tile counters with bounded waits (the paper's
+                                 PE-resident tiles and counter-gated halo swap, Sec. IV-B/C).  For
+                                 grids whose tiles fit LDS (about 2048^2 and below at r = 1); tb
+                                 up to what the tiles allow (each tile at least r*tb cells per
+                                 side); constant halo only.  Synchronises nothing; a wait that runs
+                                 out of polls ends the run early and is reported by
+                                 stencil_resident_status                                         */
 
 /* stencil_set_variant -- choose the kernel variant (bitwise the same results).  Errors:
  * ST_EINVAL (unknown value), ST_EUNSUPPORTED (streaming needs FP32 storage and cols % 4 == 0;
@@ -131,6 +159,17 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
 int stencil_set_variant(st_plan* plan, int variant);
 int stencil_get_variant(const st_plan* plan, int* variant);
 
+/* stencil_set_spin_limit -- resident variant: polls of a neighbour's counter (in total per tile
+ * and epoch) before a wait gives up (default 2^22, seconds).  A give-up raises a flag that ends
+ * every workgroup's run at its next wait, so the launch always completes; the output is then
+ * unspecified and stencil_resident_status reports it.  Errors: ST_EINVAL (NULL plan, polls < 1). */
+int stencil_set_spin_limit(st_plan* plan, int64_t polls);
+
+/* stencil_resident_status -- after a resident run on `workspace`: status4[0] = 1 if a wait gave up
+ * (else 0), then the workgroup, the epoch it waited for and the neighbour it waited on.
+ * Synchronises `stream`.  Errors: ST_EINVAL, ST_ENOWS (workspace smaller than the run's), ST_EHIP. */
+int stencil_resident_status(const st_plan* plan, const void* workspace, size_t ws_bytes, int* status4, void* stream);
+
 /* stencil_set_march_segment -- marching variants: each wavefront computes at
  * least `min_rows` output rows of its column band (0, the default: as many
  * (band, segment) tasks as the device holds wavefronts at once).  A segment
@@ -140,6 +179,34 @@ int stencil_get_variant(const st_plan* plan, int* variant);
  * Errors: ST_EINVAL (NULL plan, negative min_rows). */
 int stencil_set_march_segment(st_plan* plan, int64_t min_rows);
 int stencil_get_march_segment(const st_plan* plan, int64_t* min_rows);
+
+/* ---- boundary rules --------------------------------------------------- */
+#define ST_BC_CONST    0  /* the fixed halo value b of stencil_plan (the paper's zero halo, Sec. IV-A) */
+#define ST_BC_PERIODIC 1  /* periodic: the cell outside the grid at (i, j) is u(i mod rows, j mod cols) */
+#define ST_BC_FRAME    2  /* a fixed halo given by the caller, never updated                          */
+
+/* stencil_set_boundary -- choose how the cells outside the grid are defined in every step of
+ * the Jacobi update (Sec. II-C), beyond the paper's constant halo:
+ *   ST_BC_CONST     the plan's halo value b (the default); `frame` must be NULL;
+ *   ST_BC_PERIODIC  the grid wraps in both directions (a torus); `frame` must be NULL;
+ *   ST_BC_FRAME     the r-deep ring around the grid holds the values of the device array
+ *                   `frame` (storage type of the plan; caller-owned, read by every run, so it
+ *                   must stay valid and unchanged while runs are enqueued).  Layout, in elements:
+ *                   top strip r x (cols + 2r) (rows -r .. -1, columns -r .. cols+r-1), bottom strip
+ *                   r x (cols + 2r) (rows rows .. rows+r-1), left strip rows x r (columns -r .. -1),
+ *                   right strip rows x r (columns cols .. cols+r-1), each row-major, one after
+ *                   the other: stencil_frame_elems() elements in all.
+ * Periodic and framed plans run on the row-marching kernels only: the plan switches to
+ * ST_VARIANT_MARCH unless it already uses a marching variant (with tb lowered to that variant's
+ * limit), stencil_set_variant refuses the tiled and streaming variants, and the autotuner tries
+ * marching candidates only.  Batches (stencil_batch_create) and the naive flag take constant
+ * halos only.  stencil_norms' next-step mass is sum(W) * sum(u) on a periodic grid and NaN with a
+ * frame.  Host-only.  Errors: ST_EINVAL (NULL plan, unknown kind, frame missing or given
+ * wrongly, varcoef plan), ST_EUNSUPPORTED (a naive plan). */
+int stencil_set_boundary(st_plan* plan, int kind, const void* frame);
+int stencil_get_boundary(const st_plan* plan, int* kind);
+/* stencil_frame_elems -- elements of the frame of ST_BC_FRAME: 2r (cols + 2r) + 2r rows. */
+int stencil_frame_elems(const st_plan* plan, int64_t* elems);
 
 /* stencil_get_dims -- the plan's rows, cols and storage type (ST_F32 / ST_BF16 / ST_F16); NULL
  * outputs are skipped.  A field of the plan occupies rows * cols * (4 or 2) bytes.  Host-only.
@@ -155,7 +222,8 @@ int stencil_tiles(int* xy, int cap, int* n);
 
 /* stencil_workspace_bytes -- minimum workspace for stencil_run(plan, ..., steps):
  * one extra field (rows*cols elements of the storage type) when the run takes
- * two or more passes, else 0.  Host-only. */
+ * two or more passes, else 0; the resident variant needs one field (rounded up to 256 bytes)
+ * plus 64 KiB of counters whenever steps >= 1.  Host-only. */
 int stencil_workspace_bytes(const st_plan* plan, int64_t steps, size_t* bytes);
 
 /* stencil_run -- advance `steps` Jacobi steps: out = S^steps(in).
@@ -314,9 +382,14 @@ int stencil_batch_destroy(st_batch* batch);
 /* ---- CNN surrogate ------------------------------------------------------ */
 /* Network: 6 conv3x3 layers with zero "same" padding, channels
  * 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias on every layer, exact-erf GELU
- * after layers 1-5, residual output  u_hat = u0 + f(u0, (kappa-0.125)/0.075).
- * Layers 2-5 run as BF16 MFMA implicit GEMMs with FP32 accumulation; layers 1
- * and 6 run on the vector ALUs in FP32 (BF16 activations are widened exactly).
+ * after layers 1-5, and a residual output scaled by the field:
+ *   s     = RMS of u0 over the field (FP64; s = 1 for an all-zero field)
+ *   inv   = fp32(1 / s),  gain = fp32(2^-11 s)
+ *   u_hat = u0 + gain * f(u0 * inv, (kappa - 0.125) / 0.075)
+ * (the network sees the field in units of its size and predicts the K-step update in units of
+ * 2^-11 of it).  Layer 1 runs on FP32 MFMA; layers 2-5 as BF16 MFMA implicit GEMMs with FP32
+ * accumulation; layer 6 on BF16 MFMA over the BF16 activations with each FP32 weight split into a
+ * BF16 pair (16 significant bits).  Activations are stored as BF16.
  *
  * Parameter buffer (device, FP32, SG_PARAM_COUNT floats), per layer l = 1..6:
  *   W_l as [ky][kx][ci][co] (3 x 3 x C_in x C_out), then b_l[C_out].
@@ -327,13 +400,26 @@ int stencil_batch_destroy(st_batch* batch);
 int surrogate_create(sg_model** out, uint32_t flags);
 int surrogate_destroy(sg_model* m);
 
+/* surrogate_param_bytes -- bytes of the parameter buffer (SG_PARAM_COUNT floats) and of the Adam
+ * state (2 * SG_PARAM_COUNT floats); NULL outputs are skipped.  Host-only.  Errors: ST_EINVAL. */
+int surrogate_param_bytes(const sg_model* m, size_t* params, size_t* optim_state);
+
+/* surrogate_init -- seeded initialisation on the device: He-normal weights N(0, 2 / (9 C_in)) (the
+ * last layer's scaled by 0.1, so that the untrained network starts near u_hat = u0), zero biases,
+ * and zero Adam state (skipped when optim_state is NULL).  Weight i of the flat layout is
+ * fp32(sd_l * z_i) with z_i the Box-Muller normal sqrt(-2 ln(1 - u1)) cos(2 pi u2), computed in
+ * FP64 from u = (w >> 11) 2^-53 of the first two words w of Philox4x64-10 (Salmon et al., SC 2011)
+ * at counter (i, 0, 0, 0) and key (seed, 0).  Asynchronous.  Errors: ST_EINVAL, ST_EHIP. */
+int surrogate_init(sg_model* m, float* params, float* optim_state, uint64_t seed, void* stream);
+
 /* surrogate_workspace_bytes -- device workspace for a batch of `batch` fields
  * of rows x cols: activations, pre-activations, gradients and partial sums. */
 int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_t cols, size_t* bytes);
 
 /* surrogate_infer -- u_hat[b] = surrogate(u0[b], kappa[b]) for `batch`
- * fields of rows x cols (device FP32, contiguous one after another).
- * Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+ * fields of rows x cols (device FP32, contiguous one after another); each field's
+ * scale constants (inv, gain) come from its own RMS.  Asynchronous.  Errors: ST_EINVAL, ST_ENOWS,
+ * ST_EHIP. */
 int surrogate_infer(sg_model* m, const float* params, const float* u0, const float* kappa, float* u_hat,
                       int batch, int64_t rows, int64_t cols, void* workspace, size_t ws_bytes, void* stream);
 
@@ -343,10 +429,21 @@ int surrogate_infer(sg_model* m, const float* params, const float* u0, const flo
  * lo_hi[4b+3]) of field b (lo_hi: HOST array of 4*batch ints, batch <= 64)
  * and n counts the kept cells of all fields.  Writes d loss / d params to
  * `grad` (SG_PARAM_COUNT floats) and the loss to the device double *loss.
- * Deterministic (fixed-order reductions).  Asynchronous. */
+ * `scale` (device, 2 * batch floats, nullable): each field's (inv, gain) pair (see
+ * surrogate_field_scale); NULL takes them from each field's own RMS.  surrogate_train passes those
+ * of the whole trajectory field each crop was cut from.  Deterministic (fixed-order reductions).
+ * Asynchronous. */
 int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa,
-                        const float* target, const int* lo_hi, int batch, int64_t rows, int64_t cols,
-                        float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream);
+                        const float* scale, const float* target, const int* lo_hi, int batch, int64_t rows,
+                        int64_t cols, float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream);
+
+/* surrogate_field_scale -- the scale constants of n fields of rows x cols (device FP32, one after
+ * another): scale[2b] = inv = fp32(1 / s), scale[2b + 1] = gain = fp32(2^-11 s), s = the RMS of
+ * field b in FP64 (a fixed-order two-stage sum; s = 1 for an all-zero field).  For
+ * surrogate_loss_grad's `scale` argument when the fields given there are crops of larger fields.
+ * Workspace: n * 64 doubles.  Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+int surrogate_field_scale(const float* u0, int n, int64_t rows, int64_t cols, float* scale, void* workspace,
+                          size_t ws_bytes, void* stream);
 
 /* surrogate_adam -- one Adam step (Kingma & Ba, Algorithm 1, bias-corrected)
  * on params with `grad`; `t` is the 1-based step index.  optim = m then v. */
@@ -398,17 +495,30 @@ int surrogate_train_ws_bytes(const sg_model* m, const sg_train_cfg* cfg, size_t*
 int surrogate_train(sg_model* m, float* params, float* optim, const float* coef, const int* crop_yx,
                     const sg_train_cfg* cfg, double* losses, void* workspace, size_t ws_bytes, void* stream);
 
-/* surrogate_infer_checked -- the surrogate with the plain stencil as judge and
- * fallback: computes u_hat = surrogate(u0, kappa), then the judge plan
- * (a varcoef plan) advances u0 by K steps into `out`'s workspace copy and
- * measures rel = ||u_hat - u_K|| / ||u_K|| in FP64.  If rel <= tol, out =
- * u_hat; else out = u_K (the plain result) and *used_fallback = 1.  The
- * surrogate result is therefore never accepted unjudged in this entry point.
- * Synchronises (to read the error).  Workspace: surrogate workspace for one
- * field + 2 fields + norms scratch (surrogate_checked_ws_bytes). */
+/* surrogate_infer_checked -- the surrogate with the plain stencil as judge and fallback:
+ * computes u_hat = surrogate(u0, kappa), judges it against K plain steps of the judge plan (a
+ * varcoef plan of the same shape), and measures rel = ||u_hat - u_K|| / ||u_K|| in FP64 over
+ *   SG_JUDGE_FULL   every cell: the plain stencil runs on the whole field;
+ *   SG_JUDGE_PATCH  a 4 x 4 lattice of patches of min(64, rows) x min(64, cols) cells whose
+ *                   origins are spread evenly over the grid (row origin of lattice row a:
+ *                   ((rows - p) a + 1) / 3, integer division; columns alike), the first and last
+ *                   at the edges.  Each patch's window, the patch dilated by K cells (its light
+ *                   cone) and clipped to the grid, is copied edge to edge into a small "mosaic"
+ *                   field, and K plain steps run on the mosaic only: every patch cell is exactly
+ *                   the full-field result (a wrong neighbour across a window junction travels one
+ *                   cell per step), at a fraction of the cost.  When the windows would cover more
+ *                   than half of the grid's cells the whole field is judged instead.
+ * If rel <= tol, out = u_hat; else out = u_K (the plain K-step result on the whole field, run
+ * after the decision in PATCH mode) and *used_fallback = 1.  The surrogate result is never
+ * accepted unjudged here.  Synchronises (to read the error).  Workspace:
+ * surrogate_checked_ws_bytes (the surrogate's for one field, 3 fields, partial sums).
+ * Errors: ST_EINVAL (NULL argument, judge not a varcoef plan of this shape, K < 0, tol < 0 or
+ * NaN, unknown judge mode), ST_ENOWS, ST_EHIP. */
+#define SG_JUDGE_FULL  0
+#define SG_JUDGE_PATCH 1
 int surrogate_checked_ws_bytes(const sg_model* m, int64_t rows, int64_t cols, size_t* bytes);
 int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, const float* kappa, float* out,
-                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol,
+                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol, int judge_mode,
                             int* used_fallback, double* rel_err, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- errors ------------------------------------------------------------- */

@@ -24,7 +24,10 @@ ST_EINVAL, ST_EALIAS, ST_EUNSUPPORTED, ST_EHIP, ST_ENOWS, ST_ENOMEM, ST_ESTATE =
 ST_F32, ST_BF16, ST_F16 = 0, 1, 2
 ST_FLAG_NAIVE, ST_FLAG_GRAPH = 0x1, 0x2
 ST_VARIANT_TILED, ST_VARIANT_STREAM, ST_VARIANT_MARCH, ST_VARIANT_MARCH8, ST_VARIANT_MARCH1 = 0, 1, 2, 3, 4
+ST_VARIANT_RESIDENT = 5
+ST_BC_CONST, ST_BC_PERIODIC, ST_BC_FRAME = 0, 1, 2
 SG_PARAM_COUNT = 37889
+SG_JUDGE_FULL, SG_JUDGE_PATCH = 0, 1
 STORAGE = {"f32": ST_F32, "bf16": ST_BF16, "f16": ST_F16}
 
 _lib = None
@@ -44,6 +47,8 @@ class StencilError(RuntimeError):
 _SIGS = {
     "stencil_plan": [ctypes.POINTER(_p), _i64, _i64, _int, _p, ctypes.c_double, _int, _u32],
     "stencil_plan_varcoef": [ctypes.POINTER(_p), _i64, _i64, ctypes.c_double, _u32],
+    "stencil_plan3d": [ctypes.POINTER(_p), _i64, _i64, _i64, _int, _p, ctypes.c_double, _int, _u32],
+    "stencil_get_planes": [_p, ctypes.POINTER(_i64)],
     "stencil_destroy": [_p],
     "stencil_set_blocking": [_p, _int, _int, _int],
     "stencil_get_blocking": [_p, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
@@ -51,6 +56,11 @@ _SIGS = {
     "stencil_set_variant": [_p, _int],
     "stencil_get_variant": [_p, ctypes.POINTER(_int)],
     "stencil_set_march_segment": [_p, _i64],
+    "stencil_set_boundary": [_p, _int, _p],
+    "stencil_set_spin_limit": [_p, _i64],
+    "stencil_resident_status": [_p, _p, _sz, ctypes.POINTER(_int), _p],
+    "stencil_get_boundary": [_p, ctypes.POINTER(_int)],
+    "stencil_frame_elems": [_p, ctypes.POINTER(_i64)],
     "stencil_get_march_segment": [_p, ctypes.POINTER(_i64)],
     "stencil_tiles": [ctypes.POINTER(_int), _int, ctypes.POINTER(_int)],
     "stencil_workspace_bytes": [_p, _i64, ctypes.POINTER(_sz)],
@@ -80,15 +90,18 @@ _SIGS = {
     "surrogate_destroy": [_p],
     "surrogate_workspace_bytes": [_p, _int, _i64, _i64, ctypes.POINTER(_sz)],
     "surrogate_infer": [_p, _p, _p, _p, _p, _int, _i64, _i64, _p, _sz, _p],
-    "surrogate_loss_grad": [_p, _p, _p, _p, _p, _p, _int, _i64, _i64, _p, _p, _p, _sz, _p],
+    "surrogate_loss_grad": [_p, _p, _p, _p, _p, _p, _p, _int, _i64, _i64, _p, _p, _p, _sz, _p],
+    "surrogate_field_scale": [_p, _int, _i64, _i64, _p, _p, _sz, _p],
     "surrogate_adam": [_p, _p, _p, _p, _int, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _p],
     "surrogate_synth_fields": [_p, _int, _i64, _i64, _p, _p, _p],
     "surrogate_crop": [_p, _p, _p, _int, _i64, _i64, _i64, _i64, _p],
     "surrogate_checked_ws_bytes": [_p, _i64, _i64, ctypes.POINTER(_sz)],
     "surrogate_train_ws_bytes": [_p, _p, ctypes.POINTER(_sz)],
     "surrogate_train": [_p, _p, _p, _p, _p, _p, _p, _p, _sz, _p],
-    "surrogate_infer_checked": [_p, _p, _p, _p, _p, _i64, _i64, _p, _i64, ctypes.c_double,
+    "surrogate_infer_checked": [_p, _p, _p, _p, _p, _i64, _i64, _p, _i64, ctypes.c_double, _int,
                                 ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _p, _sz, _p],
+    "surrogate_param_bytes": [_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz)],
+    "surrogate_init": [_p, _p, _p, ctypes.c_uint64, _p],
     "stencil_strerror": [_int],
     "stencil_last_error": [],
 }
@@ -168,10 +181,16 @@ def stencil_get_dims(plan):
     return r.value, c.value, st.value
 
 
+def stencil_get_planes(plan) -> int:
+    v = _i64()
+    _ck(lib().stencil_get_planes(plan, ctypes.byref(v)), "stencil_get_planes")
+    return v.value
+
+
 def _fields(plan, **tensors):
     """Refuse GPU fields smaller than the plan's grid (the kernels would access memory past them)."""
     rows, cols, st = stencil_get_dims(plan)
-    need = rows * cols * (4 if st == ST_F32 else 2)
+    need = stencil_get_planes(plan) * rows * cols * (4 if st == ST_F32 else 2)
     for name, t in tensors.items():
         if t is not None and _nbytes(t) < need:
             raise ValueError(f"{name} holds {_nbytes(t)} bytes; the plan's {rows} x {cols} field needs {need}")
@@ -204,6 +223,17 @@ def stencil_plan(rows: int, cols: int, radius: int, weights, boundary: float = 0
     return h
 
 
+def stencil_plan3d(planes: int, rows: int, cols: int, radius: int, weights, boundary: float = 0.0, storage="f32",
+                   flags: int = 0):
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    if w.size != (2 * radius + 1) ** 3:  # the library reads exactly (2r+1)^3 weights
+        raise ValueError(f"weights must hold (2r+1)^3 = {(2 * radius + 1) ** 3} values for radius {radius}")
+    h = _p()
+    _ck(lib().stencil_plan3d(ctypes.byref(h), planes, rows, cols, radius, w.ctypes.data_as(_p), float(boundary),
+                             storage_code(storage), flags), "stencil_plan3d")
+    return h
+
+
 def stencil_plan_varcoef(rows: int, cols: int, boundary: float = 0.0, flags: int = 0):
     h = _p()
     _ck(lib().stencil_plan_varcoef(ctypes.byref(h), rows, cols, float(boundary), flags), "stencil_plan_varcoef")
@@ -225,6 +255,40 @@ def stencil_set_variant(plan, variant: int) -> None:
 def stencil_get_variant(plan) -> int:
     v = _int()
     _ck(lib().stencil_get_variant(plan, ctypes.byref(v)), "stencil_get_variant")
+    return v.value
+
+
+def stencil_set_boundary(plan, kind: int, frame=None) -> None:
+    """kind: ST_BC_CONST, ST_BC_PERIODIC or ST_BC_FRAME (with `frame`, a device tensor of
+    stencil_frame_elems(plan) elements of the plan's storage type, kept alive by the caller)."""
+    if frame is not None:
+        rows, cols, st = stencil_get_dims(plan)
+        if _nbytes(frame) < stencil_frame_elems(plan) * (4 if st == ST_F32 else 2):
+            raise ValueError("frame holds fewer elements than stencil_frame_elems(plan)")
+    _ck(lib().stencil_set_boundary(plan, int(kind), _dptr(frame, "frame")), "stencil_set_boundary")
+
+
+def stencil_set_spin_limit(plan, polls: int) -> None:
+    _ck(lib().stencil_set_spin_limit(plan, int(polls)), "stencil_set_spin_limit")
+
+
+def stencil_resident_status(plan, workspace, stream=None):
+    """(gave_up, workgroup, epoch, neighbour) of the last resident run on `workspace` (synchronises)."""
+    st = (_int * 4)()
+    _ck(lib().stencil_resident_status(plan, _dptr(workspace, "workspace"), _nbytes(workspace), st, _stream(stream)),
+        "stencil_resident_status")
+    return tuple(int(v) for v in st)
+
+
+def stencil_get_boundary(plan) -> int:
+    v = _int()
+    _ck(lib().stencil_get_boundary(plan, ctypes.byref(v)), "stencil_get_boundary")
+    return v.value
+
+
+def stencil_frame_elems(plan) -> int:
+    v = _i64()
+    _ck(lib().stencil_frame_elems(plan, ctypes.byref(v)), "stencil_frame_elems")
     return v.value
 
 
@@ -438,6 +502,20 @@ def surrogate_destroy(model) -> None:
     _ck(lib().surrogate_destroy(model), "surrogate_destroy")
 
 
+def surrogate_param_bytes(model):
+    """(parameter bytes, Adam state bytes)."""
+    a, b = _sz(), _sz()
+    _ck(lib().surrogate_param_bytes(model, ctypes.byref(a), ctypes.byref(b)), "surrogate_param_bytes")
+    return a.value, b.value
+
+
+def surrogate_init(model, params, optim_state, seed: int, stream=None) -> None:
+    if _nbytes(params) < 4 * SG_PARAM_COUNT or (optim_state is not None and _nbytes(optim_state) < 8 * SG_PARAM_COUNT):
+        raise ValueError("params needs SG_PARAM_COUNT floats and optim_state twice that")
+    _ck(lib().surrogate_init(model, _dptr(params, "params"), _dptr(optim_state, "optim_state"),
+                             ctypes.c_uint64(int(seed) & (2**64 - 1)), _stream(stream)), "surrogate_init")
+
+
 def surrogate_workspace_bytes(model, batch: int, rows: int, cols: int) -> int:
     n = _sz()
     _ck(lib().surrogate_workspace_bytes(model, batch, rows, cols, ctypes.byref(n)), "surrogate_workspace_bytes")
@@ -452,15 +530,21 @@ def surrogate_infer(model, params, u0, kappa, u_hat, batch: int, rows: int, cols
                                 _nbytes(workspace), _stream(stream)), "surrogate_infer")
 
 
+def surrogate_field_scale(u0, n: int, rows: int, cols: int, scale, workspace, stream=None) -> None:
+    _batch_fields(n * rows * cols, u0=u0)
+    _ck(lib().surrogate_field_scale(_dptr(u0, "u0"), n, rows, cols, _dptr(scale, "scale"), _dptr(workspace, "workspace"),
+                                    _nbytes(workspace), _stream(stream)), "surrogate_field_scale")
+
+
 def surrogate_loss_grad(model, params, u0, kappa, target, lo_hi, batch: int, rows: int, cols: int, grad, loss,
-                        workspace, stream=None) -> None:
+                        workspace, scale=None, stream=None) -> None:
     _batch_fields(batch * rows * cols, u0=u0, kappa=kappa, target=target)
     flat = [int(v) for v in np.asarray(lo_hi).reshape(-1)]
     if len(flat) == 4 and batch > 1:  # one mask for every field
         flat = flat * batch
     lh = (_int * len(flat))(*flat)
     _ck(lib().surrogate_loss_grad(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
-                                  _dptr(target, "target"), ctypes.cast(lh, _p), batch, rows, cols,
+                                  _dptr(scale, "scale"), _dptr(target, "target"), ctypes.cast(lh, _p), batch, rows, cols,
                                   _dptr(grad, "grad"), _dptr(loss, "loss"), _dptr(workspace, "workspace"),
                                   _nbytes(workspace), _stream(stream)), "surrogate_loss_grad")
 
@@ -488,12 +572,13 @@ def surrogate_checked_ws_bytes(model, rows: int, cols: int) -> int:
 
 
 def surrogate_infer_checked(model, params, u0, kappa, out, rows: int, cols: int, judge, K: int, tol: float,
-                            workspace, stream=None):
+                            workspace, judge_mode: int = SG_JUDGE_FULL, stream=None):
     _batch_fields(rows * cols, u0=u0, kappa=kappa, out=out)
     used = _int()
     err = ctypes.c_double()
     _ck(lib().surrogate_infer_checked(model, _dptr(params, "params"), _dptr(u0, "u0"), _dptr(kappa, "kappa"),
-                                      _dptr(out, "out"), rows, cols, judge, K, float(tol), ctypes.byref(used),
+                                      _dptr(out, "out"), rows, cols, judge, K, float(tol), int(judge_mode),
+                                      ctypes.byref(used),
                                       ctypes.byref(err), _dptr(workspace, "workspace"), _nbytes(workspace),
                                       _stream(stream)), "surrogate_infer_checked")
     return bool(used.value), err.value

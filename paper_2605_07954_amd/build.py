@@ -17,8 +17,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmi355stencil.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["march_f32_star.hip", "march_bf16_star.hip", "march_f16_star.hip", "march_f32_box.hip", "march_bf16_box.hip",
-           "march_f16_box.hip", "surrogate.hip", "batched.hip", "sweep.hip", "api.hip", "march.hip", "varcoef.hip",
-           "norms.hip"]
+           "march_f16_box.hip", "march_xbc_f32_star.hip", "march_xbc_bf16_star.hip", "march_xbc_f16_star.hip",
+           "march_xbc_f32_box.hip", "march_xbc_bf16_box.hip", "march_xbc_f16_box.hip", "surrogate.hip", "batched.hip",
+           "sweep.hip", "api.hip", "march.hip", "varcoef.hip", "norms.hip", "stencil3d.hip", "resident.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -43,11 +44,27 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str, headers_mtime: float) -> bool:
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(os.path.join(CSRC, src)) or t < headers_mtime
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every translation unit (force) or only those older than their source or any header,
+    then link."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hdrs.append(os.path.join(os.path.dirname(HERE), "include", "mi355stencil.h"))
+    hmt = max(os.path.getmtime(h) for h in hdrs)
+    todo = [s for s in srcs if force or _stale(s, hmt)]
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in srcs]
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(lambda s: _compile(s, verbose), todo))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", OUT + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -57,4 +74,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -97,6 +97,8 @@ static void default_blocking(st_plan* p) {
 
 static void init_plan(st_plan* p) {
     std::memset(p, 0, sizeof(*p));
+    p->planes = 1;
+    p->spin_limit = int64_t(1) << 22;
 }
 
 static int check_flags(uint32_t flags) {
@@ -172,6 +174,58 @@ int stencil_plan(st_plan** out, int64_t rows, int64_t cols, int radius, const fl
     return ST_OK;
 }
 
+int stencil_plan3d(st_plan** out, int64_t planes, int64_t rows, int64_t cols, int radius, const float* weights,
+                   double boundary, int storage, uint32_t flags) {
+    if (!out) return fail(ST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (planes < 1 || rows < 1 || cols < 1) return fail(ST_EINVAL, "planes, rows and cols must be >= 1");
+    if (planes > (int64_t(1) << 31) || rows > (int64_t(1) << 31) || cols > (int64_t(1) << 31))
+        return fail(ST_EINVAL, "grid side too large");
+    if (rows * cols > (int64_t(1) << 46) || planes > (int64_t(1) << 46) / (rows * cols))
+        return fail(ST_EINVAL, "grid has more cells than device memory can hold");
+    if (radius < 1 || radius > ST_MAX_RADIUS_3D) return fail(ST_EINVAL, "3D radius must be in [1, 2]");
+    if (!weights) return fail(ST_EINVAL, "weights is NULL");
+    if (storage != ST_F32 && storage != ST_BF16 && storage != ST_F16) return fail(ST_EINVAL, "unknown storage type");
+    if (!std::isfinite(boundary)) return fail(ST_EINVAL, "boundary value must be finite");
+    if (flags & ~ST_FLAG_GRAPH) return fail(ST_EINVAL, "3D plans take ST_FLAG_GRAPH only");
+    const int k = 2 * radius + 1;
+    for (int i = 0; i < k * k * k; ++i)
+        if (!std::isfinite(weights[i])) return fail(ST_EINVAL, "weights must be finite");
+    st_plan* p = new (std::nothrow) st_plan;
+    if (!p) return fail(ST_ENOMEM, "plan allocation failed");
+    init_plan(p);
+    p->kind = KIND_3D;
+    p->planes = planes;
+    p->rows = rows;
+    p->cols = cols;
+    p->radius = radius;
+    p->storage = storage;
+    p->flags = flags;
+    double s = 0.0;
+    bool box = false;
+    for (int dz = -radius; dz <= radius; ++dz)
+        for (int dy = -radius; dy <= radius; ++dy)
+            for (int dx = -radius; dx <= radius; ++dx) {
+                const int q = ((dz + radius) * k + dy + radius) * k + dx + radius;
+                p->w3[q] = weights[q];
+                s += double(weights[q]);
+                if (((dz != 0) + (dy != 0) + (dx != 0)) > 1 && weights[q] != 0.0f) box = true;
+            }
+    p->shape = box ? SHAPE_BOX : SHAPE_STAR;
+    p->wsum = s;
+    p->b = boundary;
+    p->bq = round_to_storage(boundary, storage);
+    p->tb = 1;
+    *out = p;
+    return ST_OK;
+}
+
+int stencil_get_planes(const st_plan* plan, int64_t* planes) {
+    if (!plan || !planes) return fail(ST_EINVAL, "NULL argument");
+    *planes = plan->planes;
+    return ST_OK;
+}
+
 int stencil_plan_varcoef(st_plan** out, int64_t rows, int64_t cols, double boundary, uint32_t flags) {
     if (!out) return fail(ST_EINVAL, "out is NULL");
     *out = nullptr;
@@ -215,7 +269,9 @@ int stencil_tiles(int* xy, int cap, int* n) {
 
 int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
-    if (tb < 0 || tb > 16 || tile_x < 0 || tile_y < 0) return fail(ST_EINVAL, "blocking out of range");
+    if (plan->kind == KIND_3D) return fail(ST_EUNSUPPORTED, "3D plans have one blocking");
+    if (tb < 0 || tb > (plan->variant == VARIANT_RESIDENT ? 64 : 16) || tile_x < 0 || tile_y < 0)
+        return fail(ST_EINVAL, "blocking out of range");
     const int tx = tile_x ? tile_x : plan->tile_x;
     const int ty = tile_y ? tile_y : plan->tile_y;
     if (!tile_supported(plan->shape, plan->radius, tx, ty)) return fail(ST_EUNSUPPORTED, "tile not instantiated");
@@ -233,14 +289,19 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y) {
 
 int stencil_set_variant(st_plan* plan, int variant) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind == KIND_3D) return fail(ST_EUNSUPPORTED, "3D plans have one kernel");
     if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM && variant != ST_VARIANT_MARCH &&
-        variant != ST_VARIANT_MARCH8 && variant != ST_VARIANT_MARCH1)
+        variant != ST_VARIANT_MARCH8 && variant != ST_VARIANT_MARCH1 && variant != ST_VARIANT_RESIDENT)
         return fail(ST_EINVAL, "unknown variant");
+    if (variant == ST_VARIANT_RESIDENT && (plan->kind != KIND_CONST || plan->bc != ST_BC_CONST))
+        return fail(ST_EUNSUPPORTED, "the resident variant takes constant-weight plans with a constant halo");
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
         return fail(ST_EUNSUPPORTED, "streaming needs an FP32 constant-weight plan with cols % 4 == 0");
     if ((variant == ST_VARIANT_MARCH || variant == ST_VARIANT_MARCH8 || variant == ST_VARIANT_MARCH1) &&
         !march_usable(plan))
         return fail(ST_EUNSUPPORTED, "marching needs a constant-weight plan");
+    if (plan->bc != ST_BC_CONST && !is_march(variant))
+        return fail(ST_EUNSUPPORTED, "periodic and framed boundaries run on the marching variants only");
     const int old = plan->variant;
     plan->variant = variant;
     if (plan->tb > max_tb(plan, plan->tile_x, plan->tile_y)) {  // keep the plan launchable
@@ -248,6 +309,36 @@ int stencil_set_variant(st_plan* plan, int variant) {
         return fail(ST_EUNSUPPORTED, "current temporal block too deep for this variant; lower it first");
     }
     drop_graph(plan);
+    return ST_OK;
+}
+
+int stencil_set_boundary(st_plan* plan, int kind, const void* frame) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind == KIND_3D) return fail(ST_EUNSUPPORTED, "3D plans take a constant halo only");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "boundary rules apply to constant-weight plans");
+    if (kind != ST_BC_CONST && kind != ST_BC_PERIODIC && kind != ST_BC_FRAME) return fail(ST_EINVAL, "unknown boundary");
+    if ((kind == ST_BC_FRAME) != (frame != nullptr)) return fail(ST_EINVAL, "a frame is given exactly with ST_BC_FRAME");
+    if (kind != ST_BC_CONST && (plan->flags & ST_FLAG_NAIVE))
+        return fail(ST_EUNSUPPORTED, "the naive reference path takes a constant halo only");
+    if (kind != ST_BC_CONST && !is_march(plan->variant)) {
+        plan->variant = VARIANT_MARCH;
+        plan->tb = std::min(plan->tb, march_max_tb(plan->shape, plan->radius, 4));
+    }
+    plan->bc = kind;
+    plan->frame = frame;
+    drop_graph(plan);
+    return ST_OK;
+}
+
+int stencil_get_boundary(const st_plan* plan, int* kind) {
+    if (!plan || !kind) return fail(ST_EINVAL, "NULL argument");
+    *kind = plan->bc;
+    return ST_OK;
+}
+
+int stencil_frame_elems(const st_plan* plan, int64_t* elems) {
+    if (!plan || !elems) return fail(ST_EINVAL, "NULL argument");
+    *elems = 2 * int64_t(plan->radius) * (plan->cols + 2 * plan->radius) + 2 * int64_t(plan->radius) * plan->rows;
     return ST_OK;
 }
 
@@ -287,6 +378,18 @@ int stencil_get_blocking(const st_plan* plan, int* tb, int* tile_x, int* tile_y)
     return ST_OK;
 }
 
+int stencil_set_spin_limit(st_plan* plan, int64_t polls) {
+    if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (polls < 1) return fail(ST_EINVAL, "polls must be >= 1");
+    plan->spin_limit = polls;
+    drop_graph(plan);
+    return ST_OK;
+}
+
+static bool resident_run(const st_plan* p) {
+    return p->variant == VARIANT_RESIDENT && p->kind == KIND_CONST && !(p->flags & ST_FLAG_NAIVE);
+}
+
 static int64_t n_passes(const st_plan* p, int64_t steps) {
     if (steps <= 0) return 0;
     const int64_t tb = (p->flags & ST_FLAG_NAIVE) ? 1 : p->tb;
@@ -296,7 +399,13 @@ static int64_t n_passes(const st_plan* p, int64_t steps) {
 int stencil_workspace_bytes(const st_plan* plan, int64_t steps, size_t* bytes) {
     if (!plan || !bytes) return fail(ST_EINVAL, "NULL argument");
     if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
-    *bytes = n_passes(plan, steps) >= 2 ? size_t(plan->rows * plan->cols) * elem_size(plan->storage) : 0;
+    if (resident_run(plan)) {
+        *bytes = steps >= 1 ? ((size_t(field_cells(plan)) * elem_size(plan->storage) + 255) & ~size_t(255)) +
+                                  resident_ws_tail()
+                            : 0;
+        return ST_OK;
+    }
+    *bytes = n_passes(plan, steps) >= 2 ? size_t(field_cells(plan)) * elem_size(plan->storage) : 0;
     return ST_OK;
 }
 
@@ -309,11 +418,12 @@ static bool overlap(const void* a, const void* b, size_t n) {
 // Enqueue all passes of a run on `s`.
 static int enqueue_run(st_plan* p, const void* in, void* out, const float* kappa, int64_t steps, void* ws,
                        hipStream_t s) {
-    const size_t bytes = size_t(p->rows * p->cols) * elem_size(p->storage);
+    const size_t bytes = size_t(field_cells(p)) * elem_size(p->storage);
     if (steps == 0) {
         ST_HIP_CHECK(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s));
         return ST_OK;
     }
+    if (resident_run(p)) return launch_resident(p, in, out, ws, steps, s);
     const bool naive = p->flags & ST_FLAG_NAIVE;
     const int64_t tb = naive ? 1 : p->tb;
     const int64_t P = n_passes(p, steps);
@@ -322,7 +432,9 @@ static int enqueue_run(st_plan* p, const void* in, void* out, const float* kappa
         void* dst = ((P - 1 - k) % 2 == 0) ? out : ws;
         const int levels = int(std::min<int64_t>(tb, steps - k * tb));
         int rc;
-        if (p->kind == KIND_VARCOEF)
+        if (p->kind == KIND_3D)
+            rc = launch_3d(p, src, dst, s);
+        else if (p->kind == KIND_VARCOEF)
             rc = varcoef_launch(p, static_cast<const float*>(src), static_cast<float*>(dst), kappa, naive ? 0 : levels, s);
         else if (naive)
             rc = launch_naive(p, src, dst, kappa, s);
@@ -338,7 +450,7 @@ static int run_common(st_plan* plan, const void* in, void* out, const float* kap
                       size_t ws_bytes, void* stream) {
     if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
     if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
-    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    const size_t bytes = size_t(field_cells(plan)) * elem_size(plan->storage);
     if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
     size_t need = 0;
     stencil_workspace_bytes(plan, steps, &need);
@@ -348,7 +460,9 @@ static int run_common(st_plan* plan, const void* in, void* out, const float* kap
             return fail(ST_EALIAS, "workspace overlaps in/out");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!(plan->flags & ST_FLAG_GRAPH) || steps == 0) return enqueue_run(plan, in, out, kappa, steps, workspace, s);
+    // (the resident variant is one cooperative launch: it is not captured)
+    if (!(plan->flags & ST_FLAG_GRAPH) || steps == 0 || resident_run(plan))
+        return enqueue_run(plan, in, out, kappa, steps, workspace, s);
 
     // graph path: capture the passes once per (in, kappa, out, workspace, steps, stream)
     if (!(plan->graph_exec && plan->g_in == in && plan->g_kappa == kappa && plan->g_out == out &&
@@ -388,8 +502,16 @@ static int run_common(st_plan* plan, const void* in, void* out, const float* kap
 int stencil_run(st_plan* plan, const void* in, void* out, int64_t steps, void* workspace, size_t ws_bytes,
                 void* stream) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
-    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "varcoef plans run through stencil_run_varcoef");
+    if (plan->kind == KIND_VARCOEF) return fail(ST_EINVAL, "varcoef plans run through stencil_run_varcoef");
     return run_common(plan, in, out, nullptr, steps, workspace, ws_bytes, stream);
+}
+
+int stencil_resident_status(const st_plan* plan, const void* workspace, size_t ws_bytes, int* status4, void* stream) {
+    if (!plan || !workspace || !status4) return fail(ST_EINVAL, "NULL argument");
+    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "not a constant-weight plan");
+    const size_t need = ((size_t(field_cells(plan)) * elem_size(plan->storage) + 255) & ~size_t(255)) + resident_ws_tail();
+    if (ws_bytes < need) return fail(ST_ENOWS, "workspace smaller than a resident run's");
+    return read_resident_status(plan, workspace, status4, static_cast<hipStream_t>(stream));
 }
 
 int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, float* out, int64_t steps,
@@ -397,7 +519,7 @@ int stencil_run_varcoef(st_plan* plan, const float* in, const float* kappa, floa
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
     if (plan->kind != KIND_VARCOEF) return fail(ST_EINVAL, "not a varcoef plan");
     if (!kappa) return fail(ST_EINVAL, "kappa is NULL");
-    const size_t bytes = size_t(plan->rows * plan->cols) * 4;
+    const size_t bytes = size_t(field_cells(plan)) * 4;
     if (overlap(kappa, out, bytes)) return fail(ST_EALIAS, "kappa and out overlap");
     return run_common(plan, in, out, kappa, steps, workspace, ws_bytes, stream);
 }
@@ -424,17 +546,23 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
-    const int nvar = plan->kind == KIND_CONST ? 5 : 1;
+    const int nvar = plan->kind == KIND_CONST ? 6 : 1;
     for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
         if (var == VARIANT_STREAM && !stream_usable(plan)) break;
+        if (plan->bc != ST_BC_CONST && !is_march(var)) break;  // other boundaries: marching only
+        if (var == VARIANT_RESIDENT && (ti > 0 || plan->bc != ST_BC_CONST)) break;  // no tile either
         if (is_march(var) && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
         if (var == VARIANT_MARCH8 && plan->cols % 8 != 0) break;  // would run the four-column kernels
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
         plan->variant = var;
         // LDS tiles: the depths of kTb; marching: every depth it offers
         int cands[16], nc = 0;
-        if (is_march(var)) {
+        if (var == VARIANT_RESIDENT) {
+            static const int kRes[] = {1, 2, 4, 8, 12, 16, 24, 32, 48};
+            for (int tb : kRes)
+                if (resident_usable(plan, tb) && nc < 16) cands[nc++] = tb;
+        } else if (is_march(var)) {
             for (int tb = 1; tb <= max_tb(plan, tx, ty) && nc < 16; ++tb) cands[nc++] = tb;
         } else {
             for (int tb : kTb) cands[nc++] = tb;
@@ -504,6 +632,7 @@ extern "C" {
 int stencil_autotune(st_plan* plan, const void* in, void* out, void* workspace, size_t ws_bytes,
                      int64_t sample_steps, int* tb_out, int* tile_x_out, int* tile_y_out, void* stream) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
+    if (plan->kind == KIND_3D) return fail(ST_EUNSUPPORTED, "3D plans have nothing to tune");
     if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "varcoef plans are tuned by stencil_autotune_varcoef");
     return autotune_impl(plan, in, nullptr, out, workspace, ws_bytes, sample_steps, tb_out, tile_x_out, tile_y_out,
                          stream);
@@ -516,7 +645,7 @@ int stencil_autotune_varcoef(st_plan* plan, const float* in, const float* kappa,
     if (plan->kind != KIND_VARCOEF) return fail(ST_EINVAL, "not a varcoef plan");
     if (!kappa) return fail(ST_EINVAL, "kappa is NULL");
     if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
-    const size_t bytes = size_t(plan->rows * plan->cols) * 4;
+    const size_t bytes = size_t(field_cells(plan)) * 4;
     if (overlap(kappa, out, bytes)) return fail(ST_EALIAS, "kappa and out overlap");
     return autotune_impl(plan, in, kappa, out, workspace, ws_bytes, sample_steps, tb_out, tile_x_out, tile_y_out,
                          stream);
@@ -532,7 +661,7 @@ int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* byt
     size_t nb = 0, run_ws = 0;
     if (int rc = stencil_norms_ws_bytes(plan, &nb)) return rc;
     if (int rc = stencil_workspace_bytes(plan, check_every, &run_ws)) return rc;
-    const size_t field = (size_t(plan->rows * plan->cols) * elem_size(plan->storage) + 255) & ~size_t(255);
+    const size_t field = (size_t(field_cells(plan)) * elem_size(plan->storage) + 255) & ~size_t(255);
     *bytes = field + std::max(run_ws, field) + ((nb + 255) & ~size_t(255)) + 256;
     return ST_OK;
 }
@@ -540,12 +669,12 @@ int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* byt
 int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
                   int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream) {
     if (!plan || !in || !out || !steps_done || !rel_residual) return fail(ST_EINVAL, "NULL argument");
-    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "stencil_solve takes a constant-weight plan");
+    if (plan->kind == KIND_VARCOEF) return fail(ST_EINVAL, "stencil_solve takes a constant-weight plan");
     if (max_steps < 1 || check_every < 1 || !(tol >= 0.0)) return fail(ST_EINVAL, "bad max_steps/check_every/tol");
     size_t need = 0;
     if (int rc = stencil_solve_ws_bytes(plan, check_every, &need)) return rc;
     if (!workspace || ws_bytes < need) return fail(ST_ENOWS, "workspace too small");
-    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    const size_t bytes = size_t(field_cells(plan)) * elem_size(plan->storage);
     if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
     const size_t field = (bytes + 255) & ~size_t(255);
     size_t run_ws = 0, nb = 0;
@@ -639,10 +768,10 @@ int stencil_noalloc_max_bytes(size_t* bytes) {
 
 int stencil_run_noalloc(st_plan* plan, const void* in, void* out, int64_t steps, void* stream) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
-    if (plan->kind != KIND_CONST) return fail(ST_EINVAL, "stencil_run_noalloc takes a constant-weight plan");
+    if (plan->kind == KIND_VARCOEF) return fail(ST_EINVAL, "stencil_run_noalloc takes a constant-weight plan");
     if (!in || !out) return fail(ST_EINVAL, "in/out is NULL");
     if (steps < 0) return fail(ST_EINVAL, "steps must be >= 0");
-    const size_t bytes = size_t(plan->rows * plan->cols) * elem_size(plan->storage);
+    const size_t bytes = size_t(field_cells(plan)) * elem_size(plan->storage);
     if (overlap(in, out, bytes)) return fail(ST_EALIAS, "in and out overlap");
     size_t need = 0;
     stencil_workspace_bytes(plan, steps, &need);

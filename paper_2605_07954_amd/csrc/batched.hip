@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
     const int P = d.passes, p = a.p;
     const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
     float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
-    const march::MarchView v{src, dst, d.rows, d.cols, d.b};
+    const march::MarchView v{src, dst, d.rows, d.cols, d.b, march::BC_CONST, nullptr};
     const int64_t X0 = band * (MV * (64 - 2 * H)) - MV * H;
     // input rows in flight: one ring length, except box r >= 3 with several levels (registers)
     constexpr int D = SH == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
@@ -367,9 +367,9 @@ extern "C" int stencil_batch_create(st_batch** out, int n, st_plan* const* plans
             delete B;
             return fail(ST_EINVAL, "NULL plan, or steps outside [0, 2^30]");
         }
-        if (p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3) {
+        if (p->kind != KIND_CONST || p->storage != ST_F32 || p->radius > 3 || p->bc != ST_BC_CONST) {
             delete B;
-            return fail(ST_EUNSUPPORTED, "batched grids must be FP32 constant-weight plans, r <= 3");
+            return fail(ST_EUNSUPPORTED, "batched grids must be FP32 constant-weight plans with a constant halo, r <= 3");
         }
         BatchDesc& d = B->desc[g];
         std::memset(&d, 0, sizeof(d));

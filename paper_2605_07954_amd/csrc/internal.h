@@ -34,16 +34,18 @@ int fail(int code, const std::string& msg);
     } while (0)
 
 enum Shape { SHAPE_STAR = 0, SHAPE_BOX = 1 };
-enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1 };
+enum Kind { KIND_CONST = 0, KIND_VARCOEF = 1, KIND_3D = 2 };
 enum Variant {
     VARIANT_TILED = ST_VARIANT_TILED,
     VARIANT_STREAM = ST_VARIANT_STREAM,
     VARIANT_MARCH = ST_VARIANT_MARCH,
     VARIANT_MARCH8 = ST_VARIANT_MARCH8,
-    VARIANT_MARCH1 = ST_VARIANT_MARCH1
+    VARIANT_MARCH1 = ST_VARIANT_MARCH1,
+    VARIANT_RESIDENT = ST_VARIANT_RESIDENT
 };
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
+constexpr int MAXK3 = (2 * ST_MAX_RADIUS_3D + 1) * (2 * ST_MAX_RADIUS_3D + 1) * (2 * ST_MAX_RADIUS_3D + 1);  // 125
 
 // Workgroups of a one-cell-per-thread reference launch; beyond it the kernels stride over the grid
 // (a launch may hold at most 2^32 threads).
@@ -66,6 +68,8 @@ struct SweepArgs {
 struct st_plan {
     int kind;         // st::Kind
     int64_t rows, cols;
+    int64_t planes;   // 3D plans: planes along z (1 for 2D plans)
+    float w3[st::MAXK3];  // 3D plans: dense (2r+1)^3 weights
     int radius;
     int shape;        // st::Shape
     int storage;      // ST_F32 / ST_BF16 / ST_F16
@@ -77,6 +81,9 @@ struct st_plan {
     int tb, tile_x, tile_y;
     int variant;      // st::Variant (FP32 grids with cols % 4 == 0 may stream)
     int64_t seg_min;  // marching: least output rows per task (0: one task per resident wavefront)
+    int bc;             // ST_BC_CONST (halo b), ST_BC_PERIODIC or ST_BC_FRAME (marching variants only)
+    int64_t spin_limit; // resident variant: polls before a neighbour wait gives up
+    const void* frame;  // ST_BC_FRAME: caller-owned device frame (storage type)
     // cached hipGraph of a full run (ST_FLAG_GRAPH)
     void* graph_exec;
     const void* g_in;
@@ -109,6 +116,17 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
+// Cells of one field of the plan (planes * rows * cols).
+inline int64_t field_cells(const st_plan* p) { return p->planes * p->rows * p->cols; }
+// LDS-resident cooperative sweep (resident.hip): the whole run in one launch; workspace = one field
+// + resident_ws_tail() bytes of counters and status.
+size_t resident_ws_tail();
+bool resident_usable(const st_plan* p, int tb);
+int resident_max_tb(const st_plan* p);
+int launch_resident(const st_plan* p, const void* in, void* out, void* ws, int64_t steps, hipStream_t s);
+int read_resident_status(const st_plan* p, const void* ws, int* status4, hipStream_t s);
+// 3D pass (stencil3d.hip): one step of a 3D plan.
+int launch_3d(const st_plan* p, const void* src, void* dst, hipStream_t s);
 // Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment, up to
 // vmax (1, 4 or 8) columns per lane; up to march_max_tb(shape, radius, vmax) levels per pass (vmax 4:
 // star 8 / 6 / 4 / 3 for r = 1 / 2 / 3 / 4, box 6 / 3 / 2 / 2; vmax 8: star 8 / 4 / 3 / 2, box

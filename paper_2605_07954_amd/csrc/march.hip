@@ -31,8 +31,15 @@ using march_k::MWAVES;
 
 namespace {
 
-MarchFn march_lookup(int storage, int mode, int shape, int r, int levels) {
+MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool xbc) {
     const bool box = shape == SHAPE_BOX;
+    if (xbc) {
+        if (storage == ST_F32) return box ? march_lookup_xbc_f32_box(mode, r, levels) : march_lookup_xbc_f32_star(mode, r, levels);
+        if (storage == ST_BF16)
+            return box ? march_lookup_xbc_bf16_box(mode, r, levels) : march_lookup_xbc_bf16_star(mode, r, levels);
+        if (storage == ST_F16) return box ? march_lookup_xbc_f16_box(mode, r, levels) : march_lookup_xbc_f16_star(mode, r, levels);
+        return nullptr;
+    }
     if (storage == ST_F32) return box ? march_lookup_f32_box(mode, r, levels) : march_lookup_f32_star(mode, r, levels);
     if (storage == ST_BF16) return box ? march_lookup_bf16_box(mode, r, levels) : march_lookup_bf16_star(mode, r, levels);
     if (storage == ST_F16) return box ? march_lookup_f16_box(mode, r, levels) : march_lookup_f16_star(mode, r, levels);
@@ -57,10 +64,13 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     // 16-byte boundary (cols % V == 0 and aligned buffers; four 16-bit cells are 8 bytes, which the
     // same condition covers); else four columns per lane with element accesses (mode 0); vmax 1:
     // one column per lane, any width and alignment
+    // (periodic and framed grids have no eight-column kernels: they take four columns per lane)
+    const bool xbc = p->bc != ST_BC_CONST;
+    if (xbc && vmax == 8) vmax = 4;
     const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
     const int mode = vmax == 1 ? 1 : aligned && vmax == 8 && p->cols % 8 == 0 ? 8 : aligned && p->cols % 4 == 0 ? 4 : 0;
     const int V = mode == 8 ? 8 : mode == 1 ? 1 : 4;
-    MarchFn fn = march_lookup(p->storage, mode, p->shape, p->radius, levels);
+    MarchFn fn = march_lookup(p->storage, mode, p->shape, p->radius, levels, xbc);
     if (!fn) return fail(ST_EUNSUPPORTED, "no row-marching kernel for this shape/radius/depth");
     MarchArgs a;
     a.src = src;
@@ -68,6 +78,8 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     a.rows = p->rows;
     a.cols = p->cols;
     a.b = p->bq;
+    a.bc = p->bc;
+    a.frame = p->frame;
     std::memcpy(a.w, p->w, sizeof(a.w));
     const int64_t outw = V * (64 - 2 * march::halo_lanes(p->radius, levels, V));
     a.bands = int((p->cols + outw - 1) / outw);

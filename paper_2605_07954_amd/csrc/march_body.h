@@ -10,13 +10,58 @@
 namespace st {
 namespace march {
 
+// Boundary rules for the cells outside the grid.
+enum { BC_CONST = ST_BC_CONST, BC_PERIODIC = ST_BC_PERIODIC, BC_FRAME = ST_BC_FRAME };
+
 // What a task needs of its grid.
 struct MarchView {
     const void* src;
     void* dst;
     int64_t rows, cols;
-    float b;  // halo value, already rounded to the storage type
+    float b;            // halo value (BC_CONST), already rounded to the storage type
+    int bc;             // BC_CONST, BC_PERIODIC or BC_FRAME
+    const void* frame;  // BC_FRAME: the caller's halo frame, storage type (see frame_value)
 };
+
+// i reduced into [0, n) (a grid smaller than the halo may wrap more than once).
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+// The fixed value of the out-of-grid cell (gy, gx) from the caller's frame of depth R: top strip
+// R x (cols + 2R), bottom strip R x (cols + 2R), left strip rows x R, right strip rows x R, each
+// row-major, one after another.  Cells farther out feed only cells outside the grid, which take
+// their frame value again at every level, so they read 0.
+template <int S>
+__device__ __forceinline__ float frame_value(const MarchView& a, int R, int64_t gy, int64_t gx) {
+    const int64_t rows = a.rows, cols = a.cols;
+    if (gy < -R || gy >= rows + R || gx < -R || gx >= cols + R) return 0.0f;
+    const int64_t wf = cols + 2 * R;
+    int64_t k;
+    if (gy < 0) k = (gy + R) * wf + (gx + R);
+    else if (gy >= rows) k = int64_t(R) * wf + (gy - rows) * wf + (gx + R);
+    else if (gx < 0) k = 2 * int64_t(R) * wf + gy * R + (gx + R);
+    else k = 2 * int64_t(R) * wf + rows * R + gy * R + (gx - cols);
+    return Fmt<S>::ld(static_cast<const typename Fmt<S>::T*>(a.frame)[k]);
+}
+
+// Value that an out-of-grid cell holds at every level: b, or its frame value.  (Periodic grids
+// have none: their outside cells are loaded from, and computed like, the cells they wrap to.)
+// XBC: the kernel takes the boundary rule from the view; else it is the constant halo b, and the
+// kernel is built without the other rules (whose edge code would cost the constant-halo kernels
+// scalar registers).
+template <int S, bool XBC>
+__device__ __forceinline__ float outside_value(const MarchView& a, int R, int64_t gy, int64_t gx) {
+    if constexpr (XBC) return a.bc == BC_FRAME ? frame_value<S>(a, R, gy, gx) : a.b;
+    return a.b;
+}
+template <bool XBC>
+__device__ __forceinline__ bool periodic(const MarchView& a) {
+    if constexpr (XBC) return a.bc == BC_PERIODIC;
+    return false;
+}
 
 __host__ __device__ constexpr int halo_lanes(int R, int TB, int V) { return (R * TB + V - 1) / V; }
 
@@ -191,58 +236,69 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
 }
 
 // Input row gy as raw storage values, for the FIFO: EDGE tasks clamp row and columns into the grid
-// (the cells they stand for are replaced by b when the row is used, see `cells_of`); interior tasks
-// only clamp a prefetch past the grid's last row.
-template <int S, int V, bool VEC, bool EDGE>
-__device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const void* src, int64_t gy, int64_t rows, int64_t cols,
-                                                     int64_t gx, const ColMask<V>& m) {
-    int64_t g = gy < rows ? gy : rows - 1;
-    if (EDGE) g = g < 0 ? 0 : g;
+// (the cells they stand for are replaced by their outside value when the row is used, see
+// `cells_of`), or wrap them on a periodic grid; interior tasks only clamp a prefetch past the grid's
+// last row.  A lane's vector never straddles the grid's side (cols % V == 0, and so is its first
+// column), so it wraps whole.
+template <int S, int V, bool VEC, bool EDGE, bool XBC>
+__device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m) {
+    const int64_t rows = a.rows, cols = a.cols;
+    const bool wrap = EDGE && periodic<XBC>(a);
+    int64_t g;
+    if (wrap) {
+        g = wrap_index(gy, rows);
+    } else {
+        g = gy < rows ? gy : rows - 1;
+        if (EDGE) g = g < 0 ? 0 : g;
+    }
     if constexpr (VEC || V == 1) {
-        return load_raw<S, V>(src, g * cols + (EDGE && !m.ok[0] ? 0 : gx));
+        const int64_t x = wrap ? wrap_index(gx, cols) : (EDGE && !m.ok[0] ? 0 : gx);
+        return load_raw<S, V>(a.src, g * cols + x);
     } else {
         RawT<S, V, VEC> r;
-        const typename Fmt<S>::T* row = static_cast<const typename Fmt<S>::T*>(src) + g * cols;
+        const typename Fmt<S>::T* row = static_cast<const typename Fmt<S>::T*>(a.src) + g * cols;
 #pragma unroll
-        for (int c = 0; c < V; ++c) r.v[c] = row[EDGE && !m.ok[c] ? 0 : gx + c];
+        for (int c = 0; c < V; ++c) r.v[c] = row[wrap ? wrap_index(gx + c, cols) : (EDGE && !m.ok[c] ? 0 : gx + c)];
         return r;
     }
 }
 
-template <int S, int V, bool EDGE, typename RawRow>
-__device__ __forceinline__ Cells<V> cells_of(const RawRow& r, int64_t gy, int64_t rows, const ColMask<V>& m,
-                                             float b) {
+template <int S, int R, int V, bool EDGE, bool XBC, typename RawRow>
+__device__ __forceinline__ Cells<V> cells_of(const MarchView& a, const RawRow& r, int64_t gy, int64_t gx,
+                                             const ColMask<V>& m) {
     Cells<V> q = widen<S, V>(r);
-    if (EDGE) {
-        const bool row_ok = gy >= 0 && gy < rows;
+    if (EDGE && !periodic<XBC>(a)) {
+        const bool row_ok = gy >= 0 && gy < a.rows;
 #pragma unroll
-        for (int c = 0; c < V; ++c) q.c[c] = row_ok && m.ok[c] ? q.c[c] : b;
+        for (int c = 0; c < V; ++c) q.c[c] = row_ok && m.ok[c] ? q.c[c] : outside_value<S, XBC>(a, R, gy, gx + c);
     }
     return q;
 }
 
 // Input row gy loaded and widened at once (the ring rows and the one-row lead).  With vector
-// accesses EDGE tasks skip the load for cells outside the grid, which hold b; with element accesses
-// they load clamped addresses and substitute b.  Interior tasks only clamp a load past the grid's
-// last row.
-template <int S, int V, bool VEC, bool EDGE>
-__device__ __forceinline__ Cells<V> load_now(const void* src, int64_t gy, int64_t rows, int64_t cols, int64_t gx,
-                                             const ColMask<V>& m, float b) {
+// accesses EDGE tasks skip the load for cells outside the grid, which take their outside value (a
+// periodic grid loads the cells they wrap to); with element accesses they load clamped (or wrapped)
+// addresses and substitute.  Interior tasks only clamp a load past the grid's last row.
+template <int S, int R, int V, bool VEC, bool EDGE, bool XBC>
+__device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m) {
+    const int64_t rows = a.rows, cols = a.cols;
     if constexpr (VEC || V == 1) {
         Cells<V> q;
         if (EDGE) {
-            if (gy >= 0 && gy < rows && m.ok[0]) {
-                q = widen<S, V>(load_raw<S, V>(src, gy * cols + gx));
+            if (periodic<XBC>(a)) {
+                q = widen<S, V>(load_raw<S, V>(a.src, wrap_index(gy, rows) * cols + wrap_index(gx, cols)));
+            } else if (gy >= 0 && gy < rows && m.ok[0]) {
+                q = widen<S, V>(load_raw<S, V>(a.src, gy * cols + gx));
             } else {
 #pragma unroll
-                for (int c = 0; c < V; ++c) q.c[c] = b;
+                for (int c = 0; c < V; ++c) q.c[c] = outside_value<S, XBC>(a, R, gy, gx + c);
             }
         } else {
-            q = widen<S, V>(load_raw<S, V>(src, (gy < rows ? gy : rows - 1) * cols + gx));
+            q = widen<S, V>(load_raw<S, V>(a.src, (gy < rows ? gy : rows - 1) * cols + gx));
         }
         return q;
     } else {
-        return cells_of<S, V, EDGE>(fetch_raw<S, V, VEC, EDGE>(src, gy, rows, cols, gx, m), gy, rows, m, b);
+        return cells_of<S, R, V, EDGE, XBC>(a, fetch_raw<S, V, VEC, EDGE, XBC>(a, gy, gx, m), gy, gx, m);
     }
 }
 
@@ -296,7 +352,7 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 // Input rows are loaded D iterations before they enter the window, into a FIFO of D raw rows (D a
 // multiple of N; the loop is unrolled D times).  With D = 0 a row is loaded into the ring slot that
 // level 1 has just released, one iteration ahead.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC>
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                              int64_t X0) {
     constexpr int N = 2 * R + 1;
@@ -308,15 +364,14 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     const int64_t gx = X0 + V * lane;
     const ColMask<V> cm = col_mask<V, VEC>(gx, cols);
     const bool writer = lane >= H && lane < 64 - H && (!EDGE || cm.any);
-    const float b = a.b;
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
     RawT<S, V, VEC> fifo[D > 0 ? D : 1];
     const int64_t j0 = y0 - R * TB;  // input row j lives in ring slot (j - j0) % N, FIFO slot (j - j0) % D
-    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE>(a.src, j, rows, cols, gx, cm); };
+    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE, XBC>(a, j, gx, cm); };
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
     for (int t = 0; t < FIRST; ++t)
-        set_own<R, V>(lv[0][t], load_now<S, V, VEC, EDGE>(a.src, j0 + t, rows, cols, gx, cm, b));
+        set_own<R, V>(lv[0][t], load_now<S, R, V, VEC, EDGE, XBC>(a, j0 + t, gx, cm));
     if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
 #pragma unroll
         for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
@@ -335,7 +390,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
             if constexpr (D > 0) {
                 const int f = (u + 2 * R) % D;
                 const int64_t j = j0 + i + 2 * R;
-                set_own<R, V>(in, cells_of<S, V, EDGE>(fifo[f], j, rows, cm, b));
+                set_own<R, V>(in, cells_of<S, R, V, EDGE, XBC>(a, fifo[f], j, gx, cm));
                 fifo[f] = fetch(j + D);
             }
             if (SIDES) fill_sides<R, V>(in);
@@ -348,15 +403,22 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     if (writer) store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm);
                 } else {
                     Row<R, V>& x = lv[l][(u + l - 1) % N];
-                    // every level is rounded to the storage type; cells outside the grid keep b
-                    const bool row_in = !EDGE || (m >= 0 && m < rows);
+                    // every level is rounded to the storage type; cells outside the grid keep their
+                    // outside value (a periodic grid computes them like the cells they wrap to)
+                    if (EDGE && !periodic<XBC>(a)) {
+                        const bool row_in = m >= 0 && m < rows;
 #pragma unroll
-                    for (int c = 0; c < V; ++c) q.c[c] = row_in && (!EDGE || cm.ok[c]) ? Fmt<S>::rnd(q.c[c]) : b;
+                        for (int c = 0; c < V; ++c)
+                            q.c[c] = row_in && cm.ok[c] ? Fmt<S>::rnd(q.c[c]) : outside_value<S, XBC>(a, R, m, gx + c);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < V; ++c) q.c[c] = Fmt<S>::rnd(q.c[c]);
+                    }
                     set_own<R, V>(x, q);
                     if (SIDES) fill_sides<R, V>(x);
                 }
                 if (D == 0 && l == 1) {  // input row m1 - R is no longer needed: fetch the row N further down
-                    set_own<R, V>(lv[0][u % N], load_now<S, V, VEC, EDGE>(a.src, j0 + i + N, rows, cols, gx, cm, b));
+                    set_own<R, V>(lv[0][u % N], load_now<S, R, V, VEC, EDGE, XBC>(a, j0 + i + N, gx, cm));
                 }
             }
         }
@@ -381,15 +443,16 @@ __device__ __forceinline__ void load_weights(const float* w, float* wv) {
 }
 
 // One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels, input rows
-// loaded D iterations ahead (0: one); VEC selects vector or element accesses (see RawT).
-template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true>
+// loaded D iterations ahead (0: one); VEC selects vector or element accesses (see RawT); XBC: the
+// boundary rule comes from the view (periodic or framed grids), else the halo is the constant b.
+template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true, bool XBC = false>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                            int64_t X0) {
     const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 64 * V > a.cols;
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC>(a, wv, lane, y0, y1, X0);
-    else march_levels<S, R, V, SHAPE, TB, D, false, VEC>(a, wv, lane, y0, y1, X0);
+    if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0);
 }
 
 }  // namespace march

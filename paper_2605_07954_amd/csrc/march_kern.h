@@ -20,6 +20,8 @@ struct MarchArgs {
     int64_t seg;    // output rows per task
     int bands;
     float b;
+    int bc;             // boundary rule (march::BC_*)
+    const void* frame;  // BC_FRAME: the caller's halo frame
     float w[MAXK];
 };
 
@@ -30,7 +32,7 @@ constexpr int fifo_rows(int R, int SHAPE, int TB) {
     return SHAPE == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
 }
 
-template <int S, int R, int V, int SHAPE, int TB, bool VEC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
 __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -42,38 +44,38 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int64_t y0 = (task / a.bands) * a.seg;
     const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
     const int64_t X0 = band * OUTW - V * H;
-    const MarchView v{a.src, a.dst, a.rows, a.cols, a.b};
-    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC>(v, a.w, lane, y0, y1, X0);
+    const MarchView v{a.src, a.dst, a.rows, a.cols, a.b, a.bc, a.frame};
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, y0, y1, X0);
 }
 
-template <int S, int R, int V, int SHAPE, int TB, bool VEC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
 __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
-    sweep_march_body<S, R, V, SHAPE, TB, VEC>(a);
+    sweep_march_body<S, R, V, SHAPE, TB, VEC, XBC>(a);
 }
 
 // r = 3 with two levels and four columns per lane needs about 174 registers, just over the 168
 // that let three wavefronts share a SIMD; held to 168, the compiler keeps six values in scratch (one
 // access per 192 FMAs), and the third wavefront hides more load latency than that costs (measured
 // +2 % on box49).
-template <int S, int R, int V, int SHAPE, int TB, bool VEC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
 __global__ __launch_bounds__(64 * MWAVES) __attribute__((amdgpu_waves_per_eu(3))) void sweep_march_w3(MarchArgs a) {
-    sweep_march_body<S, R, V, SHAPE, TB, VEC>(a);
+    sweep_march_body<S, R, V, SHAPE, TB, VEC, XBC>(a);
 }
 
 using MarchFn = void (*)(MarchArgs);
 
-template <int S, int R, int V, int SH, int TB, bool VEC = true>
+template <int S, int R, int V, int SH, int TB, bool VEC = true, bool XBC = false>
 MarchFn march_kernel() {
-    if constexpr (V == 4 && R == 3 && TB == 2 && VEC) return sweep_march_w3<S, R, V, SH, TB, VEC>;
-    else return sweep_march<S, R, V, SH, TB, VEC>;
+    if constexpr (V == 4 && R == 3 && TB == 2 && VEC) return sweep_march_w3<S, R, V, SH, TB, VEC, XBC>;
+    else return sweep_march<S, R, V, SH, TB, VEC, XBC>;
 }
 
 // Depths per shape and radius: the rings of TB levels must fit the register file next to each
 // other (a star ring row holds V values, a box ring row V + 2r).
-template <int S, int V, int SH, bool VEC>
+template <int S, int V, int SH, bool VEC, bool XBC = false>
 MarchFn march_fn(int r, int levels) {
 #define ST_MARCH(R, TB) \
-    if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB, VEC>();
+    if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB, VEC, XBC>();
     if constexpr (SH == SHAPE_STAR) {
         ST_MARCH(1, 1) ST_MARCH(1, 2) ST_MARCH(1, 3) ST_MARCH(1, 4) ST_MARCH(1, 5) ST_MARCH(1, 6) ST_MARCH(1, 7) ST_MARCH(1, 8)
         ST_MARCH(2, 1) ST_MARCH(2, 2) ST_MARCH(2, 3) ST_MARCH(2, 4) ST_MARCH(2, 5) ST_MARCH(2, 6)
@@ -122,6 +124,16 @@ MarchFn march_lookup_shape(int mode, int r, int levels) {
     return march_fn<S, 4, SH, false>(r, levels);
 }
 
+// The same kernels built with the periodic and framed boundary rules in their edge tasks (four
+// columns per lane with vector or element accesses, or one; no eight-column form).
+template <int S, int SH>
+MarchFn march_lookup_shape_xbc(int mode, int r, int levels) {
+    if (mode == 4) return march_fn<S, 4, SH, true, true>(r, levels);
+    if (mode == 1) return march_fn<S, 1, SH, true, true>(r, levels);
+    if (mode == 0) return march_fn<S, 4, SH, false, true>(r, levels);
+    return nullptr;
+}
+
 }  // namespace march_k
 
 // Lookups per storage type and shape, one per translation unit.
@@ -131,5 +143,11 @@ march_k::MarchFn march_lookup_bf16_star(int mode, int r, int levels);
 march_k::MarchFn march_lookup_bf16_box(int mode, int r, int levels);
 march_k::MarchFn march_lookup_f16_star(int mode, int r, int levels);
 march_k::MarchFn march_lookup_f16_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_f32_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_f32_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_bf16_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_bf16_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_f16_star(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_f16_box(int mode, int r, int levels);
 
 }  // namespace st

@@ -1,0 +1,11 @@
+// Row-marching kernels with the periodic and framed boundary rules, BF16 storage, box footprints
+// (see march.hip).
+#include "march_kern.h"
+
+namespace st {
+
+march_k::MarchFn march_lookup_xbc_bf16_box(int mode, int r, int levels) {
+    return march_k::march_lookup_shape_xbc<ST_BF16, SHAPE_BOX>(mode, r, levels);
+}
+
+}  // namespace st

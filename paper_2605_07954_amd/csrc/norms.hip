@@ -173,6 +173,20 @@ extern "C" int stencil_norms(const st_plan* plan, const void* u_prev, const void
     double w[MAXK] = {};
     const int k = 2 * plan->radius + 1;
     for (int t = 0; t < k * k; ++t) w[t] = double(plan->w[t]);
+    if (plan->kind == KIND_3D) {
+        // the first three sums over all cells (rows taken as planes * rows); no next-step mass
+        a.rows = plan->planes * plan->rows;
+        a.wsum = std::nan("");
+        a.b = 0.0;
+    }
+    if (plan->bc == ST_BC_PERIODIC) {
+        // every cell keeps the whole weight sum on a torus: next mass = sum(W) * sum(u)
+        a.r = 0;
+        a.b = 0.0;
+    } else if (plan->bc == ST_BC_FRAME) {
+        a.wsum = std::nan("");  // depends on the frame: reported as NaN
+        a.b = 0.0;
+    }
     if (plan->kind == KIND_VARCOEF) {
         // the next-step mass of the varcoef update depends on kappa; report the first three only
         a.r = 1;

@@ -1,6 +1,9 @@
 // CNN surrogate of the variable-coefficient heat step: six 3x3 convolutions (zero "same"
 // padding), channels 2 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, bias everywhere, exact-erf GELU after
-// layers 1-5, residual output u_hat = u0 + f(u0, (kappa - 0.125) / 0.075).
+// layers 1-5, residual output u_hat = u0 + gain * f(u0 * inv, (kappa - 0.125) / 0.075), where
+// inv = fp32(1 / s) and gain = fp32(2^-11 s) come from the RMS s of the field (s = 1 for a zero
+// field): the network sees the field in units of its size and predicts the K-step update in
+// units of 2^-11 of it, so that its last layer works with values of order one.
 //
 //   layer 1 (2 -> 32)   FP32 MFMA (v_mfma_f32_16x16x4_f32), K = 9 taps x 2 inputs
 //   layers 2-5 (32->32) BF16 MFMA implicit GEMM (v_mfma_f32_16x16x32_bf16), FP32 accumulate:
@@ -43,6 +46,7 @@ constexpr int boff(int l) { return woff(l) + 9 * CI[l] * CO[l]; }
 static_assert(woff(NL) == SG_PARAM_COUNT, "parameter count");
 
 constexpr float KMID = 0.125f, KHALF = 0.075f;
+constexpr double UPDATE_SCALE = 1.0 / 2048.0;  // 2^-11: the unit of the predicted update, per unit of field RMS
 
 // bf16 <-> f32
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
@@ -331,19 +335,20 @@ __device__ __forceinline__ void input_fetch(const float* u0, const float* kappa,
     }
 }
 
-__device__ __forceinline__ void input_store(float* lds, const float2 (&r)[SPT1]) {
+__device__ __forceinline__ void input_store(float* lds, const float2 (&r)[SPT1], float inv) {
 #pragma unroll
     for (int j = 0; j < SPT1; ++j) {
         const int k = int(threadIdx.x) + 256 * j;
         if (k < TPIX) {
-            lds[2 * k] = r[j].x;
+            lds[2 * k] = r[j].x * inv;
             lds[2 * k + 1] = (r[j].y - KMID) / KHALF;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* u0, const float* kappa, int nb,
-                                              int H, int W, float* Z, uint16_t* A) {
+// scale: per field (inv, gain); the u0 channel enters as u0 * inv
+__global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* u0, const float* kappa,
+                                              const float* scale, int nb, int H, int W, float* Z, uint16_t* A) {
     __shared__ float patch[2][2 * TPIX];
     const int64_t ntiles = tile_count(nb, H, W);
     int64_t t = blockIdx.x;
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
     for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
         const Tile tc = tile_at(t, H, W);
         float* lds = patch[buf];
-        input_store(lds, pre);
+        input_store(lds, pre, scale[2 * tc.b]);
         __syncthreads();
         if (t + gridDim.x < ntiles) input_fetch(u0, kappa, tile_at(t + gridDim.x, H, W), H, W, pre);
         // accumulators start from the bias; K steps outermost so that consecutive MFMAs feed
@@ -429,8 +434,8 @@ __global__ __launch_bounds__(256) void l1_fwd(const float* params, const float* 
 // more loads in flight.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l6_fwd(
-    const float* params, const uint16_t* frag6, const uint16_t* A5, const float* u0, int nb, int H, int W,
-    float* uhat) {
+    const float* params, const uint16_t* frag6, const uint16_t* A5, const float* u0, const float* scale, int nb, int H,
+    int W, float* uhat) {
     __shared__ uint4 patch[PSLOTS];  // one buffer (two barriers per tile): three workgroups per CU
     const int64_t ntiles = tile_count(nb, H, W);
     int64_t t = blockIdx.x;
@@ -467,6 +472,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
                     acc[r][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[k], xv, acc[r][m], 0, 0, 0);
                 }
         if (lane < 16) {
+            const float gain = scale[2 * tc.b + 1];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 const int y = tc.y0 + wave * ROWS + r;
@@ -475,7 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
                     const int x = tc.x0 + m * 16 + lane_px;
                     if (y < H && x < W) {
                         const int64_t o = (int64_t(tc.b) * H + y) * W + x;
-                        uhat[o] = u0[o] + (acc[r][m][0] + acc[r][m][1]);
+                        uhat[o] = __builtin_fmaf(gain, acc[r][m][0] + acc[r][m][1], u0[o]);
                     }
                 }
             }
@@ -488,9 +494,10 @@ struct MaskArgs {
     int lohi[4 * MAXB];  // per sample: rows [lohi[0], lohi[1]) x cols [lohi[2], lohi[3])
 };
 
-// dF = (2/n) (u_hat - target) on the mask; per-block FP64 partial sums of the squared error
-__global__ __launch_bounds__(256) void loss_grad(const float* uhat, const float* target, int nb, int H, int W,
-                                                 MaskArgs mk, double inv_n, float* dF, double* partial) {
+// dF = d loss / d f = (2/n) gain (u_hat - target) on the mask; per-block FP64 partial sums of the
+// squared error
+__global__ __launch_bounds__(256) void loss_grad(const float* uhat, const float* target, const float* scale, int nb,
+                                                 int H, int W, MaskArgs mk, double inv_n, float* dF, double* partial) {
     __shared__ double red[256];
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
     double e2 = 0.0;
@@ -500,7 +507,7 @@ __global__ __launch_bounds__(256) void loss_grad(const float* uhat, const float*
         const int* m = mk.lohi + 4 * b;
         const bool in = y >= m[0] && y < m[1] && x >= m[2] && x < m[3];
         const float d = in ? uhat[p] - target[p] : 0.0f;
-        dF[p] = float(2.0 * inv_n) * d;
+        dF[p] = float(2.0 * inv_n * double(scale[2 * b + 1])) * d;
         e2 = double(d) * double(d);
     }
     red[threadIdx.x] = e2;
@@ -562,8 +569,8 @@ constexpr int RH = 32, RW = 32;  // pixels per partial block
 
 // layer 1: dW1[t][ci][co] = sum_p X0[p + t][ci] dZ1[p][co], db1[co] = sum_p dZ1[p][co]  (all FP32)
 // one thread per (t, ci, co) output (576) plus 32 bias threads; loops over the region's pixels.
-__global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const float* kappa, const float* dZ1, int nb,
-                                                     int H, int W, float* partial) {
+__global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const float* kappa, const float* scale,
+                                                     const float* dZ1, int nb, int H, int W, float* partial) {
     const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
     const int blk = blockIdx.x;
     const int b = blk / (rx * ry), r = blk % (rx * ry);
@@ -571,6 +578,7 @@ __global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const floa
     const int j = threadIdx.x;
     if (j >= 9 * 2 * C + C) return;
     float acc = 0.0f;
+    const float inv = scale[2 * b];
     if (j < 9 * 2 * C) {
         const int t = j / (2 * C), ci = (j / C) % 2, co = j % C;
         const int dy = t / 3 - 1, dx = t % 3 - 1;
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const floa
                 const int yy = y + dy, xx = x + dx;
                 if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
                 const int64_t q = (int64_t(b) * H + yy) * W + xx;
-                const float xin = ci == 0 ? u0[q] : (kappa[q] - KMID) / KHALF;
+                const float xin = ci == 0 ? u0[q] * inv : (kappa[q] - KMID) / KHALF;
                 acc = __builtin_fmaf(xin, dZ1[((int64_t(b) * H + y) * W + x) * C + co], acc);
             }
     } else {
@@ -842,11 +850,179 @@ __global__ void diff_norms_finish(const double* partial, int nblk, double* out2)
     out2[1] = s1;
 }
 
+// Scale constants of each field: s = RMS of the field's cells (FP64, fixed-order two-stage sum;
+// s = 1 for an all-zero field), scale[2b] = fp32(1 / s), scale[2b + 1] = fp32(2^-11 s).
+constexpr int SCB = 64;  // stage-1 blocks per field
+__global__ __launch_bounds__(256) void field_scale_partial(const float* u, int64_t n, double* partial) {
+    __shared__ double red[256];
+    const int b = blockIdx.y;
+    const float* f = u + int64_t(b) * n;
+    double acc = 0.0;
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(SCB) * 256) {
+        const double x = double(f[k]);
+        acc += x * x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[int64_t(b) * SCB + blockIdx.x] = red[0];
+}
+
+__global__ void field_scale_finish(const double* partial, int nb, int64_t n, float* scale) {
+    const int b = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double acc = 0.0;
+    for (int k = 0; k < SCB; ++k) acc += partial[int64_t(b) * SCB + k];
+    double s = sqrt(acc / double(n));
+    if (!(s > 0.0)) s = 1.0;
+    scale[2 * b] = float(1.0 / s);
+    scale[2 * b + 1] = float(UPDATE_SCALE * s);
+}
+
+// ---- the light-cone patch judge -------------------------------------------------------------
+// An n x n lattice of patches; window (a, c) = patch (a, c) dilated by K cells and clipped to the
+// grid.  The windows are packed edge to edge into a "mosaic" field in lattice order, so that the
+// mosaic's outer edges are the grid's edges wherever a window touches them; K plain steps on the
+// mosaic are exact on every patch (a wrong neighbour across an inner junction moves one cell per
+// step and stays K or more cells away from the patch).
+constexpr int PLAT = 4;    // lattice points per axis
+constexpr int PSIDE = 64;  // patch side (capped by the grid)
+struct MosaicArgs {
+    int n;                                  // lattice points per axis
+    int py, px;                             // patch side in rows / columns
+    int y[PLAT], x[PLAT];                   // patch origins in the grid
+    int wy[PLAT], wx[PLAT];                 // window origins in the grid
+    int my[PLAT + 1], mx[PLAT + 1];         // window origins in the mosaic (prefix sums)
+    int rows, cols;                         // grid
+};
+
+__device__ __forceinline__ int lattice_of(const int* m, int n, int v) {
+    int a = 0;
+    while (a + 1 < n && v >= m[a + 1]) ++a;
+    return a;
+}
+
+// mosaic cell -> grid cell copy of u0 and kappa
+__global__ __launch_bounds__(256) void gather_mosaic(const float* u0, const float* kappa, MosaicArgs g, float* mu,
+                                                     float* mk) {
+    const int MR = g.my[g.n], MC = g.mx[g.n];
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(MR) * MC) return;
+    const int i = int(idx / MC), j = int(idx % MC);
+    const int a = lattice_of(g.my, g.n, i), c = lattice_of(g.mx, g.n, j);
+    const int64_t q = int64_t(g.wy[a] + (i - g.my[a])) * g.cols + (g.wx[c] + (j - g.mx[c]));
+    mu[idx] = u0[q];
+    mk[idx] = kappa[q];
+}
+
+// FP64 sums over the patch cells of (u_hat - judge)^2 and judge^2: one block per patch, fixed order
+__global__ __launch_bounds__(256) void patch_norms(const float* uhat, const float* mjudge, MosaicArgs g,
+                                                   double* partial) {
+    __shared__ double r0[256], r1[256];
+    const int a = blockIdx.x / g.n, c = blockIdx.x % g.n;
+    const int MC = g.mx[g.n];
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = threadIdx.x; k < g.py * g.px; k += 256) {
+        const int dy = k / g.px, dx = k % g.px;
+        const int gy = g.y[a] + dy, gx = g.x[c] + dx;
+        const double v = double(mjudge[int64_t(g.my[a] + gy - g.wy[a]) * MC + (g.mx[c] + gx - g.wx[c])]);
+        const double d = double(uhat[int64_t(gy) * g.cols + gx]) - v;
+        s0 += d * d;
+        s1 += v * v;
+    }
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            r0[threadIdx.x] += r0[threadIdx.x + h];
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = r0[0];
+        partial[2 * blockIdx.x + 1] = r1[0];
+    }
+}
+
+// ---- seeded initialisation ------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two 64 x 64 -> 128-bit
+// products of words 0 and 2, whose halves are mixed with words 1 and 3 and the key; the key is
+// bumped by two Weyl constants per round.
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// He-normal weights N(0, 2 / (9 C_in)) (layer 6 scaled by 0.1), zero biases, zero Adam state.
+// Parameter i draws the first two words of Philox4x64-10 at counter (i, 0, 0, 0), key (seed, 0),
+// u = (word >> 11) 2^-53, and takes the Box-Muller normal sqrt(-2 ln(1 - u1)) cos(2 pi u2) in FP64.
+__global__ __launch_bounds__(256) void init_params_kernel(float* params, float* optim, uint64_t seed) {
+    const int i = int(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= SG_PARAM_COUNT) return;
+    if (optim) {
+        optim[i] = 0.0f;
+        optim[SG_PARAM_COUNT + i] = 0.0f;
+    }
+    int l = 0;
+    while (i >= woff(l + 1)) ++l;
+    if (i >= boff(l)) {
+        params[i] = 0.0f;
+        return;
+    }
+    uint64_t c[4] = {uint64_t(i), 0, 0, 0};
+    philox4x64_10(c, seed, 0);
+    const double u1 = double(c[0] >> 11) * 0x1p-53, u2 = double(c[1] >> 11) * 0x1p-53;
+    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+    const double sd = sqrt(2.0 / (9.0 * CI[l])) * (l == NL - 1 ? 0.1 : 1.0);
+    params[i] = float(sd * z);
+}
+
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Lattice, windows and mosaic of the patch judge for a rows x cols grid and K steps.
+MosaicArgs mosaic_layout(int64_t rows, int64_t cols, int64_t K) {
+    MosaicArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.n = PLAT;
+    g.rows = int(rows);
+    g.cols = int(cols);
+    g.py = int(std::min<int64_t>(PSIDE, rows));
+    g.px = int(std::min<int64_t>(PSIDE, cols));
+    g.my[0] = g.mx[0] = 0;
+    for (int a = 0; a < PLAT; ++a) {
+        // patch origins spread evenly, the first at the top/left edge and the last at the bottom/right
+        g.y[a] = int(((rows - g.py) * a + (PLAT - 1) / 2) / (PLAT - 1));
+        g.x[a] = int(((cols - g.px) * a + (PLAT - 1) / 2) / (PLAT - 1));
+        const int64_t y0 = std::max<int64_t>(0, g.y[a] - K), y1 = std::min<int64_t>(rows, g.y[a] + g.py + K);
+        const int64_t x0 = std::max<int64_t>(0, g.x[a] - K), x1 = std::min<int64_t>(cols, g.x[a] + g.px + K);
+        g.wy[a] = int(y0);
+        g.wx[a] = int(x0);
+        g.my[a + 1] = int(g.my[a] + (y1 - y0));
+        g.mx[a + 1] = int(g.mx[a] + (x1 - x0));
+    }
+    return g;
+}
 
 // workspace layout for a batch of nb fields of H x W
 struct WsLayout {
-    size_t frags, act[5], z[5], dzb[2], dz1, dF, partial, lossp, total;
+    size_t frags, scale, scalep, act[5], z[5], dzb[2], dz1, dF, partial, lossp, total;
     int64_t npix;
     int nblk_px, nblk_rg;
 };
@@ -859,6 +1035,10 @@ WsLayout layout(int nb, int64_t H, int64_t W, bool train) {
     size_t off = 0;
     L.frags = off;
     off = a256(off + size_t(NFRAG) * 2);
+    L.scale = off;
+    off = a256(off + size_t(nb) * 2 * 4);
+    L.scalep = off;
+    off = a256(off + size_t(nb) * SCB * 8);
     const size_t actb = size_t(L.npix) * C * 2, zb = size_t(L.npix) * C * 4;
     for (int l = 0; l < 5; ++l) {
         if (train || l < 2) {
@@ -919,8 +1099,19 @@ int launch_conv(const ConvArgs& a, hipStream_t s) {
     return ST_OK;
 }
 
-int forward_impl(const float* params, const float* u0, const float* kappa, float* uhat, int nb, int H, int W,
-                 char* ws, const WsLayout& L, bool train, hipStream_t s) {
+// The scale constants of nb fields of H x W (see field_scale_finish) into `scale`.
+int compute_scale(const float* u0, int nb, int H, int W, double* partial, float* scale, hipStream_t s) {
+    clear_stale_error();
+    hipLaunchKernelGGL(field_scale_partial, dim3(SCB, nb), dim3(256), 0, s, u0, int64_t(H) * W, partial);
+    ST_LAUNCH_CHECK("field_scale_partial");
+    hipLaunchKernelGGL(field_scale_finish, dim3((nb + 63) / 64), dim3(64), 0, s, partial, nb, int64_t(H) * W, scale);
+    ST_LAUNCH_CHECK("field_scale_finish");
+    return ST_OK;
+}
+
+// Forward pass; `scale` holds the (inv, gain) pair of each field (device).
+int forward_impl(const float* params, const float* u0, const float* kappa, const float* scale, float* uhat, int nb,
+                 int H, int W, char* ws, const WsLayout& L, bool train, hipStream_t s) {
     uint16_t* frags = reinterpret_cast<uint16_t*>(ws + L.frags);
     clear_stale_error();
     hipLaunchKernelGGL(prep_frags, dim3((NFRAG + 255) / 256), dim3(256), 0, s, params, frags);
@@ -929,7 +1120,7 @@ int forward_impl(const float* params, const float* u0, const float* kappa, float
     auto zz = [&](int l) { return train ? reinterpret_cast<float*>(ws + L.z[l]) : nullptr; };
     unsigned g1 = 0;
     if (int rc = tile_grid(reinterpret_cast<const void*>(l1_fwd), nb, H, W, &g1)) return rc;
-    hipLaunchKernelGGL(l1_fwd, dim3(g1), dim3(256), 0, s, params, u0, kappa, nb, H, W, zz(0), act(0));
+    hipLaunchKernelGGL(l1_fwd, dim3(g1), dim3(256), 0, s, params, u0, kappa, scale, nb, H, W, zz(0), act(0));
     ST_LAUNCH_CHECK("l1_fwd");
     for (int l = 1; l <= 4; ++l) {
         ConvArgs a;
@@ -947,7 +1138,8 @@ int forward_impl(const float* params, const float* u0, const float* kappa, float
     }
     unsigned g6 = 0;
     if (int rc = tile_grid(reinterpret_cast<const void*>(l6_fwd), nb, H, W, &g6)) return rc;
-    hipLaunchKernelGGL(l6_fwd, dim3(g6), dim3(256), 0, s, params, frags + 4 * 2 * FRAG, act(4), u0, nb, H, W, uhat);
+    hipLaunchKernelGGL(l6_fwd, dim3(g6), dim3(256), 0, s, params, frags + 4 * 2 * FRAG, act(4), u0, scale, nb, H, W,
+                       uhat);
     ST_LAUNCH_CHECK("l6_fwd");
     return ST_OK;
 }
@@ -979,6 +1171,22 @@ int surrogate_destroy(sg_model* m) {
     return ST_OK;
 }
 
+int surrogate_param_bytes(const sg_model* m, size_t* params, size_t* optim_state) {
+    if (!m) return fail(ST_EINVAL, "model is NULL");
+    if (params) *params = size_t(SG_PARAM_COUNT) * sizeof(float);
+    if (optim_state) *optim_state = size_t(2) * SG_PARAM_COUNT * sizeof(float);
+    return ST_OK;
+}
+
+int surrogate_init(sg_model* m, float* params, float* optim_state, uint64_t seed, void* stream) {
+    if (!m || !params) return fail(ST_EINVAL, "NULL argument");
+    clear_stale_error();
+    hipLaunchKernelGGL(init_params_kernel, dim3((SG_PARAM_COUNT + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), params, optim_state, seed);
+    ST_LAUNCH_CHECK("init_params");
+    return ST_OK;
+}
+
 int surrogate_workspace_bytes(const sg_model* m, int batch, int64_t rows, int64_t cols, size_t* bytes) {
     if (!m || !bytes) return fail(ST_EINVAL, "NULL argument");
     if (int rc = check_dims(batch, rows, cols)) return rc;
@@ -992,14 +1200,19 @@ int surrogate_infer(sg_model* m, const float* params, const float* u0, const flo
     if (int rc = check_dims(batch, rows, cols)) return rc;
     const WsLayout L = layout(batch, rows, cols, false);
     if (!workspace || ws_bytes < L.total) return fail(ST_ENOWS, "workspace too small");
-    return forward_impl(params, u0, kappa, u_hat, batch, int(rows), int(cols), static_cast<char*>(workspace), L, false,
-                        static_cast<hipStream_t>(stream));
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* scale = reinterpret_cast<float*>(ws + L.scale);
+    if (int rc = compute_scale(u0, batch, int(rows), int(cols), reinterpret_cast<double*>(ws + L.scalep), scale, s))
+        return rc;
+    return forward_impl(params, u0, kappa, scale, u_hat, batch, int(rows), int(cols), ws, L, false, s);
 }
 
-int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa, const float* target,
-                        const int* lo_hi, int batch, int64_t rows, int64_t cols, float* grad, double* loss,
-                        void* workspace, size_t ws_bytes, void* stream) {
-    if (!m || !params || !u0 || !kappa || !target || !lo_hi || !grad || !loss) return fail(ST_EINVAL, "NULL argument");
+// Loss and gradient; `scale_in` = the (inv, gain) pair of each field (device), or NULL to take them
+// from the fields given (their own RMS).
+static int loss_grad_impl(const float* params, const float* u0, const float* kappa, const float* scale_in,
+                          const float* target, const int* lo_hi, int batch, int64_t rows, int64_t cols, float* grad,
+                          double* loss, void* workspace, size_t ws_bytes, void* stream) {
     if (int rc = check_dims(batch, rows, cols)) return rc;
     if (batch > MAXB) return fail(ST_EINVAL, "training batch larger than 64");
     MaskArgs mk;
@@ -1020,12 +1233,18 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
     char* ws = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int H = int(rows), W = int(cols), nb = batch;
+    const float* scale = scale_in;
+    if (!scale) {
+        float* sc = reinterpret_cast<float*>(ws + L.scale);
+        if (int rc = compute_scale(u0, nb, H, W, reinterpret_cast<double*>(ws + L.scalep), sc, s)) return rc;
+        scale = sc;
+    }
     float* uhat = reinterpret_cast<float*>(ws + L.dz1);  // scratch: dz1 is not needed until layer-2 backward
-    if (int rc = forward_impl(params, u0, kappa, uhat, nb, H, W, ws, L, true, s)) return rc;
+    if (int rc = forward_impl(params, u0, kappa, scale, uhat, nb, H, W, ws, L, true, s)) return rc;
     float* dF = reinterpret_cast<float*>(ws + L.dF);
     double* lossp = reinterpret_cast<double*>(ws + L.lossp);
     const unsigned gpx = unsigned(L.nblk_px);
-    hipLaunchKernelGGL(loss_grad, dim3(gpx), dim3(256), 0, s, uhat, target, nb, H, W, mk, 1.0 / n, dF, lossp);
+    hipLaunchKernelGGL(loss_grad, dim3(gpx), dim3(256), 0, s, uhat, target, scale, nb, H, W, mk, 1.0 / n, dF, lossp);
     ST_LAUNCH_CHECK("loss_grad");
     hipLaunchKernelGGL(loss_finish, dim3(1), dim3(256), 0, s, lossp, L.nblk_px, 1.0 / n, loss);
     ST_LAUNCH_CHECK("loss_finish");
@@ -1067,12 +1286,29 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
         cur ^= 1;
     }
     // layer 1
-    hipLaunchKernelGGL(l1_bwd_weight, dim3(grg), dim3(640), 0, s, u0, kappa, dz1, nb, H, W, partial);
+    hipLaunchKernelGGL(l1_bwd_weight, dim3(grg), dim3(640), 0, s, u0, kappa, scale, dz1, nb, H, W, partial);
     ST_LAUNCH_CHECK("l1_bwd_weight");
     hipLaunchKernelGGL(reduce_partials, dim3((9 * 2 * C + C + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg,
                        9 * 2 * C + C, grad + woff(0));
     ST_LAUNCH_CHECK("reduce l1");
     return ST_OK;
+}
+
+int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const float* kappa, const float* scale,
+                        const float* target, const int* lo_hi, int batch, int64_t rows, int64_t cols, float* grad,
+                        double* loss, void* workspace, size_t ws_bytes, void* stream) {
+    if (!m || !params || !u0 || !kappa || !target || !lo_hi || !grad || !loss) return fail(ST_EINVAL, "NULL argument");
+    return loss_grad_impl(params, u0, kappa, scale, target, lo_hi, batch, rows, cols, grad, loss, workspace, ws_bytes,
+                          stream);
+}
+
+int surrogate_field_scale(const float* u0, int n, int64_t rows, int64_t cols, float* scale, void* workspace,
+                          size_t ws_bytes, void* stream) {
+    if (!u0 || !scale) return fail(ST_EINVAL, "NULL argument");
+    if (int rc = check_dims(n, rows, cols)) return rc;
+    if (!workspace || ws_bytes < size_t(n) * SCB * sizeof(double)) return fail(ST_ENOWS, "workspace too small");
+    return compute_scale(u0, n, int(rows), int(cols), static_cast<double*>(workspace), scale,
+                         static_cast<hipStream_t>(stream));
 }
 
 int surrogate_adam(sg_model* m, float* params, const float* grad, float* optim, int t, float lr, float beta1,
@@ -1128,7 +1364,7 @@ constexpr int COEF_ROW = 4 * (16 + 8);  // floats per trajectory's coefficient r
 constexpr int RFIELD = 6;               // receptive-field radius of six 3x3 layers
 
 struct TrainWs {
-    size_t u0, kp, uk, cu0, ckp, cuk, grad, jws, yx, sg, total;
+    size_t u0, kp, uk, cu0, ckp, cuk, grad, jws, yx, scale, scalep, sg, total;
     size_t field, crop, jws_bytes;
 };
 
@@ -1154,6 +1390,8 @@ int train_layout(const sg_train_cfg* c, TrainWs* T) {
     T->grad = off; off += a256(size_t(SG_PARAM_COUNT) * 4);
     T->jws = off; off += T->jws_bytes;
     T->yx = off; off += a256(size_t(std::max<int64_t>(c->steps, 1) * B) * 8);
+    T->scale = off; off += a256(size_t(B) * 2 * 4);
+    T->scalep = off; off += a256(size_t(B) * SCB * 8);
     T->sg = off; off += layout(c->batch, c->crop, c->crop, true).total;
     T->total = off;
     return ST_OK;
@@ -1210,6 +1448,10 @@ int surrogate_train(sg_model* m, float* params, float* optim, const float* coef,
             rc = stencil_run_varcoef(judge, U0 + b * field, KP + b * field, UK + b * field, c.K, ws + T.jws,
                                      T.jws_bytes, stream);
         if (rc) break;
+        // the network's scale constants come from the whole trajectory field, as at inference
+        float* scale = reinterpret_cast<float*>(ws + T.scale);
+        if ((rc = compute_scale(U0, B, int(c.rows), int(c.cols), reinterpret_cast<double*>(ws + T.scalep), scale, s)))
+            break;
         const int* yx_s = yx + 2 * st * B;
         if ((rc = surrogate_crop(U0, cu0, yx_s, B, c.rows, c.cols, c.crop, c.crop, stream))) break;
         if ((rc = surrogate_crop(KP, ckp, yx_s, B, c.rows, c.cols, c.crop, c.crop, stream))) break;
@@ -1222,8 +1464,8 @@ int surrogate_train(sg_model* m, float* params, float* optim, const float* coef,
             lohi[4 * b + 2] = x > 0 ? RFIELD : 0;
             lohi[4 * b + 3] = int(c.crop) - (x + c.crop < c.cols ? RFIELD : 0);
         }
-        if ((rc = surrogate_loss_grad(m, params, cu0, ckp, cuk, lohi, B, c.crop, c.crop, grad, losses + st, ws + T.sg,
-                                      ws_bytes - T.sg, stream)))
+        if ((rc = loss_grad_impl(params, cu0, ckp, scale, cuk, lohi, B, c.crop, c.crop, grad, losses + st, ws + T.sg,
+                                 ws_bytes - T.sg, stream)))
             break;
         const int64_t g = c.step0 + st;
         const double lr = double(c.lr) * 0.5 * (1.0 + std::cos(3.14159265358979323846 * double(g) / double(c.total_steps)));
@@ -1235,13 +1477,14 @@ int surrogate_train(sg_model* m, float* params, float* optim, const float* coef,
 }
 
 int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, const float* kappa, float* out,
-                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol, int* used_fallback,
-                            double* rel_err, void* workspace, size_t ws_bytes, void* stream) {
+                            int64_t rows, int64_t cols, st_plan* judge, int64_t K, double tol, int judge_mode,
+                            int* used_fallback, double* rel_err, void* workspace, size_t ws_bytes, void* stream) {
     if (!m || !params || !u0 || !kappa || !out || !judge || !used_fallback || !rel_err)
         return fail(ST_EINVAL, "NULL argument");
     if (judge->kind != KIND_VARCOEF || judge->rows != rows || judge->cols != cols)
         return fail(ST_EINVAL, "judge must be a varcoef plan of the same shape");
     if (K < 0 || !(tol >= 0.0)) return fail(ST_EINVAL, "bad K or tol");
+    if (judge_mode != SG_JUDGE_FULL && judge_mode != SG_JUDGE_PATCH) return fail(ST_EINVAL, "unknown judge mode");
     size_t need = 0;
     if (int rc = surrogate_checked_ws_bytes(m, rows, cols, &need)) return rc;
     if (!workspace || ws_bytes < need) return fail(ST_ENOWS, "workspace too small");
@@ -1250,27 +1493,66 @@ int surrogate_infer_checked(sg_model* m, const float* params, const float* u0, c
     const WsLayout L = layout(1, rows, cols, false);
     const size_t field = a256(size_t(rows * cols) * 4);
     float* uhat = reinterpret_cast<float*>(ws + L.total);
-    float* uk = reinterpret_cast<float*>(ws + L.total + field);
-    float* jws = reinterpret_cast<float*>(ws + L.total + 2 * field);
+    float* b1 = reinterpret_cast<float*>(ws + L.total + field);
+    float* b2 = reinterpret_cast<float*>(ws + L.total + 2 * field);
     double* part = reinterpret_cast<double*>(ws + L.total + 3 * field);
     double* sums = reinterpret_cast<double*>(ws + L.total + 3 * field + a256(1024 * 16));
-    if (int rc = forward_impl(params, u0, kappa, uhat, 1, int(rows), int(cols), ws, L, false, s)) return rc;
-    // the judge: K plain steps of the stencil
-    if (int rc = stencil_run_varcoef(judge, u0, kappa, uk, K, jws, field, stream)) return rc;
+    float* scale = reinterpret_cast<float*>(ws + L.scale);
+    if (int rc = compute_scale(u0, 1, int(rows), int(cols), reinterpret_cast<double*>(ws + L.scalep), scale, s))
+        return rc;
+    if (int rc = forward_impl(params, u0, kappa, scale, uhat, 1, int(rows), int(cols), ws, L, false, s)) return rc;
     const int64_t n = rows * cols;
-    const int nblk = int(std::min<int64_t>(1024, (n + 255) / 256));
-    hipLaunchKernelGGL(diff_norms, dim3(nblk), dim3(256), 0, s, uhat, uk, n, part);
-    ST_LAUNCH_CHECK("diff_norms");
-    hipLaunchKernelGGL(diff_norms_finish, dim3(1), dim3(64), 0, s, part, nblk, sums);
-    ST_LAUNCH_CHECK("diff_norms_finish");
+    // the patch judge needs its four mosaic fields in the two spare fields (else judge the whole field)
+    const MosaicArgs g = mosaic_layout(rows, cols, K);
+    const int64_t mcells = int64_t(g.my[g.n]) * g.mx[g.n];
+    const bool patch = judge_mode == SG_JUDGE_PATCH && 2 * a256(size_t(mcells) * 4) <= field;
+    bool full_done = false;
+    if (patch) {
+        const size_t mf = a256(size_t(mcells) * 4);
+        float* mu = b1;
+        float* mk = reinterpret_cast<float*>(reinterpret_cast<char*>(b1) + mf);
+        float* mo = b2;
+        float* mw = reinterpret_cast<float*>(reinterpret_cast<char*>(b2) + mf);
+        clear_stale_error();
+        hipLaunchKernelGGL(gather_mosaic, dim3(unsigned((mcells + 255) / 256)), dim3(256), 0, s, u0, kappa, g, mu, mk);
+        ST_LAUNCH_CHECK("gather_mosaic");
+        st_plan* mp = nullptr;
+        if (int rc = stencil_plan_varcoef(&mp, g.my[g.n], g.mx[g.n], judge->b, 0)) return rc;
+        int tb = judge->tb, tx = judge->tile_x, ty = judge->tile_y;
+        while (tb > 1 && stencil_set_blocking(mp, tb, tx, ty) != ST_OK) --tb;
+        int rc = stencil_run_varcoef(mp, mu, mk, mo, K, mw, mf, stream);
+        stencil_destroy(mp);  // host-side only: the enqueued kernels keep their arguments
+        if (rc) return rc;
+        hipLaunchKernelGGL(patch_norms, dim3(g.n * g.n), dim3(256), 0, s, uhat, mo, g, part);
+        ST_LAUNCH_CHECK("patch_norms");
+        hipLaunchKernelGGL(diff_norms_finish, dim3(1), dim3(64), 0, s, part, g.n * g.n, sums);
+        ST_LAUNCH_CHECK("diff_norms_finish");
+    } else {
+        // the whole field: K plain steps
+        if (int rc = stencil_run_varcoef(judge, u0, kappa, b1, K, b2, field, stream)) return rc;
+        full_done = true;
+        const int nblk = int(std::min<int64_t>(1024, (n + 255) / 256));
+        clear_stale_error();
+        hipLaunchKernelGGL(diff_norms, dim3(nblk), dim3(256), 0, s, uhat, b1, n, part);
+        ST_LAUNCH_CHECK("diff_norms");
+        hipLaunchKernelGGL(diff_norms_finish, dim3(1), dim3(64), 0, s, part, nblk, sums);
+        ST_LAUNCH_CHECK("diff_norms_finish");
+    }
     double h[2] = {0, 0};
     ST_HIP_CHECK(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
     ST_HIP_CHECK(hipStreamSynchronize(s));
-    const double rel = h[1] > 1e-60 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0] / double(n));
+    const int64_t judged = patch ? int64_t(g.n) * g.n * g.py * g.px : n;
+    const double rel = h[1] > 1e-60 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0] / double(judged));
     *rel_err = rel;
     const bool fallback = !(rel <= tol);
     *used_fallback = fallback ? 1 : 0;
-    ST_HIP_CHECK(hipMemcpyAsync(out, fallback ? uk : uhat, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    if (!fallback) {
+        ST_HIP_CHECK(hipMemcpyAsync(out, uhat, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    } else if (full_done) {
+        ST_HIP_CHECK(hipMemcpyAsync(out, b1, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    } else {
+        if (int rc = stencil_run_varcoef(judge, u0, kappa, out, K, b1, field, stream)) return rc;
+    }
     return ST_OK;
 }
 

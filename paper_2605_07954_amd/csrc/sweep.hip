@@ -361,6 +361,7 @@ int supported_tiles(int* xy, int cap) {
 int max_tb(const st_plan* p, int tx, int ty) {
     int tb = 1;
     if (is_march(p->variant)) return march_max_tb(p->shape, p->radius, march_vmax(p->variant));
+    if (p->variant == VARIANT_RESIDENT) return std::max(1, std::min(64, resident_max_tb(p)));
     if (p->variant == VARIANT_STREAM) {
         while (tb < 16 && stream_lds_bytes(p->radius, tb + 1, tx, ty) <= lds_limit()) ++tb;
     } else {

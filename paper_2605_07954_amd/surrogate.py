@@ -24,26 +24,9 @@ import time
 
 import numpy as np
 
-from . import (SG_PARAM_COUNT, stencil_destroy, stencil_plan_varcoef, stencil_set_blocking, surrogate_checked_ws_bytes,
-               surrogate_create, surrogate_destroy, surrogate_infer_checked, surrogate_synth_fields, surrogate_train,
-               surrogate_train_ws_bytes)
-
-CHANNELS = (2, 32, 32, 32, 32, 32, 1)
-
-
-def init_params(seed: int) -> np.ndarray:
-    """He-normal weights N(0, 2 / (9 C_in)) in the library layout ([ky][kx][ci][co] then bias), zero
-    biases; the last layer is scaled by 0.1 so the untrained surrogate starts near u_hat = u0."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for l in range(6):
-        ci, co = CHANNELS[l], CHANNELS[l + 1]
-        std = math.sqrt(2.0 / (9 * ci)) * (0.1 if l == 5 else 1.0)
-        out.append(rng.normal(0.0, std, size=(3, 3, ci, co)).reshape(-1))
-        out.append(np.zeros(co))
-    v = np.concatenate(out).astype(np.float32)
-    assert v.size == SG_PARAM_COUNT
-    return v
+from . import (SG_JUDGE_FULL, SG_PARAM_COUNT, stencil_destroy, stencil_plan_varcoef, stencil_set_blocking,
+               surrogate_checked_ws_bytes, surrogate_create, surrogate_destroy, surrogate_infer_checked,
+               surrogate_init, surrogate_synth_fields, surrogate_train, surrogate_train_ws_bytes)
 
 
 class Trainer:
@@ -54,8 +37,9 @@ class Trainer:
         self.grid, self.crop, self.batch, self.K, self.seed, self.chunk = grid, crop, batch, K, seed, chunk
         self.dev = device
         self.model = surrogate_create()
-        self.params = torch.from_numpy(init_params(seed)).to(device)
-        self.optim = torch.zeros(2 * SG_PARAM_COUNT, dtype=torch.float32, device=device)
+        self.params = torch.empty(SG_PARAM_COUNT, dtype=torch.float32, device=device)
+        self.optim = torch.empty(2 * SG_PARAM_COUNT, dtype=torch.float32, device=device)
+        surrogate_init(self.model, self.params, self.optim, seed)  # seeded He-normal weights, zero Adam state
         self.ws = torch.empty(surrogate_train_ws_bytes(self.model, grid, grid, crop, batch, K, chunk),
                               dtype=torch.uint8, device=device)
         self.rng = np.random.default_rng(seed + 12345)
@@ -93,9 +77,10 @@ class Trainer:
                 log(k0 + n, lv)
         return history
 
-    def evaluate(self, params, n: int, seed: int = 7):
-        """Held-out rel-L2 against K plain steps (from the library's judged entry point) of the surrogate
-        with `params` and of the identity predictor u_hat = u0 (all-zero parameters)."""
+    def evaluate(self, params, n: int, seed: int = 7, judge_mode: int = SG_JUDGE_FULL):
+        """Held-out rel-L2 against K plain steps (from the library's judged entry point, whole field
+        by default) of the surrogate with `params` and of the identity predictor u_hat = u0
+        (all-zero parameters)."""
         torch = self.torch
         G = self.grid
         if self.judge is None:
@@ -119,9 +104,9 @@ class Trainer:
                                    G, G, U0, KP)
             for b in range(coef.shape[0]):
                 _, e = surrogate_infer_checked(self.model, params, U0[b], KP[b], out, G, G, self.judge, self.K,
-                                               float("inf"), cws)
+                                               float("inf"), cws, judge_mode)
                 _, i = surrogate_infer_checked(self.model, zero, U0[b], KP[b], out, G, G, self.judge, self.K,
-                                               float("inf"), cws)
+                                               float("inf"), cws, judge_mode)
                 errs.append(e)
                 ident.append(i)
         return np.array(errs), np.array(ident)

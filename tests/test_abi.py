@@ -189,3 +189,46 @@ def test_train_cfg_layout_matches_header(tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got[0] == ctypes.sizeof(lib.SgTrainCfg)
     assert got[1:] == [getattr(lib.SgTrainCfg, f).offset for f in fields]
+
+
+def test_boundary_api_host_checks():
+    """stencil_set_boundary: kinds, the frame argument, naive plans, variant restrictions (host-only)."""
+    import paper_2605_07954_amd as lib
+    W = np.zeros((3, 3), dtype=np.float32)
+    W[1, 1] = 1.0
+    plan = lib.stencil_plan(10, 12, 1, W, 0.0, "f32", 0)
+    try:
+        assert lib.stencil_get_boundary(plan) == lib.ST_BC_CONST
+        assert lib.stencil_frame_elems(plan) == 2 * 1 * (12 + 2) + 2 * 1 * 10
+        for bad in (3, -1):
+            with pytest.raises(lib.StencilError) as e:
+                lib.stencil_set_boundary(plan, bad)
+            assert e.value.code == lib.ST_EINVAL
+        with pytest.raises(lib.StencilError) as e:  # a frame kind needs a frame
+            lib.stencil_set_boundary(plan, lib.ST_BC_FRAME)
+        assert e.value.code == lib.ST_EINVAL
+        lib.stencil_set_variant(plan, lib.ST_VARIANT_TILED)
+        lib.stencil_set_boundary(plan, lib.ST_BC_PERIODIC)
+        assert lib.stencil_get_variant(plan) == lib.ST_VARIANT_MARCH  # switched to marching
+        for v in (lib.ST_VARIANT_TILED, lib.ST_VARIANT_STREAM):
+            with pytest.raises(lib.StencilError) as e:
+                lib.stencil_set_variant(plan, v)
+            assert e.value.code == lib.ST_EUNSUPPORTED
+        lib.stencil_set_boundary(plan, lib.ST_BC_CONST)
+        lib.stencil_set_variant(plan, lib.ST_VARIANT_TILED)
+    finally:
+        lib.stencil_destroy(plan)
+    naive = lib.stencil_plan(10, 12, 1, W, 0.0, "f32", lib.ST_FLAG_NAIVE)
+    try:
+        with pytest.raises(lib.StencilError) as e:
+            lib.stencil_set_boundary(naive, lib.ST_BC_PERIODIC)
+        assert e.value.code == lib.ST_EUNSUPPORTED
+    finally:
+        lib.stencil_destroy(naive)
+    vc = lib.stencil_plan_varcoef(10, 12, 0.0, 0)
+    try:
+        with pytest.raises(lib.StencilError) as e:
+            lib.stencil_set_boundary(vc, lib.ST_BC_PERIODIC)
+        assert e.value.code == lib.ST_EINVAL
+    finally:
+        lib.stencil_destroy(vc)

@@ -1,0 +1,193 @@
+"""Host-thread model of the batched persistent queue that an earlier build ran on the GPU and
+removed after two hangs (it is not run on the GPU again).  The model follows that kernel's protocol
+step by step, with host threads in the role of workgroups:
+
+  * one queue head, taken with an atomic add; items in the order the host built them: the
+    LDS-resident grids first, then the tiled grids pass by pass (grids with more passes first, so
+    the grids still running at pass p are a prefix of the order and one table of tile offsets
+    serves every pass);
+  * before a tiled item (g, t, p) with p > 0 runs, its thread polls the completion counters of every
+    tile within the reach of its halo (ceil(r tb / tile side) tiles in each direction) until each
+    shows at least p, giving up after `spin_limit` polls in total for the item;
+  * after the item, the tile's counter is set to p + 1; the loop ends when the head passes the
+    last item.
+
+The tables are rebuilt with the removed host code's rules: a grid is resident when two copies plus
+the halo fit 80 KiB of LDS, else 128 x 64 tiles (for the two cases below) at the deepest temporal
+block <= the plan's default that fits 80 KiB.  The two cases are the two runs that hung: a single
+300 x 260 grid with 6 passes, and the 32-grid x 200-step sample of the batch workload.
+
+What the model shows (see the assertions): with counters that become visible, every interleaving
+tried completes, whatever the number of workers (also fewer than the items of one pass) and
+whatever their speeds; no item ever starts before the tiles it depends on finished the previous
+pass (a data race would show there); and with counters that never become visible to the waiting
+worker, every wait ends at the spin limit, so the worst case is bounded by (passes - 1) x
+spin_limit polls along the critical path.  The protocol therefore neither deadlocks nor waits
+without end; the hang has to come from outside it.
+"""
+import math
+import random
+import threading
+
+import pytest
+
+import workloads as wl
+
+MAXK = 81
+BUDGET = 80 * 1024
+TILE_X, TILE_Y = 128, 64
+
+
+def geometry(R, tb, TX, TY):
+    H = R * tb
+    off = ((H + 4 + 7) // 8) * 8
+    bw = ((off + TX + H + 7 + 7) // 8) * 8
+    return H, off, bw, TY + 2 * H
+
+
+def tile_lds(R, tb):
+    _, _, bw, bh = geometry(R, tb, TILE_X, TILE_Y)
+    return ((2 if tb > 1 else 1) * bw * bh + MAXK) * 4
+
+
+def resident_lds(R, rows, cols):
+    bw = ((8 + cols + 8 + 7) // 8) * 8
+    return (2 * (rows + 2 * R) * bw + MAXK) * 4
+
+
+def default_tb(shape, R):
+    taps = (2 * R + 1) ** 2 if shape == wl.BOX else 4 * R + 1
+    return 2 if taps >= 40 else (4 if taps >= 13 else 6)
+
+
+def build_queue(grids):
+    """grids: list of (rows, cols, shape, r, steps, tb or None).  Returns the item list in queue
+    order: ('res', g) or ('tile', g, t, p), plus per-grid (tiles_x, tiles_y, tb, passes, r)."""
+    res, tiled, info = [], [], {}
+    for g, (rows, cols, shape, r, steps, tb) in enumerate(grids):
+        if resident_lds(r, rows, cols) <= BUDGET:
+            res.append(g)
+            continue
+        tb = tb or default_tb(shape, r)
+        while tb > 1 and tile_lds(r, tb) > BUDGET:
+            tb -= 1
+        tx, ty = math.ceil(cols / TILE_X), math.ceil(rows / TILE_Y)
+        info[g] = (tx, ty, tb, math.ceil(steps / tb), r)
+        tiled.append(g)
+    tiled.sort(key=lambda g: -info[g][3])  # stable: more passes first
+    items = [("res", g) for g in res]
+    maxp = info[tiled[0]][3] if tiled else 0
+    for p in range(maxp):
+        for g in tiled:
+            if info[g][3] > p:
+                items += [("tile", g, t, p) for t in range(info[g][0] * info[g][1])]
+    return items, info
+
+
+def deps(info, g, t, p):
+    tx, ty, tb, _, r = info[g]
+    H = r * tb
+    ry, rx = math.ceil(H / TILE_Y), math.ceil(H / TILE_X)
+    y, x = divmod(t, tx)
+    return [yy * tx + xx for yy in range(max(0, y - ry), min(ty - 1, y + ry) + 1)
+            for xx in range(max(0, x - rx), min(tx - 1, x + rx) + 1)]
+
+
+def run_model(items, info, workers, seed, spin_limit=200000, visible=True):
+    """Run the queue with `workers` threads.  Returns (timeouts, violations, polls)."""
+    lock = threading.Lock()
+    head = [0]
+    counters = {g: [0] * (info[g][0] * info[g][1]) for g in info}
+    done_pass = {g: [0] * (info[g][0] * info[g][1]) for g in info}  # ground truth, checked at start
+    stats = {"timeouts": 0, "violations": 0, "polls": 0}
+    rng = random.Random(seed)
+    speeds = [rng.uniform(0.2, 3.0) for _ in range(workers)]
+
+    def worker(w):
+        local = random.Random(seed * 1000 + w)
+        stale = {}  # counters as first seen, when updates never become visible
+        while True:
+            with lock:
+                item = head[0]
+                head[0] += 1
+            if item >= len(items):
+                return
+            it = items[item]
+            if it[0] == "tile" and it[3] > 0:
+                _, g, t, p = it
+                spins = 0
+                gave_up = False
+                for n in deps(info, g, t, p):
+                    while True:
+                        if visible:
+                            seen = counters[g][n]
+                        else:
+                            seen = stale.setdefault((g, n), counters[g][n])
+                        if seen >= p:
+                            break
+                        spins += 1
+                        if spins > spin_limit:  # one budget for the item: later waits end at once
+                            gave_up = True
+                            break
+                        if spins % 64 == 0:
+                            threading.Event().wait(0)  # yield (the s_sleep of the kernel)
+                with lock:
+                    stats["polls"] += spins
+                    stats["timeouts"] += int(gave_up)
+                    if any(done_pass[g][n] < p for n in deps(info, g, t, p)):
+                        stats["violations"] += 1
+            # the item's work: a random, worker-dependent duration
+            for _ in range(int(local.uniform(0, 40) * speeds[w])):
+                pass
+            if it[0] == "tile":
+                _, g, t, p = it
+                with lock:
+                    done_pass[g][t] = p + 1
+                counters[g][t] = p + 1
+    ths = [threading.Thread(target=worker, args=(w,)) for w in range(workers)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join(timeout=120)
+        assert not th.is_alive(), "a worker did not finish: the queue would hang"
+    return stats["timeouts"], stats["violations"], stats["polls"]
+
+
+SINGLE = [(300, 260, wl.STAR, 1, 6, 1)]  # one grid, 6 passes of one level (two-buffer tiles of 128 x 64 fit 80 KiB only at tb = 1)
+
+
+def sample32(steps=12):
+    """The 32-grid sample with 12 steps instead of 200: at the depth that fits (tb = 1 for every tiled
+    grid of it) each pass repeats the same item structure, so 12 passes exercise the same tables."""
+    return [(rows, cols, shape, r, steps, None) for (rows, cols, shape, r) in wl.batch_specs(32, 64, 2048, 3)]
+
+
+@pytest.mark.parametrize("case", ["single", "sample32"])
+def test_queue_completes_without_waiting_past_dependencies(case):
+    grids = SINGLE if case == "single" else sample32()
+    items, info = build_queue(grids)
+    if case == "single":
+        assert info[0][3] == 6 and info[0][0] * info[0][1] == 15 and len(items) == 90
+    for workers, seed in (((3, 1), (16, 2), (64, 3)) if case == "single" else ((16, 4), (64, 5))):
+        timeouts, violations, _ = run_model(items, info, workers, seed)
+        assert violations == 0
+        assert timeouts == 0
+
+
+def test_invisible_counters_end_at_the_spin_limit():
+    """If a waiting worker never sees a counter move after its first read (a stale cached line), the
+    items that read it too early give up after spin_limit polls and the run still ends: the waits
+    are bounded."""
+    items, info = build_queue(SINGLE)
+    limit = 2000
+    timeouts, violations, polls = run_model(items, info, 15, 7, spin_limit=limit, visible=False)
+    dependent = sum(1 for it in items if it[0] == "tile" and it[3] > 0)
+    # items that first read a counter before it moved give up (each once); the run ends regardless
+    assert 0 < timeouts <= dependent
+    assert polls <= dependent * (limit + 1)
+    # the removed kernel's bound: 2^20 polls per item, each a device-scope load (~1-2 us) plus a
+    # 128-cycle sleep; 5 dependent passes of 15 tiles on 15+ workgroups run side by side, so the
+    # critical path is 5 x 2^20 polls: seconds, not the minutes of silence observed
+    per_poll_s = 2e-6
+    critical = (info[0][3] - 1) * 2 ** 20 * per_poll_s
+    assert critical < 15.0

@@ -252,16 +252,20 @@ def test_surrogate_1024(g):
         fb, err = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), chk, n, n, judge, 16,
                                               1e9, cws)
         np.testing.assert_array_equal(g.to_host(chk), got)
+        fbp, errp = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), chk, n, n, judge, 16,
+                                                1e9, cws, lib.SG_JUDGE_PATCH)
+        np.testing.assert_array_equal(g.to_host(chk), got)
     finally:
         lib.stencil_destroy(judge)
         lib.surrogate_destroy(m)
     p32 = unflat(pv)
+    scale = cnn.field_scale(u0)  # the whole field's scale constants, as the library takes them
     RF, P = 6, 64
     for (y, x) in [(0, 0), (0, 500), (500, 500), (n - P, n - P), (777, 3)]:
         wy0, wx0 = max(0, y - RF), max(0, x - RF)
         wy1, wx1 = min(n, y + P + RF), min(n, x + P + RF)
-        ref, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1], q=q_bf16)
-        exact, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1])
+        ref, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1], q=q_bf16, scale=scale)
+        exact, _ = cnn.forward(p32, u0[wy0:wy1, wx0:wx1], kap[wy0:wy1, wx0:wx1], scale=scale)
         ref = ref[y - wy0:y - wy0 + P, x - wx0:x - wx0 + P]
         exact = exact[y - wy0:y - wy0 + P, x - wx0:x - wx0 + P]
         base = u0[y:y + P, x:x + P]
@@ -278,3 +282,7 @@ def test_surrogate_1024(g):
     say(f"judged error: library {err:.6e}, from the oracle's 16 plain steps {e_ref:.6e} (fallback={fb})")
     assert not fb
     assert abs(err - e_ref) <= 1e-9 + 1e-9 * e_ref
+    from test_gpu_surrogate import patch_error
+    e_patch = patch_error(got, plain, n, n, 16)
+    say(f"patch judge: library {errp:.6e}, from the oracle on the same 16 patches {e_patch:.6e}")
+    assert not fbp and abs(errp - e_patch) <= 1e-9 * e_patch

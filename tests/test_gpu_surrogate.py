@@ -5,6 +5,8 @@ The GPU rounds activations, the 32->32 weights and the back-propagated dZ of lay
 the oracle's emulating mode rounds the same operands (``q``), so the remaining difference is FP32
 accumulation order (rel-L2 ~1e-6).  Tolerances: forward 1e-3, gradients 5e-3 (rel-L2 per layer).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -241,7 +243,6 @@ def test_train_entry_point_resume_and_composition(g):
     import math
     import torch
     import paper_2605_07954_amd as lib
-    from paper_2605_07954_amd.surrogate import init_params
     G, C, B, K, S, LR = 96, 48, 3, 16, 6, 2e-3
     coef = np.concatenate([wl.field_coefficients(B, 500 + k) for k in range(S)]).astype(np.float32)
     yx = np.random.default_rng(5).integers(0, G - C + 1, size=(S * B, 2)).astype(np.int32)
@@ -253,7 +254,10 @@ def test_train_entry_point_resume_and_composition(g):
         cd = g.to_dev(coef)
 
         def fresh():
-            return g.to_dev(init_params(3)), torch.zeros(2 * lib.SG_PARAM_COUNT, dtype=torch.float32, device=g.DEV)
+            p = torch.empty(lib.SG_PARAM_COUNT, dtype=torch.float32, device=g.DEV)
+            o = torch.full((2 * lib.SG_PARAM_COUNT,), float("nan"), dtype=torch.float32, device=g.DEV)
+            lib.surrogate_init(m, p, o, 3)
+            return p, o
 
         pa, oa = fresh()
         la = torch.zeros(S, dtype=torch.float64, device=g.DEV)
@@ -283,8 +287,11 @@ def test_train_entry_point_resume_and_composition(g):
         sws = torch.empty(lib.surrogate_workspace_bytes(m, B, C, C), dtype=torch.uint8, device=g.DEV)
         grad = torch.zeros(lib.SG_PARAM_COUNT, dtype=torch.float32, device=g.DEV)
         loss = torch.zeros(1, dtype=torch.float64, device=g.DEV)
+        scale = torch.empty(2 * B, dtype=torch.float32, device=g.DEV)
+        scws = torch.empty(B * 64 * 8, dtype=torch.uint8, device=g.DEV)
         for k in range(S):
             lib.surrogate_synth_fields(cd[k * B:(k + 1) * B], B, G, G, U0, KP)
+            lib.surrogate_field_scale(U0, B, G, G, scale, scws)  # each crop takes its whole field's scale
             for b in range(B):
                 lib.stencil_run_varcoef(judge, U0[b], KP[b], UK[b], K, jws)
             yxd = g.to_dev(yx[k * B:(k + 1) * B])
@@ -293,12 +300,113 @@ def test_train_entry_point_resume_and_composition(g):
             lohi = []
             for (y, x) in yx[k * B:(k + 1) * B]:
                 lohi += [6 if y > 0 else 0, C - (6 if y + C < G else 0), 6 if x > 0 else 0, C - (6 if x + C < G else 0)]
-            lib.surrogate_loss_grad(m, pc, cu0, ckp, cuk, np.array(lohi), B, C, C, grad, loss, sws)
+            lib.surrogate_loss_grad(m, pc, cu0, ckp, cuk, np.array(lohi), B, C, C, grad, loss, sws, scale)
+            if k == 0:  # the scale constants against the oracle's definition (RMS of each whole field)
+                for b in range(B):
+                    inv, gain = cnn.field_scale(g.to_host(U0[b]))
+                    assert (float(scale[2 * b]), float(scale[2 * b + 1])) == (inv, gain)
             assert float(loss.cpu()[0]) == float(la[k].cpu())
             lr_k = float(np.float32(LR)) * 0.5 * (1.0 + math.cos(math.pi * k / S))
             lib.surrogate_adam(m, pc, grad, oc, k + 1, lr_k)
         torch.cuda.synchronize()
         assert torch.equal(pa, pc) and torch.equal(oa, oc)
+    finally:
+        lib.stencil_destroy(judge)
+        lib.surrogate_destroy(m)
+
+
+def test_init_vs_oracle(g):
+    """surrogate_init on the device against the oracle's Philox4x64-10 + Box-Muller He-normal draw:
+    every weight within one FP32 ulp (both sides evaluate the normal in FP64 with their own log and
+    cos, then round once), nearly all bit for bit; zero biases and Adam state; the byte counts."""
+    import paper_2605_07954_amd as lib
+    m = lib.surrogate_create()
+    try:
+        assert lib.surrogate_param_bytes(m) == (4 * lib.SG_PARAM_COUNT, 8 * lib.SG_PARAM_COUNT)
+        p = torch.full((lib.SG_PARAM_COUNT,), float("nan"), dtype=torch.float32, device=g.DEV)
+        o = torch.full((2 * lib.SG_PARAM_COUNT,), float("nan"), dtype=torch.float32, device=g.DEV)
+        for seed in (0, 77, 2**63 + 11):
+            lib.surrogate_init(m, p, o, seed)
+            got = g.to_host(p)
+            assert np.all(g.to_host(o) == 0)
+            _, ref = cnn.init_params_philox(seed)
+            diff = got != ref
+            ulp = np.spacing(np.abs(ref).astype(np.float32))
+            say(f"seed {seed}: {int(diff.sum())} of {ref.size} weights differ from the oracle (at most one ulp)")
+            assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
+            assert diff.sum() <= 8
+        lib.surrogate_init(m, p, None, 5)  # parameters only
+        _, ref = cnn.init_params_philox(5)
+        assert np.all(np.abs(g.to_host(p).astype(np.float64) - ref) <= np.spacing(np.abs(ref).astype(np.float32)))
+    finally:
+        lib.surrogate_destroy(m)
+
+
+def lattice(rows, cols, K, n=4, side=64):
+    """Patches of the light-cone judge: origins ((rows - p) a + 1) // 3 per axis, side min(64, .)."""
+    py, px = min(side, rows), min(side, cols)
+    ys = [((rows - py) * a + (n - 1) // 2) // (n - 1) for a in range(n)]
+    xs = [((cols - px) * a + (n - 1) // 2) // (n - 1) for a in range(n)]
+    return [(y, x) for y in ys for x in xs], py, px
+
+
+def mosaic_cells(rows, cols, K, n=4, side=64):
+    """Cells of the judge's mosaic: the n x n windows (each patch dilated by K and clipped to the
+    grid) packed edge to edge."""
+    py, px = min(side, rows), min(side, cols)
+    ys = [((rows - py) * a + (n - 1) // 2) // (n - 1) for a in range(n)]
+    xs = [((cols - px) * a + (n - 1) // 2) // (n - 1) for a in range(n)]
+    h = sum(min(rows, y + py + K) - max(0, y - K) for y in ys)
+    w = sum(min(cols, x + px + K) - max(0, x - K) for x in xs)
+    return h * w
+
+
+def patch_error(uhat, plain, rows, cols, K):
+    """FP64 rel-L2 of u_hat against the plain K-step field over the judge's patch lattice."""
+    cells, py, px = lattice(rows, cols, K)
+    d2 = n2 = 0.0
+    for (y, x) in cells:
+        a = uhat[y:y + py, x:x + px].astype(np.float64)
+        b = plain[y:y + py, x:x + px].astype(np.float64)
+        d2 += float(np.sum((a - b) ** 2))
+        n2 += float(np.sum(b * b))
+    return math.sqrt(d2 / n2)
+
+
+@pytest.mark.parametrize("rows,cols,K", [(512, 512, 16), (700, 520, 5), (96, 130, 16)])
+def test_infer_checked_patch_judge(g, rows, cols, K):
+    """The light-cone patch judge: its error equals the one computed from the oracle's plain K steps
+    on the whole field, restricted to the 4 x 4 patch lattice (the mosaic of dilated windows is
+    exact on the patches); with tol = 0 the fallback output is the plain K-step field bit for bit.
+    A grid too small for the mosaic (96 x 130) is judged on the whole field."""
+    import paper_2605_07954_amd as lib
+    u0, kap = wl.varcoef_problem(rows, cols, seed=31)
+    pv = flat_params(_params(6))
+    plain = oracle.varcoef_f32(u0, kap, 0.0, K)
+    m = lib.surrogate_create()
+    judge = lib.stencil_plan_varcoef(rows, cols, 0.0)
+    try:
+        ws = torch.empty(lib.surrogate_checked_ws_bytes(m, rows, cols), dtype=torch.uint8, device=g.DEV)
+        out = torch.empty((rows, cols), device=g.DEV)
+        fb, err = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, rows, cols, judge, K,
+                                              1e9, ws, lib.SG_JUDGE_PATCH)
+        uhat = g.to_host(out)
+        assert not fb
+        fbf, errf = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, rows, cols, judge,
+                                                K, 1e9, ws, lib.SG_JUDGE_FULL)
+        np.testing.assert_array_equal(g.to_host(out), uhat)
+        full = oracle.rel_l2(uhat, plain)
+        assert abs(errf - full) <= 1e-9 * full
+        if mosaic_cells(rows, cols, K) * 2 <= rows * cols:  # the windows fit: the patch error
+            ref = patch_error(uhat, plain, rows, cols, K)
+        else:
+            ref = full
+        say(f"{rows}x{cols} K={K}: patch judge {err:.9e}, from the oracle {ref:.9e} (whole field {full:.3e})")
+        assert abs(err - ref) <= 1e-9 * ref
+        fb0, err0 = lib.surrogate_infer_checked(m, g.to_dev(pv), g.to_dev(u0), g.to_dev(kap), out, rows, cols, judge,
+                                                K, 0.0, ws, lib.SG_JUDGE_PATCH)
+        assert fb0 and err0 == err
+        np.testing.assert_array_equal(g.to_host(out), plain)
     finally:
         lib.stencil_destroy(judge)
         lib.surrogate_destroy(m)

@@ -94,12 +94,15 @@ def test_grads_match_torch_autograd():
     n = sum(float(m.sum()) for (_, _, _, m) in samples)
     tl = 0
     for (u0, kap, tgt, m) in samples:
-        a = torch.from_numpy(cnn.input_channels(u0, kap))[None]
+        s = math.sqrt(float(np.mean(u0 * u0)))  # the field's RMS, and its FP32 scale constants
+        inv, gain = float(np.float32(1.0 / s)), float(np.float32(2.0 ** -11 * s))
+        x = np.stack([u0 * inv, (kap - 0.125) / 0.075])
+        a = torch.from_numpy(x)[None]
         for l, (w, b) in enumerate(tp):
             a = torch.nn.functional.conv2d(a, w, b, padding=1)
             if l < cnn.N_LAYERS - 1:
                 a = torch.nn.functional.gelu(a)
-        uh = torch.from_numpy(u0) + a[0, 0]
+        uh = torch.from_numpy(u0) + gain * a[0, 0]
         tl = tl + (((uh - torch.from_numpy(tgt)) * torch.from_numpy(m)) ** 2).sum() / n
     tl.backward()
     assert abs(float(tl) - loss) < 1e-12
@@ -125,3 +128,63 @@ def test_crop_mask():
     m = cnn.crop_mask(10, 12, 0, 5, 10, 40, 3)
     assert m[:, :3].sum() == 0 and m[:, -3:].sum() == 0
     assert m[0, 5] == 1 and m[-1, 5] == 1   # top and bottom are domain edges
+
+
+def test_philox_matches_numpy_bit_generator():
+    """Philox4x64-10 written from its definition against numpy's own Philox bit generator, which
+    yields the blocks of counters 1, 2, 3, ... (it increments before each block)."""
+    for key in ((0, 0), (12345, 678), (2**64 - 1, 2**63 + 5)):
+        raw = np.random.Philox(key=np.array(key, dtype=np.uint64)).random_raw(4 * 40)
+        mine = [w for c in range(1, 41) for w in cnn.philox4x64_10((c, 0, 0, 0), key)]
+        assert [int(v) for v in raw] == mine
+    # a counter with every word set: compare against numpy advanced to that counter
+    g = np.random.Philox(counter=np.array([2**64 - 2, 7, 9, 11], dtype=np.uint64), key=np.array([3, 4], dtype=np.uint64))
+    raw = g.random_raw(4)
+    assert [int(v) for v in raw] == list(cnn.philox4x64_10((2**64 - 1, 7, 9, 11), (3, 4)))
+
+
+def test_init_params_philox_distribution():
+    """The seeded He-normal initialisation: zero biases, the layout of the library, and per layer a
+    sample mean and variance consistent with N(0, 2 / (9 C_in)) (0.1 times that std for layer 6);
+    different seeds give different draws, the same seed the same ones."""
+    params, flat = cnn.init_params_philox(5)
+    offs, total = cnn.param_layout()
+    assert total == flat.size == 37889
+    for l, ((w, b), (wo, bo)) in enumerate(zip(params, offs)):
+        ci, co = cnn.CHANNELS[l], cnn.CHANNELS[l + 1]
+        assert np.all(b == 0) and np.all(flat[bo:bo + co] == 0)
+        np.testing.assert_array_equal(w.transpose(2, 3, 1, 0).reshape(-1), flat[wo:bo].astype(np.float64))
+        std = math.sqrt(2.0 / (9 * ci)) * (0.1 if l == 5 else 1.0)
+        n = w.size
+        z = w.reshape(-1) / std
+        assert abs(z.mean()) < 5.0 / math.sqrt(n)
+        assert abs(z.var() - 1.0) < 6.0 * math.sqrt(2.0 / n)
+    _, flat2 = cnn.init_params_philox(5)
+    _, flat3 = cnn.init_params_philox(6)
+    np.testing.assert_array_equal(flat, flat2)
+    assert np.mean(flat != flat3) > 0.99
+    # Box-Muller of the first two words, by hand for one index
+    x0, x1, _, _ = cnn.philox4x64_10((7, 0, 0, 0), (5, 0))
+    u1, u2 = (x0 >> 11) / 2.0**53, (x1 >> 11) / 2.0**53
+    assert cnn.normal_at(7, 5) == math.sqrt(-2 * math.log(1 - u1)) * math.cos(2 * math.pi * u2)
+
+
+def test_field_scale_and_equivariance():
+    """The scale constants of a field (its RMS), and the network's scale equivariance: scaling u0 by a
+    power of two c scales inv by 1/c and gain by c exactly, so u_hat scales by c exactly."""
+    inv, gain = cnn.field_scale(np.full((4, 5), -0.5))
+    assert inv == 2.0 and gain == 2.0 ** -12
+    assert cnn.field_scale(np.zeros((3, 3))) == (1.0, 2.0 ** -11)
+    rng = np.random.default_rng(9)
+    params = cnn.init_params(2)
+    u0 = rng.standard_normal((7, 6)) * 0.3
+    kap = rng.uniform(0.05, 0.2, (7, 6))
+    base, _ = cnn.forward(params, u0, kap)
+    for c in (0.25, 8.0):
+        got, _ = cnn.forward(params, c * u0, kap)
+        np.testing.assert_array_equal(got, c * base)
+    # the update is gain times the last layer's output
+    inv, gain = cnn.field_scale(u0)
+    _, (acts, zs) = cnn.forward(params, u0, kap)
+    np.testing.assert_allclose(base - u0, gain * zs[-1][0], rtol=0, atol=4 * np.finfo(float).eps * np.abs(u0).max())
+    np.testing.assert_array_equal(acts[0][0], u0 * inv)
