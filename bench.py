@@ -52,8 +52,9 @@ def gstencil_s(steps: int, rows: int, cols: int, seconds: float) -> float:
     return steps * rows * cols / (seconds * 1e9)
 
 
-KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march", 4: "sweep_march"}
-VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1"}
+KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march", 4: "sweep_march",
+                5: "sweep_resident"}
+VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1", 5: "resident"}
 
 
 def kernel_source_hash() -> str:
@@ -362,6 +363,125 @@ def extra_surrogate(torch, lib, stream) -> dict:
             "cnn_tflops": 75456.0 * 1024 * 1024 / ts / 1e12, "cnn_frac_of_bf16_mfma_peak": 75456.0 * 1024 * 1024 / ts / 2.5e15}
 
 
+def extra_surrogate_trained(torch, lib, stream) -> dict:
+    """The surrogate trained on 20k GPU-generated 1024^2 trajectories (about 10 s), then judged on 200
+    held-out ones: mean rel-L2 of the trained network and of the identity predictor u_hat = u0
+    against 16 plain steps, next to the times of inference, of judged inference (light-cone patch
+    judge and whole-field judge) and of the plain 16 steps."""
+    from paper_2605_07954_amd.surrogate import Trainer
+    tr = Trainer(grid=1024, crop=256, batch=8, K=16, seed=0)
+    try:
+        t0 = time.perf_counter()
+        tr.train(20000, log=None)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        e_tr, e_id = tr.evaluate(tr.params, 200)
+        u0, kap = wl.varcoef_problem(1024, 1024, seed=0)
+        u = torch.from_numpy(u0).to("cuda")
+        k = torch.from_numpy(kap).to("cuda")
+        o = torch.empty_like(u)
+        w = torch.empty_like(u)
+        judge = tr.judge
+        vplan = lib.stencil_plan_varcoef(1024, 1024, 0.0, lib.ST_FLAG_GRAPH)
+        lib.stencil_autotune_varcoef(vplan, u, k, o, w, 16, stream)
+        plain = lambda: lib.stencil_run_varcoef(vplan, u, k, o, 16, w, stream)  # noqa: E731
+        plain()
+        t_plain = time_median(plain, 20, stream)
+        cws = torch.empty(lib.surrogate_checked_ws_bytes(tr.model, 1024, 1024), dtype=torch.uint8, device="cuda")
+        sws = torch.empty(lib.surrogate_workspace_bytes(tr.model, 1, 1024, 1024), dtype=torch.uint8, device="cuda")
+        uh = torch.empty((1, 1024, 1024), device="cuda")
+        inf = lambda: lib.surrogate_infer(tr.model, tr.params, u, k, uh, 1, 1024, 1024, sws, stream)  # noqa: E731
+        inf()
+        t_inf = time_median(inf, 20, stream)
+
+        def checked(mode):
+            t = []
+            for _ in range(10):  # each call synchronises to read the judged error: host wall time
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lib.surrogate_infer_checked(tr.model, tr.params, u, k, o, 1024, 1024, judge, 16, 1.0, cws, mode, stream)
+                t.append(time.perf_counter() - t0)
+            return float(np.median(t))
+        t_patch = checked(lib.SG_JUDGE_PATCH)
+        t_full = checked(lib.SG_JUDGE_FULL)
+        lib.stencil_destroy(vplan)
+    finally:
+        tr.close()
+    return {"train_trajectories": 20000, "train_s": train_s, "heldout": 200,
+            "rel_l2_trained_mean": float(e_tr.mean()), "rel_l2_identity_mean": float(e_id.mean()),
+            "trained_over_identity": float(e_tr.mean() / e_id.mean()),
+            "plain_16_steps_us": t_plain * 1e6, "infer_us": t_inf * 1e6,
+            "checked_patch_us_host": t_patch * 1e6, "checked_full_us_host": t_full * 1e6,
+            "speedup_infer_vs_plain": t_plain / t_inf}
+
+
+def extra_surrogate_profile(torch, lib, stream) -> dict:
+    """A short surrogate workload for counter profiles: 10 inferences on 1024^2 and 20 optimiser steps
+    of training (batch 8, 256^2 crops of 1024^2 trajectories), every forward and backward kernel."""
+    from paper_2605_07954_amd.surrogate import Trainer
+    tr = Trainer(grid=1024, crop=256, batch=8, K=16, seed=0, chunk=20)
+    try:
+        u0, kap = wl.varcoef_problem(1024, 1024, seed=0)
+        u = torch.from_numpy(u0).to("cuda")
+        k = torch.from_numpy(kap).to("cuda")
+        sws = torch.empty(lib.surrogate_workspace_bytes(tr.model, 1, 1024, 1024), dtype=torch.uint8, device="cuda")
+        uh = torch.empty((1, 1024, 1024), device="cuda")
+        for _ in range(10):
+            lib.surrogate_infer(tr.model, tr.params, u, k, uh, 1, 1024, 1024, sws, stream)
+        t0 = time.perf_counter()
+        tr.train(160, log=None)
+        torch.cuda.synchronize()
+        return {"train_20_steps_s": time.perf_counter() - t0}
+    finally:
+        tr.close()
+
+
+def extra_3d(torch, lib, stream) -> dict:
+    """3D 7-point star (c0 0.4, 0.1 per neighbour) on 512^3 FP32, 50 steps: one level per pass, 8 bytes
+    and 13 FLOP per update, against the HBM roof (1000 GStencil/s at 8 TB/s)."""
+    n, T = 512, 50
+    W = np.zeros((3, 3, 3), dtype=np.float32)
+    W[1, 1, 1] = 0.4
+    for d in [(0, 1, 1), (2, 1, 1), (1, 0, 1), (1, 2, 1), (1, 1, 0), (1, 1, 2)]:
+        W[d] = 0.1
+    x = torch.rand((n, n, n), device="cuda")
+    out = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    plan = lib.stencil_plan3d(n, n, n, 1, W, 0.0, "f32", 0)
+    run = lambda: lib.stencil_run(plan, x, out, T, ws, stream)  # noqa: E731
+    run()
+    t = time_median(run, 10, stream)
+    lib.stencil_destroy(plan)
+    del x, out, ws
+    torch.cuda.empty_cache()
+    gst = T * n ** 3 / t / 1e9
+    return {"gstencil_s": gst, "ms": t * 1e3, "alg_bytes_per_update": 8.0, "hbm_roof_gstencil": HBM_PEAK / 8 / 1e9,
+            "frac_of_hbm_roof": gst / (HBM_PEAK / 8 / 1e9), "alg_hbm_gbps": gst * 8}
+
+
+def extra_periodic(torch, lib, stream) -> dict:
+    """Star-2D9P 8192^2 x 500 FP32 on a torus (periodic boundary; four-column marching kernels),
+    autotuned, next to the same run with the zero halo."""
+    p = wl.star9_precision(rows=8192, cols=8192, steps=500)
+    x = torch.from_numpy(p.u0).to("cuda")
+    o = torch.empty_like(x)
+    w2 = torch.empty_like(x)
+    res = {}
+    for name, bc in (("periodic", lib.ST_BC_PERIODIC), ("dirichlet", lib.ST_BC_CONST)):
+        plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, "f32", 0)
+        lib.stencil_set_boundary(plan, bc)
+        tb, _, _ = lib.stencil_autotune(plan, x, o, w2, 120, stream)
+        var = lib.stencil_get_variant(plan)
+        run = lambda: lib.stencil_run(plan, x, o, p.steps, w2, stream)  # noqa: E731
+        run()
+        t = time_median(run, 10, stream)
+        lib.stencil_destroy(plan)
+        res[name] = {"gstencil_s": gstencil_s(p.steps, p.rows, p.cols, t), "tb": tb, "variant": VARIANT_NAMES[var]}
+    del x, o, w2
+    torch.cuda.empty_cache()
+    return res
+
+
 def extra_norms(torch, lib, stream) -> dict:
     """FP64 norms of a 16384^2 field and its predecessor (residual, energy, mass, next-step mass for
     the box49 weights): 8 bytes read per cell, against the HBM peak."""
@@ -385,11 +505,13 @@ def extra_norms(torch, lib, stream) -> dict:
 EXTRAS = {"box49_tb1": ("box49_16384_tb1", extra_box49_tb1), "heat2d": ("heat2d_512_100", extra_heat2d),
           "star9": ("star9_8192_500", extra_star9),
           "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate),
+          "surrogate_trained": ("surrogate_1024_K16_trained", extra_surrogate_trained),
+          "star7_3d": ("star7_3d_512", extra_3d), "surrogate_profile": ("surrogate_profile", extra_surrogate_profile), "periodic": ("star9_8192_periodic", extra_periodic),
           "norms": ("norms_16384", extra_norms)}
 
 
 def extras(torch, lib, stream) -> dict:
-    return {key: fn(torch, lib, stream) for key, fn in EXTRAS.values()}
+    return {key: fn(torch, lib, stream) for key, fn in EXTRAS.values() if key != "surrogate_profile"}
 
 
 def main():

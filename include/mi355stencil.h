@@ -52,6 +52,8 @@ extern "C" {
 /* ---- plan flags -------------------------------------------------------- */
 #define ST_FLAG_NAIVE  0x1u  /* one step per launch, no LDS tiling: the plain GPU reference path */
 #define ST_FLAG_GRAPH  0x2u  /* stencil_run replays its passes from a cached hipGraph            */
+#define ST_FLAG_ALLOW_MFMA 0x4u /* stencil_autotune may pick ST_VARIANT_MFMA, whose results are
+                                   within FP32 rounding of the canonical order, not bit for bit */
 
 #define ST_MAX_RADIUS 4
 #define ST_MAX_RADIUS_3D 2
@@ -158,6 +160,16 @@ int stencil_set_blocking(st_plan* plan, int tb, int tile_x, int tile_y);
  * kernels. */
 int stencil_set_variant(st_plan* plan, int variant);
 int stencil_get_variant(const st_plan* plan, int* variant);
+
+#define ST_VARIANT_MFMA    6  /* the update as a dense contraction on the matrix cores: per 16 x 16
+                                 output block and footprint row, a 16 x 32 window of the field times
+                                 a banded 32 x 16 Toeplitz block of the weights
+                                 (v_mfma_f32_16x16x32_bf16), every FP32 operand split exactly into
+                                 three BF16 parts and the six products above 2^-24 relative summed
+                                 in FP32.  One level per pass (tb = 1); FP32 storage, constant halo.
+                                 NOT bitwise the canonical order: within FP32 rounding of it (the
+                                 paper's tensor-core family, Sec. V, for MI355X).  The autotuner
+                                 considers it only for plans created with ST_FLAG_ALLOW_MFMA     */
 
 /* stencil_set_spin_limit -- resident variant: polls of a neighbour's counter (in total per tile
  * and epoch) before a wait gives up (default 2^22, seconds).  A give-up raises a flag that ends

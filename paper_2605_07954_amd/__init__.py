@@ -22,9 +22,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mi355stencil.h")
 ST_OK = 0
 ST_EINVAL, ST_EALIAS, ST_EUNSUPPORTED, ST_EHIP, ST_ENOWS, ST_ENOMEM, ST_ESTATE = -1, -2, -3, -4, -5, -6, -7
 ST_F32, ST_BF16, ST_F16 = 0, 1, 2
-ST_FLAG_NAIVE, ST_FLAG_GRAPH = 0x1, 0x2
+ST_FLAG_NAIVE, ST_FLAG_GRAPH, ST_FLAG_ALLOW_MFMA = 0x1, 0x2, 0x4
 ST_VARIANT_TILED, ST_VARIANT_STREAM, ST_VARIANT_MARCH, ST_VARIANT_MARCH8, ST_VARIANT_MARCH1 = 0, 1, 2, 3, 4
-ST_VARIANT_RESIDENT = 5
+ST_VARIANT_RESIDENT, ST_VARIANT_MFMA = 5, 6
 ST_BC_CONST, ST_BC_PERIODIC, ST_BC_FRAME = 0, 1, 2
 SG_PARAM_COUNT = 37889
 SG_JUDGE_FULL, SG_JUDGE_PATCH = 0, 1

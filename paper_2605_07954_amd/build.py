@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["march_f32_star.hip", "march_bf16_star.hip", "march_f16_star.hip", "march_f32_box.hip", "march_bf16_box.hip",
            "march_f16_box.hip", "march_xbc_f32_star.hip", "march_xbc_bf16_star.hip", "march_xbc_f16_star.hip",
            "march_xbc_f32_box.hip", "march_xbc_bf16_box.hip", "march_xbc_f16_box.hip", "surrogate.hip", "batched.hip",
-           "sweep.hip", "api.hip", "march.hip", "varcoef.hip", "norms.hip", "stencil3d.hip", "resident.hip"]
+           "sweep.hip", "api.hip", "march.hip", "varcoef.hip", "norms.hip", "stencil3d.hip", "resident.hip", "mfma_stencil.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

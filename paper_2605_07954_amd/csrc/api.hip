@@ -102,7 +102,7 @@ static void init_plan(st_plan* p) {
 }
 
 static int check_flags(uint32_t flags) {
-    if (flags & ~(ST_FLAG_NAIVE | ST_FLAG_GRAPH)) return fail(ST_EINVAL, "unknown flag bits");
+    if (flags & ~(ST_FLAG_NAIVE | ST_FLAG_GRAPH | ST_FLAG_ALLOW_MFMA)) return fail(ST_EINVAL, "unknown flag bits");
     return ST_OK;
 }
 
@@ -291,8 +291,11 @@ int stencil_set_variant(st_plan* plan, int variant) {
     if (!plan) return fail(ST_EINVAL, "plan is NULL");
     if (plan->kind == KIND_3D) return fail(ST_EUNSUPPORTED, "3D plans have one kernel");
     if (variant != ST_VARIANT_TILED && variant != ST_VARIANT_STREAM && variant != ST_VARIANT_MARCH &&
-        variant != ST_VARIANT_MARCH8 && variant != ST_VARIANT_MARCH1 && variant != ST_VARIANT_RESIDENT)
+        variant != ST_VARIANT_MARCH8 && variant != ST_VARIANT_MARCH1 && variant != ST_VARIANT_RESIDENT &&
+        variant != ST_VARIANT_MFMA)
         return fail(ST_EINVAL, "unknown variant");
+    if (variant == ST_VARIANT_MFMA && !mfma_usable(plan))
+        return fail(ST_EUNSUPPORTED, "the matrix-core variant takes FP32 constant-weight plans with a constant halo");
     if (variant == ST_VARIANT_RESIDENT && (plan->kind != KIND_CONST || plan->bc != ST_BC_CONST))
         return fail(ST_EUNSUPPORTED, "the resident variant takes constant-weight plans with a constant halo");
     if (variant == ST_VARIANT_STREAM && (plan->kind != KIND_CONST || !stream_usable(plan)))
@@ -546,19 +549,22 @@ static int autotune_impl(st_plan* plan, const void* in, const float* kappa, void
     ST_HIP_CHECK(hipEventCreate(&e0));
     ST_HIP_CHECK(hipEventCreate(&e1));
     int rc = ST_OK;
-    const int nvar = plan->kind == KIND_CONST ? 6 : 1;
+    const int nvar = plan->kind == KIND_CONST ? 7 : 1;
     for (int var = 0; var < nvar && rc == ST_OK; ++var)
     for (int ti = 0; ti < nt && rc == ST_OK; ++ti) {
         if (var == VARIANT_STREAM && !stream_usable(plan)) break;
         if (plan->bc != ST_BC_CONST && !is_march(var)) break;  // other boundaries: marching only
         if (var == VARIANT_RESIDENT && (ti > 0 || plan->bc != ST_BC_CONST)) break;  // no tile either
+        if (var == VARIANT_MFMA && (ti > 0 || !(saved_flags & ST_FLAG_ALLOW_MFMA) || !mfma_usable(plan))) break;
         if (is_march(var) && (ti > 0 || !march_usable(plan))) break;  // marching has no tile
         if (var == VARIANT_MARCH8 && plan->cols % 8 != 0) break;  // would run the four-column kernels
         const int tx = tiles[2 * ti], ty = tiles[2 * ti + 1];
         plan->variant = var;
         // LDS tiles: the depths of kTb; marching: every depth it offers
         int cands[16], nc = 0;
-        if (var == VARIANT_RESIDENT) {
+        if (var == VARIANT_MFMA) {
+            cands[nc++] = 1;
+        } else if (var == VARIANT_RESIDENT) {
             static const int kRes[] = {1, 2, 4, 8, 12, 16, 24, 32, 48};
             for (int tb : kRes)
                 if (resident_usable(plan, tb) && nc < 16) cands[nc++] = tb;

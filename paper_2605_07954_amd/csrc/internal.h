@@ -41,7 +41,8 @@ enum Variant {
     VARIANT_MARCH = ST_VARIANT_MARCH,
     VARIANT_MARCH8 = ST_VARIANT_MARCH8,
     VARIANT_MARCH1 = ST_VARIANT_MARCH1,
-    VARIANT_RESIDENT = ST_VARIANT_RESIDENT
+    VARIANT_RESIDENT = ST_VARIANT_RESIDENT,
+    VARIANT_MFMA = ST_VARIANT_MFMA
 };
 
 constexpr int MAXK = (2 * ST_MAX_RADIUS + 1) * (2 * ST_MAX_RADIUS + 1);  // 81
@@ -125,6 +126,10 @@ bool resident_usable(const st_plan* p, int tb);
 int resident_max_tb(const st_plan* p);
 int launch_resident(const st_plan* p, const void* in, void* out, void* ws, int64_t steps, hipStream_t s);
 int read_resident_status(const st_plan* p, const void* ws, int* status4, hipStream_t s);
+// Matrix-core pass (mfma_stencil.hip): one level, FP32 storage, constant halo; not the canonical
+// FMA order bit for bit (within FP32 rounding of it).
+bool mfma_usable(const st_plan* p);
+int launch_mfma(const st_plan* p, const void* src, void* dst, hipStream_t s);
 // 3D pass (stencil3d.hip): one step of a 3D plan.
 int launch_3d(const st_plan* p, const void* src, void* dst, hipStream_t s);
 // Row-marching pass (march.hip): constant-weight plans of any storage, width and alignment, up to

@@ -13,6 +13,11 @@
 // more by then).  A workgroup writes exchange field e+2 only after it saw its neighbours publish
 // epoch e+1, which they do only after they finished reading field e: two fields suffice.
 //
+// Ordering: the tile's stores and the neighbours' halo loads are device-scope relaxed atomics
+// (coherent across the XCDs' L2 caches); a workgroup waits for its stores to complete before its
+// thread 0 raises the counter, and a reader issues its halo loads only after its counter poll
+// returned the new value.
+//
 // Every wait is bounded: thread 0 polls a neighbour's counter at most spin_limit times (in total
 // per epoch), checks a shared give-up flag every 64 polls, and on running out raises the flag and
 // records (workgroup, epoch, neighbour); every workgroup that sees the flag leaves its epoch loop,
@@ -50,6 +55,18 @@ __device__ __forceinline__ int64_t part_lo(int i, int n, int64_t len) { return (
 template <int S>
 __device__ __forceinline__ typename Fmt<S>::T* as_field(void* p) {
     return static_cast<typename Fmt<S>::T*>(p);
+}
+
+// Exchange-field accesses as device-scope relaxed atomics: coherent across the chip's L2 caches
+// without the whole-cache write-back and invalidate of a device-scope fence (which cost ~40 us
+// per swap with one fence pair per workgroup and epoch).
+template <typename T>
+__device__ __forceinline__ void xstore(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T xload(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait until every neighbour of workgroup (ty, tx) published epoch `want`.  Returns true when the
@@ -112,14 +129,15 @@ __global__ __launch_bounds__(NTR) void sweep_resident(ResArgs a) {
         __syncthreads();  // the tile's state is complete in bufs[cur]
         for (int k = threadIdx.x; k < th * tw; k += NTR) {
             const int y = k / tw, x = k % tw;
-            xg[(y0 + y) * a.cols + x0 + x] = Fmt<S>::st(bufs[cur][(y + H) * BW + x + H]);
+            xstore(xg + (y0 + y) * a.cols + x0 + x, Fmt<S>::st(bufs[cur][(y + H) * BW + x + H]));
         }
-        __threadfence();  // the tile is visible device-wide before the counter says so
+        // every store of the tile has completed (reached the device's coherence point) before the
+        // counter is raised; the readers load the field at that point too, after seeing the counter
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __hip_atomic_store(a.flags + wg, e + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.flags + wg, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             quit = wait_neighbours(a, ty, tx, e + 1, wg) ? 1 : 0;
-            __threadfence();  // acquire: the neighbours' tiles are read after their counters
         }
         __syncthreads();
         if (quit) {
@@ -134,7 +152,7 @@ __global__ __launch_bounds__(NTR) void sweep_resident(ResArgs a) {
             if (y >= H && y < H + th && x >= H && x < H + tw) continue;
             const int64_t gyy = y0 + y - H, gxx = x0 + x - H;
             float v = a.b;
-            if (gyy >= 0 && gyy < a.rows && gxx >= 0 && gxx < a.cols) v = Fmt<S>::ld(xg[gyy * a.cols + gxx]);
+            if (gyy >= 0 && gyy < a.rows && gxx >= 0 && gxx < a.cols) v = Fmt<S>::ld(xload(xg + gyy * a.cols + gxx));
             cb[y * BW + x] = v;
         }
         __syncthreads();

@@ -6,8 +6,9 @@
 //
 // One workgroup owns a TY x TX column of the grid and marches along z over a segment of planes:
 // the 2r + 1 input planes of the current output plane sit in an LDS ring, each with its r-deep
-// (y, x) halo; every iteration loads one new plane into the slot the oldest one leaves, then each
-// thread computes its cells of the output plane from the ring.  A wavefront covers one row of the
+// (y, x) halo; every iteration stores the plane fetched during the previous one into the slot the
+// oldest plane leaves, starts fetching the next plane into registers, and computes its cells of the
+// output plane from the ring while that fetch is in flight.  A wavefront covers one row of the
 // tile (64 consecutive columns), so loads and stores are coalesced and LDS reads of one tap hit 64
 // consecutive words.  One level per pass (no temporal blocking): HBM-bound for the 7-point star
 // (8 bytes and 13 FLOP per update), LDS-bound for large boxes.
@@ -32,25 +33,47 @@ struct Args3 {
     float w[MAXK3];
 };
 
+// One plane of the tile with its r-deep (y, x) halo, in the storage type's FP32 values: fetched into
+// registers (PER values per thread) while the previous plane computes, stored into LDS afterwards.
+template <int R>
+struct PlaneRegs {
+    static constexpr int PW = TX + 2 * R, PH = TY + 2 * R, PS = PW * PH;
+    static constexpr int PER = (PS + NT3 - 1) / NT3;
+    float v[PER];
+};
+
 template <int S, int R>
-__device__ __forceinline__ void load_plane(const Args3& a, float* slot, int64_t z, int64_t y0, int64_t x0) {
+__device__ __forceinline__ void fetch_plane(const Args3& a, PlaneRegs<R>& p, int64_t z, int64_t y0, int64_t x0) {
     using T = typename Fmt<S>::T;
-    constexpr int PW = TX + 2 * R, PH = TY + 2 * R;
+    using P = PlaneRegs<R>;
     const T* src = static_cast<const T*>(a.src);
     const bool zin = z >= 0 && z < a.planes;
-    for (int k = threadIdx.x; k < PW * PH; k += NT3) {
-        const int py = k / PW, px = k % PW;
+#pragma unroll
+    for (int j = 0; j < P::PER; ++j) {
+        const int k = int(threadIdx.x) + NT3 * j;
+        const int py = k / P::PW, px = k % P::PW;
         const int64_t y = y0 - R + py, x = x0 - R + px;
         float v = a.b;
-        if (zin && y >= 0 && y < a.rows && x >= 0 && x < a.cols) v = Fmt<S>::ld(src[(z * a.rows + y) * a.cols + x]);
-        slot[k] = v;
+        if (k < P::PS && zin && y >= 0 && y < a.rows && x >= 0 && x < a.cols) v = Fmt<S>::ld(src[(z * a.rows + y) * a.cols + x]);
+        p.v[j] = v;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void store_plane(float* slot, const PlaneRegs<R>& p) {
+    using P = PlaneRegs<R>;
+#pragma unroll
+    for (int j = 0; j < P::PER; ++j) {
+        const int k = int(threadIdx.x) + NT3 * j;
+        if (k < P::PS) slot[k] = p.v[j];
     }
 }
 
 template <int S, int R, int SHAPE>
 __global__ __launch_bounds__(NT3) void sweep3d(Args3 a) {
     constexpr int K = 2 * R + 1;
-    constexpr int PW = TX + 2 * R, PH = TY + 2 * R, PS = PW * PH;
+    using P = PlaneRegs<R>;
+    constexpr int PW = P::PW, PS = P::PS;
     __shared__ float ring[K][PS];
     const int64_t t = blockIdx.x;
     const int64_t tile = t % (a.tiles_x * a.tiles_y), seg = t / (a.tiles_x * a.tiles_y);
@@ -60,11 +83,16 @@ __global__ __launch_bounds__(NT3) void sweep3d(Args3 a) {
     using T = typename Fmt<S>::T;
     T* dst = static_cast<T*>(a.dst);
     // planes z0 - R .. z0 + R - 1 into slots; plane z lives in slot (z - z0 + R) mod K
-    for (int q = 0; q < 2 * R; ++q) load_plane<S, R>(a, ring[q], z0 - R + q, y0, x0);
+    P pre;
+    for (int q = 0; q < 2 * R; ++q) {
+        fetch_plane<S, R>(a, pre, z0 - R + q, y0, x0);
+        store_plane<R>(ring[q], pre);
+    }
+    fetch_plane<S, R>(a, pre, z0 + R, y0, x0);
     for (int64_t z = z0; z < z1; ++z) {
-        const int in_slot = int((z - z0 + 2 * R) % K);
-        load_plane<S, R>(a, ring[in_slot], z + R, y0, x0);
+        store_plane<R>(ring[int((z - z0 + 2 * R) % K)], pre);  // plane z + R
         __syncthreads();
+        if (z + 1 < z1) fetch_plane<S, R>(a, pre, z + 1 + R, y0, x0);  // in flight while plane z computes
         const int c_slot = int((z - z0 + R) % K);
 #pragma unroll
         for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {

@@ -362,6 +362,7 @@ int max_tb(const st_plan* p, int tx, int ty) {
     int tb = 1;
     if (is_march(p->variant)) return march_max_tb(p->shape, p->radius, march_vmax(p->variant));
     if (p->variant == VARIANT_RESIDENT) return std::max(1, std::min(64, resident_max_tb(p)));
+    if (p->variant == VARIANT_MFMA) return 1;
     if (p->variant == VARIANT_STREAM) {
         while (tb < 16 && stream_lds_bytes(p->radius, tb + 1, tx, ty) <= lds_limit()) ++tb;
     } else {
@@ -395,6 +396,7 @@ int launch_pass(const st_plan* p, const void* src, void* dst, const float* kappa
         return fail(ST_EUNSUPPORTED, "launch_pass called on a naive plan");
     }
     const int ti = tile_index(p->tile_x, p->tile_y);
+    if (p->variant == VARIANT_MFMA && levels == 1 && mfma_usable(p)) return launch_mfma(p, src, dst, s);
     if (is_march(p->variant) && march_usable(p) &&
         levels <= march_max_tb(p->shape, p->radius, march_vmax(p->variant)))
         return launch_march(p, src, dst, levels, march_vmax(p->variant), s);
