@@ -53,8 +53,8 @@ def gstencil_s(steps: int, rows: int, cols: int, seconds: float) -> float:
 
 
 KERNEL_NAMES = {0: "sweep_tiled", 1: "sweep_stream", 2: "sweep_march", 3: "sweep_march", 4: "sweep_march",
-                5: "sweep_resident"}
-VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1", 5: "resident"}
+                5: "sweep_resident", 6: "sweep_mfma"}
+VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1", 5: "resident", 6: "mfma"}
 
 
 def kernel_source_hash() -> str:

@@ -295,7 +295,9 @@ int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double
  * {1, 2, 3, 4, 6, 8} within their LDS budget; marching with one, four and, when cols % 8 == 0,
  * eight columns per lane at every depth each offers, each depth above 1 also with segments of
  * at least 1/2 (when that is 2 rows or more), 1, 2, 4 and 8 x r (tb - 1) rows
- * (stencil_set_march_segment).
+ * (stencil_set_march_segment); the resident variant at swap depths {1, 2, 4, 8, 12, 16, 24, 32, 48}
+ * where the grid's tiles allow them; the matrix-core variant only for plans created with
+ * ST_FLAG_ALLOW_MFMA (periodic and framed plans: the marching variants only).
  * Clobbers out and workspace (which must be sized for sample_steps).  Writes
  * the chosen values to *tb_out, *tile_x_out, *tile_y_out when non-NULL.
  * Synchronises the stream.  Errors: as stencil_run; ST_EINVAL for a varcoef plan (see
@@ -453,7 +455,7 @@ int surrogate_loss_grad(sg_model* m, const float* params, const float* u0, const
  * another): scale[2b] = inv = fp32(1 / s), scale[2b + 1] = gain = fp32(2^-11 s), s = the RMS of
  * field b in FP64 (a fixed-order two-stage sum; s = 1 for an all-zero field).  For
  * surrogate_loss_grad's `scale` argument when the fields given there are crops of larger fields.
- * Workspace: n * 64 doubles.  Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
+ * Workspace: n * 256 doubles.  Asynchronous.  Errors: ST_EINVAL, ST_ENOWS, ST_EHIP. */
 int surrogate_field_scale(const float* u0, int n, int64_t rows, int64_t cols, float* scale, void* workspace,
                           size_t ws_bytes, void* stream);
 

@@ -852,7 +852,7 @@ __global__ void diff_norms_finish(const double* partial, int nblk, double* out2)
 
 // Scale constants of each field: s = RMS of the field's cells (FP64, fixed-order two-stage sum;
 // s = 1 for an all-zero field), scale[2b] = fp32(1 / s), scale[2b + 1] = fp32(2^-11 s).
-constexpr int SCB = 64;  // stage-1 blocks per field
+constexpr int SCB = 256;  // stage-1 blocks per field
 __global__ __launch_bounds__(256) void field_scale_partial(const float* u, int64_t n, double* partial) {
     __shared__ double red[256];
     const int b = blockIdx.y;

@@ -288,7 +288,7 @@ def test_train_entry_point_resume_and_composition(g):
         grad = torch.zeros(lib.SG_PARAM_COUNT, dtype=torch.float32, device=g.DEV)
         loss = torch.zeros(1, dtype=torch.float64, device=g.DEV)
         scale = torch.empty(2 * B, dtype=torch.float32, device=g.DEV)
-        scws = torch.empty(B * 64 * 8, dtype=torch.uint8, device=g.DEV)
+        scws = torch.empty(B * 256 * 8, dtype=torch.uint8, device=g.DEV)
         for k in range(S):
             lib.surrogate_synth_fields(cd[k * B:(k + 1) * B], B, G, G, U0, KP)
             lib.surrogate_field_scale(U0, B, G, G, scale, scws)  # each crop takes its whole field's scale
