@@ -322,7 +322,12 @@ int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* byt
  * device and read back; the loop stops once it is <= tol or after max_steps steps.  `out`
  * receives the last iterate, *steps_done the number of steps taken (a multiple of check_every
  * unless max_steps cut the last interval), *rel_residual the last residual.  The result is
- * bitwise the same as stencil_run(plan, in, out, *steps_done).  Synchronises at every check.
+ * bitwise the same as stencil_run(plan, in, out, *steps_done).  With a marching variant the
+ * test itself runs on the device and raises a flag that turns the passes enqueued after
+ * convergence into no-ops, so the host enqueues checks in chunks of 1, 2, 4, ... 64 and
+ * synchronises once per chunk; other variants synchronise at every check.  The call returns
+ * with the stream idle.  The workspace (stencil_solve_ws_bytes) holds the previous iterate,
+ * stencil_run's ping-pong field, the reduction's partial sums and the device-side record.
  * Errors: as stencil_run; ST_EINVAL for a varcoef plan or bad counts. */
 int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
                   int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream);

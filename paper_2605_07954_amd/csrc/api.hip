@@ -668,9 +668,43 @@ int stencil_solve_ws_bytes(const st_plan* plan, int64_t check_every, size_t* byt
     if (int rc = stencil_norms_ws_bytes(plan, &nb)) return rc;
     if (int rc = stencil_workspace_bytes(plan, check_every, &run_ws)) return rc;
     const size_t field = (size_t(field_cells(plan)) * elem_size(plan->storage) + 255) & ~size_t(255);
-    *bytes = field + std::max(run_ws, field) + ((nb + 255) & ~size_t(255)) + 256;
+    *bytes = field + std::max(run_ws, field) + ((nb + 255) & ~size_t(255)) + 256 + 256;
     return ST_OK;
 }
+
+}  // extern "C"
+
+namespace st {
+namespace {
+
+// Solve bookkeeping on the device: rec = {stop flag, pad, steps done (int64), relative residual}.
+struct SolveRec {
+    int stop;
+    int pad;
+    int64_t steps;
+    double rel;
+};
+
+__global__ void solve_reset(SolveRec* r) {
+    r->stop = 0;
+    r->steps = 0;
+    r->rel = 0.0;
+}
+
+// After an interval: the relative residual of its last step; raise the stop flag at convergence
+// or at the last interval, and record where the run stopped.
+__global__ void solve_check(const double* sums, double tol, int64_t steps_after, int last, SolveRec* r) {
+    if (r->stop) return;
+    const double rel = sums[1] > 0.0 ? sqrt(sums[0] / sums[1]) : sqrt(sums[0]);
+    r->rel = rel;
+    r->steps = steps_after;
+    if (rel <= tol || last) r->stop = 1;
+}
+
+}  // namespace
+}  // namespace st
+
+extern "C" {
 
 int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, int64_t check_every, double tol,
                   int64_t* steps_done, double* rel_residual, void* workspace, size_t ws_bytes, void* stream) {
@@ -692,15 +726,55 @@ int stencil_solve(st_plan* plan, const void* in, void* out, int64_t max_steps, i
     const size_t scratch_bytes = std::max(run_ws, field);
     void* nscr = ws + field + scratch_bytes;           // norms partial sums
     double* sums = reinterpret_cast<double*>(static_cast<char*>(nscr) + ((nb + 255) & ~size_t(255)));
+    SolveRec* rec = reinterpret_cast<SolveRec*>(reinterpret_cast<char*>(sums) + 256);
     hipStream_t s = static_cast<hipStream_t>(stream);
     // the two runs per check differ in their buffers and step counts, so a cached graph would be
     // captured again on every call: enqueue directly for the duration of the solve
-    struct FlagsGuard {
+    struct Guard {
         st_plan* p;
         uint32_t saved;
-        ~FlagsGuard() { p->flags = saved; }
+        ~Guard() {
+            p->flags = saved;
+            p->stop = nullptr;
+        }
     } guard{plan, plan->flags};
     plan->flags &= ~ST_FLAG_GRAPH;
+    // Marching plans: the convergence test runs on the device, where it raises a flag that turns
+    // the remaining passes and reductions into no-ops, so the host enqueues checks in growing
+    // chunks (1, 2, 4, ... 64) and synchronises once per chunk, not once per check.  Other
+    // variants read the residual back at every check.
+    const bool on_device = plan->kind == KIND_CONST && !(plan->flags & ST_FLAG_NAIVE) && is_march(plan->variant) &&
+                           march_usable(plan) &&
+                           plan->tb <= march_max_tb(plan->shape, plan->radius, march_vmax(plan->variant));
+    if (on_device) {
+        clear_stale_error();
+        hipLaunchKernelGGL(solve_reset, dim3(1), dim3(1), 0, s, rec);
+        ST_LAUNCH_CHECK("solve_reset");
+        plan->stop = &rec->stop;
+        const void* cur = in;
+        int64_t enq = 0;
+        for (int64_t chunk = 1; enq < max_steps; chunk = std::min<int64_t>(chunk * 2, 64)) {
+            for (int64_t c = 0; c < chunk && enq < max_steps; ++c) {
+                const int64_t k = std::min(check_every, max_steps - enq);
+                if (int rc = stencil_run(plan, cur, prev, k - 1, scratch, scratch_bytes, stream)) return rc;
+                if (int rc = stencil_run(plan, prev, out, 1, scratch, scratch_bytes, stream)) return rc;
+                enq += k;
+                if (int rc = launch_norms(plan, prev, out, sums, nscr, nb, &rec->stop, s)) return rc;
+                hipLaunchKernelGGL(solve_check, dim3(1), dim3(1), 0, s, sums, tol, enq, enq == max_steps ? 1 : 0, rec);
+                ST_LAUNCH_CHECK("solve_check");
+                cur = out;
+            }
+            SolveRec h;
+            ST_HIP_CHECK(hipMemcpyAsync(&h, rec, sizeof(h), hipMemcpyDeviceToHost, s));
+            ST_HIP_CHECK(hipStreamSynchronize(s));
+            if (h.stop) {
+                *steps_done = h.steps;
+                *rel_residual = h.rel;
+                return ST_OK;
+            }
+        }
+        return fail(ST_ESTATE, "internal: the solve ended without its stop record");
+    }
     const void* cur = in;
     int64_t done = 0;
     double rel = 0.0;

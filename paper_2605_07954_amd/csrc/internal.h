@@ -84,6 +84,7 @@ struct st_plan {
     int64_t seg_min;  // marching: least output rows per task (0: one task per resident wavefront)
     int bc;             // ST_BC_CONST (halo b), ST_BC_PERIODIC or ST_BC_FRAME (marching variants only)
     int64_t spin_limit; // resident variant: polls before a neighbour wait gives up
+    const int* stop;    // while a solve runs: device flag that turns its marching passes into no-ops
     const void* frame;  // ST_BC_FRAME: caller-owned device frame (storage type)
     // cached hipGraph of a full run (ST_FLAG_GRAPH)
     void* graph_exec;
@@ -117,6 +118,9 @@ int prepare_lds(const void* fn, size_t bytes);
 // Workgroups of NT threads with `lds` bytes of dynamic LDS that fit the device at once.
 int resident_blocks(const void* fn, size_t lds, int* blocks);
 bool stream_usable(const st_plan* p);
+// FP64 norms (norms.hip) with an optional device stop flag (NULL: always run).
+int launch_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace, size_t ws_bytes,
+                 const int* stop, hipStream_t s);
 // Cells of one field of the plan (planes * rows * cols).
 inline int64_t field_cells(const st_plan* p) { return p->planes * p->rows * p->cols; }
 // LDS-resident cooperative sweep (resident.hip): the whole run in one launch; workspace = one field

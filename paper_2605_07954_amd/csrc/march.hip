@@ -80,6 +80,7 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     a.b = p->bq;
     a.bc = p->bc;
     a.frame = p->frame;
+    a.stop = p->stop;
     std::memcpy(a.w, p->w, sizeof(a.w));
     const int64_t outw = V * (64 - 2 * march::halo_lanes(p->radius, levels, V));
     a.bands = int((p->cols + outw - 1) / outw);

@@ -21,6 +21,7 @@ struct MarchArgs {
     int bands;
     float b;
     int bc;             // boundary rule (march::BC_*)
+    const int* stop;    // nullable: when it holds a nonzero value the pass does nothing
     const void* frame;  // BC_FRAME: the caller's halo frame
     float w[MAXK];
 };
@@ -38,6 +39,7 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t task = int64_t(blockIdx.x) * MWAVES + wave;
     if (task >= a.tasks) return;
+    if (a.stop && __hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     constexpr int H = halo_lanes(R, TB, V);
     constexpr int OUTW = V * (64 - 2 * H);
     const int64_t band = task % a.bands;

@@ -17,6 +17,7 @@ struct NormArgs {
     const void* up;
     double* partial;  // [NBLK][4]
     double* out4;
+    const int* stop;  // nullable: a nonzero value skips the reduction
     int64_t rows, cols;
     int r;
     double b;
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(NT) void norms_stage1(NormArgs a) {
     using T = typename F::T;
     const T* u = static_cast<const T*>(a.u);
     const T* up = static_cast<const T*>(a.up);
+    if (a.stop && __hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     __shared__ double P[PMAX];
     for (int t = threadIdx.x; t < PMAX; t += NT) P[t] = a.P[t];
     __syncthreads();
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(NT) void norms_stage1(NormArgs a) {
 }
 
 __global__ __launch_bounds__(NT) void norms_stage2(NormArgs a) {
+    if (a.stop && __hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     __shared__ double red[4][NT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -158,9 +161,15 @@ extern "C" int stencil_norms_ws_bytes(const st_plan* plan, size_t* bytes) {
 
 extern "C" int stencil_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
                              size_t ws_bytes, void* stream) {
+    return launch_norms(plan, u_prev, u, out4, workspace, ws_bytes, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int st::launch_norms(const st_plan* plan, const void* u_prev, const void* u, double* out4, void* workspace,
+                     size_t ws_bytes, const int* stop, hipStream_t s) {
     if (!plan || !u || !out4) return fail(ST_EINVAL, "NULL argument");
     if (!workspace || ws_bytes < size_t(NBLK) * 4 * sizeof(double)) return fail(ST_ENOWS, "workspace too small");
     NormArgs a;
+    a.stop = stop;
     a.u = u;
     a.up = u_prev;
     a.partial = static_cast<double*>(workspace);
@@ -200,7 +209,6 @@ extern "C" int stencil_norms(const st_plan* plan, const void* u_prev, const void
         for (int x = 0; x < kk; ++x)
             a.P[(y + 1) * (kk + 1) + x + 1] =
                 w[y * kk + x] + a.P[y * (kk + 1) + x + 1] + a.P[(y + 1) * (kk + 1) + x] - a.P[y * (kk + 1) + x];
-    hipStream_t s = static_cast<hipStream_t>(stream);
     // groups of four cells with one vector load each when rows hold whole groups and both fields
     // start on a group boundary (16 bytes for FP32, 8 for 16-bit storage)
     const size_t gbytes = plan->storage == ST_F32 ? 16 : 8;

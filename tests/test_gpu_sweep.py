@@ -594,3 +594,51 @@ def test_solve_until_converged(g, flags):
     a = oracle.stencil_f32(u0, W, b, done - 100).astype(np.float64)
     a1 = oracle.stencil_f32(u0, W, b, done - 101).astype(np.float64)
     assert np.sqrt(np.sum((a - a1) ** 2) / np.sum(a * a)) > 1e-6   # the previous check had not converged
+
+
+def _rel_residual(u0, W, b, t):
+    a = oracle.stencil_f32(u0, W, b, t).astype(np.float64)
+    a1 = oracle.stencil_f32(u0, W, b, t - 1).astype(np.float64)
+    return np.sqrt(np.sum((a - a1) ** 2) / np.sum(a * a))
+
+
+@pytest.mark.parametrize("variant", [2, 3, 4, 0])
+def test_solve_check_chunks(g, variant):
+    """The convergence test at short intervals, so that the solve crosses several of its chunks of
+    checks (marching variants decide on the device; the tiled variant reads every residual back):
+    the field is bitwise the plain run of the steps taken, the first check at or below tol is the
+    one it stops at, a budget that ends inside an interval stops there, and a tolerance met at the
+    first check stops after one interval."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, b = 48, 72, 0.5
+    W = wl.heat5_weights()
+    u0 = np.random.default_rng(23).random((rows, cols), dtype=np.float32)
+    plan = lib.stencil_plan(rows, cols, 1, W, b, "f32", 0)
+    try:
+        lib.stencil_set_variant(plan, variant)
+        lib.stencil_set_blocking(plan, 2, 0, 0)
+        x = g.to_dev(u0)
+        out = torch.empty_like(x)
+        ce = 7
+        ws = torch.empty(lib.stencil_solve_ws_bytes(plan, ce), dtype=torch.uint8, device=g.DEV)
+        tol = 5e-6
+        done, res = lib.stencil_solve(plan, x, out, 100000, ce, tol, ws)
+        got = g.to_host(out)
+        say(f"variant {variant}: {done} steps ({done // ce} checks), relative residual {res:.3e}")
+        assert done % ce == 0 and done // ce > 130      # several chunks of 1, 2, 4, ... 64 checks
+        np.testing.assert_array_equal(got, oracle.stencil_f32(u0, W, b, done))
+        rr = _rel_residual(u0, W, b, done)
+        assert abs(rr - res) <= 1e-9 * rr and res <= tol
+        assert _rel_residual(u0, W, b, done - ce) > tol
+        # a budget that ends inside an interval, never converged: stops at max_steps exactly
+        done2, res2 = lib.stencil_solve(plan, x, out, 100, ce, 0.0, ws)
+        assert done2 == 100
+        np.testing.assert_array_equal(g.to_host(out), oracle.stencil_f32(u0, W, b, 100))
+        assert abs(_rel_residual(u0, W, b, 100) - res2) <= 1e-9 * res2
+        # met at the first check
+        done3, _ = lib.stencil_solve(plan, x, out, 1000, ce, 1.0, ws)
+        assert done3 == ce
+        np.testing.assert_array_equal(g.to_host(out), oracle.stencil_f32(u0, W, b, ce))
+    finally:
+        lib.stencil_destroy(plan)
