@@ -22,6 +22,7 @@ The JSON line also carries
 from __future__ import annotations
 
 import argparse
+import functools
 import hashlib
 import json
 import math
@@ -302,6 +303,26 @@ def extra_star9(torch, lib, stream) -> dict:
     return res
 
 
+def extra_star9_profile(torch, lib, stream, variant: int = 2, tb: int = 6, storage: str = "f32") -> dict:
+    """Star-2D9P 8192^2 with one fixed engine and depth and no tuning, 48 steps: a short run for
+    counter profiles of one marching kernel."""
+    p = wl.star9_precision(rows=8192, cols=8192, steps=48)
+    xh = torch.from_numpy(p.u0).to("cuda")
+    if storage != "f32":
+        xh = xh.to(torch.bfloat16 if storage == "bf16" else torch.float16).view(torch.int16)
+    o = torch.empty_like(xh)
+    w2 = torch.empty_like(xh)
+    plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, storage, 0)
+    lib.stencil_set_variant(plan, variant)
+    lib.stencil_set_blocking(plan, tb)
+    run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
+    run()
+    t = time_median(run, 3, stream)
+    lib.stencil_destroy(plan)
+    return {"storage": storage, "variant": VARIANT_NAMES[variant], "tb": tb,
+            "gstencil_s": gstencil_s(p.steps, p.rows, p.cols, t)}
+
+
 def extra_batched(torch, lib, stream) -> dict:
     """256 grids, one hipGraph launch of the batched kernels vs per-grid launches (each grid autotuned)."""
     probs = wl.batch_problems()
@@ -506,12 +527,16 @@ EXTRAS = {"box49_tb1": ("box49_16384_tb1", extra_box49_tb1), "heat2d": ("heat2d_
           "star9": ("star9_8192_500", extra_star9),
           "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate),
           "surrogate_trained": ("surrogate_1024_K16_trained", extra_surrogate_trained),
-          "star7_3d": ("star7_3d_512", extra_3d), "surrogate_profile": ("surrogate_profile", extra_surrogate_profile), "periodic": ("star9_8192_periodic", extra_periodic),
+          "star7_3d": ("star7_3d_512", extra_3d), "surrogate_profile": ("surrogate_profile", extra_surrogate_profile),
+          "star9_profile": ("star9_profile", extra_star9_profile), "periodic": ("star9_8192_periodic", extra_periodic),
           "norms": ("norms_16384", extra_norms)}
 
 
+PROFILE_ONLY = ("surrogate_profile", "star9_profile")  # short runs for counter profiles, not figures
+
+
 def extras(torch, lib, stream) -> dict:
-    return {key: fn(torch, lib, stream) for key, fn in EXTRAS.values() if key != "surrogate_profile"}
+    return {key: fn(torch, lib, stream) for key, fn in EXTRAS.values() if key not in PROFILE_ONLY}
 
 
 def main():
@@ -532,6 +557,7 @@ def main():
     ap.add_argument("--cpu-oracle-timings", action="store_true",
                     help="only time the CPU oracle on every configuration (host cores; no GPU work)")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"], help="star9_profile: storage type")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -554,6 +580,8 @@ def main():
     stream = torch.cuda.current_stream()
     if args.workload != "box49":
         key, fn = EXTRAS[args.workload]
+        if args.workload == "star9_profile":
+            fn = functools.partial(fn, variant=args.variant or 2, tb=args.tb or 6, storage=args.storage)
         print(json.dumps({"workload": key, **fn(torch, lib, stream)}), flush=True)
         return
     p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)

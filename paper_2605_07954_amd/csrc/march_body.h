@@ -229,6 +229,16 @@ __device__ __forceinline__ void store_cells(void* dst, int64_t off, const Cells<
     }
 }
 
+// A register copy that the compiler cannot fold away.  An FP32 row moves from its FIFO slot into the
+// ring unchanged; folded, the two slots become one register set live for D + 2R + 1 iterations,
+// longer than the unrolled loop, and the copies that restore the allocation at the loop's back edge
+// then wait for every load in flight.  Copied, each set lives for at most U iterations.
+template <int V>
+__device__ __forceinline__ void pin_copy(Cells<V>& q) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) asm volatile("v_mov_b32 %0, %1" : "=v"(q.c[c]) : "v"(q.c[c]));
+}
+
 template <int R, int V>
 __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
 #pragma unroll
@@ -377,30 +387,44 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
         for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
     }
     if constexpr (D > 0) {
+        // the ring's first rows arrive before the FIFO is filled: the loop's entry then carries no
+        // pending load into a ring register, so the loop waits only for the FIFO row it consumes
+        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-        for (int t = 0; t < D; ++t) fifo[(2 * R + t) % D] = fetch(j0 + 2 * R + t);
+        for (int t = 0; t < D; ++t) {
+            // issued in the order the loop consumes them (the scheduler would otherwise reorder
+            // these independent loads, and the first row needed could be the last to arrive)
+            fifo[(2 * R + t) % D] = fetch(j0 + 2 * R + t);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
-    const int64_t iters = (y1 - y0) + 2 * R * (TB - 1);
-    for (int64_t i0 = 0; i0 < iters; i0 += U) {
+    // The loop runs whole groups of U iterations: the last group may run up to U - 1 iterations past
+    // the segment, on rows whose loads are clamped (or take their outside value) and whose outputs
+    // are not stored.  No exit from inside a group keeps the FIFO registers fixed across the loop's
+    // back edge, so the loads in flight there are not waited for.  (A task spans at most 2^31 + 2R(TB
+    // - 1) iterations, so the counter fits 32 bits, whose compares are scalar instructions.)
+    const uint32_t iters = uint32_t((y1 - y0) + 2 * R * (TB - 1));
+    for (uint32_t i0 = 0; i0 < iters; i0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u;
-            if (i >= iters) break;
+            const uint32_t i = i0 + u;
             Row<R, V>& in = lv[0][(u + 2 * R) % N];  // input row j0 + i + 2R enters the window
             if constexpr (D > 0) {
                 const int f = (u + 2 * R) % D;
                 const int64_t j = j0 + i + 2 * R;
-                set_own<R, V>(in, cells_of<S, R, V, EDGE, XBC>(a, fifo[f], j, gx, cm));
+                Cells<V> q = cells_of<S, R, V, EDGE, XBC>(a, fifo[f], j, gx, cm);
+                if constexpr (S == ST_F32) pin_copy<V>(q);
+                set_own<R, V>(in, q);
                 fifo[f] = fetch(j + D);
             }
             if (SIDES) fill_sides<R, V>(in);
 #pragma unroll
             for (int l = 1; l <= TB; ++l) {
-                if (i < 2 * R * (l - 1)) break;  // level l - 1 does not have 2R+1 rows yet
-                const int64_t m = y0 - R * (TB - 1) + i - int64_t(l - 1) * R;  // row of level l
+                if (i < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
+                const int64_t m = y0 - R * (TB - 1) + int64_t(i) - int64_t(l - 1) * R;  // row of level l
                 Cells<V> q = apply<R, V, SHAPE, N>(lv[l - 1], u + l - 1, w);
                 if (l == TB) {
-                    if (writer) store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm);
+                    if (writer && m < y1) store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm);
                 } else {
                     Row<R, V>& x = lv[l][(u + l - 1) % N];
                     // every level is rounded to the storage type; cells outside the grid keep their
