@@ -5,6 +5,7 @@
 #pragma once
 
 #include "internal.h"
+#include "star_centre.h"
 #include "storage.h"
 
 namespace st {
@@ -333,6 +334,34 @@ __device__ __forceinline__ void store_row(void* dst, int64_t row_off, int64_t gx
 template <int R, int V, int SHAPE, int N>
 __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const float* w) {
     constexpr int K = 2 * R + 1;
+    if constexpr (SHAPE == SHAPE_STAR && V >= 4) {
+        // the centre row's side taps take the neighbouring lanes' columns as DPP-shifted FMA operands
+        // (star_centre.h), which saves the 2R lane moves per row and level; same order of operations
+        const Row<R, V>& mid = ring[(base + R) % N];
+        Cells<V> o;
+#pragma unroll
+        for (int c = 0; c < V; ++c) o.c[c] = w[R * K + R] * mid.v[R + c];
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+            if (dy == 0) {
+                float x[V], ws[2 * R];
+#pragma unroll
+                for (int c = 0; c < V; ++c) x[c] = mid.v[R + c];
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    ws[t] = w[R * K + t];              // dx = t - R
+                    ws[R + t] = w[R * K + R + 1 + t];  // dx = t + 1
+                }
+                StarCentre<R, V>::apply(o.c, x, ws);
+                continue;
+            }
+            const Row<R, V>& x = ring[(base + R + dy) % N];
+            const float wt = w[(dy + R) * K + R];
+#pragma unroll
+            for (int c = 0; c < V; ++c) o.c[c] = __builtin_fmaf(wt, x.v[R + c], o.c[c]);
+        }
+        return o;
+    }
     Row<R, V> mid = ring[(base + R) % N];
     if constexpr (SHAPE == SHAPE_STAR) fill_sides<R, V>(mid);
     Cells<V> o;
@@ -457,7 +486,10 @@ __device__ __forceinline__ void load_weights(const float* w, float* wv) {
     constexpr int K = 2 * R + 1;
 #pragma unroll
     for (int q = 0; q < K * K; ++q) {
-        if constexpr (V == 1 && SHAPE == SHAPE_BOX && R >= 3) {
+        // (a star's centre-row side weights feed the DPP FMAs of star_centre.h, whose second
+        // operand must be a vector register)
+        const bool star_side = SHAPE == SHAPE_STAR && V >= 4 && q / K == R && q % K != R;
+        if ((V == 1 && SHAPE == SHAPE_BOX && R >= 3) || star_side) {
             const float sw = w[q];
             asm volatile("v_mov_b32 %0, %1" : "=v"(wv[q]) : "s"(sw));
         } else {
