@@ -355,6 +355,29 @@ def extra_batched(torch, lib, stream) -> dict:
             "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
 
 
+def extra_batched_profile(torch, lib, stream, config: str = "") -> dict:
+    """The 256-grid batch with a fixed configuration and no tuning, run 3 times: a short run for
+    counter profiles.  `config`: comma-separated shape:radius:engine:depth:segment_rows entries,
+    e.g. "star:1:march:8:0" (segment_rows 0: the default sizing)."""
+    probs = wl.batch_problems()
+    ins = [torch.from_numpy(q.u0).to("cuda") for q in probs]
+    outs = [torch.empty_like(i) for i in ins]
+    plans = [lib.stencil_plan(q.rows, q.cols, q.radius, q.weights, 0.0, "f32", 0) for q in probs]
+    batch = lib.stencil_batch_create(plans, [q.steps for q in probs], lib.ST_FLAG_GRAPH)
+    for ent in filter(None, config.split(",")):
+        shape, r, engine, depth, seg = ent.split(":")
+        lib.stencil_batch_set_class(batch, shape, int(r), engine, int(depth))
+        lib.stencil_batch_set_segment(batch, shape, int(r), int(seg))
+    bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        lib.stencil_run_batched(batch, ins, outs, bws, stream)
+    torch.cuda.synchronize()
+    lib.stencil_batch_destroy(batch)
+    for pl in plans:
+        lib.stencil_destroy(pl)
+    return {"config": config, "updates": sum(q.rows * q.cols * q.steps for q in probs)}
+
+
 def extra_surrogate(torch, lib, stream) -> dict:
     """Surrogate inference on 1024^2 (75,456 FLOP per cell on the MFMA path) vs the fastest plain 16
     varcoef steps (autotuned tile and depth); timing only, the accuracy of a trained network is
@@ -528,11 +551,12 @@ EXTRAS = {"box49_tb1": ("box49_16384_tb1", extra_box49_tb1), "heat2d": ("heat2d_
           "batched": ("batched_256", extra_batched), "surrogate": ("surrogate_1024_K16", extra_surrogate),
           "surrogate_trained": ("surrogate_1024_K16_trained", extra_surrogate_trained),
           "star7_3d": ("star7_3d_512", extra_3d), "surrogate_profile": ("surrogate_profile", extra_surrogate_profile),
-          "star9_profile": ("star9_profile", extra_star9_profile), "periodic": ("star9_8192_periodic", extra_periodic),
+          "star9_profile": ("star9_profile", extra_star9_profile),
+          "batched_profile": ("batched_profile", extra_batched_profile), "periodic": ("star9_8192_periodic", extra_periodic),
           "norms": ("norms_16384", extra_norms)}
 
 
-PROFILE_ONLY = ("surrogate_profile", "star9_profile")  # short runs for counter profiles, not figures
+PROFILE_ONLY = ("surrogate_profile", "star9_profile", "batched_profile")  # short runs for counter profiles, not figures
 
 
 def extras(torch, lib, stream) -> dict:
@@ -558,6 +582,7 @@ def main():
                     help="only time the CPU oracle on every configuration (host cores; no GPU work)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"], help="star9_profile: storage type")
+    ap.add_argument("--batch-config", default="", help="batched_profile: shape:radius:engine:depth:segment_rows,...")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -582,6 +607,8 @@ def main():
         key, fn = EXTRAS[args.workload]
         if args.workload == "star9_profile":
             fn = functools.partial(fn, variant=args.variant or 2, tb=args.tb or 6, storage=args.storage)
+        elif args.workload == "batched_profile":
+            fn = functools.partial(fn, config=args.batch_config)
         print(json.dumps({"workload": key, **fn(torch, lib, stream)}), flush=True)
         return
     p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)

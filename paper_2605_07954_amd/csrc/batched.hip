@@ -145,8 +145,14 @@ __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
     if (task >= pre[a.n]) return;
     const int k = upper_index(pre, a.n + 1, task);
     const BatchDesc& d = a.desc[a.order[a.s0 + k]];
+    // a grid's tasks go down each band in turn, so a workgroup's wavefronts take neighbouring
+    // segments, and every other segment is marched upwards: two neighbours then read the rows they
+    // share (the r tb rows either side of their boundary) at the same time -- both at their start or
+    // both at their end -- and the second read finds them in the cache of the first.  Wavefronts 0
+    // and 2 of a workgroup go up, so the pairs that meet at their start (the surest to be in step)
+    // are wavefronts 0-1 and 2-3 whatever segment the workgroup starts at.
     const int64_t t = task - pre[k];
-    const int64_t band = t % d.tiles_x, segi = t / d.tiles_x;
+    const int64_t segi = t % d.tiles_y, band = t / d.tiles_y;
     constexpr int H = march::halo_lanes(R, TB, MV);
     const int64_t y0 = segi * d.seg;
     const int64_t y1 = y0 + d.seg < d.rows ? y0 + d.seg : d.rows;
@@ -157,8 +163,9 @@ __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
     const int64_t X0 = band * (MV * (64 - 2 * H)) - MV * H;
     // input rows in flight: one ring length, except box r >= 3 with several levels (registers)
     constexpr int D = SH == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
-    if (d.vec) march::march_task<ST_F32, R, MV, SH, TB, D, true>(v, d.w, lane, y0, y1, X0);
-    else march::march_task<ST_F32, R, MV, SH, TB, D, false>(v, d.w, lane, y0, y1, X0);
+    const bool up = !(wave & 1);
+    if (d.vec) march::march_task_dir<ST_F32, R, MV, SH, TB, D, true>(v, d.w, lane, y0, y1, X0, up);
+    else march::march_task_dir<ST_F32, R, MV, SH, TB, D, false>(v, d.w, lane, y0, y1, X0, up);
 }
 
 using MarchPassFn = void (*)(MarchPassArgs);

@@ -178,6 +178,28 @@ __device__ __forceinline__ Raw<S, V> load_raw(const void* src, int64_t off) {
     return *reinterpret_cast<const Raw<S, V>*>(static_cast<const typename Fmt<S>::T*>(src) + off);
 }
 
+// Interior tasks address a lane's cells as a wavefront-uniform pointer (row start plus the band's
+// first column, scalar registers) plus the lane's byte offset V * lane * sizeof(T) < 2 KiB, which the
+// global loads and stores take as their 32-bit vector offset: no per-lane 64-bit address arithmetic.
+template <int S, int V>
+__device__ __forceinline__ uint32_t lane_bytes() {
+    return uint32_t(V * int(threadIdx.x & 63) * int(sizeof(typename Fmt<S>::T)));
+}
+template <int S, int V>
+__device__ __forceinline__ Raw<S, V> load_lane(const void* src, int64_t first, uint32_t loff) {
+    const char* p = reinterpret_cast<const char*>(static_cast<const typename Fmt<S>::T*>(src) + first);
+    return *reinterpret_cast<const Raw<S, V>*>(p + loff);
+}
+
+// Row clamps of interior tasks in 32-bit scalar compares (row indices of an interior task lie in
+// [-2^31, 2^32), grids have at most 2^31 rows): a prefetch past the last row (first row, upwards).
+__device__ __forceinline__ int64_t clamp_last(int64_t gy, int64_t rows) {
+    return uint32_t(gy) < uint32_t(rows) ? gy : rows - 1;
+}
+__device__ __forceinline__ int64_t clamp_first(int64_t gy) {
+    return int32_t(uint32_t(uint64_t(gy) >> 32)) < 0 ? 0 : gy;
+}
+
 // Exact widening to FP32.
 template <int S, int V>
 __device__ __forceinline__ Cells<V> widen(Raw<S, V> r) {
@@ -251,18 +273,23 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
 // `cells_of`), or wrap them on a periodic grid; interior tasks only clamp a prefetch past the grid's
 // last row.  A lane's vector never straddles the grid's side (cols % V == 0, and so is its first
 // column), so it wraps whole.
-template <int S, int V, bool VEC, bool EDGE, bool XBC>
-__device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m) {
+template <int S, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
+__device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
+                                                     int64_t X0) {
     const int64_t rows = a.rows, cols = a.cols;
     const bool wrap = EDGE && periodic<XBC>(a);
     int64_t g;
     if (wrap) {
         g = wrap_index(gy, rows);
-    } else {
+    } else if (EDGE) {
         g = gy < rows ? gy : rows - 1;
-        if (EDGE) g = g < 0 ? 0 : g;
+        g = g < 0 ? 0 : g;
+    } else {  // an interior task's prefetch runs past the grid's last row (first, marching upwards)
+        g = UP ? clamp_first(gy) : clamp_last(gy, rows);
     }
-    if constexpr (VEC || V == 1) {
+    if constexpr (!EDGE && (VEC || V == 1)) {
+        return load_lane<S, V>(a.src, g * cols + X0, lane_bytes<S, V>());
+    } else if constexpr (VEC || V == 1) {
         const int64_t x = wrap ? wrap_index(gx, cols) : (EDGE && !m.ok[0] ? 0 : gx);
         return load_raw<S, V>(a.src, g * cols + x);
     } else {
@@ -290,8 +317,9 @@ __device__ __forceinline__ Cells<V> cells_of(const MarchView& a, const RawRow& r
 // accesses EDGE tasks skip the load for cells outside the grid, which take their outside value (a
 // periodic grid loads the cells they wrap to); with element accesses they load clamped (or wrapped)
 // addresses and substitute.  Interior tasks only clamp a load past the grid's last row.
-template <int S, int R, int V, bool VEC, bool EDGE, bool XBC>
-__device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m) {
+template <int S, int R, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
+__device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
+                                             int64_t X0) {
     const int64_t rows = a.rows, cols = a.cols;
     if constexpr (VEC || V == 1) {
         Cells<V> q;
@@ -305,19 +333,23 @@ __device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int
                 for (int c = 0; c < V; ++c) q.c[c] = outside_value<S, XBC>(a, R, gy, gx + c);
             }
         } else {
-            q = widen<S, V>(load_raw<S, V>(a.src, (gy < rows ? gy : rows - 1) * cols + gx));
+            const int64_t g = UP ? clamp_first(gy) : clamp_last(gy, rows);
+            q = widen<S, V>(load_lane<S, V>(a.src, g * cols + X0, lane_bytes<S, V>()));
         }
         return q;
     } else {
-        return cells_of<S, R, V, EDGE, XBC>(a, fetch_raw<S, V, VEC, EDGE, XBC>(a, gy, gx, m), gy, gx, m);
+        return cells_of<S, R, V, EDGE, XBC>(a, fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, gy, gx, m, X0), gy, gx, m);
     }
 }
 
 // A lane's V outputs of one row: one vector store, or one element store per column inside the grid.
 template <int S, int V, bool VEC, bool EDGE>
 __device__ __forceinline__ void store_row(void* dst, int64_t row_off, int64_t gx, const Cells<V>& q,
-                                          const ColMask<V>& m) {
-    if constexpr (VEC || V == 1) {
+                                          const ColMask<V>& m, int64_t X0) {
+    if constexpr (!EDGE && (VEC || V == 1)) {
+        char* p = reinterpret_cast<char*>(static_cast<typename Fmt<S>::T*>(dst) + row_off + X0);
+        store_cells<S, V>(p + lane_bytes<S, V>(), 0, q);
+    } else if constexpr (VEC || V == 1) {
         store_cells<S, V>(dst, row_off + gx, q);
     } else {
         typename Fmt<S>::T* row = static_cast<typename Fmt<S>::T*>(dst) + row_off;
@@ -331,9 +363,10 @@ __device__ __forceinline__ void store_row(void* dst, int64_t row_off, int64_t gx
 // footprint reads the side columns of every row, which each ring row therefore carries from the
 // moment it enters; a star footprint reads them on the centre row only, so ring rows hold their own
 // columns and the centre row's sides are produced here, once per row and level as well.
-template <int R, int V, int SHAPE, int N>
+template <int R, int V, int SHAPE, int N, bool UP = false>
 __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const float* w) {
     constexpr int K = 2 * R + 1;
+    constexpr int DS = UP ? -1 : 1;  // marching upwards the ring holds the rows in the other order
     if constexpr (SHAPE == SHAPE_STAR && V >= 4) {
         // the centre row's side taps take the neighbouring lanes' columns as DPP-shifted FMA operands
         // (star_centre.h), which saves the 2R lane moves per row and level; same order of operations
@@ -355,7 +388,7 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
                 StarCentre<R, V>::apply(o.c, x, ws);
                 continue;
             }
-            const Row<R, V>& x = ring[(base + R + dy) % N];
+            const Row<R, V>& x = ring[(base + R + DS * dy) % N];
             const float wt = w[(dy + R) * K + R];
 #pragma unroll
             for (int c = 0; c < V; ++c) o.c[c] = __builtin_fmaf(wt, x.v[R + c], o.c[c]);
@@ -369,7 +402,7 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
     for (int c = 0; c < V; ++c) o.c[c] = w[R * K + R] * mid.v[R + c];
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
-        const Row<R, V>& x = dy == 0 ? mid : ring[(base + R + dy) % N];
+        const Row<R, V>& x = dy == 0 ? mid : ring[(base + R + DS * dy) % N];
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
             if ((dy == 0 && dx == 0) || !tap_on(SHAPE, dy, dx)) continue;
@@ -391,7 +424,11 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 // Input rows are loaded D iterations before they enter the window, into a FIFO of D raw rows (D a
 // multiple of N; the loop is unrolled D times).  With D = 0 a row is loaded into the ring slot that
 // level 1 has just released, one iteration ahead.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC>
+//
+// UP marches the segment from its last row to its first: the same steps with the row order
+// reversed (iteration i computes level-1 row y1 - 1 + R(TB-1) - i, and so on), and each ring read
+// through the reversed slot order, so that every cell still takes its taps in row-major order.
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC, bool UP = false>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                              int64_t X0) {
     constexpr int N = 2 * R + 1;
@@ -405,12 +442,14 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     const bool writer = lane >= H && lane < 64 - H && (!EDGE || cm.any);
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
     RawT<S, V, VEC> fifo[D > 0 ? D : 1];
-    const int64_t j0 = y0 - R * TB;  // input row j lives in ring slot (j - j0) % N, FIFO slot (j - j0) % D
-    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE, XBC>(a, j, gx, cm); };
+    // input row j lives in ring slot |j - j0| % N, FIFO slot |j - j0| % D
+    constexpr int64_t SG = UP ? -1 : 1;  // row step of the march
+    const int64_t j0 = UP ? y1 - 1 + R * TB : y0 - R * TB;
+    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, j, gx, cm, X0); };
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
     for (int t = 0; t < FIRST; ++t)
-        set_own<R, V>(lv[0][t], load_now<S, R, V, VEC, EDGE, XBC>(a, j0 + t, gx, cm));
+        set_own<R, V>(lv[0][t], load_now<S, R, V, VEC, EDGE, XBC, UP>(a, j0 + SG * t, gx, cm, X0));
     if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
 #pragma unroll
         for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
@@ -423,7 +462,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
         for (int t = 0; t < D; ++t) {
             // issued in the order the loop consumes them (the scheduler would otherwise reorder
             // these independent loads, and the first row needed could be the last to arrive)
-            fifo[(2 * R + t) % D] = fetch(j0 + 2 * R + t);
+            fifo[(2 * R + t) % D] = fetch(j0 + SG * (2 * R + t));
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -437,23 +476,31 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = i0 + u;
-            Row<R, V>& in = lv[0][(u + 2 * R) % N];  // input row j0 + i + 2R enters the window
+            Row<R, V>& in = lv[0][(u + 2 * R) % N];  // input row j0 +- (i + 2R) enters the window
             if constexpr (D > 0) {
                 const int f = (u + 2 * R) % D;
-                const int64_t j = j0 + i + 2 * R;
+                const int64_t j = j0 + SG * (int64_t(i) + 2 * R);
                 Cells<V> q = cells_of<S, R, V, EDGE, XBC>(a, fifo[f], j, gx, cm);
                 if constexpr (S == ST_F32) pin_copy<V>(q);
                 set_own<R, V>(in, q);
-                fifo[f] = fetch(j + D);
+                fifo[f] = fetch(j + SG * D);
             }
             if (SIDES) fill_sides<R, V>(in);
 #pragma unroll
             for (int l = 1; l <= TB; ++l) {
                 if (i < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
-                const int64_t m = y0 - R * (TB - 1) + int64_t(i) - int64_t(l - 1) * R;  // row of level l
-                Cells<V> q = apply<R, V, SHAPE, N>(lv[l - 1], u + l - 1, w);
+                // row of level l
+                const int64_t m = UP ? y1 - 1 + R * (TB - 1) - int64_t(i) + int64_t(l - 1) * R
+                                     : y0 - R * (TB - 1) + int64_t(i) - int64_t(l - 1) * R;
+                Cells<V> q = apply<R, V, SHAPE, N, UP>(lv[l - 1], u + l - 1, w);
                 if (l == TB) {
-                    if (writer && m < y1) store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm);
+                    // (the row against the segment's far end in 32-bit scalar compares: downwards
+                    // m >= y0 here and m - y0 < 2^32; upwards the sign of m - y0)
+                    const int64_t mr = m - y0;
+                    const bool in_seg = UP ? int32_t(uint32_t(uint64_t(mr) >> 32)) >= 0
+                                           : uint32_t(mr) < uint32_t(y1 - y0);
+                    if (writer && in_seg)
+                        store_row<S, V, VEC, EDGE>(a.dst, m * cols, gx, q, cm, X0);
                 } else {
                     Row<R, V>& x = lv[l][(u + l - 1) % N];
                     // every level is rounded to the storage type; cells outside the grid keep their
@@ -470,8 +517,9 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     set_own<R, V>(x, q);
                     if (SIDES) fill_sides<R, V>(x);
                 }
-                if (D == 0 && l == 1) {  // input row m1 - R is no longer needed: fetch the row N further down
-                    set_own<R, V>(lv[0][u % N], load_now<S, R, V, VEC, EDGE, XBC>(a, j0 + i + N, gx, cm));
+                if (D == 0 && l == 1) {  // input row m1 -+ R is no longer needed: fetch the row N further on
+                    set_own<R, V>(lv[0][u % N],
+                                  load_now<S, R, V, VEC, EDGE, XBC, UP>(a, j0 + SG * (int64_t(i) + N), gx, cm, X0));
                 }
             }
         }
@@ -509,6 +557,20 @@ __device__ __forceinline__ void march_task(const MarchView& a, const float* w, i
     load_weights<R, V, SHAPE>(w, wv);
     if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0);
     else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0);
+}
+
+// The same task marched upwards when `up` is set (constant halo).  Upward tasks take the general
+// (edge) form only, which keeps the kernel's code to one more copy of the loop.
+template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true>
+__device__ __forceinline__ void march_task_dir(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
+                                               int64_t X0, bool up) {
+    if (!up) {
+        march_task<S, R, V, SHAPE, TB, D, VEC, false>(a, w, lane, y0, y1, X0);
+        return;
+    }
+    float wv[(2 * R + 1) * (2 * R + 1)];
+    load_weights<R, V, SHAPE>(w, wv);
+    march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, true>(a, wv, lane, y0, y1, X0);
 }
 
 }  // namespace march

@@ -567,62 +567,94 @@ __global__ __launch_bounds__(256) void l6_bwd_data(const float* params, const fl
 // ---------------------------------------------------------------------------
 constexpr int RH = 32, RW = 32;  // pixels per partial block
 
+// Layers 1 and 6 take their region in chunks of WCH rows staged in LDS (the chunk's gradient rows
+// and its input rows with a one-pixel halo, zero outside the grid), so that each output's sum over
+// the region reads LDS instead of waiting on a global load per pixel.  Pixels are visited row by row
+// as before; a zero-padded input or gradient adds an exact zero.
+constexpr int WCH = 8;  // rows per staged chunk
+
 // layer 1: dW1[t][ci][co] = sum_p X0[p + t][ci] dZ1[p][co], db1[co] = sum_p dZ1[p][co]  (all FP32)
-// one thread per (t, ci, co) output (576) plus 32 bias threads; loops over the region's pixels.
+// one thread per (t, ci, co) output (576) plus 32 bias threads.
 __global__ __launch_bounds__(640) void l1_bwd_weight(const float* u0, const float* kappa, const float* scale,
                                                      const float* dZ1, int nb, int H, int W, float* partial) {
+    __shared__ float gz[WCH][RW][C];           // dZ1 of the chunk
+    __shared__ float xin[WCH + 2][RW + 2][2];  // X0 (scaled u0, centred kappa) with halo
     const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
     const int blk = blockIdx.x;
     const int b = blk / (rx * ry), r = blk % (rx * ry);
     const int y0 = (r / rx) * RH, x0 = (r % rx) * RW;
     const int j = threadIdx.x;
-    if (j >= 9 * 2 * C + C) return;
-    float acc = 0.0f;
     const float inv = scale[2 * b];
-    if (j < 9 * 2 * C) {
-        const int t = j / (2 * C), ci = (j / C) % 2, co = j % C;
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        for (int y = y0; y < min(y0 + RH, H); ++y)
-            for (int x = x0; x < min(x0 + RW, W); ++x) {
-                const int yy = y + dy, xx = x + dx;
-                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-                const int64_t q = (int64_t(b) * H + yy) * W + xx;
-                const float xin = ci == 0 ? u0[q] * inv : (kappa[q] - KMID) / KHALF;
-                acc = __builtin_fmaf(xin, dZ1[((int64_t(b) * H + y) * W + x) * C + co], acc);
-            }
-    } else {
-        const int co = j - 9 * 2 * C;
-        for (int y = y0; y < min(y0 + RH, H); ++y)
-            for (int x = x0; x < min(x0 + RW, W); ++x) acc += dZ1[((int64_t(b) * H + y) * W + x) * C + co];
+    const int t = j / (2 * C), ci = (j / C) % 2, co = j % C;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    float acc = 0.0f;
+    for (int c0 = y0; c0 < y0 + RH; c0 += WCH) {
+        __syncthreads();  // the previous chunk is no longer read
+        for (int e = j; e < WCH * RW * C; e += 640) {
+            const int k = e % C, x = (e / C) % RW, y = e / (C * RW);
+            const int gy = c0 + y, gx = x0 + x;
+            gz[y][x][k] = (gy < H && gx < W) ? dZ1[((int64_t(b) * H + gy) * W + gx) * C + k] : 0.0f;
+        }
+        for (int e = j; e < (WCH + 2) * (RW + 2); e += 640) {
+            const int x = e % (RW + 2), y = e / (RW + 2);
+            const int gy = c0 + y - 1, gx = x0 + x - 1;
+            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const int64_t q = (int64_t(b) * H + gy) * W + gx;
+            xin[y][x][0] = in ? u0[q] * inv : 0.0f;
+            xin[y][x][1] = in ? (kappa[q] - KMID) / KHALF : 0.0f;
+        }
+        __syncthreads();
+        if (j < 9 * 2 * C) {
+            for (int y = 0; y < WCH; ++y)
+#pragma unroll 8
+                for (int x = 0; x < RW; ++x) acc = __builtin_fmaf(xin[y + 1 + dy][x + 1 + dx][ci], gz[y][x][co], acc);
+        } else if (j < 9 * 2 * C + C) {
+            const int cb = j - 9 * 2 * C;
+            for (int y = 0; y < WCH; ++y)
+#pragma unroll 8
+                for (int x = 0; x < RW; ++x) acc += gz[y][x][cb];
+        }
     }
-    partial[int64_t(blk) * (9 * 2 * C + C) + j] = acc;
+    if (j < 9 * 2 * C + C) partial[int64_t(blk) * (9 * 2 * C + C) + j] = acc;
 }
 
 // layer 6: dW6[t][ci] = sum_p A5[p + t][ci] dF[p], db6 = sum_p dF[p]
 __global__ __launch_bounds__(320) void l6_bwd_weight(const uint16_t* A5, const float* dF, int nb, int H, int W,
                                                      float* partial) {
+    __shared__ float at[WCH + 2][RW + 2][C + 1];  // A5 with halo (padded: lanes of one row differ in ci)
+    __shared__ float gf[WCH][RW];
     const int rx = (W + RW - 1) / RW, ry = (H + RH - 1) / RH;
     const int blk = blockIdx.x;
     const int b = blk / (rx * ry), r = blk % (rx * ry);
     const int y0 = (r / rx) * RH, x0 = (r % rx) * RW;
     const int j = threadIdx.x;
-    if (j >= 9 * C + 1) return;
+    const int t = j / C, ci = j % C;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
     float acc = 0.0f;
-    if (j < 9 * C) {
-        const int t = j / C, ci = j % C;
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        for (int y = y0; y < min(y0 + RH, H); ++y)
-            for (int x = x0; x < min(x0 + RW, W); ++x) {
-                const int yy = y + dy, xx = x + dx;
-                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-                acc = __builtin_fmaf(bf2f(A5[((int64_t(b) * H + yy) * W + xx) * C + ci]),
-                                     dF[(int64_t(b) * H + y) * W + x], acc);
-            }
-    } else {
-        for (int y = y0; y < min(y0 + RH, H); ++y)
-            for (int x = x0; x < min(x0 + RW, W); ++x) acc += dF[(int64_t(b) * H + y) * W + x];
+    for (int c0 = y0; c0 < y0 + RH; c0 += WCH) {
+        __syncthreads();
+        for (int e = j; e < (WCH + 2) * (RW + 2) * C; e += 320) {
+            const int k = e % C, x = (e / C) % (RW + 2), y = e / (C * (RW + 2));
+            const int gy = c0 + y - 1, gx = x0 + x - 1;
+            at[y][x][k] = (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                              ? bf2f(A5[((int64_t(b) * H + gy) * W + gx) * C + k]) : 0.0f;
+        }
+        for (int e = j; e < WCH * RW; e += 320) {
+            const int x = e % RW, y = e / RW;
+            const int gy = c0 + y, gx = x0 + x;
+            gf[y][x] = (gy < H && gx < W) ? dF[(int64_t(b) * H + gy) * W + gx] : 0.0f;
+        }
+        __syncthreads();
+        if (j < 9 * C) {
+            for (int y = 0; y < WCH; ++y)
+#pragma unroll 8
+                for (int x = 0; x < RW; ++x) acc = __builtin_fmaf(at[y + 1 + dy][x + 1 + dx][ci], gf[y][x], acc);
+        } else if (j == 9 * C) {
+            for (int y = 0; y < WCH; ++y)
+                for (int x = 0; x < RW; ++x) acc += gf[y][x];
+        }
     }
-    partial[int64_t(blk) * (9 * C + 1) + j] = acc;
+    if (j < 9 * C + 1) partial[int64_t(blk) * (9 * C + 1) + j] = acc;
 }
 
 // layers 2-5: dW[t][ci][co] = sum_p A[p + t][ci] dZ[p][co] on MFMA.  The region is processed in
@@ -721,12 +753,26 @@ __global__ __launch_bounds__(256) void mfma_bwd_weight(const uint16_t* A, const 
 }
 
 // grad[off + j] = sum_{blk} partial[blk][j] in block order (FP64 accumulation)
-__global__ void reduce_partials(const float* partial, int nblk, int len, float* grad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= len) return;
+// Block g sums outputs j = 64 g .. 64 g + 63 over the nblk partials: wave q takes the partials
+// k = q, q + 16, ... (one coalesced 256-byte row segment per load), and the sixteen FP64 sums are
+// added in wave order.  A fixed order, so the gradient is reproducible run to run.
+constexpr int RP_WAVES = 16;
+__global__ __launch_bounds__(64 * RP_WAVES) void reduce_partials(const float* partial, int nblk, int len, float* grad) {
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += double(partial[int64_t(k) * len + j]);
-    grad[j] = float(s);
+    if (j < len)
+#pragma unroll 4
+        for (int k = q; k < nblk; k += RP_WAVES) s += double(partial[int64_t(k) * len + j]);
+    __shared__ double red[RP_WAVES][64];
+    red[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && j < len) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < RP_WAVES; ++w) t += red[w][lane];
+        grad[j] = float(t);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1255,7 +1301,7 @@ static int loss_grad_impl(const float* params, const float* u0, const float* kap
     // layer 6
     hipLaunchKernelGGL(l6_bwd_weight, dim3(grg), dim3(320), 0, s, act(4), dF, nb, H, W, partial);
     ST_LAUNCH_CHECK("l6_bwd_weight");
-    hipLaunchKernelGGL(reduce_partials, dim3((9 * C + 1 + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg, 9 * C + 1,
+    hipLaunchKernelGGL(reduce_partials, dim3((9 * C + 1 + 63) / 64), dim3(64 * RP_WAVES), 0, s, partial, L.nblk_rg, 9 * C + 1,
                        grad + woff(5));
     ST_LAUNCH_CHECK("reduce l6");
     uint16_t* dzb[2] = {reinterpret_cast<uint16_t*>(ws + L.dzb[0]), reinterpret_cast<uint16_t*>(ws + L.dzb[1])};
@@ -1268,7 +1314,7 @@ static int loss_grad_impl(const float* params, const float* u0, const float* kap
     for (int l = 4; l >= 1; --l) {
         hipLaunchKernelGGL(mfma_bwd_weight, dim3(grg), dim3(256), 0, s, act(l - 1), dzb[cur], nb, H, W, partial);
         ST_LAUNCH_CHECK("mfma_bwd_weight");
-        hipLaunchKernelGGL(reduce_partials, dim3((9 * C * C + C + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg,
+        hipLaunchKernelGGL(reduce_partials, dim3((9 * C * C + C + 63) / 64), dim3(64 * RP_WAVES), 0, s, partial, L.nblk_rg,
                            9 * C * C + C, grad + woff(l));
         ST_LAUNCH_CHECK("reduce mfma layer");
         ConvArgs a;
@@ -1288,7 +1334,7 @@ static int loss_grad_impl(const float* params, const float* u0, const float* kap
     // layer 1
     hipLaunchKernelGGL(l1_bwd_weight, dim3(grg), dim3(640), 0, s, u0, kappa, scale, dz1, nb, H, W, partial);
     ST_LAUNCH_CHECK("l1_bwd_weight");
-    hipLaunchKernelGGL(reduce_partials, dim3((9 * 2 * C + C + 255) / 256), dim3(256), 0, s, partial, L.nblk_rg,
+    hipLaunchKernelGGL(reduce_partials, dim3((9 * 2 * C + C + 63) / 64), dim3(64 * RP_WAVES), 0, s, partial, L.nblk_rg,
                        9 * 2 * C + C, grad + woff(0));
     ST_LAUNCH_CHECK("reduce l1");
     return ST_OK;
