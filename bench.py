@@ -355,9 +355,9 @@ def extra_batched(torch, lib, stream) -> dict:
             "per_grid_gstencil_s": cells / t_per / 1e9, "speedup_vs_per_grid": t_per / t_b}
 
 
-def extra_batched_profile(torch, lib, stream, config: str = "") -> dict:
-    """The 256-grid batch with a fixed configuration and no tuning, run 3 times: a short run for
-    counter profiles.  `config`: comma-separated shape:radius:engine:depth:segment_rows entries,
+def extra_batched_profile(torch, lib, stream, config: str = "", timed: bool = False) -> dict:
+    """The 256-grid batch with a fixed configuration and no tuning, run 3 times (then timed over 10
+    runs if `timed`): a short run for counter profiles and A/B timing.  `config`: comma-separated shape:radius:engine:depth:segment_rows entries,
     e.g. "star:1:march:8:0" (segment_rows 0: the default sizing)."""
     probs = wl.batch_problems()
     ins = [torch.from_numpy(q.u0).to("cuda") for q in probs]
@@ -369,13 +369,16 @@ def extra_batched_profile(torch, lib, stream, config: str = "") -> dict:
         lib.stencil_batch_set_class(batch, shape, int(r), engine, int(depth))
         lib.stencil_batch_set_segment(batch, shape, int(r), int(seg))
     bws = torch.empty(lib.stencil_batch_workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+    runb = lambda: lib.stencil_run_batched(batch, ins, outs, bws, stream)  # noqa: E731
     for _ in range(3):
-        lib.stencil_run_batched(batch, ins, outs, bws, stream)
+        runb()
     torch.cuda.synchronize()
+    t = time_median(runb, 10, stream) if timed else None
     lib.stencil_batch_destroy(batch)
     for pl in plans:
         lib.stencil_destroy(pl)
-    return {"config": config, "updates": sum(q.rows * q.cols * q.steps for q in probs)}
+    return {"config": config, "updates": sum(q.rows * q.cols * q.steps for q in probs),
+            "ms": t * 1e3 if t else None}
 
 
 def extra_surrogate(torch, lib, stream) -> dict:
@@ -583,6 +586,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"], help="star9_profile: storage type")
     ap.add_argument("--batch-config", default="", help="batched_profile: shape:radius:engine:depth:segment_rows,...")
+    ap.add_argument("--timed", action="store_true", help="batched_profile: also time 10 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -608,7 +612,7 @@ def main():
         if args.workload == "star9_profile":
             fn = functools.partial(fn, variant=args.variant or 2, tb=args.tb or 6, storage=args.storage)
         elif args.workload == "batched_profile":
-            fn = functools.partial(fn, config=args.batch_config)
+            fn = functools.partial(fn, config=args.batch_config, timed=args.timed)
         print(json.dumps({"workload": key, **fn(torch, lib, stream)}), flush=True)
         return
     p, value, ms, roof, (tb, tx, ty, variant), tune_s = main_line(args, torch, lib, stream)

@@ -136,36 +136,59 @@ struct MarchPassArgs {
 constexpr int MW = 4;  // wavefronts per workgroup of the marching engine
 constexpr int MV = 4;  // columns per lane of the marching engine (vector or element accesses per grid)
 
+// LDS of a batched marching workgroup: the input rows that the two wavefronts of a pair share (2 r tb
+// rows of 64 lanes x 16 bytes per pair).
+constexpr size_t march_share_bytes(int r, int tb) { return size_t(MW / 2) * 2 * r * tb * 64 * sizeof(float4); }
+
 template <int R, int SH, int TB>
 __global__ __launch_bounds__(64 * MW) void batched_march(MarchPassArgs a) {
+    extern __shared__ float4 shared_rows[];
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t* pre = a.task_prefix + a.s0;
-    const int64_t task = pre[0] + int64_t(blockIdx.x) * MW + wave;
-    if (task >= pre[a.n]) return;
+    const int64_t task_in = pre[0] + int64_t(blockIdx.x) * MW + wave;
+    const bool active = task_in < pre[a.n];
+    // a wavefront past the launch's last task computes as that task (its setup is then a plain load
+    // chain from the descriptor table, like the others') but stages nothing and stops at the barrier
+    const int64_t task = active ? task_in : pre[a.n] - 1;
+    // a grid's tasks go down each band in turn, so a workgroup's wavefronts take neighbouring
+    // segments.  Wavefronts 0 and 2 march upwards and 1 and 3 downwards, so the pairs 0-1 and 2-3
+    // meet at their start: each stages its own half of the 2 r tb input rows around the boundary in
+    // LDS, and both read the whole overlap from there instead of reading it from HBM twice.
+    const bool up = !(wave & 1);
+    constexpr int H = march::halo_lanes(R, TB, MV);
+    constexpr int64_t RT = int64_t(R) * TB;
     const int k = upper_index(pre, a.n + 1, task);
     const BatchDesc& d = a.desc[a.order[a.s0 + k]];
-    // a grid's tasks go down each band in turn, so a workgroup's wavefronts take neighbouring
-    // segments, and every other segment is marched upwards: two neighbours then read the rows they
-    // share (the r tb rows either side of their boundary) at the same time -- both at their start or
-    // both at their end -- and the second read finds them in the cache of the first.  Wavefronts 0
-    // and 2 of a workgroup go up, so the pairs that meet at their start (the surest to be in step)
-    // are wavefronts 0-1 and 2-3 whatever segment the workgroup starts at.
     const int64_t t = task - pre[k];
     const int64_t segi = t % d.tiles_y, band = t / d.tiles_y;
-    constexpr int H = march::halo_lanes(R, TB, MV);
     const int64_t y0 = segi * d.seg;
     const int64_t y1 = y0 + d.seg < d.rows ? y0 + d.seg : d.rows;
+    // the partner: the next task for an upward wavefront, the previous one for a downward one
+    const int64_t pt = up ? task + 1 : task - 1;
+    bool paired = false;
+    if (active && pt >= pre[k] && pt < pre[k + 1] && pt < pre[a.n]) {
+        const int64_t tp = pt - pre[k];
+        paired = tp / d.tiles_y == band && (up ? tp % d.tiles_y == segi + 1 : tp % d.tiles_y + 1 == segi);
+    }
+    const int64_t yb = up ? y1 : y0;  // the pair's boundary
     const int P = d.passes, p = a.p;
     const float* src = p == 0 ? d.in : (((P - p) % 2 == 0) ? d.out : d.ws);  // written by pass p-1
     float* dst = ((P - 1 - p) % 2 == 0) ? d.out : d.ws;
     const march::MarchView v{src, dst, d.rows, d.cols, d.b, march::BC_CONST, nullptr};
     const int64_t X0 = band * (MV * (64 - 2 * H)) - MV * H;
+    float4* mine = shared_rows + (wave >> 1) * (2 * RT * 64);
+    if (paired) {  // each stages the rows on its own side of the boundary
+        if (d.vec) march::stage_rows<ST_F32, R, MV, TB, true>(v, lane, y0, y1, X0, up ? yb - RT : yb, yb - RT, mine);
+        else march::stage_rows<ST_F32, R, MV, TB, false>(v, lane, y0, y1, X0, up ? yb - RT : yb, yb - RT, mine);
+    }
+    __syncthreads();  // every wavefront of the workgroup reaches it once
+    if (!active) return;
+    const march::SharedRows sh{paired ? mine : nullptr, yb - RT, yb + RT};
     // input rows in flight: one ring length, except box r >= 3 with several levels (registers)
     constexpr int D = SH == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
-    const bool up = !(wave & 1);
-    if (d.vec) march::march_task_dir<ST_F32, R, MV, SH, TB, D, true>(v, d.w, lane, y0, y1, X0, up);
-    else march::march_task_dir<ST_F32, R, MV, SH, TB, D, false>(v, d.w, lane, y0, y1, X0, up);
+    if (d.vec) march::march_task_dir<ST_F32, R, MV, SH, TB, D, true>(v, d.w, lane, y0, y1, X0, up, sh);
+    else march::march_task_dir<ST_F32, R, MV, SH, TB, D, false>(v, d.w, lane, y0, y1, X0, up, sh);
 }
 
 using MarchPassFn = void (*)(MarchPassArgs);
@@ -262,7 +285,8 @@ static int64_t march_segment(int64_t band_rows, int64_t waves) {
 static int64_t march_waves(int shape, int r, int tb) {
     MarchPassFn fn = batched_march_lookup(shape, r, tb);
     int blocks = 0;
-    if (!fn || resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks) != ST_OK || blocks < 1) {
+    if (!fn || resident_blocks(reinterpret_cast<const void*>(fn), march_share_bytes(r, tb), &blocks) != ST_OK ||
+        blocks < 1) {
         (void)hipGetLastError();
         return 4096;
     }
@@ -487,7 +511,7 @@ static int enqueue_march_class(st_batch* B, int c, char* ws, hipStream_t s) {
         a.p = L.p;
         const int64_t blocks = (L.tasks + MW - 1) / MW;
         clear_stale_error();
-        hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(64 * MW), 0, s, a);
+        hipLaunchKernelGGL(fn, dim3(unsigned(blocks)), dim3(64 * MW), march_share_bytes(d0.r, L.levels), s, a);
         ST_LAUNCH_CHECK("batched_march");
     }
     return ST_OK;

@@ -173,9 +173,54 @@ __device__ __forceinline__ ColMask<V> col_mask(int64_t gx, int64_t cols) {
     return m;
 }
 
+// The fields live in global memory, and every access goes through a global-qualified pointer: the
+// compiler then emits global loads and stores even where it cannot trace a pointer to a kernel
+// argument (the batched kernels read theirs from a descriptor table).  Flat accesses would also count
+// against the LDS counter, so every wait for an LDS read would wait for the loads in flight too.
+template <typename T>
+using Glob = __attribute__((address_space(1))) T;
+template <int B>
+struct Bits;  // a native type of B bytes
+template <>
+struct Bits<2> {
+    using type = unsigned short;
+};
+template <>
+struct Bits<4> {
+    using type = unsigned;
+};
+template <>
+struct Bits<8> {
+    using type = unsigned __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Bits<16> {
+    using type = unsigned __attribute__((ext_vector_type(4)));
+};
+template <typename X>
+__device__ __forceinline__ X gload(const void* p) {
+    if constexpr (sizeof(X) == 32) {  // two 16-byte halves
+        using H = typename Bits<16>::type;
+        struct Two {
+            H a, b;
+        } t;
+        t.a = ((const Glob<H>*)p)[0];
+        t.b = ((const Glob<H>*)p)[1];
+        return __builtin_bit_cast(X, t);
+    } else {
+        using B = typename Bits<sizeof(X)>::type;
+        return __builtin_bit_cast(X, *(const Glob<B>*)p);
+    }
+}
+template <typename X>
+__device__ __forceinline__ void gstore(void* p, const X& x) {
+    using B = typename Bits<sizeof(X)>::type;
+    *(Glob<B>*)p = __builtin_bit_cast(B, x);
+}
+
 template <int S, int V>
 __device__ __forceinline__ Raw<S, V> load_raw(const void* src, int64_t off) {
-    return *reinterpret_cast<const Raw<S, V>*>(static_cast<const typename Fmt<S>::T*>(src) + off);
+    return gload<Raw<S, V>>(static_cast<const typename Fmt<S>::T*>(src) + off);
 }
 
 // Interior tasks address a lane's cells as a wavefront-uniform pointer (row start plus the band's
@@ -188,16 +233,31 @@ __device__ __forceinline__ uint32_t lane_bytes() {
 template <int S, int V>
 __device__ __forceinline__ Raw<S, V> load_lane(const void* src, int64_t first, uint32_t loff) {
     const char* p = reinterpret_cast<const char*>(static_cast<const typename Fmt<S>::T*>(src) + first);
-    return *reinterpret_cast<const Raw<S, V>*>(p + loff);
+    return gload<Raw<S, V>>(p + loff);
 }
 
-// Row clamps of interior tasks in 32-bit scalar compares (row indices of an interior task lie in
-// [-2^31, 2^32), grids have at most 2^31 rows): a prefetch past the last row (first row, upwards).
-__device__ __forceinline__ int64_t clamp_last(int64_t gy, int64_t rows) {
-    return uint32_t(gy) < uint32_t(rows) ? gy : rows - 1;
+// The rows a task loads: its input rows y0 - R TB .. y1 - 1 + R TB, cut to the grid.  Fetches past
+// them (the FIFO's lead beyond the last row needed and the last group's extra iterations) re-read
+// the nearest needed row, which the cache holds, rather than rows of the neighbouring segment.
+struct RowSpan {
+    int64_t lo, hi;
+};
+// Input rows [o0, o1) that a neighbouring wavefront of the workgroup staged in LDS (one 16-byte raw
+// lane vector per lane and row, row-major): fetched from there instead of HBM.  lds == nullptr: none.
+struct SharedRows {
+    const float4* lds;
+    int64_t o0, o1;
+};
+
+// d < 0 from the high word of d: a scalar compare where a 64-bit one would take a vector compare
+__device__ __forceinline__ bool negative(int64_t d) { return int32_t(uint32_t(uint64_t(d) >> 32)) < 0; }
+// An interior task's rows only run past its span on the side it marches towards.
+template <bool UP>
+__device__ __forceinline__ int64_t clamp_interior(int64_t gy, const RowSpan& sp) {
+    return UP ? (negative(gy - sp.lo) ? sp.lo : gy) : (negative(sp.hi - gy) ? sp.hi : gy);
 }
-__device__ __forceinline__ int64_t clamp_first(int64_t gy) {
-    return int32_t(uint32_t(uint64_t(gy) >> 32)) < 0 ? 0 : gy;
+__device__ __forceinline__ int64_t clamp_span(int64_t gy, const RowSpan& sp) {
+    return gy < sp.lo ? sp.lo : gy > sp.hi ? sp.hi : gy;
 }
 
 // Exact widening to FP32.
@@ -239,16 +299,19 @@ template <int S, int V>
 __device__ __forceinline__ void store_cells(void* dst, int64_t off, const Cells<V>& q) {
     using T = typename Fmt<S>::T;
     if constexpr (V == 1) {
-        static_cast<T*>(dst)[off] = Fmt<S>::st(q.c[0]);
-    } else if constexpr (V == 8 && S != ST_F32) {  // eight 16-bit cells: one 16-byte store
-        uint32_t w[4];
+        gstore(static_cast<T*>(dst) + off, Fmt<S>::st(q.c[0]));
+    } else if constexpr (S != ST_F32) {  // four (eight) 16-bit cells: one 8-byte (16-byte) store
+        uint32_t w[V / 2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < V / 2; ++k)
             w[k] = uint32_t(Fmt<S>::st(q.c[2 * k])) | (uint32_t(Fmt<S>::st(q.c[2 * k + 1])) << 16);
-        *reinterpret_cast<uint4*>(static_cast<T*>(dst) + off) = make_uint4(w[0], w[1], w[2], w[3]);
+        gstore(static_cast<T*>(dst) + off, w);
     } else {
 #pragma unroll
-        for (int k = 0; k < V; k += 4) store4<S>(static_cast<T*>(dst) + off + k, q.c + k);
+        for (int k = 0; k < V; k += 4) {
+            const float v4[4] = {q.c[k], q.c[k + 1], q.c[k + 2], q.c[k + 3]};
+            gstore(static_cast<T*>(dst) + off + k, v4);
+        }
     }
 }
 
@@ -268,25 +331,20 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
     for (int c = 0; c < V; ++c) x.v[R + c] = q.c[c];
 }
 
-// Input row gy as raw storage values, for the FIFO: EDGE tasks clamp row and columns into the grid
-// (the cells they stand for are replaced by their outside value when the row is used, see
-// `cells_of`), or wrap them on a periodic grid; interior tasks only clamp a prefetch past the grid's
-// last row.  A lane's vector never straddles the grid's side (cols % V == 0, and so is its first
-// column), so it wraps whole.
+// Input row gy as raw storage values, for the FIFO: the row is clamped into the task's row span
+// (which EDGE tasks cut to the grid; the cells a clamped row stands for are replaced by their
+// outside value when it is used, see `cells_of`, or never feed a stored output), and EDGE tasks
+// clamp columns into the grid too, or wrap row and columns on a periodic grid.  A lane's vector
+// never straddles the grid's side (cols % V == 0, and so is its first column), so it wraps whole.
 template <int S, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
 __device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
-                                                     int64_t X0) {
+                                                     int64_t X0, const RowSpan& sp) {
     const int64_t rows = a.rows, cols = a.cols;
     const bool wrap = EDGE && periodic<XBC>(a);
     int64_t g;
-    if (wrap) {
-        g = wrap_index(gy, rows);
-    } else if (EDGE) {
-        g = gy < rows ? gy : rows - 1;
-        g = g < 0 ? 0 : g;
-    } else {  // an interior task's prefetch runs past the grid's last row (first, marching upwards)
-        g = UP ? clamp_first(gy) : clamp_last(gy, rows);
-    }
+    if (wrap) g = wrap_index(gy, rows);
+    else if (EDGE) g = clamp_span(gy, sp);
+    else g = clamp_interior<UP>(gy, sp);
     if constexpr (!EDGE && (VEC || V == 1)) {
         return load_lane<S, V>(a.src, g * cols + X0, lane_bytes<S, V>());
     } else if constexpr (VEC || V == 1) {
@@ -296,7 +354,8 @@ __device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t
         RawT<S, V, VEC> r;
         const typename Fmt<S>::T* row = static_cast<const typename Fmt<S>::T*>(a.src) + g * cols;
 #pragma unroll
-        for (int c = 0; c < V; ++c) r.v[c] = row[wrap ? wrap_index(gx + c, cols) : (EDGE && !m.ok[c] ? 0 : gx + c)];
+        for (int c = 0; c < V; ++c)
+            r.v[c] = gload<typename Fmt<S>::T>(row + (wrap ? wrap_index(gx + c, cols) : (EDGE && !m.ok[c] ? 0 : gx + c)));
         return r;
     }
 }
@@ -316,10 +375,10 @@ __device__ __forceinline__ Cells<V> cells_of(const MarchView& a, const RawRow& r
 // Input row gy loaded and widened at once (the ring rows and the one-row lead).  With vector
 // accesses EDGE tasks skip the load for cells outside the grid, which take their outside value (a
 // periodic grid loads the cells they wrap to); with element accesses they load clamped (or wrapped)
-// addresses and substitute.  Interior tasks only clamp a load past the grid's last row.
+// addresses and substitute.  Rows are clamped into the task's row span as in `fetch_raw`.
 template <int S, int R, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
 __device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
-                                             int64_t X0) {
+                                             int64_t X0, const RowSpan& sp) {
     const int64_t rows = a.rows, cols = a.cols;
     if constexpr (VEC || V == 1) {
         Cells<V> q;
@@ -327,18 +386,17 @@ __device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int
             if (periodic<XBC>(a)) {
                 q = widen<S, V>(load_raw<S, V>(a.src, wrap_index(gy, rows) * cols + wrap_index(gx, cols)));
             } else if (gy >= 0 && gy < rows && m.ok[0]) {
-                q = widen<S, V>(load_raw<S, V>(a.src, gy * cols + gx));
+                q = widen<S, V>(load_raw<S, V>(a.src, clamp_span(gy, sp) * cols + gx));
             } else {
 #pragma unroll
                 for (int c = 0; c < V; ++c) q.c[c] = outside_value<S, XBC>(a, R, gy, gx + c);
             }
         } else {
-            const int64_t g = UP ? clamp_first(gy) : clamp_last(gy, rows);
-            q = widen<S, V>(load_lane<S, V>(a.src, g * cols + X0, lane_bytes<S, V>()));
+            q = widen<S, V>(load_lane<S, V>(a.src, clamp_interior<UP>(gy, sp) * cols + X0, lane_bytes<S, V>()));
         }
         return q;
     } else {
-        return cells_of<S, R, V, EDGE, XBC>(a, fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, gy, gx, m, X0), gy, gx, m);
+        return cells_of<S, R, V, EDGE, XBC>(a, fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, gy, gx, m, X0, sp), gy, gx, m);
     }
 }
 
@@ -355,7 +413,7 @@ __device__ __forceinline__ void store_row(void* dst, int64_t row_off, int64_t gx
         typename Fmt<S>::T* row = static_cast<typename Fmt<S>::T*>(dst) + row_off;
 #pragma unroll
         for (int c = 0; c < V; ++c)
-            if (!EDGE || m.ok[c]) row[gx + c] = Fmt<S>::st(q.c[c]);
+            if (!EDGE || m.ok[c]) gstore(row + gx + c, Fmt<S>::st(q.c[c]));
     }
 }
 
@@ -428,9 +486,10 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 // UP marches the segment from its last row to its first: the same steps with the row order
 // reversed (iteration i computes level-1 row y1 - 1 + R(TB-1) - i, and so on), and each ring read
 // through the reversed slot order, so that every cell still takes its taps in row-major order.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC, bool UP = false>
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC, bool UP = false,
+          bool SHARE = false>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                             int64_t X0) {
+                                             int64_t X0, const SharedRows& sh = SharedRows{nullptr, 0, 0}) {
     constexpr int N = 2 * R + 1;
     static_assert(D % N == 0, "the FIFO length must be a multiple of the ring length");
     constexpr int U = D > 0 ? D : N;  // unroll
@@ -445,11 +504,28 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     // input row j lives in ring slot |j - j0| % N, FIFO slot |j - j0| % D
     constexpr int64_t SG = UP ? -1 : 1;  // row step of the march
     const int64_t j0 = UP ? y1 - 1 + R * TB : y0 - R * TB;
-    auto fetch = [&](int64_t j) { return fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, j, gx, cm, X0); };
+    const int64_t need_lo = y0 - R * TB, need_hi = y1 - 1 + R * TB;  // within the grid unless EDGE
+    const RowSpan sp{EDGE && need_lo < 0 ? 0 : need_lo, EDGE && need_hi > rows - 1 ? rows - 1 : need_hi};
+    using RawR = RawT<S, V, VEC>;
+    auto fetch = [&](int64_t j) -> RawR {
+        if constexpr (SHARE) {
+            static_assert(sizeof(RawR) == sizeof(float4), "shared rows hold one 16-byte vector per lane");
+            // (read through an LDS-qualified pointer: a generic one would let the compiler merge this
+            // read and the global one below into a flat load, which waits on both counters)
+            using LdsVec = __attribute__((address_space(3))) const float4;
+            if (sh.lds && !negative(j - sh.o0) && negative(j - sh.o1))
+                return __builtin_bit_cast(RawR, ((LdsVec*)sh.lds)[(j - sh.o0) * 64 + lane]);
+        }
+        return fetch_raw<S, V, VEC, EDGE, XBC, UP>(a, j, gx, cm, X0, sp);
+    };
+    // a row loaded and widened at once (the ring's first rows, and the one-row lead when D = 0)
+    auto load_row = [&](int64_t j) -> Cells<V> {
+        if constexpr (SHARE) return cells_of<S, R, V, EDGE, XBC>(a, fetch(j), j, gx, cm);
+        return load_now<S, R, V, VEC, EDGE, XBC, UP>(a, j, gx, cm, X0, sp);
+    };
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
-    for (int t = 0; t < FIRST; ++t)
-        set_own<R, V>(lv[0][t], load_now<S, R, V, VEC, EDGE, XBC, UP>(a, j0 + SG * t, gx, cm, X0));
+    for (int t = 0; t < FIRST; ++t) set_own<R, V>(lv[0][t], load_row(j0 + SG * t));
     if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
 #pragma unroll
         for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
@@ -518,8 +594,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     if (SIDES) fill_sides<R, V>(x);
                 }
                 if (D == 0 && l == 1) {  // input row m1 -+ R is no longer needed: fetch the row N further on
-                    set_own<R, V>(lv[0][u % N],
-                                  load_now<S, R, V, VEC, EDGE, XBC, UP>(a, j0 + SG * (int64_t(i) + N), gx, cm, X0));
+                    set_own<R, V>(lv[0][u % N], load_row(j0 + SG * (int64_t(i) + N)));
                 }
             }
         }
@@ -546,31 +621,62 @@ __device__ __forceinline__ void load_weights(const float* w, float* wv) {
     }
 }
 
+// A task reads or writes outside the grid, or near enough to need the edge checks.
+template <int R, int TB>
+__device__ __forceinline__ bool task_edge(const MarchView& a, int64_t y0, int64_t y1, int64_t X0, int V) {
+    return y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 64 * V > a.cols;
+}
+
 // One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels, input rows
 // loaded D iterations ahead (0: one); VEC selects vector or element accesses (see RawT); XBC: the
 // boundary rule comes from the view (periodic or framed grids), else the halo is the constant b.
 template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true, bool XBC = false>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                            int64_t X0) {
-    const bool edge = y0 - R * TB < 0 || y1 + R * TB > a.rows || X0 < 0 || X0 + 64 * V > a.cols;
+    const bool edge = task_edge<R, TB>(a, y0, y1, X0, V);
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
     if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0);
     else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0);
 }
 
-// The same task marched upwards when `up` is set (constant halo).  Upward tasks take the general
-// (edge) form only, which keeps the kernel's code to one more copy of the loop.
+// The same task marched upwards when `up` is set (constant halo), taking the input rows `sh` from LDS.
+// Upward tasks take the general (edge) form only, which keeps the kernel's code to one more copy of
+// the loop.
 template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true>
 __device__ __forceinline__ void march_task_dir(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                               int64_t X0, bool up) {
-    if (!up) {
-        march_task<S, R, V, SHAPE, TB, D, VEC, false>(a, w, lane, y0, y1, X0);
-        return;
-    }
+                                               int64_t X0, bool up, const SharedRows& sh) {
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, true>(a, wv, lane, y0, y1, X0);
+    if (up) march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, true, true>(a, wv, lane, y0, y1, X0, sh);
+    else if (task_edge<R, TB>(a, y0, y1, X0, V))
+        march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, false, true>(a, wv, lane, y0, y1, X0, sh);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false, false, true>(a, wv, lane, y0, y1, X0, sh);
+}
+
+// Stage input rows r0 .. r0 + R TB - 1 of the task (y0, y1, X0) in LDS (`dst[(row - o0) * 64 + lane]`) as
+// the task's own fetches would return them, for the neighbouring task that shares them.  All loads are
+// issued before the first LDS write, so staging costs one memory latency.
+template <int S, int R, int V, int TB, bool VEC = true>
+__device__ __forceinline__ void stage_rows(const MarchView& a, int lane, int64_t y0, int64_t y1, int64_t X0,
+                                           int64_t r0, int64_t o0, float4* dst) {
+    using RawR = RawT<S, V, VEC>;
+    constexpr int RT = R * TB;
+    const int64_t gx = X0 + V * lane;
+    const ColMask<V> cm = col_mask<V, VEC>(gx, a.cols);
+    const int64_t need_lo = y0 - R * TB, need_hi = y1 - 1 + R * TB;
+    RawR raw[RT];
+    if (task_edge<R, TB>(a, y0, y1, X0, V)) {
+        const RowSpan sp{need_lo < 0 ? 0 : need_lo, need_hi > a.rows - 1 ? a.rows - 1 : need_hi};
+#pragma unroll
+        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, true, false>(a, r0 + t, gx, cm, X0, sp);
+    } else {
+        const RowSpan sp{need_lo, need_hi};
+#pragma unroll
+        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, false, false>(a, r0 + t, gx, cm, X0, sp);
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) dst[(r0 + t - o0) * 64 + lane] = __builtin_bit_cast(float4, raw[t]);
 }
 
 }  // namespace march
