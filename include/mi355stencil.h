@@ -182,12 +182,15 @@ int stencil_set_spin_limit(st_plan* plan, int64_t polls);
  * Synchronises `stream`.  Errors: ST_EINVAL, ST_ENOWS (workspace smaller than the run's), ST_EHIP. */
 int stencil_resident_status(const st_plan* plan, const void* workspace, size_t ws_bytes, int* status4, void* stream);
 
-/* stencil_set_march_segment -- marching variants: each wavefront computes at
- * least `min_rows` output rows of its column band (0, the default: as many
+/* stencil_set_march_segment -- marching variants: each wavefront computes about
+ * `min_rows` output rows of its column band at least (0, the default: as many
  * (band, segment) tasks as the device holds wavefronts at once).  A segment
  * recomputes r (tb - 1) rows of the lower levels at either end, which on
- * small grids costs more than the idle SIMDs of fewer, longer tasks.  Bitwise
- * the same results; values above rows act as rows.  stencil_autotune sets it.
+ * small grids costs more than the idle SIMDs of fewer, longer tasks.  The
+ * launch then adjusts the segment by fewer than 2r + 1 rows so that its row
+ * loop fills whole unrolled groups (down when the tasks do not fill the
+ * device, else up).  Bitwise the same results; values above rows act as rows.
+ * stencil_autotune sets it.
  * Errors: ST_EINVAL (NULL plan, negative min_rows). */
 int stencil_set_march_segment(st_plan* plan, int64_t min_rows);
 int stencil_get_march_segment(const st_plan* plan, int64_t* min_rows);

@@ -526,14 +526,7 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     constexpr int FIRST = D > 0 ? 2 * R : N;  // rows loaded straight into the ring
 #pragma unroll
     for (int t = 0; t < FIRST; ++t) set_own<R, V>(lv[0][t], load_row(j0 + SG * t));
-    if constexpr (SIDES) {  // after all the loads: one wait for the whole prologue
-#pragma unroll
-        for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
-    }
     if constexpr (D > 0) {
-        // the ring's first rows arrive before the FIFO is filled: the loop's entry then carries no
-        // pending load into a ring register, so the loop waits only for the FIFO row it consumes
-        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             // issued in the order the loop consumes them (the scheduler would otherwise reorder
@@ -541,6 +534,13 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
             fifo[(2 * R + t) % D] = fetch(j0 + SG * (2 * R + t));
             __builtin_amdgcn_sched_barrier(0);
         }
+        // one wait for the whole prologue (ring rows and FIFO, loaded together): the loop's entry
+        // then carries no pending load, so each iteration waits only for the FIFO row it consumes
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    if constexpr (SIDES) {  // after all the loads
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) fill_sides<R, V>(lv[0][t]);
     }
     // The loop runs whole groups of U iterations: the last group may run up to U - 1 iterations past
     // the segment, on rows whose loads are clamped (or take their outside value) and whose outputs
