@@ -188,8 +188,8 @@ int stencil_resident_status(const st_plan* plan, const void* workspace, size_t w
  * recomputes r (tb - 1) rows of the lower levels at either end, which on
  * small grids costs more than the idle SIMDs of fewer, longer tasks.  The
  * launch then adjusts the segment by fewer than 2r + 1 rows so that its row
- * loop fills whole unrolled groups (down when the tasks do not fill the
- * device, else up).  Bitwise the same results; values above rows act as rows.
+ * loop fills whole unrolled groups.  Bitwise the same results; values above
+ * rows act as rows.
  * stencil_autotune sets it.
  * Errors: ST_EINVAL (NULL plan, negative min_rows). */
 int stencil_set_march_segment(st_plan* plan, int64_t min_rows);

@@ -4,6 +4,8 @@
 // march_levels walks one band of columns over a segment of rows, TB levels per pass.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 #include "star_centre.h"
 #include "storage.h"
@@ -548,7 +550,11 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     // back edge, so the loads in flight there are not waited for.  (A task spans at most 2^31 + 2R(TB
     // - 1) iterations, so the counter fits 32 bits, whose compares are scalar instructions.)
     const uint32_t iters = uint32_t((y1 - y0) + 2 * R * (TB - 1));
-    for (uint32_t i0 = 0; i0 < iters; i0 += U) {
+    // One group of U iterations.  WARM: the group may start before every level has 2R+1 rows of the
+    // level below (i < 2R(TB-1)), so each level checks.  One-column bands, whose levels are a few
+    // instructions each, run the groups after the warm-up from a second copy without the checks (a
+    // compare and a branch per level and row); wider bands keep one copy (their registers).
+    auto group = [&](uint32_t i0, auto warm) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = i0 + u;
@@ -564,7 +570,8 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
             if (SIDES) fill_sides<R, V>(in);
 #pragma unroll
             for (int l = 1; l <= TB; ++l) {
-                if (i < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
+                if constexpr (decltype(warm)::value)
+                    if (i < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
                 // row of level l
                 const int64_t m = UP ? y1 - 1 + R * (TB - 1) - int64_t(i) + int64_t(l - 1) * R
                                      : y0 - R * (TB - 1) + int64_t(i) - int64_t(l - 1) * R;
@@ -598,6 +605,14 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                 }
             }
         }
+    };
+    constexpr uint32_t WARM = 2 * R * (TB - 1);  // the first iteration at which every level computes
+    uint32_t i0 = 0;
+    if constexpr (V == 1 && TB > 1) {
+        for (; i0 < iters && i0 < WARM; i0 += U) group(i0, std::true_type{});
+        for (; i0 < iters; i0 += U) group(i0, std::false_type{});
+    } else {
+        for (; i0 < iters; i0 += U) group(i0, std::bool_constant<(TB > 1)>{});
     }
 }
 
