@@ -187,7 +187,7 @@ int stencil_resident_status(const st_plan* plan, const void* workspace, size_t w
  * (band, segment) tasks as the device holds wavefronts at once).  A segment
  * recomputes r (tb - 1) rows of the lower levels at either end, which on
  * small grids costs more than the idle SIMDs of fewer, longer tasks.  The
- * launch then adjusts the segment by fewer than 2r + 1 rows so that its row
+ * launch then lengthens the segment by fewer than 2r + 1 rows so that its row
  * loop fills whole unrolled groups.  Bitwise the same results; values above
  * rows act as rows.
  * stencil_autotune sets it.

@@ -93,15 +93,11 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     // longer segments (fewer tasks than wavefronts) cost less than the recomputation they avoid
     a.seg = std::max<int64_t>(a.seg, std::min<int64_t>(p->seg_min, p->rows));
     // A task's row loop runs whole groups of 2r + 1 iterations (seg + 2r(levels - 1) of them, rounded
-    // up), so the segment is adjusted to fill its last group.  Rounded up, every task runs the same
-    // iterations as before and there are fewer tasks; rounded down, each task runs a group fewer,
-    // which pays when the tasks do not fill the device and shortening adds few of them.
+    // up), so the segment is rounded up to fill its last group: every task runs the same iterations
+    // as before and there are fewer tasks (rounding down measured slower even on small grids, where
+    // the extra tasks cost more than the shorter ones save).
     const int64_t ring = 2 * p->radius + 1, part = (a.seg + 2 * p->radius * (levels - 1)) % ring;
-    if (part && a.seg < p->rows) {
-        const int64_t down = a.seg - part;
-        const int64_t tasks_down = down >= 1 ? a.bands * ((p->rows + down - 1) / down) : 0;
-        a.seg = 5 * down >= 4 * a.seg && tasks_down <= waves ? down : a.seg + ring - part;
-    }
+    if (part && a.seg < p->rows) a.seg += ring - part;
     const int64_t segs = (p->rows + a.seg - 1) / a.seg;
     a.tasks = segs * a.bands;
     const int64_t grid = (a.tasks + MWAVES - 1) / MWAVES;

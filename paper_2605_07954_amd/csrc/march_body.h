@@ -554,14 +554,17 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     // level below (i < 2R(TB-1)), so each level checks.  One-column bands, whose levels are a few
     // instructions each, run the groups after the warm-up from a second copy without the checks (a
     // compare and a branch per level and row); wider bands keep one copy (their registers).
-    auto group = [&](uint32_t i0, auto warm) {
+    // (the iteration index is 64-bit, so that the row and address arithmetic derived from it is
+    // strength-reduced; the compares use its low 32 bits, which are scalar instructions)
+    auto group = [&](int64_t i0, auto warm) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = i0 + u;
+            const int64_t i = i0 + u;
+            const uint32_t ic = uint32_t(i);
             Row<R, V>& in = lv[0][(u + 2 * R) % N];  // input row j0 +- (i + 2R) enters the window
             if constexpr (D > 0) {
                 const int f = (u + 2 * R) % D;
-                const int64_t j = j0 + SG * (int64_t(i) + 2 * R);
+                const int64_t j = j0 + SG * (i + 2 * R);
                 Cells<V> q = cells_of<S, R, V, EDGE, XBC>(a, fifo[f], j, gx, cm);
                 if constexpr (S == ST_F32) pin_copy<V>(q);
                 set_own<R, V>(in, q);
@@ -571,10 +574,10 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
 #pragma unroll
             for (int l = 1; l <= TB; ++l) {
                 if constexpr (decltype(warm)::value)
-                    if (i < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
+                    if (ic < uint32_t(2 * R * (l - 1))) break;  // level l - 1 does not have 2R+1 rows yet
                 // row of level l
-                const int64_t m = UP ? y1 - 1 + R * (TB - 1) - int64_t(i) + int64_t(l - 1) * R
-                                     : y0 - R * (TB - 1) + int64_t(i) - int64_t(l - 1) * R;
+                const int64_t m = UP ? y1 - 1 + R * (TB - 1) - i + int64_t(l - 1) * R
+                                     : y0 - R * (TB - 1) + i - int64_t(l - 1) * R;
                 Cells<V> q = apply<R, V, SHAPE, N, UP>(lv[l - 1], u + l - 1, w);
                 if (l == TB) {
                     // (the row against the segment's far end in 32-bit scalar compares: downwards
@@ -601,18 +604,18 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     if (SIDES) fill_sides<R, V>(x);
                 }
                 if (D == 0 && l == 1) {  // input row m1 -+ R is no longer needed: fetch the row N further on
-                    set_own<R, V>(lv[0][u % N], load_row(j0 + SG * (int64_t(i) + N)));
+                    set_own<R, V>(lv[0][u % N], load_row(j0 + SG * (i + N)));
                 }
             }
         }
     };
     constexpr uint32_t WARM = 2 * R * (TB - 1);  // the first iteration at which every level computes
-    uint32_t i0 = 0;
+    int64_t i0 = 0;
     if constexpr (V == 1 && TB > 1) {
-        for (; i0 < iters && i0 < WARM; i0 += U) group(i0, std::true_type{});
-        for (; i0 < iters; i0 += U) group(i0, std::false_type{});
+        for (; uint32_t(i0) < iters && uint32_t(i0) < WARM; i0 += U) group(i0, std::true_type{});
+        for (; uint32_t(i0) < iters; i0 += U) group(i0, std::false_type{});
     } else {
-        for (; i0 < iters; i0 += U) group(i0, std::bool_constant<(TB > 1)>{});
+        for (; uint32_t(i0) < iters; i0 += U) group(i0, std::bool_constant<(TB > 1)>{});
     }
 }
 
