@@ -305,8 +305,7 @@ __device__ __forceinline__ void store_cells(void* dst, int64_t off, const Cells<
     } else if constexpr (S != ST_F32) {  // four (eight) 16-bit cells: one 8-byte (16-byte) store
         uint32_t w[V / 2];
 #pragma unroll
-        for (int k = 0; k < V / 2; ++k)
-            w[k] = uint32_t(Fmt<S>::st(q.c[2 * k])) | (uint32_t(Fmt<S>::st(q.c[2 * k + 1])) << 16);
+        for (int k = 0; k < V / 2; ++k) w[k] = Fmt<S>::st2(q.c[2 * k], q.c[2 * k + 1]);
         gstore(static_cast<T*>(dst) + off, w);
     } else {
 #pragma unroll
@@ -325,6 +324,18 @@ template <int V>
 __device__ __forceinline__ void pin_copy(Cells<V>& q) {
 #pragma unroll
     for (int c = 0; c < V; ++c) asm volatile("v_mov_b32 %0, %1" : "=v"(q.c[c]) : "v"(q.c[c]));
+}
+
+// A level's V cells rounded to the storage type (16-bit types two at a time).
+template <int S, int V>
+__device__ __forceinline__ void round_cells(Cells<V>& q) {
+    if constexpr (S != ST_F32 && V % 2 == 0) {
+#pragma unroll
+        for (int c = 0; c < V; c += 2) Fmt<S>::rnd2(q.c[c], q.c[c + 1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < V; ++c) q.c[c] = Fmt<S>::rnd(q.c[c]);
+    }
 }
 
 template <int R, int V>
@@ -591,14 +602,12 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
                     Row<R, V>& x = lv[l][(u + l - 1) % N];
                     // every level is rounded to the storage type; cells outside the grid keep their
                     // outside value (a periodic grid computes them like the cells they wrap to)
+                    round_cells<S, V>(q);
                     if (EDGE && !periodic<XBC>(a)) {
                         const bool row_in = m >= 0 && m < rows;
 #pragma unroll
                         for (int c = 0; c < V; ++c)
-                            q.c[c] = row_in && cm.ok[c] ? Fmt<S>::rnd(q.c[c]) : outside_value<S, XBC>(a, R, m, gx + c);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < V; ++c) q.c[c] = Fmt<S>::rnd(q.c[c]);
+                            q.c[c] = row_in && cm.ok[c] ? q.c[c] : outside_value<S, XBC>(a, R, m, gx + c);
                     }
                     set_own<R, V>(x, q);
                     if (SIDES) fill_sides<R, V>(x);

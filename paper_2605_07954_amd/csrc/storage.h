@@ -30,8 +30,11 @@ __device__ __forceinline__ float as_fp32(float x) {
     return x;
 }
 
+typedef float F32x2 __attribute__((ext_vector_type(2)));
+
 // bfloat16: the upper 16 bits of a binary32; widening is a shift, rounding is
-// gfx950's hardware convert (round to nearest even).
+// gfx950's hardware convert (round to nearest even).  Pairs convert in one
+// instruction (a in the low half), the same rounding as one at a time.
 template <>
 struct Fmt<ST_BF16> {
     using T = uint16_t;
@@ -42,9 +45,20 @@ struct Fmt<ST_BF16> {
         return __builtin_bit_cast(uint16_t, h);
     }
     __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
+    __device__ __forceinline__ static uint32_t st2(float a, float b) {
+        typedef __bf16 B2 __attribute__((ext_vector_type(2)));
+        const F32x2 v = {as_fp32(a), as_fp32(b)};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, B2));
+    }
+    __device__ __forceinline__ static void rnd2(float& a, float& b) {
+        const uint32_t p = st2(a, b);
+        a = __uint_as_float(p << 16);
+        b = __uint_as_float(p & 0xffff0000u);
+    }
 };
 
-// IEEE binary16 with subnormals; hardware convert, round to nearest even.
+// IEEE binary16 with subnormals; hardware convert, round to nearest even.  Pairs
+// convert in one instruction (a in the low half), the same rounding.
 template <>
 struct Fmt<ST_F16> {
     using T = uint16_t;
@@ -55,6 +69,16 @@ struct Fmt<ST_F16> {
         return __builtin_bit_cast(uint16_t, h);
     }
     __device__ __forceinline__ static float rnd(float x) { return ld(st(x)); }
+    __device__ __forceinline__ static uint32_t st2(float a, float b) {
+        typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+        const F32x2 v = {as_fp32(a), as_fp32(b)};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, H2));
+    }
+    __device__ __forceinline__ static void rnd2(float& a, float& b) {
+        const uint32_t p = st2(a, b);
+        a = ld(uint16_t(p & 0xffffu));
+        b = ld(uint16_t(p >> 16));
+    }
 };
 
 // Load one 16-byte chunk (VEC elements) and widen to FP32.
