@@ -313,8 +313,8 @@ def extra_star9_profile(torch, lib, stream, variant: int = 2, tb: int = 6, stora
     o = torch.empty_like(xh)
     w2 = torch.empty_like(xh)
     plan = lib.stencil_plan(p.rows, p.cols, 2, p.weights, 0.0, storage, 0)
+    lib.stencil_set_blocking(plan, tb)  # (the depth first: the default may be too deep for the variant)
     lib.stencil_set_variant(plan, variant)
-    lib.stencil_set_blocking(plan, tb)
     run = lambda: lib.stencil_run(plan, xh, o, p.steps, w2, stream)  # noqa: E731
     run()
     t = time_median(run, 3, stream)
