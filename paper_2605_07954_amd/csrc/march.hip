@@ -16,10 +16,13 @@
 // H = ceil(r tb / V) halo lanes per side.
 //
 // Segments are sized on the host so that the number of (band, segment) tasks is close to the number
-// of wavefronts the device holds at once: every wavefront runs one task of equal length.  A plan may
-// ask for longer segments (stencil_set_march_segment), which the autotuner does for small grids.
+// of wavefronts the device holds at once: every wavefront runs one task of about equal duration (the
+// tasks that take the grid's edge checks get proportionally shorter segments, see march_layout).  A
+// plan may ask for longer segments (stencil_set_march_segment), which the autotuner does for small
+// grids.
 
 #include <algorithm>
+#include <cmath>
 
 #include "march_kern.h"
 
@@ -44,6 +47,67 @@ MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool x
     if (storage == ST_BF16) return box ? march_lookup_bf16_box(mode, r, levels) : march_lookup_bf16_star(mode, r, levels);
     if (storage == ST_F16) return box ? march_lookup_f16_box(mode, r, levels) : march_lookup_f16_star(mode, r, levels);
     return nullptr;
+}
+
+// How a pass's tasks cover the grid (see MarchArgs).
+struct MarchLayout {
+    int64_t seg, seg_first, seg_short, segs_inner, tasks_outer, tasks;
+    int inner, band0, outer, ends_first;
+};
+
+// Every band split into segments of seg rows, in order, bands minor.
+MarchLayout uniform_layout(int64_t rows, int bands, int64_t seg) {
+    MarchLayout L;
+    L.seg = L.seg_first = L.seg_short = seg;
+    L.segs_inner = (rows + seg - 1) / seg;
+    L.inner = bands;
+    L.band0 = 0;
+    L.outer = 0;
+    L.ends_first = 0;
+    L.tasks_outer = 0;
+    L.tasks = int64_t(bands) * L.segs_inner;
+    return L;
+}
+
+// Tasks that take the edge checks (the two outer bands, and the segments of an inner band that lie
+// within r * levels rows of the grid's top or bottom) spend about 1.5 more instructions per cell and
+// level than the footprint's taps (measured: star r = 2 edge tasks run 17 % longer than inner ones
+// of the same length).  A launch lasts as long as its slowest wavefront, so those tasks get shorter
+// segments: the outer bands' segments, and an inner band's first and last segment, which are kept
+// at least r * levels rows long so that the segments between take no edge checks.  Lengths are
+// whole loop groups (2r + 1 rows; a task runs its segment plus `lag` = 2r(levels - 1) iterations)
+// where they can be.
+// `cut`: rows by which the outer bands' segments are shorter than seg (whole loop groups).
+MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t lag, int64_t reach, int64_t ring) {
+    MarchLayout L;
+    L.seg = seg;
+    L.seg_short = std::max<int64_t>(seg - cut, 1);
+    L.inner = bands >= 3 ? bands - 2 : 0;
+    L.band0 = 1;
+    L.outer = bands >= 2 ? 2 : 1;
+    L.ends_first = 1;
+    if (rows <= L.seg_short) {
+        L.segs_inner = 1;
+        L.seg_first = rows;
+    } else {
+        // m middle segments; the first and last share the rest (at most 2 seg_short rows, so
+        // neither is longer than seg_short), or one middle segment more when that leaves them no
+        // longer than seg and keeps the middle ones `reach` rows from the edges
+        int64_t m = std::max<int64_t>(0, (rows - 2 * L.seg_short + seg - 1) / seg);
+        int64_t rest = rows - m * seg;
+        if (m > 0 && rest < 2 * reach && rest <= seg) {
+            --m;
+            rest += seg;
+        }
+        int64_t first = rest / 2;
+        const int64_t aligned = first - (first + lag) % ring;
+        if (aligned >= std::max<int64_t>(reach, 1)) first = aligned;
+        L.seg_first = std::max<int64_t>(first, 1);
+        L.segs_inner = m + 2;
+    }
+    L.tasks_outer = L.outer * ((rows + L.seg_short - 1) / L.seg_short);
+    L.tasks = L.tasks_outer + int64_t(L.inner) * L.segs_inner;
+    return L;
 }
 
 }  // namespace
@@ -88,18 +152,48 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     if (int rc = resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks)) return rc;
     const int64_t waves = int64_t(blocks) * MWAVES;
     const int64_t per_band = std::max<int64_t>(1, waves / a.bands);  // segments per band
-    a.seg = (p->rows + per_band - 1) / per_band;
+    const int64_t natural = (p->rows + per_band - 1) / per_band;
     // a segment recomputes r (levels - 1) rows of the lower levels at either end: on small grids
     // longer segments (fewer tasks than wavefronts) cost less than the recomputation they avoid
-    a.seg = std::max<int64_t>(a.seg, std::min<int64_t>(p->seg_min, p->rows));
+    int64_t seg = std::max<int64_t>(natural, std::min<int64_t>(p->seg_min, p->rows));
     // A task's row loop runs whole groups of 2r + 1 iterations (seg + 2r(levels - 1) of them, rounded
     // up), so the segment is rounded up to fill its last group: every task runs the same iterations
     // as before and there are fewer tasks (rounding down measured slower even on small grids, where
     // the extra tasks cost more than the shorter ones save).
-    const int64_t ring = 2 * p->radius + 1, part = (a.seg + 2 * p->radius * (levels - 1)) % ring;
-    if (part && a.seg < p->rows) a.seg += ring - part;
-    const int64_t segs = (p->rows + a.seg - 1) / a.seg;
-    a.tasks = segs * a.bands;
+    const int64_t ring = 2 * p->radius + 1, part = (seg + 2 * p->radius * (levels - 1)) % ring;
+    if (part && seg < p->rows) seg += ring - part;
+    const int taps = p->shape == SHAPE_STAR ? 4 * p->radius + 1 : (2 * p->radius + 1) * (2 * p->radius + 1);
+
+    const int64_t lag = 2 * p->radius * (levels - 1), reach = int64_t(p->radius) * levels;
+    // an edge task of seg_short rows runs as long as an inner one of seg rows:
+    // kappa (seg_short + lag) = seg + lag, kappa = 1 + 1.5 / taps
+    const double kappa = 1.0 + 1.5 / taps;
+    int64_t groups = std::llround(double(seg + lag) * (1.0 - 1.0 / kappa) / double(ring));
+    // Segments raised by the plan's minimum (small grids, fewer tasks than wavefronts) keep the
+    // uniform layout: there the tuner has weighed segment length against task count.  The shorter
+    // edge segments add tasks: give up groups of the cut until they fit the wavefronts the device
+    // holds at once, else keep the uniform layout.
+    if (p->seg_min > natural) groups = 0;
+    MarchLayout L = uniform_layout(p->rows, a.bands, seg);
+    for (; groups > 0; --groups) {
+        if (groups * ring >= seg) continue;
+        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, lag, reach, ring);
+        if (C.tasks <= std::max(waves, L.tasks)) {
+            L = C;
+            break;
+        }
+    }
+    a.seg = L.seg;
+    a.seg_first = L.seg_first;
+    a.seg_short = L.seg_short;
+    a.segs_inner = L.segs_inner;
+    a.inner = L.inner;
+    a.outer = L.outer;
+    a.tasks_outer = L.tasks_outer;
+    a.band0 = L.band0;
+    a.ends_first = L.ends_first;
+    a.tasks = L.tasks;
+    if (a.tasks >= (int64_t(1) << 31)) return fail(ST_EUNSUPPORTED, "too many marching tasks for one pass");
     const int64_t grid = (a.tasks + MWAVES - 1) / MWAVES;
     clear_stale_error();
     hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(64 * MWAVES), 0, s, a);

@@ -16,9 +16,24 @@ struct MarchArgs {
     const void* src;
     void* dst;
     int64_t rows, cols;
-    int64_t tasks;  // bands * segments
-    int64_t seg;    // output rows per task
+    // Tasks: first the outer bands' (band 0 and bands - 1 alternating, segments of seg_short rows),
+    // then the inner bands' (task t: band band0 + t % inner, row of tasks q = t / inner: segment q,
+    // or with ends_first segment 0, then the last one, then segments 1, 2, ...).  An inner band's
+    // first segment is seg_first rows, its last one the rest, and the segments between seg rows.
+    // The tasks that take the edge checks come first: the oldest wavefronts on a SIMD are issued
+    // first.  (The uniform layout: no outer tasks, every band inner from band0 = 0, segments of seg
+    // rows in order.)
+    int64_t tasks;
+    int64_t tasks_outer;  // outer * ceil(rows / seg_short)
+    int64_t seg;          // rows of an inner band's middle segments
+    int64_t seg_first;    // rows of an inner band's first segment
+    int64_t seg_short;    // rows of an outer band's segments
+    int64_t segs_inner;   // segments of an inner band
     int bands;
+    int inner;            // inner bands
+    int band0;            // the first inner band (1, or 0 in the uniform layout)
+    int outer;            // outer bands: 0, 1 or 2
+    int ends_first;       // inner bands run their first and last segments first
     float b;
     int bc;             // boundary rule (march::BC_*)
     const int* stop;    // nullable: when it holds a nonzero value the pass does nothing
@@ -42,9 +57,20 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     if (a.stop && __hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     constexpr int H = halo_lanes(R, TB, V);
     constexpr int OUTW = V * (64 - 2 * H);
-    const int64_t band = task % a.bands;
-    const int64_t y0 = (task / a.bands) * a.seg;
-    const int64_t y1 = y0 + a.seg < a.rows ? y0 + a.seg : a.rows;
+    // (task indices fit 32 bits: one 32-bit division, on the path to the task's first load)
+    int64_t band, y0, y1;
+    if (task < a.tasks_outer) {
+        const bool two = a.outer == 2;
+        band = two && (task & 1) ? a.bands - 1 : 0;
+        y0 = (two ? task >> 1 : task) * a.seg_short;
+        y1 = y0 + a.seg_short < a.rows ? y0 + a.seg_short : a.rows;
+    } else {
+        const uint32_t t = uint32_t(task - a.tasks_outer), q = t / uint32_t(a.inner);
+        band = a.band0 + int64_t(t - q * uint32_t(a.inner));
+        const int64_t k = !a.ends_first ? int64_t(q) : q == 1 ? a.segs_inner - 1 : q > 1 ? int64_t(q) - 1 : 0;
+        y0 = k == 0 ? 0 : a.seg_first + (k - 1) * a.seg;
+        y1 = k == a.segs_inner - 1 ? a.rows : k == 0 ? a.seg_first : y0 + a.seg;
+    }
     const int64_t X0 = band * OUTW - V * H;
     const MarchView v{a.src, a.dst, a.rows, a.cols, a.b, a.bc, a.frame};
     march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, y0, y1, X0);

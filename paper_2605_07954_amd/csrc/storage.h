@@ -63,7 +63,14 @@ template <>
 struct Fmt<ST_F16> {
     using T = uint16_t;
     static constexpr int VEC = 8;
-    __device__ __forceinline__ static float ld(T v) { return (float)__builtin_bit_cast(_Float16, v); }
+    // (the widened value is kept as an FP32 register: left alone, the compiler folds the widening
+    // into mixed-precision FMAs, which measured slower on gfx950 and save no instruction: the row is
+    // widened for the later rows' taps anyway)
+    __device__ __forceinline__ static float ld(T v) {
+        float x = (float)__builtin_bit_cast(_Float16, v);
+        asm("" : "+v"(x));
+        return x;
+    }
     __device__ __forceinline__ static T st(float x) {
         _Float16 h = (_Float16)as_fp32(x);
         return __builtin_bit_cast(uint16_t, h);

@@ -500,7 +500,7 @@ def _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, ste
             torch.cuda.synchronize()
             np.testing.assert_array_equal(g.to_host(out), ref, err_msg=f"variant {variant} tb {tb}")
             # longer segments than one task per resident wavefront: bitwise the same
-            for seg in sorted({max(1, r * (tb - 1)), 7, rows, 3 * rows}):
+            for seg in sorted({max(1, r * (tb - 1)), 7, 40, rows, 3 * rows}):
                 lib.stencil_set_march_segment(plan, seg)
                 out.fill_(float("nan"))
                 lib.stencil_run(plan, x, out, steps, ws)
