@@ -518,6 +518,43 @@ def _march_variant_depths(g, lib, torch, x, ref, rows, cols, shape, r, W, b, ste
             lib.stencil_destroy(plan)
 
 
+BALANCED_CASES = [  # (rows, cols, shape, r, b, steps, variant, tb): tall grids whose default segments
+    # are long enough for the edge tasks to get shorter ones (outer bands, an inner band's first and
+    # last segments): five and six bands of four columns per lane, two bands, four eight-column
+    # bands; step counts that end with a shallower pass
+    (4096, 1000, wl.STAR, 2, 0.0, 13, "march", 6), (6000, 1200, wl.STAR, 2, 0.25, 10, "march", 5),
+    (8192, 300, wl.STAR, 1, 0.0, 17, "march", 8), (8000, 1600, wl.BOX, 1, 0.0, 7, "march8", 3),
+    (5000, 700, wl.BOX, 1, -0.5, 7, "march", 6)]
+
+
+@pytest.mark.parametrize("case", BALANCED_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-{c[6]}-tb{c[7]}" for c in BALANCED_CASES])
+def test_march_edge_task_layout_bitwise(g, case):
+    """With default segments on tall grids the marching pass gives the tasks that take the edge
+    checks shorter segments than the inner ones and runs them first; every row of every band is
+    still computed by exactly one task, so the whole field equals the FP32-canonical oracle bit for
+    bit (a gap or an overlap in the layout would leave NaN rows or wrong values)."""
+    import torch
+    import paper_2605_07954_amd as lib
+    rows, cols, shape, r, b, steps, variant, tb = case
+    W = _weights(shape, r, rows + cols + 11 * r)
+    u0 = np.random.default_rng(rows + 3 * cols).random((rows, cols), dtype=np.float32)
+    ref = oracle.stencil_f32(u0, W, b, steps)
+    plan = lib.stencil_plan(rows, cols, r, W, b, "f32", 0)
+    try:
+        lib.stencil_set_blocking(plan, 1)
+        lib.stencil_set_variant(plan, lib.ST_VARIANT_MARCH if variant == "march" else lib.ST_VARIANT_MARCH8)
+        lib.stencil_set_blocking(plan, tb)
+        x = g.to_dev(u0)
+        out = torch.full_like(x, float("nan"))
+        ws = torch.empty_like(x)
+        say(f"edge-task layout {rows}x{cols} {shape}{r} {variant} tb {tb}")
+        lib.stencil_run(plan, x, out, steps, ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(g.to_host(out), ref)
+    finally:
+        lib.stencil_destroy(plan)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 @pytest.mark.parametrize("rows,cols,shape,r,b,steps", [(300, 260, wl.STAR, 2, 0.0, 23), (129, 500, wl.BOX, 1, 0.5, 11),
                                                       (40, 996, wl.BOX, 3, 0.0, 5), (7, 8, wl.STAR, 4, -0.25, 4),
