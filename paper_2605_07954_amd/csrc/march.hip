@@ -78,13 +78,15 @@ MarchLayout uniform_layout(int64_t rows, int bands, int64_t seg) {
 // whole loop groups (2r + 1 rows; a task runs its segment plus `lag` = 2r(levels - 1) iterations)
 // where they can be.
 // `cut`: rows by which the outer bands' segments are shorter than seg (whole loop groups).
-MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t lag, int64_t reach, int64_t ring) {
+// `outer_edges`: the first and last bands take the column checks (else every band is inner).
+MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t lag, int64_t reach, int64_t ring,
+                         bool outer_edges) {
     MarchLayout L;
     L.seg = seg;
     L.seg_short = std::max<int64_t>(seg - cut, 1);
-    L.inner = bands >= 3 ? bands - 2 : 0;
-    L.band0 = 1;
-    L.outer = bands >= 2 ? 2 : 1;
+    L.inner = !outer_edges ? bands : bands >= 3 ? bands - 2 : 0;
+    L.band0 = outer_edges ? 1 : 0;
+    L.outer = !outer_edges ? 0 : bands >= 2 ? 2 : 1;
     L.ends_first = 1;
     if (rows <= L.seg_short) {
         L.segs_inner = 1;
@@ -105,7 +107,7 @@ MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int6
         L.seg_first = std::max<int64_t>(first, 1);
         L.segs_inner = m + 2;
     }
-    L.tasks_outer = L.outer * ((rows + L.seg_short - 1) / L.seg_short);
+    L.tasks_outer = L.outer ? L.outer * ((rows + L.seg_short - 1) / L.seg_short) : 0;
     L.tasks = L.tasks_outer + int64_t(L.inner) * L.segs_inner;
     return L;
 }
@@ -146,8 +148,18 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     a.frame = p->frame;
     a.stop = p->stop;
     std::memcpy(a.w, p->w, sizeof(a.w));
-    const int64_t outw = V * (64 - 2 * march::halo_lanes(p->radius, levels, V));
+    const int64_t H = march::halo_lanes(p->radius, levels, V), outw = V * (64 - 2 * H);
     a.bands = int((p->cols + outw - 1) / outw);
+    // A constant halo of +0 with vector accesses: the first band starts at column 0 and the last
+    // ends at the last column, storing the lanes a halo would otherwise take (see MarchArgs), so a
+    // grid needs up to two bands fewer and its side bands take no column checks.
+    const float zero = 0.0f;
+    a.zero_sides = !xbc && (mode == 4 || mode == 8) && std::memcmp(&p->bq, &zero, sizeof(float)) == 0 &&
+                   p->cols >= 2 * 64 * V;
+    if (a.zero_sides) {
+        const int64_t sides = 2 * V * (64 - H);
+        a.bands = int(2 + (p->cols > sides ? (p->cols - sides + outw - 1) / outw : 0));
+    }
     int blocks = 0;
     if (int rc = resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks)) return rc;
     const int64_t waves = int64_t(blocks) * MWAVES;
@@ -177,7 +189,7 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     MarchLayout L = uniform_layout(p->rows, a.bands, seg);
     for (; groups > 0; --groups) {
         if (groups * ring >= seg) continue;
-        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, lag, reach, ring);
+        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, lag, reach, ring, !a.zero_sides);
         if (C.tasks <= std::max(waves, L.tasks)) {
             L = C;
             break;

@@ -502,7 +502,8 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC, bool UP = false,
           bool SHARE = false>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                             int64_t X0, const SharedRows& sh = SharedRows{nullptr, 0, 0}) {
+                                             int64_t X0, const SharedRows& sh = SharedRows{nullptr, 0, 0},
+                                             int lo = -1, int hi = -1) {
     constexpr int N = 2 * R + 1;
     static_assert(D % N == 0, "the FIFO length must be a multiple of the ring length");
     constexpr int U = D > 0 ? D : N;  // unroll
@@ -511,7 +512,9 @@ __device__ __forceinline__ void march_levels(const MarchView& a, const float* w,
     const int64_t rows = a.rows, cols = a.cols;
     const int64_t gx = X0 + V * lane;
     const ColMask<V> cm = col_mask<V, VEC>(gx, cols);
-    const bool writer = lane >= H && lane < 64 - H && (!EDGE || cm.any);
+    // lanes [lo, hi) store (default [H, 64 - H)); a band that starts or ends at the grid's side with
+    // a zero halo also stores its lanes there, see sweep_march_body
+    const bool writer = lane >= (lo < 0 ? H : lo) && lane < (hi < 0 ? 64 - H : hi) && (!EDGE || cm.any);
     Row<R, V> lv[TB][N];  // lv[0]: input rows; lv[l]: level l < TB (the output level is stored directly)
     RawT<S, V, VEC> fifo[D > 0 ? D : 1];
     // input row j lives in ring slot |j - j0| % N, FIFO slot |j - j0| % D
@@ -675,12 +678,13 @@ __device__ __forceinline__ bool task_edge(const MarchView& a, int64_t y0, int64_
 // boundary rule comes from the view (periodic or framed grids), else the halo is the constant b.
 template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true, bool XBC = false>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
-                                           int64_t X0) {
+                                           int64_t X0, int lo = -1, int hi = -1) {
     const bool edge = task_edge<R, TB>(a, y0, y1, X0, V);
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0);
-    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0);
+    const SharedRows none{nullptr, 0, 0};
+    if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0, none, lo, hi);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0, none, lo, hi);
 }
 
 // The same task marched upwards when `up` is set (constant halo), taking the input rows `sh` from LDS.

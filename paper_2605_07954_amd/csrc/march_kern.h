@@ -34,6 +34,8 @@ struct MarchArgs {
     int band0;            // the first inner band (1, or 0 in the uniform layout)
     int outer;            // outer bands: 0, 1 or 2
     int ends_first;       // inner bands run their first and last segments first
+    int zero_sides;       // the first band starts at column 0 and the last ends at the last column
+                          // (constant halo of +0 and vector accesses, see sweep_march_body)
     float b;
     int bc;             // boundary rule (march::BC_*)
     const int* stop;    // nullable: when it holds a nonzero value the pass does nothing
@@ -71,9 +73,29 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
         y0 = k == 0 ? 0 : a.seg_first + (k - 1) * a.seg;
         y1 = k == a.segs_inner - 1 ? a.rows : k == 0 ? a.seg_first : y0 + a.seg;
     }
-    const int64_t X0 = band * OUTW - V * H;
+    // With a halo of +0 the lane shifts that bring a lane its neighbours' columns bring 0 into
+    // lane 0 (resp. 63), exactly the halo's value at every level: a band that starts at column 0
+    // stores its first H lanes too, and one that ends at the last column its last H (the grid's
+    // sides need no halo lanes).  The bands between follow the first at OUTW columns each, the
+    // last of them moved left where it would pass the last band's end (its overlap with the last
+    // band stores the same values).
+    int64_t X0 = band * OUTW - V * H;
+    int lo = -1, hi = -1;
+    if (a.zero_sides) {
+        const int64_t last = a.cols - 64 * V;
+        if (band == 0) {
+            X0 = 0;
+            lo = 0;
+        } else if (band == a.bands - 1) {
+            X0 = last;
+            hi = 64;
+        } else {
+            X0 = (band - 1) * OUTW + V * (64 - 2 * H);
+            if (X0 > last) X0 = last;
+        }
+    }
     const MarchView v{a.src, a.dst, a.rows, a.cols, a.b, a.bc, a.frame};
-    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, y0, y1, X0);
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, y0, y1, X0, lo, hi);
 }
 
 template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
