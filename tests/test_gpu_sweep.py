@@ -462,7 +462,9 @@ MARCH_CASES = [  # (rows, cols, shape, r, b, steps): narrower than one band, exa
     # widths that are not a multiple of 4 (element accesses): narrower than a band, one band
     # plus one column, many bands with a ragged end
     (3, 5, wl.BOX, 2, 0.0, 3), (70, 63, wl.STAR, 1, 0.5, 9), (41, 58, wl.BOX, 3, 0.0, 4), (300, 517, wl.BOX, 1, -0.5, 7),
-    (257, 1001, wl.STAR, 2, 0.0, 6), (130, 263, wl.BOX, 3, 0.25, 5), (90, 301, wl.STAR, 4, 0.0, 3)]
+    (257, 1001, wl.STAR, 2, 0.0, 6), (130, 263, wl.BOX, 3, 0.25, 5), (90, 301, wl.STAR, 4, 0.0, 3),
+    # a halo of -0.0: not the +0 whose side bands start at the grid's edge (lane shifts bring in +0)
+    (129, 1104, wl.STAR, 2, -0.0, 7), (97, 1600, wl.BOX, 1, -0.0, 5)]
 
 
 @pytest.mark.parametrize("case", MARCH_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}-b{c[4]}-T{c[5]}" for c in MARCH_CASES])
