@@ -93,7 +93,7 @@ def deps(info, g, t, p):
             for xx in range(max(0, x - rx), min(tx - 1, x + rx) + 1)]
 
 
-def run_model(items, info, workers, seed, spin_limit=200000, visible=True):
+def run_model(items, info, workers, seed, spin_limit=2000000, visible=True):
     """Run the queue with `workers` threads.  Returns (timeouts, violations, polls)."""
     lock = threading.Lock()
     head = [0]
@@ -129,8 +129,11 @@ def run_model(items, info, workers, seed, spin_limit=200000, visible=True):
                         if spins > spin_limit:  # one budget for the item: later waits end at once
                             gave_up = True
                             break
-                        if spins % 64 == 0:
-                            threading.Event().wait(0)  # yield (the s_sleep of the kernel)
+                        if spins % 64 == 0 or visible:
+                            # yield (the s_sleep of the kernel); with visible counters every poll
+                            # yields, so that a loaded host cannot starve the producers past the
+                            # limit (the model checks the protocol, not the host's scheduler)
+                            threading.Event().wait(0)
                 with lock:
                     stats["polls"] += spins
                     stats["timeouts"] += int(gave_up)
