@@ -51,64 +51,56 @@ MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool x
 
 // How a pass's tasks cover the grid (see MarchArgs).
 struct MarchLayout {
-    int64_t seg, seg_first, seg_short, segs_inner, tasks_outer, tasks;
+    int64_t seg, seg_short, tasks_outer, tasks;
+    int64_t n_top, n_mid, n_bot;
     int inner, band0, outer, ends_first;
 };
 
 // Every band split into segments of seg rows, in order, bands minor.
 MarchLayout uniform_layout(int64_t rows, int bands, int64_t seg) {
     MarchLayout L;
-    L.seg = L.seg_first = L.seg_short = seg;
-    L.segs_inner = (rows + seg - 1) / seg;
+    L.seg = L.seg_short = seg;
+    L.n_top = 0;
+    L.n_mid = rows / seg;
+    L.n_bot = rows % seg ? 1 : 0;
     L.inner = bands;
     L.band0 = 0;
     L.outer = 0;
     L.ends_first = 0;
     L.tasks_outer = 0;
-    L.tasks = int64_t(bands) * L.segs_inner;
+    L.tasks = int64_t(bands) * (L.n_mid + L.n_bot);
     return L;
 }
 
 // Tasks that take the edge checks (the two outer bands, and the segments of an inner band that lie
-// within r * levels rows of the grid's top or bottom) spend about 1.5 more instructions per cell and
-// level than the footprint's taps (measured: star r = 2 edge tasks run 17 % longer than inner ones
-// of the same length).  A launch lasts as long as its slowest wavefront, so those tasks get shorter
-// segments: the outer bands' segments, and an inner band's first and last segment, which are kept
-// at least r * levels rows long so that the segments between take no edge checks.  Lengths are
-// whole loop groups (2r + 1 rows; a task runs its segment plus `lag` = 2r(levels - 1) iterations)
-// where they can be.
-// `cut`: rows by which the outer bands' segments are shorter than seg (whole loop groups).
-// `outer_edges`: the first and last bands take the column checks (else every band is inner).
-MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t lag, int64_t reach, int64_t ring,
-                         bool outer_edges) {
+// within `reach` = r * levels rows of the grid's top or bottom) spend about 1.5 more instructions
+// per cell and level than the footprint's taps (measured: star r = 2 edge tasks run 17 % longer
+// than inner ones of the same length).  A launch lasts as long as its slowest wavefront, so those
+// tasks get segments of seg_short = seg - cut rows: the outer bands' segments, and the segments
+// that cover an inner band's top and bottom `reach` rows; the middle segments, of seg rows, then
+// take no edge checks.  `outer_edges`: the first and last bands take the column checks (else every
+// band is inner).
+MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t reach, bool outer_edges) {
     MarchLayout L;
     L.seg = seg;
-    L.seg_short = std::max<int64_t>(seg - cut, 1);
+    const int64_t ss = L.seg_short = std::max<int64_t>(seg - cut, 1);
     L.inner = !outer_edges ? bands : bands >= 3 ? bands - 2 : 0;
     L.band0 = outer_edges ? 1 : 0;
     L.outer = !outer_edges ? 0 : bands >= 2 ? 2 : 1;
     L.ends_first = 1;
-    if (rows <= L.seg_short) {
-        L.segs_inner = 1;
-        L.seg_first = rows;
+    L.n_top = std::max<int64_t>(1, (reach + ss - 1) / ss);
+    if (L.n_top * ss >= rows) {  // short segments only
+        L.n_top = (rows + ss - 1) / ss;
+        L.n_mid = L.n_bot = 0;
     } else {
-        // m middle segments; the first and last share the rest (at most 2 seg_short rows, so
-        // neither is longer than seg_short), or one middle segment more when that leaves them no
-        // longer than seg and keeps the middle ones `reach` rows from the edges
-        int64_t m = std::max<int64_t>(0, (rows - 2 * L.seg_short + seg - 1) / seg);
-        int64_t rest = rows - m * seg;
-        if (m > 0 && rest < 2 * reach && rest <= seg) {
-            --m;
-            rest += seg;
-        }
-        int64_t first = rest / 2;
-        const int64_t aligned = first - (first + lag) % ring;
-        if (aligned >= std::max<int64_t>(reach, 1)) first = aligned;
-        L.seg_first = std::max<int64_t>(first, 1);
-        L.segs_inner = m + 2;
+        // middle segments end at least `reach` rows above the grid's end; the rest (at least
+        // `reach` rows, or all that is left) is cut into short ones
+        const int64_t top = L.n_top * ss;
+        L.n_mid = std::max<int64_t>(0, (rows - top - reach) / seg);
+        L.n_bot = (rows - top - L.n_mid * seg + ss - 1) / ss;
     }
-    L.tasks_outer = L.outer ? L.outer * ((rows + L.seg_short - 1) / L.seg_short) : 0;
-    L.tasks = L.tasks_outer + int64_t(L.inner) * L.segs_inner;
+    L.tasks_outer = L.outer ? L.outer * ((rows + ss - 1) / ss) : 0;
+    L.tasks = L.tasks_outer + int64_t(L.inner) * (L.n_top + L.n_mid + L.n_bot);
     return L;
 }
 
@@ -150,12 +142,12 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     std::memcpy(a.w, p->w, sizeof(a.w));
     const int64_t H = march::halo_lanes(p->radius, levels, V), outw = V * (64 - 2 * H);
     a.bands = int((p->cols + outw - 1) / outw);
-    // A constant halo of +0 with vector accesses: the first band starts at column 0 and the last
-    // ends at the last column, storing the lanes a halo would otherwise take (see MarchArgs), so a
-    // grid needs up to two bands fewer and its side bands take no column checks.
+    // A constant halo of +0 with whole-lane accesses (vector, or one column per lane): the first
+    // band starts at column 0 and the last ends at the last column, storing the lanes a halo would
+    // otherwise take (see MarchArgs), so a grid needs up to two bands fewer and its side bands take
+    // no column checks.
     const float zero = 0.0f;
-    a.zero_sides = !xbc && (mode == 4 || mode == 8) && std::memcmp(&p->bq, &zero, sizeof(float)) == 0 &&
-                   p->cols >= 2 * 64 * V;
+    a.zero_sides = !xbc && mode != 0 && std::memcmp(&p->bq, &zero, sizeof(float)) == 0 && p->cols >= 2 * 64 * V;
     if (a.zero_sides) {
         const int64_t sides = 2 * V * (64 - H);
         a.bands = int(2 + (p->cols > sides ? (p->cols - sides + outw - 1) / outw : 0));
@@ -178,27 +170,31 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
 
     const int64_t lag = 2 * p->radius * (levels - 1), reach = int64_t(p->radius) * levels;
     // an edge task of seg_short rows runs as long as an inner one of seg rows:
-    // kappa (seg_short + lag) = seg + lag, kappa = 1 + 1.5 / taps
+    // kappa (seg_short + lag) = seg + lag, kappa = 1 + 1.5 / taps (in whole loop groups)
     const double kappa = 1.0 + 1.5 / taps;
     int64_t groups = std::llround(double(seg + lag) * (1.0 - 1.0 / kappa) / double(ring));
-    // Segments raised by the plan's minimum (small grids, fewer tasks than wavefronts) keep the
-    // uniform layout: there the tuner has weighed segment length against task count.  The shorter
-    // edge segments add tasks: give up groups of the cut until they fit the wavefronts the device
-    // holds at once, else keep the uniform layout.
-    if (p->seg_min > natural) groups = 0;
+    // Segments raised by the plan's minimum (small grids, fewer tasks than wavefronts: the tuner
+    // has weighed segment length against task count) keep the uniform layout, unless the side
+    // bands take no column checks (then only the few segments at the grid's top and bottom get
+    // shorter).  The shorter segments add tasks: give up groups of the cut until they fit the
+    // wavefronts the device holds at once, else keep the uniform layout.
+    if (p->seg_min > natural && !a.zero_sides) groups = 0;
     MarchLayout L = uniform_layout(p->rows, a.bands, seg);
     for (; groups > 0; --groups) {
         if (groups * ring >= seg) continue;
-        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, lag, reach, ring, !a.zero_sides);
+        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, reach, !a.zero_sides);
         if (C.tasks <= std::max(waves, L.tasks)) {
             L = C;
             break;
         }
     }
+    if (L.n_top + L.n_mid + L.n_bot >= (int64_t(1) << 31) / std::max(1, L.inner))
+        return fail(ST_EUNSUPPORTED, "too many marching tasks for one pass");
     a.seg = L.seg;
-    a.seg_first = L.seg_first;
     a.seg_short = L.seg_short;
-    a.segs_inner = L.segs_inner;
+    a.n_top = int(L.n_top);
+    a.n_mid = int(L.n_mid);
+    a.n_bot = int(L.n_bot);
     a.inner = L.inner;
     a.outer = L.outer;
     a.tasks_outer = L.tasks_outer;

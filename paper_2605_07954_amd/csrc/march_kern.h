@@ -17,18 +17,19 @@ struct MarchArgs {
     void* dst;
     int64_t rows, cols;
     // Tasks: first the outer bands' (band 0 and bands - 1 alternating, segments of seg_short rows),
-    // then the inner bands' (task t: band band0 + t % inner, row of tasks q = t / inner: segment q,
-    // or with ends_first segment 0, then the last one, then segments 1, 2, ...).  An inner band's
-    // first segment is seg_first rows, its last one the rest, and the segments between seg rows.
-    // The tasks that take the edge checks come first: the oldest wavefronts on a SIMD are issued
-    // first.  (The uniform layout: no outer tasks, every band inner from band0 = 0, segments of seg
-    // rows in order.)
+    // then the inner bands' (task t: band band0 + t % inner, row of tasks q = t / inner).  An inner
+    // band runs n_top segments of seg_short rows from its top, then n_mid of seg rows, then n_bot
+    // of seg_short rows (the last one cut at the grid's end); with ends_first the rows of tasks q
+    // take the top segments, then the bottom ones, then the middle ones, else they go in order.
+    // The short segments are those within r * levels rows of the grid's top or bottom, which take
+    // the edge checks, and they come first: the oldest wavefronts on a SIMD are issued first.  (The
+    // uniform layout: no outer tasks, every band inner from band0 = 0, n_top = 0, segments of seg
+    // rows in order and the rest.)
     int64_t tasks;
     int64_t tasks_outer;  // outer * ceil(rows / seg_short)
     int64_t seg;          // rows of an inner band's middle segments
-    int64_t seg_first;    // rows of an inner band's first segment
-    int64_t seg_short;    // rows of an outer band's segments
-    int64_t segs_inner;   // segments of an inner band
+    int64_t seg_short;    // rows of the segments at the grid's top and bottom and of the outer bands
+    int n_top, n_mid, n_bot;
     int bands;
     int inner;            // inner bands
     int band0;            // the first inner band (1, or 0 in the uniform layout)
@@ -69,9 +70,21 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     } else {
         const uint32_t t = uint32_t(task - a.tasks_outer), q = t / uint32_t(a.inner);
         band = a.band0 + int64_t(t - q * uint32_t(a.inner));
-        const int64_t k = !a.ends_first ? int64_t(q) : q == 1 ? a.segs_inner - 1 : q > 1 ? int64_t(q) - 1 : 0;
-        y0 = k == 0 ? 0 : a.seg_first + (k - 1) * a.seg;
-        y1 = k == a.segs_inner - 1 ? a.rows : k == 0 ? a.seg_first : y0 + a.seg;
+        const uint32_t nt = uint32_t(a.n_top), nm = uint32_t(a.n_mid), nb = uint32_t(a.n_bot);
+        // k: the segment's place from the top
+        const uint32_t k = !a.ends_first || q < nt ? q : q < nt + nb ? q + nm : q - nb;
+        int64_t len;
+        if (k < nt) {
+            y0 = int64_t(k) * a.seg_short;
+            len = a.seg_short;
+        } else if (k < nt + nm) {
+            y0 = int64_t(nt) * a.seg_short + int64_t(k - nt) * a.seg;
+            len = a.seg;
+        } else {
+            y0 = int64_t(nt) * a.seg_short + int64_t(nm) * a.seg + int64_t(k - nt - nm) * a.seg_short;
+            len = a.seg_short;
+        }
+        y1 = y0 + len < a.rows ? y0 + len : a.rows;
     }
     // With a halo of +0 the lane shifts that bring a lane its neighbours' columns bring 0 into
     // lane 0 (resp. 63), exactly the halo's value at every level: a band that starts at column 0
