@@ -188,11 +188,13 @@ int stencil_resident_status(const st_plan* plan, const void* workspace, size_t w
  * recomputes r (tb - 1) rows of the lower levels at either end, which on
  * small grids costs more than the idle SIMDs of fewer, longer tasks.  The
  * launch then lengthens the segment by fewer than 2r + 1 rows so that its row
- * loop fills whole unrolled groups.  With the default segments, the tasks that
- * take the grid's edge checks (the outer bands, and each band's segments at the
- * top and bottom) get proportionally shorter ones, so that every task takes
- * about the same time; a segment raised by min_rows keeps one length per band.
- * Bitwise the same results; values above rows act as rows.
+ * loop fills whole unrolled groups.  The tasks that take the grid's edge checks
+ * (the outer bands, and the segments within r tb rows of the top and bottom)
+ * get proportionally shorter segments, so that every task takes about the same
+ * time; a segment raised by min_rows keeps one length per band, except that
+ * with a halo of +0 (whose side bands take no column checks) the top and
+ * bottom rows still go to short segments.  Bitwise the same results; values
+ * above rows act as rows.
  * stencil_autotune sets it.
  * Errors: ST_EINVAL (NULL plan, negative min_rows). */
 int stencil_set_march_segment(st_plan* plan, int64_t min_rows);
