@@ -61,7 +61,7 @@ VARIANT_NAMES = {0: "tiled", 1: "stream", 2: "march", 3: "march8", 4: "march1", 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("sweep.hip", "sweep_body.h", "storage.h", "internal.h", "march.hip", "march_body.h", "march_kern.h",
-              "march_f32_box.hip"):
+              "march_layout.h", "march_f32_box.hip"):
         with open(os.path.join(ROOT, "paper_2605_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -17,7 +17,7 @@
 //
 // Segments are sized on the host so that the number of (band, segment) tasks is close to the number
 // of wavefronts the device holds at once: every wavefront runs one task of about equal duration (the
-// tasks that take the grid's edge checks get proportionally shorter segments, see march_layout).  A
+// tasks that take the grid's edge checks get proportionally shorter segments, see march_layout.h).  A
 // plan may ask for longer segments (stencil_set_march_segment), which the autotuner does for small
 // grids.
 
@@ -49,61 +49,6 @@ MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool x
     return nullptr;
 }
 
-// How a pass's tasks cover the grid (see MarchArgs).
-struct MarchLayout {
-    int64_t seg, seg_short, tasks_outer, tasks;
-    int64_t n_top, n_mid, n_bot;
-    int inner, band0, outer, ends_first;
-};
-
-// Every band split into segments of seg rows, in order, bands minor.
-MarchLayout uniform_layout(int64_t rows, int bands, int64_t seg) {
-    MarchLayout L;
-    L.seg = L.seg_short = seg;
-    L.n_top = 0;
-    L.n_mid = rows / seg;
-    L.n_bot = rows % seg ? 1 : 0;
-    L.inner = bands;
-    L.band0 = 0;
-    L.outer = 0;
-    L.ends_first = 0;
-    L.tasks_outer = 0;
-    L.tasks = int64_t(bands) * (L.n_mid + L.n_bot);
-    return L;
-}
-
-// Tasks that take the edge checks (the two outer bands, and the segments of an inner band that lie
-// within `reach` = r * levels rows of the grid's top or bottom) spend about 1.5 more instructions
-// per cell and level than the footprint's taps (measured: star r = 2 edge tasks run 17 % longer
-// than inner ones of the same length).  A launch lasts as long as its slowest wavefront, so those
-// tasks get segments of seg_short = seg - cut rows: the outer bands' segments, and the segments
-// that cover an inner band's top and bottom `reach` rows; the middle segments, of seg rows, then
-// take no edge checks.  `outer_edges`: the first and last bands take the column checks (else every
-// band is inner).
-MarchLayout march_layout(int64_t rows, int bands, int64_t seg, int64_t cut, int64_t reach, bool outer_edges) {
-    MarchLayout L;
-    L.seg = seg;
-    const int64_t ss = L.seg_short = std::max<int64_t>(seg - cut, 1);
-    L.inner = !outer_edges ? bands : bands >= 3 ? bands - 2 : 0;
-    L.band0 = outer_edges ? 1 : 0;
-    L.outer = !outer_edges ? 0 : bands >= 2 ? 2 : 1;
-    L.ends_first = 1;
-    L.n_top = std::max<int64_t>(1, (reach + ss - 1) / ss);
-    if (L.n_top * ss >= rows) {  // short segments only
-        L.n_top = (rows + ss - 1) / ss;
-        L.n_mid = L.n_bot = 0;
-    } else {
-        // middle segments end at least `reach` rows above the grid's end; the rest (at least
-        // `reach` rows, or all that is left) is cut into short ones
-        const int64_t top = L.n_top * ss;
-        L.n_mid = std::max<int64_t>(0, (rows - top - reach) / seg);
-        L.n_bot = (rows - top - L.n_mid * seg + ss - 1) / ss;
-    }
-    L.tasks_outer = L.outer ? L.outer * ((rows + ss - 1) / ss) : 0;
-    L.tasks = L.tasks_outer + int64_t(L.inner) * (L.n_top + L.n_mid + L.n_bot);
-    return L;
-}
-
 }  // namespace
 
 int march_max_tb(int shape, int radius, int vmax) {
@@ -133,76 +78,23 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     MarchArgs a;
     a.src = src;
     a.dst = dst;
-    a.rows = p->rows;
-    a.cols = p->cols;
     a.b = p->bq;
     a.bc = p->bc;
     a.frame = p->frame;
     a.stop = p->stop;
     std::memcpy(a.w, p->w, sizeof(a.w));
-    const int64_t H = march::halo_lanes(p->radius, levels, V), outw = V * (64 - 2 * H);
-    a.bands = int((p->cols + outw - 1) / outw);
     // A constant halo of +0 with whole-lane accesses (vector, or one column per lane): the first
-    // band starts at column 0 and the last ends at the last column, storing the lanes a halo would
-    // otherwise take (see MarchArgs), so a grid needs up to two bands fewer and its side bands take
-    // no column checks.
+    // band starts at column 0 and the last ends at the last column (march_layout.h).
     const float zero = 0.0f;
-    a.zero_sides = !xbc && mode != 0 && std::memcmp(&p->bq, &zero, sizeof(float)) == 0 && p->cols >= 2 * 64 * V;
-    if (a.zero_sides) {
-        const int64_t sides = 2 * V * (64 - H);
-        a.bands = int(2 + (p->cols > sides ? (p->cols - sides + outw - 1) / outw : 0));
-    }
+    const bool zero_sides =
+        !xbc && mode != 0 && std::memcmp(&p->bq, &zero, sizeof(float)) == 0 && p->cols >= 2 * 64 * V;
     int blocks = 0;
     if (int rc = resident_blocks(reinterpret_cast<const void*>(fn), 0, &blocks)) return rc;
-    const int64_t waves = int64_t(blocks) * MWAVES;
-    const int64_t per_band = std::max<int64_t>(1, waves / a.bands);  // segments per band
-    const int64_t natural = (p->rows + per_band - 1) / per_band;
-    // a segment recomputes r (levels - 1) rows of the lower levels at either end: on small grids
-    // longer segments (fewer tasks than wavefronts) cost less than the recomputation they avoid
-    int64_t seg = std::max<int64_t>(natural, std::min<int64_t>(p->seg_min, p->rows));
-    // A task's row loop runs whole groups of 2r + 1 iterations (seg + 2r(levels - 1) of them, rounded
-    // up), so the segment is rounded up to fill its last group: every task runs the same iterations
-    // as before and there are fewer tasks (rounding down measured slower even on small grids, where
-    // the extra tasks cost more than the shorter ones save).
-    const int64_t ring = 2 * p->radius + 1, part = (seg + 2 * p->radius * (levels - 1)) % ring;
-    if (part && seg < p->rows) seg += ring - part;
     const int taps = p->shape == SHAPE_STAR ? 4 * p->radius + 1 : (2 * p->radius + 1) * (2 * p->radius + 1);
-
-    const int64_t lag = 2 * p->radius * (levels - 1), reach = int64_t(p->radius) * levels;
-    // an edge task of seg_short rows runs as long as an inner one of seg rows:
-    // kappa (seg_short + lag) = seg + lag, kappa = 1 + 1.5 / taps (in whole loop groups)
-    const double kappa = 1.0 + 1.5 / taps;
-    int64_t groups = std::llround(double(seg + lag) * (1.0 - 1.0 / kappa) / double(ring));
-    // Segments raised by the plan's minimum (small grids, fewer tasks than wavefronts: the tuner
-    // has weighed segment length against task count) keep the uniform layout, unless the side
-    // bands take no column checks (then only the few segments at the grid's top and bottom get
-    // shorter).  The shorter segments add tasks: give up groups of the cut until they fit the
-    // wavefronts the device holds at once, else keep the uniform layout.
-    if (p->seg_min > natural && !a.zero_sides) groups = 0;
-    MarchLayout L = uniform_layout(p->rows, a.bands, seg);
-    for (; groups > 0; --groups) {
-        if (groups * ring >= seg) continue;
-        const MarchLayout C = march_layout(p->rows, a.bands, seg, groups * ring, reach, !a.zero_sides);
-        if (C.tasks <= std::max(waves, L.tasks)) {
-            L = C;
-            break;
-        }
-    }
-    if (L.n_top + L.n_mid + L.n_bot >= (int64_t(1) << 31) / std::max(1, L.inner))
+    if (!march::plan_march_tasks(a.map, p->rows, p->cols, V, p->radius, levels, taps, int64_t(blocks) * MWAVES,
+                                 p->seg_min, zero_sides))
         return fail(ST_EUNSUPPORTED, "too many marching tasks for one pass");
-    a.seg = L.seg;
-    a.seg_short = L.seg_short;
-    a.n_top = int(L.n_top);
-    a.n_mid = int(L.n_mid);
-    a.n_bot = int(L.n_bot);
-    a.inner = L.inner;
-    a.outer = L.outer;
-    a.tasks_outer = L.tasks_outer;
-    a.band0 = L.band0;
-    a.ends_first = L.ends_first;
-    a.tasks = L.tasks;
-    if (a.tasks >= (int64_t(1) << 31)) return fail(ST_EUNSUPPORTED, "too many marching tasks for one pass");
-    const int64_t grid = (a.tasks + MWAVES - 1) / MWAVES;
+    const int64_t grid = (a.map.tasks + MWAVES - 1) / MWAVES;
     clear_stale_error();
     hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(64 * MWAVES), 0, s, a);
     ST_LAUNCH_CHECK("sweep_march");

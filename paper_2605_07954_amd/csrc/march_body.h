@@ -7,6 +7,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "march_layout.h"
 #include "star_centre.h"
 #include "storage.h"
 
@@ -66,7 +67,6 @@ __device__ __forceinline__ bool periodic(const MarchView& a) {
     return false;
 }
 
-__host__ __device__ constexpr int halo_lanes(int R, int TB, int V) { return (R * TB + V - 1) / V; }
 
 // DPP wave shifts over the whole wavefront: lane l receives lane l-1 (resp. l+1); lane 0 (resp. 63)
 // receives 0, which only feeds outputs that are never stored.

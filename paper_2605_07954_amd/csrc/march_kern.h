@@ -15,28 +15,7 @@ constexpr int MWAVES = 4;  // wavefronts per workgroup, each with its own task
 struct MarchArgs {
     const void* src;
     void* dst;
-    int64_t rows, cols;
-    // Tasks: first the outer bands' (band 0 and bands - 1 alternating, segments of seg_short rows),
-    // then the inner bands' (task t: band band0 + t % inner, row of tasks q = t / inner).  An inner
-    // band runs n_top segments of seg_short rows from its top, then n_mid of seg rows, then n_bot
-    // of seg_short rows (the last one cut at the grid's end); with ends_first the rows of tasks q
-    // take the top segments, then the bottom ones, then the middle ones, else they go in order.
-    // The short segments are those within r * levels rows of the grid's top or bottom, which take
-    // the edge checks, and they come first: the oldest wavefronts on a SIMD are issued first.  (The
-    // uniform layout: no outer tasks, every band inner from band0 = 0, n_top = 0, segments of seg
-    // rows in order and the rest.)
-    int64_t tasks;
-    int64_t tasks_outer;  // outer * ceil(rows / seg_short)
-    int64_t seg;          // rows of an inner band's middle segments
-    int64_t seg_short;    // rows of the segments at the grid's top and bottom and of the outer bands
-    int n_top, n_mid, n_bot;
-    int bands;
-    int inner;            // inner bands
-    int band0;            // the first inner band (1, or 0 in the uniform layout)
-    int outer;            // outer bands: 0, 1 or 2
-    int ends_first;       // inner bands run their first and last segments first
-    int zero_sides;       // the first band starts at column 0 and the last ends at the last column
-                          // (constant halo of +0 and vector accesses, see sweep_march_body)
+    TaskMap map;        // how the pass's tasks cover the grid (march_layout.h)
     float b;
     int bc;             // boundary rule (march::BC_*)
     const int* stop;    // nullable: when it holds a nonzero value the pass does nothing
@@ -56,59 +35,13 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t task = int64_t(blockIdx.x) * MWAVES + wave;
-    if (task >= a.tasks) return;
+    if (task >= a.map.tasks) return;
     if (a.stop && __hip_atomic_load(a.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     constexpr int H = halo_lanes(R, TB, V);
-    constexpr int OUTW = V * (64 - 2 * H);
-    // (task indices fit 32 bits: one 32-bit division, on the path to the task's first load)
-    int64_t band, y0, y1;
-    if (task < a.tasks_outer) {
-        const bool two = a.outer == 2;
-        band = two && (task & 1) ? a.bands - 1 : 0;
-        y0 = (two ? task >> 1 : task) * a.seg_short;
-        y1 = y0 + a.seg_short < a.rows ? y0 + a.seg_short : a.rows;
-    } else {
-        const uint32_t t = uint32_t(task - a.tasks_outer), q = t / uint32_t(a.inner);
-        band = a.band0 + int64_t(t - q * uint32_t(a.inner));
-        const uint32_t nt = uint32_t(a.n_top), nm = uint32_t(a.n_mid), nb = uint32_t(a.n_bot);
-        // k: the segment's place from the top
-        const uint32_t k = !a.ends_first || q < nt ? q : q < nt + nb ? q + nm : q - nb;
-        int64_t len;
-        if (k < nt) {
-            y0 = int64_t(k) * a.seg_short;
-            len = a.seg_short;
-        } else if (k < nt + nm) {
-            y0 = int64_t(nt) * a.seg_short + int64_t(k - nt) * a.seg;
-            len = a.seg;
-        } else {
-            y0 = int64_t(nt) * a.seg_short + int64_t(nm) * a.seg + int64_t(k - nt - nm) * a.seg_short;
-            len = a.seg_short;
-        }
-        y1 = y0 + len < a.rows ? y0 + len : a.rows;
-    }
-    // With a halo of +0 the lane shifts that bring a lane its neighbours' columns bring 0 into
-    // lane 0 (resp. 63), exactly the halo's value at every level: a band that starts at column 0
-    // stores its first H lanes too, and one that ends at the last column its last H (the grid's
-    // sides need no halo lanes).  The bands between follow the first at OUTW columns each, the
-    // last of them moved left where it would pass the last band's end (its overlap with the last
-    // band stores the same values).
-    int64_t X0 = band * OUTW - V * H;
-    int lo = -1, hi = -1;
-    if (a.zero_sides) {
-        const int64_t last = a.cols - 64 * V;
-        if (band == 0) {
-            X0 = 0;
-            lo = 0;
-        } else if (band == a.bands - 1) {
-            X0 = last;
-            hi = 64;
-        } else {
-            X0 = (band - 1) * OUTW + V * (64 - 2 * H);
-            if (X0 > last) X0 = last;
-        }
-    }
-    const MarchView v{a.src, a.dst, a.rows, a.cols, a.b, a.bc, a.frame};
-    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, y0, y1, X0, lo, hi);
+    const TaskRows tr = task_rows(a.map, task);
+    const BandCols bc = band_cols(a.map, tr.band, V, H);
+    const MarchView v{a.src, a.dst, a.map.rows, a.map.cols, a.b, a.bc, a.frame};
+    march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, tr.y0, tr.y1, bc.x0, bc.lo, bc.hi);
 }
 
 template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
