@@ -34,13 +34,15 @@ using march_k::MWAVES;
 
 namespace {
 
-MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool xbc) {
+MarchFn march_lookup(int storage, int mode, int shape, int r, int levels, bool xbc, bool periodic) {
     const bool box = shape == SHAPE_BOX;
     if (xbc) {
-        if (storage == ST_F32) return box ? march_lookup_xbc_f32_box(mode, r, levels) : march_lookup_xbc_f32_star(mode, r, levels);
+        if (storage == ST_F32)
+            return box ? march_lookup_xbc_f32_box(mode, r, levels, periodic) : march_lookup_xbc_f32_star(mode, r, levels, periodic);
         if (storage == ST_BF16)
-            return box ? march_lookup_xbc_bf16_box(mode, r, levels) : march_lookup_xbc_bf16_star(mode, r, levels);
-        if (storage == ST_F16) return box ? march_lookup_xbc_f16_box(mode, r, levels) : march_lookup_xbc_f16_star(mode, r, levels);
+            return box ? march_lookup_xbc_bf16_box(mode, r, levels, periodic) : march_lookup_xbc_bf16_star(mode, r, levels, periodic);
+        if (storage == ST_F16)
+            return box ? march_lookup_xbc_f16_box(mode, r, levels, periodic) : march_lookup_xbc_f16_star(mode, r, levels, periodic);
         return nullptr;
     }
     if (storage == ST_F32) return box ? march_lookup_f32_box(mode, r, levels) : march_lookup_f32_star(mode, r, levels);
@@ -73,7 +75,7 @@ int launch_march(const st_plan* p, const void* src, void* dst, int levels, int v
     const bool aligned = (reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % 16) == 0;
     const int mode = vmax == 1 ? 1 : aligned && vmax == 8 && p->cols % 8 == 0 ? 8 : aligned && p->cols % 4 == 0 ? 4 : 0;
     const int V = mode == 8 ? 8 : mode == 1 ? 1 : 4;
-    MarchFn fn = march_lookup(p->storage, mode, p->shape, p->radius, levels, xbc);
+    MarchFn fn = march_lookup(p->storage, mode, p->shape, p->radius, levels, xbc, p->bc == ST_BC_PERIODIC);
     if (!fn) return fail(ST_EUNSUPPORTED, "no row-marching kernel for this shape/radius/depth");
     MarchArgs a;
     a.src = src;

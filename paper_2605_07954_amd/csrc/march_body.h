@@ -53,18 +53,18 @@ __device__ __forceinline__ float frame_value(const MarchView& a, int R, int64_t 
 
 // Value that an out-of-grid cell holds at every level: b, or its frame value.  (Periodic grids
 // have none: their outside cells are loaded from, and computed like, the cells they wrap to.)
-// XBC: the kernel takes the boundary rule from the view; else it is the constant halo b, and the
-// kernel is built without the other rules (whose edge code would cost the constant-halo kernels
-// scalar registers).
-template <int S, bool XBC>
+// XBC: the boundary rule the kernel is built for (XBC_CONST: the constant halo b; XBC_PERIODIC;
+// XBC_FRAME), so that each kernel carries the edge code of one rule only (the others' would cost it
+// registers: built for both, the periodic edge loop ran ten times the instructions of the inner one).
+constexpr int XBC_CONST = 0, XBC_PERIODIC = 1, XBC_FRAME = 2;
+template <int S, int XBC>
 __device__ __forceinline__ float outside_value(const MarchView& a, int R, int64_t gy, int64_t gx) {
-    if constexpr (XBC) return a.bc == BC_FRAME ? frame_value<S>(a, R, gy, gx) : a.b;
+    if constexpr (XBC == XBC_FRAME) return frame_value<S>(a, R, gy, gx);
     return a.b;
 }
-template <bool XBC>
-__device__ __forceinline__ bool periodic(const MarchView& a) {
-    if constexpr (XBC) return a.bc == BC_PERIODIC;
-    return false;
+template <int XBC>
+__device__ __forceinline__ constexpr bool periodic(const MarchView&) {
+    return XBC == XBC_PERIODIC;
 }
 
 
@@ -349,7 +349,7 @@ __device__ __forceinline__ void set_own(Row<R, V>& x, const Cells<V>& q) {
 // outside value when it is used, see `cells_of`, or never feed a stored output), and EDGE tasks
 // clamp columns into the grid too, or wrap row and columns on a periodic grid.  A lane's vector
 // never straddles the grid's side (cols % V == 0, and so is its first column), so it wraps whole.
-template <int S, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
+template <int S, int V, bool VEC, bool EDGE, int XBC, bool UP = false>
 __device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
                                                      int64_t X0, const RowSpan& sp) {
     const int64_t rows = a.rows, cols = a.cols;
@@ -373,7 +373,7 @@ __device__ __forceinline__ RawT<S, V, VEC> fetch_raw(const MarchView& a, int64_t
     }
 }
 
-template <int S, int R, int V, bool EDGE, bool XBC, typename RawRow>
+template <int S, int R, int V, bool EDGE, int XBC, typename RawRow>
 __device__ __forceinline__ Cells<V> cells_of(const MarchView& a, const RawRow& r, int64_t gy, int64_t gx,
                                              const ColMask<V>& m) {
     Cells<V> q = widen<S, V>(r);
@@ -389,7 +389,7 @@ __device__ __forceinline__ Cells<V> cells_of(const MarchView& a, const RawRow& r
 // accesses EDGE tasks skip the load for cells outside the grid, which take their outside value (a
 // periodic grid loads the cells they wrap to); with element accesses they load clamped (or wrapped)
 // addresses and substitute.  Rows are clamped into the task's row span as in `fetch_raw`.
-template <int S, int R, int V, bool VEC, bool EDGE, bool XBC, bool UP = false>
+template <int S, int R, int V, bool VEC, bool EDGE, int XBC, bool UP = false>
 __device__ __forceinline__ Cells<V> load_now(const MarchView& a, int64_t gy, int64_t gx, const ColMask<V>& m,
                                              int64_t X0, const RowSpan& sp) {
     const int64_t rows = a.rows, cols = a.cols;
@@ -499,7 +499,7 @@ __device__ __forceinline__ Cells<V> apply(const Row<R, V>* ring, int base, const
 // UP marches the segment from its last row to its first: the same steps with the row order
 // reversed (iteration i computes level-1 row y1 - 1 + R(TB-1) - i, and so on), and each ring read
 // through the reversed slot order, so that every cell still takes its taps in row-major order.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, bool XBC, bool UP = false,
+template <int S, int R, int V, int SHAPE, int TB, int D, bool EDGE, bool VEC, int XBC, bool UP = false,
           bool SHARE = false>
 __device__ __forceinline__ void march_levels(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                              int64_t X0, const SharedRows& sh = SharedRows{nullptr, 0, 0},
@@ -675,8 +675,8 @@ __device__ __forceinline__ bool task_edge(const MarchView& a, int64_t y0, int64_
 
 // One task: output rows [y0, y1) of the band whose first loaded column is X0, TB levels, input rows
 // loaded D iterations ahead (0: one); VEC selects vector or element accesses (see RawT); XBC: the
-// boundary rule comes from the view (periodic or framed grids), else the halo is the constant b.
-template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true, bool XBC = false>
+// boundary rule of the edge tasks (XBC_PERIODIC, XBC_FRAME, else the constant halo b).
+template <int S, int R, int V, int SHAPE, int TB, int D, bool VEC = true, int XBC = XBC_CONST>
 __device__ __forceinline__ void march_task(const MarchView& a, const float* w, int lane, int64_t y0, int64_t y1,
                                            int64_t X0, int lo = -1, int hi = -1) {
     const bool edge = task_edge<R, TB>(a, y0, y1, X0, V);
@@ -684,7 +684,7 @@ __device__ __forceinline__ void march_task(const MarchView& a, const float* w, i
     load_weights<R, V, SHAPE>(w, wv);
     const SharedRows none{nullptr, 0, 0};
     if (edge) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC>(a, wv, lane, y0, y1, X0, none, lo, hi);
-    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false>(a, wv, lane, y0, y1, X0, none, lo, hi);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, XBC_CONST>(a, wv, lane, y0, y1, X0, none, lo, hi);
 }
 
 // The same task marched upwards when `up` is set (constant halo), taking the input rows `sh` from LDS.
@@ -695,10 +695,10 @@ __device__ __forceinline__ void march_task_dir(const MarchView& a, const float* 
                                                int64_t X0, bool up, const SharedRows& sh) {
     float wv[(2 * R + 1) * (2 * R + 1)];
     load_weights<R, V, SHAPE>(w, wv);
-    if (up) march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, true, true>(a, wv, lane, y0, y1, X0, sh);
+    if (up) march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC_CONST, true, true>(a, wv, lane, y0, y1, X0, sh);
     else if (task_edge<R, TB>(a, y0, y1, X0, V))
-        march_levels<S, R, V, SHAPE, TB, D, true, VEC, false, false, true>(a, wv, lane, y0, y1, X0, sh);
-    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, false, false, true>(a, wv, lane, y0, y1, X0, sh);
+        march_levels<S, R, V, SHAPE, TB, D, true, VEC, XBC_CONST, false, true>(a, wv, lane, y0, y1, X0, sh);
+    else march_levels<S, R, V, SHAPE, TB, D, false, VEC, XBC_CONST, false, true>(a, wv, lane, y0, y1, X0, sh);
 }
 
 // Stage input rows r0 .. r0 + R TB - 1 of the task (y0, y1, X0) in LDS (`dst[(row - o0) * 64 + lane]`) as
@@ -716,11 +716,11 @@ __device__ __forceinline__ void stage_rows(const MarchView& a, int lane, int64_t
     if (task_edge<R, TB>(a, y0, y1, X0, V)) {
         const RowSpan sp{need_lo < 0 ? 0 : need_lo, need_hi > a.rows - 1 ? a.rows - 1 : need_hi};
 #pragma unroll
-        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, true, false>(a, r0 + t, gx, cm, X0, sp);
+        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, true, XBC_CONST>(a, r0 + t, gx, cm, X0, sp);
     } else {
         const RowSpan sp{need_lo, need_hi};
 #pragma unroll
-        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, false, false>(a, r0 + t, gx, cm, X0, sp);
+        for (int t = 0; t < RT; ++t) raw[t] = fetch_raw<S, V, VEC, false, XBC_CONST>(a, r0 + t, gx, cm, X0, sp);
     }
 #pragma unroll
     for (int t = 0; t < RT; ++t) dst[(r0 + t - o0) * 64 + lane] = __builtin_bit_cast(float4, raw[t]);

@@ -30,7 +30,7 @@ constexpr int fifo_rows(int R, int SHAPE, int TB) {
     return SHAPE == SHAPE_STAR || R <= 2 || TB == 1 ? 2 * R + 1 : 0;
 }
 
-template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, int XBC>
 __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     const int lane = int(threadIdx.x & 63);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -44,7 +44,7 @@ __device__ __forceinline__ void sweep_march_body(const MarchArgs& a) {
     march_task<S, R, V, SHAPE, TB, fifo_rows(R, SHAPE, TB), VEC, XBC>(v, a.w, lane, tr.y0, tr.y1, bc.x0, bc.lo, bc.hi);
 }
 
-template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, int XBC>
 __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
     sweep_march_body<S, R, V, SHAPE, TB, VEC, XBC>(a);
 }
@@ -53,14 +53,14 @@ __global__ __launch_bounds__(64 * MWAVES) void sweep_march(MarchArgs a) {
 // that let three wavefronts share a SIMD; held to 168, the compiler keeps six values in scratch (one
 // access per 192 FMAs), and the third wavefront hides more load latency than that costs (measured
 // +2 % on box49).
-template <int S, int R, int V, int SHAPE, int TB, bool VEC, bool XBC>
+template <int S, int R, int V, int SHAPE, int TB, bool VEC, int XBC>
 __global__ __launch_bounds__(64 * MWAVES) __attribute__((amdgpu_waves_per_eu(3))) void sweep_march_w3(MarchArgs a) {
     sweep_march_body<S, R, V, SHAPE, TB, VEC, XBC>(a);
 }
 
 using MarchFn = void (*)(MarchArgs);
 
-template <int S, int R, int V, int SH, int TB, bool VEC = true, bool XBC = false>
+template <int S, int R, int V, int SH, int TB, bool VEC = true, int XBC = XBC_CONST>
 MarchFn march_kernel() {
     if constexpr (V == 4 && R == 3 && TB == 2 && VEC) return sweep_march_w3<S, R, V, SH, TB, VEC, XBC>;
     else return sweep_march<S, R, V, SH, TB, VEC, XBC>;
@@ -68,7 +68,7 @@ MarchFn march_kernel() {
 
 // Depths per shape and radius: the rings of TB levels must fit the register file next to each
 // other (a star ring row holds V values, a box ring row V + 2r).
-template <int S, int V, int SH, bool VEC, bool XBC = false>
+template <int S, int V, int SH, bool VEC, int XBC = XBC_CONST>
 MarchFn march_fn(int r, int levels) {
 #define ST_MARCH(R, TB) \
     if (r == R && levels == TB) return march_kernel<S, R, V, SH, TB, VEC, XBC>();
@@ -120,14 +120,19 @@ MarchFn march_lookup_shape(int mode, int r, int levels) {
     return march_fn<S, 4, SH, false>(r, levels);
 }
 
-// The same kernels built with the periodic and framed boundary rules in their edge tasks (four
+// The same kernels built with the periodic or the framed boundary rule in their edge tasks (four
 // columns per lane with vector or element accesses, or one; no eight-column form).
-template <int S, int SH>
-MarchFn march_lookup_shape_xbc(int mode, int r, int levels) {
-    if (mode == 4) return march_fn<S, 4, SH, true, true>(r, levels);
-    if (mode == 1) return march_fn<S, 1, SH, true, true>(r, levels);
-    if (mode == 0) return march_fn<S, 4, SH, false, true>(r, levels);
+template <int S, int SH, int XBC>
+MarchFn march_lookup_shape_rule(int mode, int r, int levels) {
+    if (mode == 4) return march_fn<S, 4, SH, true, XBC>(r, levels);
+    if (mode == 1) return march_fn<S, 1, SH, true, XBC>(r, levels);
+    if (mode == 0) return march_fn<S, 4, SH, false, XBC>(r, levels);
     return nullptr;
+}
+template <int S, int SH>
+MarchFn march_lookup_shape_xbc(int mode, int r, int levels, bool periodic) {
+    return periodic ? march_lookup_shape_rule<S, SH, XBC_PERIODIC>(mode, r, levels)
+                    : march_lookup_shape_rule<S, SH, XBC_FRAME>(mode, r, levels);
 }
 
 }  // namespace march_k
@@ -139,11 +144,11 @@ march_k::MarchFn march_lookup_bf16_star(int mode, int r, int levels);
 march_k::MarchFn march_lookup_bf16_box(int mode, int r, int levels);
 march_k::MarchFn march_lookup_f16_star(int mode, int r, int levels);
 march_k::MarchFn march_lookup_f16_box(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_f32_star(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_f32_box(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_bf16_star(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_bf16_box(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_f16_star(int mode, int r, int levels);
-march_k::MarchFn march_lookup_xbc_f16_box(int mode, int r, int levels);
+march_k::MarchFn march_lookup_xbc_f32_star(int mode, int r, int levels, bool periodic);
+march_k::MarchFn march_lookup_xbc_f32_box(int mode, int r, int levels, bool periodic);
+march_k::MarchFn march_lookup_xbc_bf16_star(int mode, int r, int levels, bool periodic);
+march_k::MarchFn march_lookup_xbc_bf16_box(int mode, int r, int levels, bool periodic);
+march_k::MarchFn march_lookup_xbc_f16_star(int mode, int r, int levels, bool periodic);
+march_k::MarchFn march_lookup_xbc_f16_box(int mode, int r, int levels, bool periodic);
 
 }  // namespace st

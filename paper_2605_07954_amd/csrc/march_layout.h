@@ -167,7 +167,7 @@ inline bool zoned_map(TaskMap& m, int64_t seg, int64_t cut, int64_t reach, bool 
 // accesses, cols >= 2 * 64 V), `taps` the footprint's taps.  Returns false when the pass would need
 // 2^31 tasks or more.
 inline bool plan_march_tasks(TaskMap& m, int64_t rows, int64_t cols, int V, int r, int levels, int taps,
-                             int64_t waves, int64_t seg_min, bool zero_sides) {
+                             int64_t waves, int64_t seg_min, bool zero_sides, double edge_cost = 1.5) {
     const int H = halo_lanes(r, levels, V);
     const int64_t outw = int64_t(V) * (64 - 2 * H);
     m.rows = rows;
@@ -192,7 +192,7 @@ inline bool plan_march_tasks(TaskMap& m, int64_t rows, int64_t cols, int V, int 
     const int64_t ring = 2 * r + 1, lag = 2 * int64_t(r) * (levels - 1), reach = int64_t(r) * levels;
     const int64_t part = (seg + lag) % ring;
     if (part && seg < rows) seg += ring - part;
-    const double kappa = 1.0 + 1.5 / taps;
+    const double kappa = 1.0 + edge_cost / taps;
     int64_t groups = std::llround(double(seg + lag) * (1.0 - 1.0 / kappa) / double(ring));
     // Segments raised by the plan's minimum (small grids, fewer tasks than wavefronts: the tuner has
     // weighed segment length against task count) keep the uniform layout, unless the sides are zero

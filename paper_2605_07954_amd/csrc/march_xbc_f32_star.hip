@@ -4,8 +4,8 @@
 
 namespace st {
 
-march_k::MarchFn march_lookup_xbc_f32_star(int mode, int r, int levels) {
-    return march_k::march_lookup_shape_xbc<ST_F32, SHAPE_STAR>(mode, r, levels);
+march_k::MarchFn march_lookup_xbc_f32_star(int mode, int r, int levels, bool periodic) {
+    return march_k::march_lookup_shape_xbc<ST_F32, SHAPE_STAR>(mode, r, levels, periodic);
 }
 
 }  // namespace st
