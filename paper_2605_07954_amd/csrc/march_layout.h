@@ -167,7 +167,8 @@ inline bool zoned_map(TaskMap& m, int64_t seg, int64_t cut, int64_t reach, bool 
 // accesses, cols >= 2 * 64 V), `taps` the footprint's taps.  Returns false when the pass would need
 // 2^31 tasks or more.
 inline bool plan_march_tasks(TaskMap& m, int64_t rows, int64_t cols, int V, int r, int levels, int taps,
-                             int64_t waves, int64_t seg_min, bool zero_sides, double edge_cost = 1.5) {
+                             int64_t waves, int64_t seg_min, bool zero_sides) {
+    constexpr double edge_cost = 1.5;  // extra instructions per cell and level of an edge task
     const int H = halo_lanes(r, levels, V);
     const int64_t outw = int64_t(V) * (64 - 2 * H);
     m.rows = rows;
