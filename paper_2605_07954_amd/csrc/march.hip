@@ -13,7 +13,9 @@
 // slots become fixed registers because the row loop is unrolled over the ring length.  With several
 // levels per pass further rings hold the intermediate levels.  Level l is exact on columns at
 // least r*l away from the band's loaded edge, so a band writes V (64 - 2 H) columns with
-// H = ceil(r tb / V) halo lanes per side.
+// H = ceil(r tb / V) halo lanes per side (with a halo of +0 the bands at the grid's sides write
+// theirs too, see march_layout.h).  A wavefront lowers its priority as its task progresses, so the
+// tasks sharing a SIMD finish together (march_body.h).
 //
 // Segments are sized on the host so that the number of (band, segment) tasks is close to the number
 // of wavefronts the device holds at once: every wavefront runs one task of about equal duration (the
