@@ -6,9 +6,9 @@
 //
 // One workgroup owns a TY x TX column of the grid and marches along z over a segment of planes:
 // the 2r + 1 input planes of the current output plane sit in an LDS ring, each with its r-deep
-// (y, x) halo; every iteration stores the plane fetched during the previous one into the slot the
-// oldest plane leaves, starts fetching the next plane into registers, and computes its cells of the
-// output plane from the ring while that fetch is in flight.  A wavefront covers one row of the
+// (y, x) halo; every iteration stores a plane fetched earlier into the slot the oldest plane leaves,
+// starts fetching the plane after next into registers (two register sets, so two planes are in
+// flight), and computes its cells of the output plane from the ring meanwhile.  A wavefront covers one row of the
 // tile (64 consecutive columns), so loads and stores are coalesced and LDS reads of one tap hit 64
 // consecutive words.  One level per pass (no temporal blocking): HBM-bound for the 7-point star
 // (8 bytes and 13 FLOP per update), LDS-bound for large boxes.
@@ -88,11 +88,12 @@ __global__ __launch_bounds__(NT3) void sweep3d(Args3 a) {
         fetch_plane<S, R>(a, pre, z0 - R + q, y0, x0);
         store_plane<R>(ring[q], pre);
     }
+    // planes fetched two ahead (two register sets, the loop unrolled by two): twice the bytes in
+    // flight per workgroup while a plane computes
+    P pre2;
     fetch_plane<S, R>(a, pre, z0 + R, y0, x0);
-    for (int64_t z = z0; z < z1; ++z) {
-        store_plane<R>(ring[int((z - z0 + 2 * R) % K)], pre);  // plane z + R
-        __syncthreads();
-        if (z + 1 < z1) fetch_plane<S, R>(a, pre, z + 1 + R, y0, x0);  // in flight while plane z computes
+    if (z0 + 1 < z1) fetch_plane<S, R>(a, pre2, z0 + 1 + R, y0, x0);
+    auto compute = [&](int64_t z) {
         const int c_slot = int((z - z0 + R) % K);
 #pragma unroll
         for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {
@@ -114,7 +115,19 @@ __global__ __launch_bounds__(NT3) void sweep3d(Args3 a) {
             const int64_t y = y0 + ty, x = x0 + tx;
             if (y < a.rows && x < a.cols) dst[(z * a.rows + y) * a.cols + x] = Fmt<S>::st(acc);
         }
-        __syncthreads();  // every thread is done with the slot the next iteration overwrites
+    };
+    for (int64_t z = z0; z < z1; z += 2) {
+        store_plane<R>(ring[int((z - z0 + 2 * R) % K)], pre);  // plane z + R
+        __syncthreads();
+        if (z + 2 < z1) fetch_plane<S, R>(a, pre, z + 2 + R, y0, x0);
+        compute(z);
+        __syncthreads();  // every thread is done with the slot the next store overwrites
+        if (z + 1 >= z1) break;
+        store_plane<R>(ring[int((z + 1 - z0 + 2 * R) % K)], pre2);  // plane z + 1 + R
+        __syncthreads();
+        if (z + 3 < z1) fetch_plane<S, R>(a, pre2, z + 3 + R, y0, x0);
+        compute(z + 1);
+        __syncthreads();
     }
 }
 
