@@ -21,8 +21,8 @@ namespace st {
 
 namespace {
 
-constexpr int TX = 64, TY = 16, NT3 = 256;
-constexpr int ROWS_PER_THREAD = TY / (NT3 / TX);  // 4
+constexpr int TX = 64, TY = 32, NT3 = 256;
+constexpr int ROWS_PER_THREAD = TY / (NT3 / TX);  // 8
 
 struct Args3 {
     const void* src;
